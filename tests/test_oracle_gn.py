@@ -1,0 +1,245 @@
+"""Pins of the oracle's graph step: eq. (1) residual, Huber/IRLS (Sec. III-A), E_global eq. (5), the
+Jacobians of eq. (6) with the -/+Ad endpoint maps, eq. (7) and the epsilon ladder.
+
+Independent pins: a hand-worked residual (golden fixture), finite differences of the oracle's own
+scalar cost and of its residual vector (so an analytic Jacobian with a wrong sign, index or dropped
+term fails), exact-correspondence graphs whose optimum is the ground truth (quadratic convergence of
+Gauss-Newton), gauge invariance of E, numpy's dense solver, and forced factorisation failures."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.helpers import exact_graph, perturb
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tangent_step(poses, k, tau):
+    T = np.zeros((poses.shape[0], 7))
+    T[k] = tau
+    return O.sim3_update(poses, T)
+
+
+def test_residual_golden():
+    """Hand-worked eq. (1) for one match (tests/golden/residual_case.json)."""
+    case = json.load(open(os.path.join(GOLDEN, "residual_case.json")))
+    xyz = [np.array(case["X_i"], float).reshape(1, 1, 3), np.array(case["X_j"], float).reshape(1, 1, 3)]
+    conf = [np.array([[case["C_i"]]], float), np.array([[case["C_j"]]], float)]
+    g = O.Graph(xyz, conf, [(0, 1)], [np.array([0], np.int32)])
+    poses = np.array([case["pose_i"], case["pose_j"]], float)
+    r, w, ok = O.edge_residuals(g, poses, 0)
+    assert ok[0]
+    assert np.allclose(r[0], case["r_expected"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(w[0], case["w_expected"], rtol=1e-12)
+    assert abs(O.cost(g, poses) - case["E_expected"]) < 1e-9 * case["E_expected"]
+
+
+def test_huber_continuity_and_values():
+    """rho and w from E and residuals: inside kappa rho = r^2/2, w = 1; outside k|r| - k^2/2, k/|r|."""
+    k = 1.345
+    for r0 in [0.3, k - 1e-9, k + 1e-9, 4.0, -7.5]:
+        # one match, range row only: X_i at distance 100 along z, X_j at 100 + delta (ray residual 0)
+        delta = r0 * 10.0  # q = 1 -> r = e / sigma_d
+        xyz = [np.array([[[0, 0, 100.0]]]), np.array([[[0, 0, 100.0 + delta]]])]
+        conf = [np.ones((1, 1)), np.ones((1, 1))]
+        g = O.Graph(xyz, conf, [(0, 1)], [np.array([0], np.int32)])
+        poses = np.array([[0, 0, 0, 0, 0, 0, 1, 1.0]] * 2)
+        r, w, _ = O.edge_residuals(g, poses, 0)
+        assert abs(r[0, 3] - r0) < 1e-9 and np.all(r[0, :3] == 0)
+        a = abs(r0)
+        rho = 0.5 * r0 * r0 if a <= k else k * a - 0.5 * k * k
+        assert abs(O.cost(g, poses) - rho) < 1e-9
+        assert abs(w[0, 3] - (1.0 if a <= k else k / a)) < 1e-12
+
+
+def _graph(seed=0, n_kf=3, H=10, W=12, scale_e=1.0):
+    xyz, conf, edges, idx, poses = exact_graph(n_kf=n_kf, H=H, W=W, seed=seed)
+    g = O.Graph(xyz, conf, edges, idx, anchors=())
+    return g, poses
+
+
+@pytest.mark.parametrize("noise", [0.002, 0.05])
+def test_gradient_matches_finite_differences(noise):
+    """g of eq. (7) equals dE/dtau (central FD through Exp) - inliers (0.002) and outliers (0.05)."""
+    g, gt = _graph(seed=1)
+    rng = np.random.default_rng(2)
+    poses = perturb(gt, rng, rot=noise, trans=noise, scale=noise, fixed=())
+    H, gvec, E, cnt, _, _ = O.gn_assemble(g, poses)
+    h = 1e-6
+    fd = np.zeros_like(gvec)
+    for k in range(g.n_kf):
+        for a in range(7):
+            d = np.zeros(7)
+            d[a] = h
+            fd[7 * k + a] = (O.cost(g, tangent_step(poses, k, d)) - O.cost(g, tangent_step(poses, k, -d))) / (2 * h)
+    assert np.abs(fd - gvec).max() <= 1e-5 * np.abs(gvec).max()
+
+
+def test_hessian_matches_fd_jacobian_of_residuals():
+    """H = sum_c w_c J_c^T J_c with J the whitened-residual Jacobian w.r.t. both pose tangents, taken
+    here by central differences of the oracle's residual vector."""
+    g, gt = _graph(seed=3, n_kf=2)
+    rng = np.random.default_rng(4)
+    poses = perturb(gt, rng, rot=0.01, trans=0.01, scale=0.01, fixed=())
+    H, gvec, E, cnt, _, _ = O.gn_assemble(g, poses)
+    r0, w0, ok = O.edge_residuals(g, poses, 0)
+    h = 1e-6
+    J = np.zeros((r0.shape[0], 4, 14))
+    for k in range(2):
+        for a in range(7):
+            d = np.zeros(7)
+            d[a] = h
+            rp, _, _ = O.edge_residuals(g, tangent_step(poses, k, d), 0)
+            rm, _, _ = O.edge_residuals(g, tangent_step(poses, k, -d), 0)
+            J[:, :, 7 * k + a] = (rp - rm) / (2 * h)
+    J = J[ok]
+    w = w0[ok]
+    Hfd = np.einsum("pc,pca,pcb->ab", w, J, J)
+    gfd = np.einsum("pc,pca,pc->a", w, J, r0[ok])
+    # g in eq. (7) is J_e^T W e with W = w q / sigma^2, i.e. sum_c w_c r_c dr_c/dtau
+    i, j = int(g.ei[0]), int(g.ej[0])
+    blk = np.ix_(list(range(7 * i, 7 * i + 7)) + list(range(7 * j, 7 * j + 7)),
+                 list(range(7 * i, 7 * i + 7)) + list(range(7 * j, 7 * j + 7)))
+    assert np.abs(H[blk] - Hfd).max() <= 2e-6 * np.abs(H).max()
+    assert np.abs(gvec[[*range(7 * i, 7 * i + 7), *range(7 * j, 7 * j + 7)]] - gfd).max() <= 2e-6 * np.abs(gvec).max()
+    # endpoint structure of the text after eq. (6): blocks [[A, -A], [-A, A]]
+    A = H[7 * j:7 * j + 7, 7 * j:7 * j + 7]
+    assert np.abs(H[7 * i:7 * i + 7, 7 * i:7 * i + 7] - A).max() <= 1e-9 * np.abs(A).max()
+    assert np.abs(H[7 * i:7 * i + 7, 7 * j:7 * j + 7] + A).max() <= 1e-9 * np.abs(A).max()
+
+
+def test_exact_correspondences_recover_ground_truth():
+    """Zero-residual graphs: GN from perturbed poses converges to the true poses, quadratically."""
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=4, H=12, W=16, seed=5)
+    g = O.Graph(xyz, conf, edges, idx, anchors=(0,))
+    rng = np.random.default_rng(6)
+    poses = perturb(gt, rng, rot=0.01, trans=0.02, scale=0.01)
+    errs = [O.pose_error(poses, gt).max()]
+    for _ in range(6):
+        poses, c, st, _ = O.gn_step(g, poses)
+        assert st == 0
+        errs.append(O.pose_error(poses, gt).max())
+    assert errs[-1] < 1e-9
+    # quadratic phase: err_{k+1} <= C err_k^2 once small
+    assert errs[2] < 50 * errs[1] ** 2 + 1e-12
+    assert np.array_equal(poses[0], gt[0])  # the anchor never moves
+    assert O.cost(g, poses) < 1e-12
+
+
+def test_gauge_invariance():
+    g, gt = _graph(seed=8, n_kf=3)
+    rng = np.random.default_rng(9)
+    poses = perturb(gt, rng, rot=0.05, trans=0.05, scale=0.05, fixed=())
+    E0 = O.cost(g, poses)
+    G = O.sim3_exp(rng.normal(size=7))[0]
+    moved = np.stack([O.compose(G, p) for p in poses])
+    assert abs(O.cost(g, moved) - E0) <= 1e-10 * E0
+
+
+def test_anchor_rows_are_identity():
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=3, seed=10)
+    g = O.Graph(xyz, conf, edges, idx, anchors=(1,))
+    poses = perturb(gt, np.random.default_rng(1), fixed=())
+    H, gv, *_ = O.gn_assemble(g, poses)
+    assert np.array_equal(H[7:14, 7:14], np.eye(7))
+    assert np.all(H[7:14, :7] == 0) and np.all(H[:7, 7:14] == 0) and np.all(gv[7:14] == 0)
+    new, _, _, tau = O.gn_step(g, poses)
+    assert np.all(tau[7:14] == 0) and np.array_equal(new[1], poses[1])
+
+
+def test_chol_ladder_solves_spd():
+    rng = np.random.default_rng(12)
+    A = rng.normal(size=(30, 30))
+    H = A @ A.T + 0.1 * np.eye(30)
+    gv = rng.normal(size=30)
+    tau, st = O.chol_ladder(H, gv)
+    assert st == 0
+    M = H + 1e-6 * np.eye(30)
+    assert np.linalg.norm(M @ tau + gv) <= 1e-10 * np.linalg.norm(gv)
+    assert np.allclose(tau, np.linalg.solve(M, -gv), rtol=1e-9, atol=1e-12)
+    tau, st = O.chol_ladder(H, gv, lam=0.5)
+    M = H + 0.5 * np.diag(np.diag(H)) + 1e-6 * np.eye(30)
+    assert st == 0 and np.allclose(tau, np.linalg.solve(M, -gv), rtol=1e-9, atol=1e-12)
+
+
+def test_chol_ladder_escalates_and_gives_up():
+    """Failure handling of the text after eq. (7): eps_r = 1e-6 * 100^r, six attempts, zero step."""
+    rng = np.random.default_rng(13)
+    Q, _ = np.linalg.qr(rng.normal(size=(12, 12)))
+    ev = np.linspace(1.0, 5.0, 12)
+    ev[0] = -0.5
+    H = Q @ np.diag(ev) @ Q.T
+    gv = rng.normal(size=12)
+    tau, st = O.chol_ladder(H, gv)
+    assert st == 3  # 1e-6, 1e-4, 1e-2 fail; 1.0 makes the smallest eigenvalue +0.5
+    assert np.allclose(tau, np.linalg.solve(H + np.eye(12), -gv), rtol=1e-9)
+    ev[0] = -1e5
+    H = Q @ np.diag(ev) @ Q.T
+    tau, st = O.chol_ladder(H, gv)
+    assert st == -1 and np.all(tau == 0)
+    Hn = H.copy()
+    Hn[3, 3] = np.nan
+    tau, st = O.chol_ladder(Hn, gv)
+    assert st == -1 and np.all(tau == 0)
+
+
+def test_invalid_pixels_skipped():
+    """Holes (zero or non-finite points) and idx = -1 never reach H, g or E."""
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=2, seed=14)
+    poses = perturb(gt, np.random.default_rng(2), fixed=())
+    g = O.Graph(xyz, conf, edges, idx, anchors=())
+    H0, g0, E0, n0, _, _ = O.gn_assemble(g, poses)
+    xyz2 = [x.copy() for x in xyz]
+    valid = np.nonzero(idx[0] >= 0)[0]
+    victims = valid[:3]
+    xyz2[1].reshape(-1, 3)[victims[0]] = np.nan
+    xyz2[1].reshape(-1, 3)[victims[1]] = 0.0
+    idx2 = [idx[0].copy()]
+    idx2[0][victims[2]] = -1
+    g2 = O.Graph(xyz2, conf, edges, idx2, anchors=())
+    H2, g2v, E2, n2, _, _ = O.gn_assemble(g2, poses)
+    assert n2 == n0 - 3 and np.all(np.isfinite(H2)) and np.isfinite(E2)
+    # removing the same three pixels from the idx instead gives identical sums
+    idx3 = [idx[0].copy()]
+    idx3[0][victims] = -1
+    g3 = O.Graph(xyz, conf, edges, idx3, anchors=())
+    H3, g3v, E3, n3, _, _ = O.gn_assemble(g3, poses)
+    assert np.allclose(H2, H3, rtol=1e-12) and np.allclose(g2v, g3v, rtol=1e-12, atol=1e-12) and abs(E2 - E3) < 1e-9
+
+
+def test_cost_gradient_matches_finite_differences():
+    """Adjoint of E w.r.t. pointmaps, confidences and pose tangents (matches fixed) vs central FD."""
+    g, gt = _graph(seed=15, n_kf=3, H=6, W=8)
+    rng = np.random.default_rng(16)
+    poses = perturb(gt, rng, rot=0.01, trans=0.01, scale=0.01, fixed=())
+    E, gx, gc, gt_tau = O.cost_grad(g, poses)
+    assert abs(E - O.cost(g, poses)) < 1e-9 * E
+    h = 1e-6
+    # pose tangents
+    for k in range(g.n_kf):
+        for a in range(7):
+            d = np.zeros(7)
+            d[a] = h
+            fd = (O.cost(g, tangent_step(poses, k, d)) - O.cost(g, tangent_step(poses, k, -d))) / (2 * h)
+            assert abs(fd - gt_tau[k, a]) <= 1e-5 * np.abs(gt_tau).max()
+    # pointmap entries and confidences (sampled)
+    for flat in rng.choice(g.xyz.size, 20, replace=False):
+        save = g.xyz.flat[flat]
+        g.xyz.flat[flat] = save + h
+        ep = O.cost(g, poses)
+        g.xyz.flat[flat] = save - h
+        em = O.cost(g, poses)
+        g.xyz.flat[flat] = save
+        assert abs((ep - em) / (2 * h) - gx.flat[flat]) <= 1e-5 * max(1.0, abs(gx.flat[flat]))
+    for flat in rng.choice(g.conf.size, 20, replace=False):
+        save = g.conf[flat]
+        g.conf[flat] = save + h
+        ep = O.cost(g, poses)
+        g.conf[flat] = save - h
+        em = O.cost(g, poses)
+        g.conf[flat] = save
+        assert abs((ep - em) / (2 * h) - gc[flat]) <= 1e-5 * max(1.0, abs(gc[flat]))
