@@ -1,0 +1,272 @@
+/*
+ * ds3.h — C ABI of the dense Sim(3) back-end for AMD MI355X (gfx950).
+ *
+ * The library implements the data-parallel back-end path of CoMo3R-SLAM (collaborative monocular dense
+ * SLAM with learned 3D priors): bidirectional projective matching of dense pointmaps between keyframe
+ * pairs (Sec. III-A "Learned geometry", Sec. III-B), gauge synchronisation of map components
+ * (Sec. III-C, eqs. 3-4), and Gauss-Newton/IRLS refinement of the unified Sim(3) keyframe graph
+ * (Sec. III-D, eqs. 1, 5, 6, 7), plus the gradient of the graph cost (eq. 5) with respect to pointmaps,
+ * confidences and poses.
+ *
+ * Conventions shared by every call
+ *   - Pointers marked (device) are HIP device pointers owned by the caller; pointers marked (host) are
+ *     host memory read during the call. The library never frees caller memory.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*, NULL = default stream) unless
+ *     the description says the call synchronises. Results are valid after the stream completes.
+ *   - Return value: DS3_OK (0) or a negative DS3_E* code. ds3_status_string() gives a description of
+ *     the last error of the calling thread. No C++ exception crosses this boundary.
+ *   - Numerical failure of the pose solve is NOT an error: following the text after eq. (7) it yields
+ *     a zero update and status -1 (see ds3_sim3_gn_step).
+ *   - Pose layout (float64, 8 per keyframe): [tx, ty, tz, qx, qy, qz, qw, s], T_WC = [[sR, t], [0, 1]]
+ *     with R from the unit quaternion and s > 0 (Sec. III-A, "Ray-range tracking").
+ *   - Tangent layout (float64, 7 per keyframe): tau = (v, omega, zeta), T <- Exp(tau) T (Sec. III-D).
+ *   - Pixel grid: row-major, pixel (u, v) at index v*W + u, u the column.
+ *   - Keyframe data lives in an "xyzc arena": per pixel x, y, z of the canonical pointmap (the
+ *     keyframe's points in its own camera frame) and its confidence c, packed as 4 x float32 (16 B,
+ *     DS3_F32) or 4 x bfloat16 (8 B, DS3_BF16, round-to-nearest-even). Arenas are 16 B aligned.
+ */
+#ifndef DS3_H
+#define DS3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DS3_OK 0
+#define DS3_EINVAL (-1)   /* null pointer, bad size, misaligned arena, index out of range */
+#define DS3_ENOTSUP (-2)  /* unsupported dtype or device architecture */
+#define DS3_EHIP (-3)     /* HIP runtime error (detail in ds3_status_string) */
+#define DS3_ENOSPACE (-4) /* workspace smaller than the size the *_workspace_bytes call returned */
+
+typedef enum { DS3_F32 = 0, DS3_BF16 = 1 } ds3_dtype;
+
+/* One keyframe image inside an xyzc arena: H x W pixels starting at pixel px_offset. */
+typedef struct {
+  int32_t H, W;
+  int64_t px_offset;
+} ds3_image;
+
+/* One graph edge (i, j) of E_global (eq. 5): its matches are H_j*W_j int32 entries at idx_offset of an
+ * idx arena; entry n is the pixel m of keyframe i matched to pixel n of keyframe j, or -1. */
+typedef struct {
+  int32_t i, j;
+  int64_t idx_offset;
+} ds3_edge;
+
+/* Matching constants. nu_min is the paper's admission gate (Sec. III-B, 0.1). The remaining values are
+ * readings where the paper is silent: Levenberg-Marquardt on the bilinear ray interpolant (max_iters
+ * trial steps, damping lambda0, floor lambda_min, stop after an accepted step below step_tol_px),
+ * validity = no hole, final angular residual <= ang_tol_px * min(|ds/du|, |ds/dv|), and
+ * | |x| - |X_ref[idx]| | <= range_rel_tol * |X_ref[idx]|; mutual check within a Chebyshev radius;
+ * q_min the confidence sqrt(C_i C_j) needed to count towards nu.
+ * Defaults: 10, 1e-4, 1e-9, 1e-4, 0.5, 0.10, 1, 1.5, 0.1. */
+typedef struct {
+  int32_t max_iters;
+  double lambda0, lambda_min, step_tol_px, ang_tol_px, range_rel_tol;
+  int32_t mutual_radius_px;
+  double q_min, nu_min;
+} ds3_match_params;
+
+/* Graph-step constants: sigma_r = 0.003, sigma_d = 10, Huber kappa = 1.345 (Sec. IV-A); eq. (7) damping
+ * lambda (0 for the back-end) and the epsilon ladder eps_r = eps0 * eps_mult^r, r < max_attempts
+ * (1e-6, 100, 6; text after eq. 7). */
+typedef struct {
+  double sigma_ray, sigma_dist, huber_k, lambda, eps0, eps_mult;
+  int32_t max_attempts;
+} ds3_gn_params;
+
+void ds3_default_match_params(ds3_match_params* p);
+void ds3_default_gn_params(ds3_gn_params* p);
+const char* ds3_status_string(int code);
+int ds3_version(void);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Keyframe layout (ray operator input, Sec. III-A)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* Pack n_px pixels of xyz (device, float32, 3 per px) and conf (device, float32) into an xyzc arena
+ * (device, 16 B per px for DS3_F32, 8 B for DS3_BF16 with round-to-nearest-even; NaN stays NaN). */
+int ds3_pack_xyzc(const float* xyz, const float* conf, int64_t n_px, ds3_dtype dtype, void* xyzc_out,
+                  void* stream);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Projective matching (Sec. III-A "Learned geometry": p* = argmin_p |psi([X_ref]_p) - psi(x)|^2) and
+ * bidirectional verification (Sec. III-B)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* Workspace bytes for ds3_match (one direction) and ds3_match_bidir. */
+size_t ds3_match_workspace_bytes(int32_t H_ref, int32_t W_ref);
+size_t ds3_match_bidir_workspace_bytes(int32_t H_i, int32_t W_i, int32_t H_j, int32_t W_j);
+
+/* One direction. ref_xyzc: the reference keyframe's canonical pointmap (device arena, image `ref`).
+ * qry_xyzc: the other view's points expressed in the reference camera (device arena, image `qry`), its
+ * confidence in c. For every query pixel n: idx_out[n] (device, int32, H_q*W_q) = v*W_ref + u of
+ * round(p*) (ties up), or -1 when the query is a hole, a bilinear sample touched a hole, or a validity
+ * test failed. Optional diagnostics (device, may be NULL): p_out (2 float per query, the continuous
+ * optimum), iters_out (int32, LM trial steps). Needs H_ref, W_ref >= 2. */
+int ds3_match(const void* ref_xyzc, ds3_image ref, const void* qry_xyzc, ds3_image qry, ds3_dtype dtype,
+              const ds3_match_params* params, int32_t* idx_out, float* p_out, int32_t* iters_out,
+              void* workspace, size_t ws_bytes, void* stream);
+
+/* Both decoded directions of a candidate pair, the mutual check and the nu gate.
+ *   X_ii: canonical pointmap of i (image img_i), X_ji: j's points in camera i (image img_j geometry),
+ *   X_jj: canonical pointmap of j, X_ij: i's points in camera j (img_i geometry); all device arenas
+ *   with confidences in c.
+ * Outputs (device): idx_j2i (int32 H_j*W_j; the match of pixel n of j in i, -1 unless mutually valid),
+ *   valid_j (uint8 H_j*W_j), nu (float32 [nu_i, nu_j]: fraction of pixels of i resp. j with a mutually
+ *   valid match of confidence sqrt(C_i C_j) >= q_min), admit (int32: min(nu) >= nu_min). */
+int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const void* X_ij,
+                    ds3_image img_i, ds3_image img_j, ds3_dtype dtype, const ds3_match_params* params,
+                    int32_t* idx_j2i, uint8_t* valid_j, float* nu, int32_t* admit, void* workspace,
+                    size_t ws_bytes, void* stream);
+
+/* Batched bidirectional matching of many edges in few launches.
+ *   kf_arena (device) + kf (host, n_kf images): canonical pointmaps.
+ *   cross_arena (device): per edge e two cross-view pointmaps, X^j_i (H_j*W_j px) at cross_off[2e] and
+ *   X^i_j (H_i*W_i px) at cross_off[2e+1] (host int64 pixel offsets).
+ *   edges (host): (i, j, idx_offset) per edge; outputs written at idx_offset of idx_arena (int32) and
+ *   valid_arena (uint8); nu (device float32, 2 per edge), admit (device int32, 1 per edge).
+ * Workspace from ds3_match_batch_workspace_bytes. */
+size_t ds3_match_batch_workspace_bytes(int32_t n_kf, const ds3_image* kf, int32_t n_edges,
+                                       const ds3_edge* edges);
+int ds3_match_batch(const void* kf_arena, const ds3_image* kf, int32_t n_kf, const void* cross_arena,
+                    const int64_t* cross_off, const ds3_edge* edges, int32_t n_edges, ds3_dtype dtype,
+                    const ds3_match_params* params, int32_t* idx_arena, uint8_t* valid_arena, float* nu,
+                    int32_t* admit, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Gauge synchronisation (Sec. III-C)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* Closed-form similarity of eq. (4) between the matches of one admitted edge lifted to world frames:
+ * x = T_i X_i[m], y = T_j X_j[n] over valid_j. ref_is_i = 1 aligns j's component onto i's (T* maps y to
+ * x), 0 the reverse. With fewer than nc_min correspondences, or a rank < 2 cross-covariance, T* is the
+ * endpoint transform T_ref T_mov^-1. Outputs (device): T_out (8 float64), used_umeyama (int32). */
+int ds3_gauge_align(const void* X_i, ds3_image img_i, const void* X_j, ds3_image img_j, ds3_dtype dtype,
+                    const int32_t* idx_j2i, const uint8_t* valid_j, const double* poses, int32_t i,
+                    int32_t j, int32_t ref_is_i, int32_t nc_min, double* T_out, int32_t* used_umeyama,
+                    void* workspace, size_t ws_bytes, void* stream);
+/* Workspace bytes of ds3_gauge_align and ds3_gauge_sync for a graph of n_kf keyframes. */
+size_t ds3_gauge_workspace_bytes(int32_t n_kf);
+
+/* Left-multiply T (device, 8 float64) onto every pose k (device, n_kf x 8) with mask[k] != 0 (device
+ * uint8): re-gauges a map component while keeping its internal relative poses. */
+int ds3_apply_gauge(double* poses, int32_t n_kf, const uint8_t* mask, const double* T, void* stream);
+
+/* The component tracker of Sec. III-C over a whole graph: walks the edges in order; every admitted
+ * edge (admit, device int32 per edge) between keyframes of different agents (agent_of_kf, host) whose
+ * agents are still in different components aligns the moving component onto the reference (the one
+ * holding agent 0, else the one with the smaller smallest agent id) with ds3_gauge_align and
+ * ds3_apply_gauge. Synchronises the stream once to read the admit flags. n_links_out (host) receives
+ * the number of merges. */
+int ds3_gauge_sync(double* poses, int32_t n_kf, const int32_t* agent_of_kf, const void* kf_arena,
+                   const ds3_image* kf, ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges,
+                   const int32_t* idx_arena, const uint8_t* valid_arena, const int32_t* admit,
+                   int32_t nc_min, int32_t* n_links_out, void* workspace, size_t ws_bytes,
+                   void* stream);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Sim(3) (Sec. III-A pose model, Sec. III-D left perturbation); float64 on the device
+ * ------------------------------------------------------------------------------------------------- */
+int ds3_sim3_exp(const double* tau, double* poses_out, int32_t n, void* stream);
+int ds3_sim3_log(const double* poses, double* tau_out, int32_t n, void* stream);
+/* poses[k] <- Exp(tau[k]) poses[k] for every k with fixed == NULL or fixed[k] == 0 (device arrays). */
+int ds3_sim3_update(double* poses, const double* tau, const uint8_t* fixed, int32_t n, void* stream);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Graph step (eqs. 1, 5, 6, 7)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* Workspace bytes of ds3_gn_linearize / ds3_sim3_gn_step / ds3_gn_cost / ds3_gn_cost_adjoint for a
+ * graph with n_kf keyframes and these edges (host), at this dtype. */
+size_t ds3_gn_workspace_bytes(int32_t n_kf, const ds3_image* kf, int32_t n_edges, const ds3_edge* edges,
+                              ds3_dtype dtype);
+
+/* Assemble the normal equations of eq. (7) at `poses` (device, n_kf x 8):
+ * H (device, (7 n_kf)^2 float64, row-major, full symmetric) and g (device, 7 n_kf float64) summed over
+ * every valid match of every edge (eq. 5), with the rows and columns of each anchor keyframe (host list)
+ * replaced by identity and its g by 0; cost_out (device float64) = E_global at `poses`; count_out
+ * (device int64, may be NULL) = matches used. Pixels with idx = -1, non-finite or zero-range points and
+ * non-finite confidences are skipped. Plain form: one launch per edge. */
+int ds3_gn_linearize(const double* poses, int32_t n_kf, const ds3_image* kf, const void* xyzc_arena,
+                     ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges, const int32_t* idx_arena,
+                     const ds3_gn_params* params, const int32_t* anchors, int32_t n_anchors, double* H,
+                     double* g, double* cost_out, int64_t* count_out, void* workspace, size_t ws_bytes,
+                     void* stream);
+
+/* One Gauss-Newton/IRLS step of eq. (5) via eq. (7) (plain form: one residual launch per edge, no
+ * graph): assemble as ds3_gn_linearize, solve (H + lambda diag H + eps_r I) tau = -g with the epsilon
+ * ladder, update poses (device, in/out) by T <- Exp(tau) T except anchors. cost_out (device float64) =
+ * E at the input poses; status_out (device int32) = ladder attempt used, -1 for a zero update after
+ * max_attempts failures. tau_out (device, 7 n_kf float64) may be NULL. */
+int ds3_sim3_gn_step(double* poses, int32_t n_kf, const ds3_image* kf, const void* xyzc_arena,
+                     ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges, const int32_t* idx_arena,
+                     const ds3_gn_params* params, const int32_t* anchors, int32_t n_anchors,
+                     double* cost_out, int32_t* status_out, double* tau_out, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+/* Solve (H + lambda diag(H) + eps_r I) tau = -g for a symmetric n x n H (device, row-major, float64;
+ * only the lower triangle is read) with eps_r = eps0 * mult^r, r = 0 .. attempts-1; tau (device, n) = 0
+ * and status (device int32) = -1 when every factorisation fails, else status = r. Workspace from
+ * ds3_chol_workspace_bytes(n). */
+size_t ds3_chol_workspace_bytes(int32_t n);
+int ds3_chol_ladder_solve(const double* H, const double* g, int32_t n, double lambda, double eps0,
+                          double mult, int32_t attempts, double* tau, int32_t* status, void* workspace,
+                          size_t ws_bytes, void* stream);
+
+/* Batched form: one plan per graph topology. Creation uploads the topology, counts valid matches per
+ * tile, orders (edge, tile) items longest first, picks tile shapes (opts->autotune: timed candidates,
+ * cached per device, dtype and shape mix; synchronises) and captures one GN iteration in a hipGraph.
+ * The plan owns its device buffers and graph; the keyframe arena, idx arena and poses stay the
+ * caller's and must outlive the plan. ds3_gn_plan_run replays the iteration `iters` times on `stream`
+ * with no host synchronisation, writing E at each iteration's input poses to cost_per_iter (device,
+ * iters float64) and the ladder status to status_per_iter (device, iters int32; either may be NULL). */
+typedef struct {
+  int32_t autotune;        /* 1: time candidate tile shapes at creation */
+  int32_t px_per_thread;   /* tile shape when not autotuning (0 = default) */
+  int32_t use_graph;       /* 1: capture the iteration in a hipGraph (default), 0: direct launches */
+} ds3_plan_opts;
+
+int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena, ds3_dtype dtype,
+                       const ds3_edge* edges, int32_t n_edges, const int32_t* idx_arena,
+                       const ds3_gn_params* params, const int32_t* anchors, int32_t n_anchors,
+                       const ds3_plan_opts* opts, double* poses, void** plan_out, void* stream);
+int ds3_gn_plan_run(void* plan, int32_t iters, double* cost_per_iter, int32_t* status_per_iter,
+                    void* stream);
+/* Timing hook for the fused residual/Hessian kernel alone: launches it `reps` times on `stream` at the
+ * plan's current poses (device prep included), bracketed by events; *ms_out (host) = mean ms per
+ * launch. Synchronises. */
+int ds3_gn_plan_time_reduce(void* plan, int32_t reps, float* ms_out, void* stream);
+/* Plan facts (host): [n_items, px_per_thread, total px scanned, total valid px, bytes read per
+ * iteration by the residual kernel under the streaming model]. */
+int ds3_gn_plan_info(void* plan, int64_t* info5);
+int ds3_gn_plan_destroy(void* plan);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Cost and its adjoint (gradient of eq. 5 with the matches held fixed)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* E_global at poses (device float64 scalar); per-edge recomputation, no stored Jacobians. */
+int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const void* xyzc_arena,
+                ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges, const int32_t* idx_arena,
+                const ds3_gn_params* params, double* cost_out, void* workspace, size_t ws_bytes,
+                void* stream);
+
+/* dE/dX and dE/dC per arena pixel (device float32, 3 resp. 1 per pixel, ACCUMULATED into the caller's
+ * buffers: zero them first) and dE/dtau per keyframe (device float64 n_kf x 7, overwritten), all scaled
+ * by dcost (host float). The per-pixel scatter onto the gathered side uses float atomics, so those sums
+ * are not bitwise reproducible. */
+int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, const void* xyzc_arena,
+                        ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges,
+                        const int32_t* idx_arena, const ds3_gn_params* params, float dcost,
+                        float* grad_xyz, float* grad_conf, double* grad_tau, void* workspace,
+                        size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DS3_H */

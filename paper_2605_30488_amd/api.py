@@ -1,0 +1,428 @@
+"""Python binding of libds3: argument marshalling only. Every step runs in the library's HIP kernels;
+torch provides device memory and the current stream.
+
+Conventions (see include/ds3.h): poses are float64 (N, 8) [t, q(xyzw), s]; tangents float64 (N, 7)
+(v, omega, zeta); keyframes live in an xyzc arena (float32 (P, 4) or bfloat16-as-int16 (P, 4)).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+from ._lib import call
+
+DTYPES = {"f32": L.F32, "bf16": L.BF16}
+
+
+def _dt(dtype) -> int:
+    if isinstance(dtype, int):
+        return dtype
+    return DTYPES[dtype]
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libds3 takes device tensors")
+        if t is not None and not t.is_contiguous():
+            raise ValueError("libds3 takes contiguous tensors")
+
+
+def default_match_params() -> L.MatchParams:
+    p = L.MatchParams()
+    L.load().ds3_default_match_params(C.byref(p))
+    return p
+
+
+def default_gn_params() -> L.GNParams:
+    p = L.GNParams()
+    L.load().ds3_default_gn_params(C.byref(p))
+    return p
+
+
+def version() -> int:
+    return L.load().ds3_version()
+
+
+# ------------------------------------------------------------------------------------------------
+# Keyframe layout
+# ------------------------------------------------------------------------------------------------
+def pack_xyzc(xyz: torch.Tensor, conf: torch.Tensor, dtype="f32", out: torch.Tensor | None = None):
+    """(P, 3) float32 + (P,) float32 -> xyzc arena: (P, 4) float32, or (P, 4) int16 holding bfloat16."""
+    xyz = xyz.reshape(-1, 3).contiguous()
+    conf = conf.reshape(-1).contiguous()
+    _need_cuda(xyz, conf)
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32 if _dt(dtype) == L.F32 else torch.int16,
+                          device=xyz.device)
+    call("ds3_pack_xyzc", _ptr(xyz), _ptr(conf), n, _dt(dtype), _ptr(out), _stream())
+    return out
+
+
+@dataclass
+class Arena:
+    """Keyframe pointmaps packed back to back, plus their image table."""
+    data: torch.Tensor           # (P, 4) float32 or int16 (bfloat16 bits)
+    images: list                 # [(H, W, px_offset)]
+    dtype: str
+
+    def table(self):
+        arr = (L.Image * len(self.images))()
+        for k, (H, W, off) in enumerate(self.images):
+            arr[k] = L.Image(H, W, off)
+        return arr
+
+    def image(self, k) -> L.Image:
+        H, W, off = self.images[k]
+        return L.Image(H, W, off)
+
+    def view(self, k) -> torch.Tensor:
+        H, W, off = self.images[k]
+        return self.data[off:off + H * W]
+
+
+def build_arena(xyz_list, conf_list, dtype="f32", device="cuda") -> Arena:
+    """Pack per-keyframe (H, W, 3) pointmaps and (H, W) confidences into one arena."""
+    images, off = [], 0
+    for x in xyz_list:
+        H, W = int(x.shape[0]), int(x.shape[1])
+        images.append((H, W, off))
+        off += H * W
+    xyz = torch.cat([torch.as_tensor(x, dtype=torch.float32).reshape(-1, 3) for x in xyz_list]).to(device)
+    conf = torch.cat([torch.as_tensor(c, dtype=torch.float32).reshape(-1) for c in conf_list]).to(device)
+    return Arena(pack_xyzc(xyz, conf, dtype), images, dtype)
+
+
+def edge_table(edges, idx_offsets):
+    arr = (L.Edge * len(edges))()
+    for e, ((i, j), off) in enumerate(zip(edges, idx_offsets)):
+        arr[e] = L.Edge(int(i), int(j), int(off))
+    return arr
+
+
+# ------------------------------------------------------------------------------------------------
+# Matching
+# ------------------------------------------------------------------------------------------------
+def match(ref: torch.Tensor, ref_hw, qry: torch.Tensor, qry_hw, dtype="f32", params=None,
+          diagnostics=False):
+    """One direction (ds3_match): queries (the other view's points in the reference camera) against
+    the reference's canonical pointmap; both as xyzc arenas. Returns idx (int32 Hq*Wq) and, with
+    diagnostics, (p (Hq*Wq, 2) float32, iters int32)."""
+    _need_cuda(ref, qry)
+    P = params or default_match_params()
+    Hr, Wr = ref_hw
+    Hq, Wq = qry_hw
+    dev = ref.device
+    idx = torch.empty(Hq * Wq, dtype=torch.int32, device=dev)
+    p = torch.empty((Hq * Wq, 2), dtype=torch.float32, device=dev) if diagnostics else None
+    it = torch.empty(Hq * Wq, dtype=torch.int32, device=dev) if diagnostics else None
+    nb = L.load().ds3_match_workspace_bytes(Hr, Wr)
+    ws = _ws(nb, dev)
+    call("ds3_match", _ptr(ref), L.Image(Hr, Wr, 0), _ptr(qry), L.Image(Hq, Wq, 0), _dt(dtype), C.byref(P),
+         _ptr(idx), _ptr(p), _ptr(it), _ptr(ws), ws.numel(), _stream())
+    return (idx, p, it) if diagnostics else idx
+
+
+def match_bidir(X_ii, X_ji, X_jj, X_ij, hw_i, hw_j, dtype="f32", params=None):
+    """Both directions + mutual check + nu gate (ds3_match_bidir). Returns (idx_j2i int32, valid_j uint8,
+    nu float32[2] = (nu_i, nu_j), admit int32[1]) on the device."""
+    _need_cuda(X_ii, X_ji, X_jj, X_ij)
+    P = params or default_match_params()
+    Hi, Wi = hw_i
+    Hj, Wj = hw_j
+    dev = X_ii.device
+    idx = torch.empty(Hj * Wj, dtype=torch.int32, device=dev)
+    valid = torch.empty(Hj * Wj, dtype=torch.uint8, device=dev)
+    nu = torch.empty(2, dtype=torch.float32, device=dev)
+    admit = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = _ws(L.load().ds3_match_bidir_workspace_bytes(Hi, Wi, Hj, Wj), dev)
+    call("ds3_match_bidir", _ptr(X_ii), _ptr(X_ji), _ptr(X_jj), _ptr(X_ij), L.Image(Hi, Wi, 0),
+         L.Image(Hj, Wj, 0), _dt(dtype), C.byref(P), _ptr(idx), _ptr(valid), _ptr(nu), _ptr(admit),
+         _ptr(ws), ws.numel(), _stream())
+    return idx, valid, nu, admit
+
+
+def match_batch(arena: Arena, cross: torch.Tensor, cross_off, edges, idx_offsets, idx_total, params=None,
+                idx_out=None, valid_out=None, ws=None):
+    """Batched bidirectional matching of every edge (ds3_match_batch). cross: xyzc arena of the
+    cross-view pointmaps; cross_off[2e], cross_off[2e+1] their pixel offsets (X^j_i, X^i_j).
+    Returns (idx arena int32, valid arena uint8, nu (E, 2) float32, admit (E,) int32)."""
+    _need_cuda(arena.data, cross)
+    P = params or default_match_params()
+    dev = arena.data.device
+    kf = arena.table()
+    et = edge_table(edges, idx_offsets)
+    ne = len(edges)
+    off = (C.c_int64 * (2 * ne))(*[int(v) for v in cross_off])
+    idx = idx_out if idx_out is not None else torch.empty(idx_total, dtype=torch.int32, device=dev)
+    valid = valid_out if valid_out is not None else torch.empty(idx_total, dtype=torch.uint8, device=dev)
+    nu = torch.empty((ne, 2), dtype=torch.float32, device=dev)
+    admit = torch.empty(ne, dtype=torch.int32, device=dev)
+    nb = L.load().ds3_match_batch_workspace_bytes(len(arena.images), kf, ne, et)
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, dev)
+    call("ds3_match_batch", _ptr(arena.data), kf, len(arena.images), _ptr(cross), off, et, ne,
+         _dt(arena.dtype), C.byref(P), _ptr(idx), _ptr(valid), _ptr(nu), _ptr(admit), _ptr(ws), ws.numel(),
+         _stream())
+    return idx, valid, nu, admit
+
+
+def match_batch_workspace(arena: Arena, edges, idx_offsets) -> torch.Tensor:
+    kf = arena.table()
+    et = edge_table(edges, idx_offsets)
+    nb = L.load().ds3_match_batch_workspace_bytes(len(arena.images), kf, len(edges), et)
+    return _ws(nb, arena.data.device)
+
+
+# ------------------------------------------------------------------------------------------------
+# Gauge synchronisation
+# ------------------------------------------------------------------------------------------------
+def gauge_align(arena: Arena, i: int, j: int, idx_j2i, valid_j, poses, ref_is_i=True, nc_min=64):
+    """T* of eq. (4) for one edge (ds3_gauge_align). Returns (T (8,) float64, used_umeyama int32[1])."""
+    dev = arena.data.device
+    T = torch.empty(8, dtype=torch.float64, device=dev)
+    used = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = _ws(L.load().ds3_gauge_workspace_bytes(len(arena.images)), dev)
+    call("ds3_gauge_align", _ptr(arena.data), arena.image(i), _ptr(arena.data), arena.image(j),
+         _dt(arena.dtype), _ptr(idx_j2i), _ptr(valid_j), _ptr(poses), i, j, int(bool(ref_is_i)), nc_min,
+         _ptr(T), _ptr(used), _ptr(ws), ws.numel(), _stream())
+    return T, used
+
+
+def apply_gauge(poses, mask, T):
+    call("ds3_apply_gauge", _ptr(poses), poses.shape[0], _ptr(mask), _ptr(T), _stream())
+    return poses
+
+
+def gauge_sync(poses, agent_of_kf, arena: Arena, edges, idx_offsets, idx_arena, valid_arena, admit,
+               nc_min=64):
+    """Component tracker of Sec. III-C over the whole graph (ds3_gauge_sync); poses updated in place.
+    Returns the number of merges."""
+    n = poses.shape[0]
+    ag = (C.c_int32 * n)(*[int(a) for a in agent_of_kf])
+    et = edge_table(edges, idx_offsets)
+    links = C.c_int32(0)
+    ws = _ws(L.load().ds3_gauge_workspace_bytes(n), poses.device)
+    call("ds3_gauge_sync", _ptr(poses), n, ag, _ptr(arena.data), arena.table(), _dt(arena.dtype), et,
+         len(edges), _ptr(idx_arena), _ptr(valid_arena), _ptr(admit), nc_min, C.byref(links), _ptr(ws),
+         ws.numel(), _stream())
+    return links.value
+
+
+# ------------------------------------------------------------------------------------------------
+# Sim(3)
+# ------------------------------------------------------------------------------------------------
+def sim3_exp(tau: torch.Tensor) -> torch.Tensor:
+    tau = tau.reshape(-1, 7).contiguous()
+    out = torch.empty((tau.shape[0], 8), dtype=torch.float64, device=tau.device)
+    call("ds3_sim3_exp", _ptr(tau), _ptr(out), tau.shape[0], _stream())
+    return out
+
+
+def sim3_log(poses: torch.Tensor) -> torch.Tensor:
+    poses = poses.reshape(-1, 8).contiguous()
+    out = torch.empty((poses.shape[0], 7), dtype=torch.float64, device=poses.device)
+    call("ds3_sim3_log", _ptr(poses), _ptr(out), poses.shape[0], _stream())
+    return out
+
+
+def sim3_update(poses: torch.Tensor, tau: torch.Tensor, fixed: torch.Tensor | None = None):
+    """In place: poses[k] <- Exp(tau[k]) poses[k] except where fixed."""
+    call("ds3_sim3_update", _ptr(poses), _ptr(tau), _ptr(fixed), poses.shape[0], _stream())
+    return poses
+
+
+# ------------------------------------------------------------------------------------------------
+# Graph step
+# ------------------------------------------------------------------------------------------------
+class Graph:
+    """A keyframe graph on the device: arena, edges (i, j) with idx offsets and the idx arena."""
+
+    def __init__(self, arena: Arena, edges, idx_arena: torch.Tensor, idx_offsets=None, anchors=(0,)):
+        self.arena = arena
+        self.edges = [(int(i), int(j)) for i, j in edges]
+        if idx_offsets is None:
+            idx_offsets, off = [], 0
+            for i, j in self.edges:
+                idx_offsets.append(off)
+                H, W, _ = arena.images[j]
+                off += H * W
+        self.idx_offsets = [int(o) for o in idx_offsets]
+        self.idx = idx_arena
+        self.anchors = list(anchors)
+        self.kf = arena.table()
+        self.et = edge_table(self.edges, self.idx_offsets)
+        self.n_kf = len(arena.images)
+        self.an = (C.c_int32 * max(len(self.anchors), 1))(*self.anchors)
+        self._ws = None
+
+    @property
+    def dtype(self):
+        return _dt(self.arena.dtype)
+
+    def workspace(self):
+        nb = L.load().ds3_gn_workspace_bytes(self.n_kf, self.kf, len(self.edges), self.et, self.dtype)
+        if nb == 0:
+            raise ValueError("invalid graph topology")
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = _ws(nb, self.arena.data.device)
+        return self._ws
+
+
+def gn_linearize(graph: Graph, poses, params=None):
+    """Normal equations of eq. (7) at poses: (H (7N, 7N), g (7N), cost (1,), count (1,)) float64/int64."""
+    P = params or default_gn_params()
+    dev = poses.device
+    n = 7 * graph.n_kf
+    H = torch.empty((n, n), dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    cost = torch.empty(1, dtype=torch.float64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = graph.workspace()
+    call("ds3_gn_linearize", _ptr(poses), graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
+         len(graph.edges), _ptr(graph.idx), C.byref(P), graph.an, len(graph.anchors), _ptr(H), _ptr(g),
+         _ptr(cost), _ptr(cnt), _ptr(ws), ws.numel(), _stream())
+    return H, g, cost, cnt
+
+
+def sim3_gn_step(graph: Graph, poses, params=None, want_tau=False):
+    """One plain-form GN step (ds3_sim3_gn_step); poses updated in place. Returns (cost at the input
+    poses (1,), ladder status (1,) int32[, tau (7N,)])."""
+    P = params or default_gn_params()
+    dev = poses.device
+    cost = torch.empty(1, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    tau = torch.empty(7 * graph.n_kf, dtype=torch.float64, device=dev) if want_tau else None
+    ws = graph.workspace()
+    call("ds3_sim3_gn_step", _ptr(poses), graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
+         len(graph.edges), _ptr(graph.idx), C.byref(P), graph.an, len(graph.anchors), _ptr(cost), _ptr(st),
+         _ptr(tau), _ptr(ws), ws.numel(), _stream())
+    return (cost, st, tau) if want_tau else (cost, st)
+
+
+def chol_ladder_solve(H, g, lam=0.0, eps0=1e-6, mult=100.0, attempts=6):
+    """(H + lam diag H + eps_r I) tau = -g with the epsilon ladder. Returns (tau, status int32[1])."""
+    H = H.contiguous()
+    g = g.contiguous()
+    n = g.numel()
+    tau = torch.empty(n, dtype=torch.float64, device=H.device)
+    st = torch.empty(1, dtype=torch.int32, device=H.device)
+    ws = _ws(L.load().ds3_chol_workspace_bytes(n), H.device)
+    call("ds3_chol_ladder_solve", _ptr(H), _ptr(g), n, float(lam), float(eps0), float(mult), int(attempts),
+         _ptr(tau), _ptr(st), _ptr(ws), ws.numel(), _stream())
+    return tau, st
+
+
+class GNPlan:
+    """Batched form (ds3_gn_plan_*): one persistent residual launch per iteration, captured with the
+    rest of the iteration in a hipGraph. Binds to `poses`, which every run updates in place."""
+
+    def __init__(self, graph: Graph, poses, params=None, autotune=False, px_per_thread=0, use_graph=True):
+        self.graph = graph
+        self.poses = poses
+        P = params or default_gn_params()
+        opts = L.PlanOpts(int(autotune), int(px_per_thread), int(use_graph))
+        h = C.c_void_p()
+        call("ds3_gn_plan_create", graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
+             len(graph.edges), _ptr(graph.idx), C.byref(P), graph.an, len(graph.anchors), C.byref(opts),
+             _ptr(poses), C.byref(h), _stream())
+        self.handle = h
+
+    def run(self, iters: int):
+        """Returns (cost per iteration (iters,) float64, ladder status (iters,) int32) on the device."""
+        dev = self.poses.device
+        cost = torch.empty(max(iters, 1), dtype=torch.float64, device=dev)
+        st = torch.empty(max(iters, 1), dtype=torch.int32, device=dev)
+        call("ds3_gn_plan_run", self.handle, iters, _ptr(cost), _ptr(st), _stream())
+        return cost[:iters], st[:iters]
+
+    def time_reduce(self, reps: int = 10) -> float:
+        ms = C.c_float()
+        call("ds3_gn_plan_time_reduce", self.handle, reps, C.byref(ms), _stream())
+        return ms.value
+
+    def info(self) -> dict:
+        a = (C.c_int64 * 5)()
+        call("ds3_gn_plan_info", self.handle, a)
+        return {"items": a[0], "px_per_thread": a[1], "px_scanned": a[2], "px_valid": a[3],
+                "bytes_streaming": a[4]}
+
+    def close(self):
+        if self.handle:
+            L.load().ds3_gn_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------------------------------
+# Cost and adjoint
+# ------------------------------------------------------------------------------------------------
+def gn_cost(graph: Graph, poses, params=None):
+    P = params or default_gn_params()
+    cost = torch.empty(1, dtype=torch.float64, device=poses.device)
+    ws = graph.workspace()
+    call("ds3_gn_cost", _ptr(poses), graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
+         len(graph.edges), _ptr(graph.idx), C.byref(P), _ptr(cost), _ptr(ws), ws.numel(), _stream())
+    return cost
+
+
+def gn_cost_adjoint(graph: Graph, poses, dcost=1.0, params=None):
+    """(dE/dxyz (P, 3) float32, dE/dconf (P,) float32, dE/dtau (N, 7) float64), scaled by dcost."""
+    P = params or default_gn_params()
+    dev = poses.device
+    npx = graph.arena.data.shape[0]
+    gx = torch.zeros((npx, 3), dtype=torch.float32, device=dev)
+    gc = torch.zeros(npx, dtype=torch.float32, device=dev)
+    gt = torch.empty((graph.n_kf, 7), dtype=torch.float64, device=dev)
+    ws = graph.workspace()
+    call("ds3_gn_cost_adjoint", _ptr(poses), graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype,
+         graph.et, len(graph.edges), _ptr(graph.idx), C.byref(P), float(dcost), _ptr(gx), _ptr(gc), _ptr(gt),
+         _ptr(ws), ws.numel(), _stream())
+    return gx, gc, gt
+
+
+class DenseSim3Cost(torch.autograd.Function):
+    """E_global (eq. 5) as an autograd function of (xyz (P, 3), conf (P,), tau (N, 7)) at poses
+    Exp(tau) T0 with tau = 0 at the evaluation point: forward packs the pointmaps into a float32 arena
+    and evaluates the cost; backward runs the hand-written adjoint (per-edge recomputation)."""
+
+    @staticmethod
+    def forward(ctx, xyz, conf, tau, graph: Graph, poses0, params=None):
+        arena = Arena(pack_xyzc(xyz.detach().float().contiguous(), conf.detach().float().contiguous(), "f32"),
+                      graph.arena.images, "f32")
+        g = Graph(arena, graph.edges, graph.idx, graph.idx_offsets, graph.anchors)
+        poses = poses0.clone()
+        sim3_update(poses, tau.detach().to(torch.float64).contiguous())
+        cost = gn_cost(g, poses, params)
+        ctx.save_for_backward(xyz, conf, tau)
+        ctx.graph, ctx.poses, ctx.params = g, poses, params
+        return cost.reshape(())
+
+    @staticmethod
+    def backward(ctx, dE):
+        xyz, conf, tau = ctx.saved_tensors
+        d = float(dE.item())
+        gx, gc, gt = gn_cost_adjoint(ctx.graph, ctx.poses, d, ctx.params)
+        return (gx.to(xyz.dtype).reshape(xyz.shape), gc.to(conf.dtype).reshape(conf.shape),
+                gt.to(tau.dtype), None, None, None)

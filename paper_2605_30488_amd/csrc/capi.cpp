@@ -1,0 +1,765 @@
+// C ABI of libds3 (declared in include/ds3.h): argument checks, workspace layout, launch sequences of the
+// plain form, and the batched plan (work-item ordering, tile autotuning, hipGraph capture).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "match_internal.hpp"
+
+namespace ds3 {
+
+// ---- error state -----------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return DS3_OK;
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return DS3_EHIP;
+}
+
+int device_cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+static int check_arch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(DS3_EHIP, "no HIP device");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(DS3_EHIP, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(DS3_ENOTSUP, std::string("libds3 is built for gfx950, device is ") + prop.gcnArchName);
+  return DS3_OK;
+}
+
+static hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+// Upload a host vector into a device region (the copy is staged before the call returns).
+template <class T>
+static int upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return DS3_OK;
+  return check_hip(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s),
+                   "hipMemcpyAsync(upload)");
+}
+
+// ---- graph topology on the host ---------------------------------------------------------------------
+struct Topology {
+  int n_kf = 0, n_edges = 0, n_pairs = 0, total_tiles = 0, max_tiles = 0, tile_px = 0;
+  std::vector<EdgeDev> edges;
+  std::vector<int32_t> node_ptr, node_adj, pair_ptr, pair_edges, pair_ij;
+  std::vector<uint8_t> anchor;
+};
+
+static int build_topology(int n_kf, const ds3_image* kf, int n_edges, const ds3_edge* edges,
+                          const int32_t* anchors, int n_anchors, int tile_px, Topology& T) {
+  if (n_kf <= 0 || !kf) return fail(DS3_EINVAL, "n_kf must be positive with a keyframe table");
+  if (n_edges < 0 || (n_edges > 0 && !edges)) return fail(DS3_EINVAL, "bad edge table");
+  if (n_anchors < 0 || (n_anchors > 0 && !anchors)) return fail(DS3_EINVAL, "bad anchor list");
+  T.n_kf = n_kf;
+  T.n_edges = n_edges;
+  T.tile_px = tile_px;
+  for (int k = 0; k < n_kf; ++k)
+    if (kf[k].H <= 0 || kf[k].W <= 0 || kf[k].px_offset < 0 || int64_t(kf[k].H) * kf[k].W > INT32_MAX)
+      return fail(DS3_EINVAL, "bad keyframe image " + std::to_string(k));
+  T.edges.resize(n_edges);
+  T.total_tiles = 0;
+  T.max_tiles = 0;
+  for (int e = 0; e < n_edges; ++e) {
+    const ds3_edge& E = edges[e];
+    if (E.i < 0 || E.i >= n_kf || E.j < 0 || E.j >= n_kf || E.i == E.j || E.idx_offset < 0)
+      return fail(DS3_EINVAL, "bad edge " + std::to_string(e));
+    EdgeDev D;
+    D.off_i = kf[E.i].px_offset;
+    D.off_j = kf[E.j].px_offset;
+    D.idx_off = E.idx_offset;
+    D.npx_i = kf[E.i].H * kf[E.i].W;
+    D.npx_j = kf[E.j].H * kf[E.j].W;
+    D.i = E.i;
+    D.j = E.j;
+    D.tile0 = T.total_tiles;
+    D.n_tiles = (D.npx_j + tile_px - 1) / tile_px;
+    T.total_tiles += D.n_tiles;
+    T.max_tiles = std::max(T.max_tiles, D.n_tiles);
+    T.edges[e] = D;
+  }
+  // incidence lists (edge index order) and keyframe pairs
+  std::vector<std::vector<int32_t>> inc(n_kf);
+  std::map<std::pair<int, int>, std::vector<int32_t>> pairs;
+  for (int e = 0; e < n_edges; ++e) {
+    inc[edges[e].i].push_back(e << 1);
+    inc[edges[e].j].push_back((e << 1) | 1);
+    int a = std::min(edges[e].i, edges[e].j), b = std::max(edges[e].i, edges[e].j);
+    pairs[{a, b}].push_back(e);
+  }
+  T.node_ptr.assign(n_kf + 1, 0);
+  T.node_adj.clear();
+  for (int k = 0; k < n_kf; ++k) {
+    T.node_ptr[k] = int32_t(T.node_adj.size());
+    T.node_adj.insert(T.node_adj.end(), inc[k].begin(), inc[k].end());
+  }
+  T.node_ptr[n_kf] = int32_t(T.node_adj.size());
+  T.pair_ptr.clear();
+  T.pair_edges.clear();
+  T.pair_ij.clear();
+  for (auto& kv : pairs) {
+    T.pair_ptr.push_back(int32_t(T.pair_edges.size()));
+    T.pair_edges.insert(T.pair_edges.end(), kv.second.begin(), kv.second.end());
+    T.pair_ij.push_back(kv.first.first);
+    T.pair_ij.push_back(kv.first.second);
+  }
+  T.n_pairs = int(pairs.size());
+  T.pair_ptr.push_back(int32_t(T.pair_edges.size()));
+  T.anchor.assign(n_kf, 0);
+  for (int a = 0; a < n_anchors; ++a) {
+    if (anchors[a] < 0 || anchors[a] >= n_kf) return fail(DS3_EINVAL, "anchor out of range");
+    T.anchor[anchors[a]] = 1;
+  }
+  return DS3_OK;
+}
+
+// Device buffers of one graph step, carved from a workspace.
+struct GnBuffers {
+  EdgeDev* edges;
+  EdgeXf* xf;
+  double* Ad;
+  float* partials;
+  double *A_e, *b_e, *cost_e;
+  int64_t* count_e;
+  int32_t *node_ptr, *node_adj, *pair_ptr, *pair_edges, *pair_ij;
+  uint8_t* anchor;
+  double *H, *g, *tau;
+  double* cost_tmp;
+  int64_t* count_tmp;
+  unsigned* counter;
+  float* part7;
+  void* chol_ws;
+};
+
+int adjoint_part_floats(int n_edges, int max_npx_j);
+int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
+                   const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c, float dcost,
+                   float* grad_xyz, float* grad_conf, float* part7, double* b_e, int n_kf,
+                   const int32_t* node_ptr, const int32_t* node_adj, double* grad_tau, hipStream_t s);
+
+static int max_npx_j(const Topology& T) {
+  int m = 0;
+  for (auto& E : T.edges) m = std::max(m, int(E.npx_j));
+  return m;
+}
+
+static size_t carve_gn(void* base, const Topology& T, GnBuffers& B) {
+  Carver c(base);
+  const int E = std::max(T.n_edges, 1);
+  const size_t n = 7 * size_t(T.n_kf);
+  B.edges = c.take<EdgeDev>(E);
+  B.xf = c.take<EdgeXf>(E);
+  B.Ad = c.take<double>(49 * size_t(E));
+  B.partials = c.take<float>(size_t(std::max(T.total_tiles, 1)) * kPartial);
+  B.A_e = c.take<double>(49 * size_t(E));
+  B.b_e = c.take<double>(7 * size_t(E));
+  B.cost_e = c.take<double>(E);
+  B.count_e = c.take<int64_t>(E);
+  B.node_ptr = c.take<int32_t>(T.n_kf + 1);
+  B.node_adj = c.take<int32_t>(2 * size_t(E));
+  B.pair_ptr = c.take<int32_t>(size_t(E) + 1);
+  B.pair_edges = c.take<int32_t>(E);
+  B.pair_ij = c.take<int32_t>(2 * size_t(E));
+  B.anchor = c.take<uint8_t>(T.n_kf);
+  B.H = c.take<double>(n * n);
+  B.g = c.take<double>(n);
+  B.tau = c.take<double>(n);
+  B.cost_tmp = c.take<double>(1);
+  B.count_tmp = c.take<int64_t>(1);
+  B.counter = c.take<unsigned>(64);
+  B.part7 = c.take<float>(size_t(std::max(adjoint_part_floats(T.n_edges, max_npx_j(T)), 8)));
+  B.chol_ws = c.take<char>(chol_workspace_bytes(int(n)));
+  return c.used;
+}
+
+static int upload_topology(const Topology& T, GnBuffers& B, hipStream_t s) {
+  DS3_TRY(upload(B.edges, T.edges, s));
+  DS3_TRY(upload(B.node_ptr, T.node_ptr, s));
+  DS3_TRY(upload(B.node_adj, T.node_adj, s));
+  DS3_TRY(upload(B.pair_ptr, T.pair_ptr, s));
+  DS3_TRY(upload(B.pair_edges, T.pair_edges, s));
+  DS3_TRY(upload(B.pair_ij, T.pair_ij, s));
+  DS3_TRY(upload(B.anchor, T.anchor, s));
+  return DS3_OK;
+}
+
+constexpr int kPlainPPT = 16;
+
+static int check_gn_args(const double* poses, const void* arena, const int32_t* idx, ds3_dtype dt,
+                         const ds3_gn_params* p) {
+  if (!poses || !arena || !idx || !p) return fail(DS3_EINVAL, "null pointer");
+  if (dt != DS3_F32 && dt != DS3_BF16) return fail(DS3_ENOTSUP, "dtype");
+  if ((reinterpret_cast<uintptr_t>(arena) & 15) != 0) return fail(DS3_EINVAL, "arena must be 16 B aligned");
+  if (!(p->sigma_ray > 0) || !(p->sigma_dist > 0) || !(p->huber_k > 0))
+    return fail(DS3_EINVAL, "sigma and kappa must be positive");
+  if (p->max_attempts < 1 || p->max_attempts > 16) return fail(DS3_EINVAL, "max_attempts out of range");
+  return DS3_OK;
+}
+
+// Plain-form linearisation: prep, one residual launch per edge, finalize, assembly, cost sum.
+static int gn_linearize_plain(const double* poses, const Topology& T, const GnBuffers& B,
+                              const void* arena, ds3_dtype dt, const int32_t* idx,
+                              const ds3_gn_params& p, double* H, double* g, double* cost_out,
+                              int64_t* count_out, hipStream_t s) {
+  const GnConst c = make_gn_const(p);
+  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
+  for (int e = 0; e < T.n_edges; ++e)
+    DS3_TRY(launch_edge_reduce_one(dt, kPlainPPT, arena, T.edges[e], e, B.xf, idx, B.partials, c, s));
+  DS3_TRY(launch_edge_finalize(B.edges, T.n_edges, B.partials, B.Ad, B.A_e, B.b_e, B.cost_e, B.count_e, s));
+  const size_t n = 7 * size_t(T.n_kf);
+  DS3_TRY(launch_fill(H, n * n, 0.0, s));
+  DS3_TRY(launch_assemble(T.n_kf, B.node_ptr, B.node_adj, B.pair_ptr, B.pair_edges, B.pair_ij, T.n_pairs,
+                          B.A_e, B.b_e, B.anchor, H, g, s));
+  return launch_sum_costs(B.cost_e, B.count_e, T.n_edges, cost_out, count_out, s);
+}
+
+}  // namespace ds3
+
+using namespace ds3;
+
+// =====================================================================================================
+// Basics
+// =====================================================================================================
+extern "C" {
+
+void ds3_default_match_params(ds3_match_params* p) {
+  if (!p) return;
+  p->max_iters = 10;
+  p->lambda0 = 1e-4;
+  p->lambda_min = 1e-9;
+  p->step_tol_px = 1e-4;
+  p->ang_tol_px = 0.5;
+  p->range_rel_tol = 0.10;
+  p->mutual_radius_px = 1;
+  p->q_min = 1.5;
+  p->nu_min = 0.1;
+}
+
+void ds3_default_gn_params(ds3_gn_params* p) {
+  if (!p) return;
+  p->sigma_ray = 0.003;
+  p->sigma_dist = 10.0;
+  p->huber_k = 1.345;
+  p->lambda = 0.0;
+  p->eps0 = 1e-6;
+  p->eps_mult = 100.0;
+  p->max_attempts = 6;
+}
+
+const char* ds3_status_string(int code) {
+  static thread_local std::string msg;
+  const char* name = code == DS3_OK ? "ok"
+                     : code == DS3_EINVAL ? "invalid argument"
+                     : code == DS3_ENOTSUP ? "not supported"
+                     : code == DS3_EHIP ? "HIP error"
+                     : code == DS3_ENOSPACE ? "workspace too small"
+                                            : "unknown";
+  msg = std::string(name) + (g_last_error.empty() ? "" : " (" + g_last_error + ")");
+  return msg.c_str();
+}
+
+int ds3_version(void) { return 100; }
+
+int ds3_pack_xyzc(const float* xyz, const float* conf, int64_t n_px, ds3_dtype dtype, void* out,
+                  void* stream) {
+  if (n_px < 0 || (n_px > 0 && (!xyz || !conf || !out))) return fail(DS3_EINVAL, "pack: bad arguments");
+  if (dtype != DS3_F32 && dtype != DS3_BF16) return fail(DS3_ENOTSUP, "pack: dtype");
+  if ((reinterpret_cast<uintptr_t>(out) & 15) != 0) return fail(DS3_EINVAL, "pack: output not 16 B aligned");
+  DS3_TRY(check_arch());
+  return launch_pack(xyz, conf, n_px, dtype, out, S(stream));
+}
+
+// =====================================================================================================
+// Sim(3)
+// =====================================================================================================
+int ds3_sim3_exp(const double* tau, double* poses_out, int32_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!tau || !poses_out))) return fail(DS3_EINVAL, "sim3_exp: bad arguments");
+  DS3_TRY(check_arch());
+  return launch_sim3_exp(tau, poses_out, n, S(stream));
+}
+
+int ds3_sim3_log(const double* poses, double* tau_out, int32_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!poses || !tau_out))) return fail(DS3_EINVAL, "sim3_log: bad arguments");
+  DS3_TRY(check_arch());
+  return launch_sim3_log(poses, tau_out, n, S(stream));
+}
+
+int ds3_sim3_update(double* poses, const double* tau, const uint8_t* fixed, int32_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!poses || !tau))) return fail(DS3_EINVAL, "sim3_update: bad arguments");
+  DS3_TRY(check_arch());
+  return launch_sim3_update(poses, tau, fixed, n, S(stream));
+}
+
+// =====================================================================================================
+// Cholesky ladder
+// =====================================================================================================
+size_t ds3_chol_workspace_bytes(int32_t n) { return n > 0 ? chol_workspace_bytes(n) : 0; }
+
+int ds3_chol_ladder_solve(const double* H, const double* g, int32_t n, double lambda, double eps0,
+                          double mult, int32_t attempts, double* tau, int32_t* status, void* workspace,
+                          size_t ws_bytes, void* stream) {
+  if (n <= 0 || !H || !g || !tau || !status || !workspace) return fail(DS3_EINVAL, "chol: bad arguments");
+  if (ws_bytes < chol_workspace_bytes(n)) return fail(DS3_ENOSPACE, "chol: workspace too small");
+  DS3_TRY(check_arch());
+  return launch_chol_ladder(H, g, n, lambda, eps0, mult, attempts, tau, status, workspace, S(stream));
+}
+
+// =====================================================================================================
+// Graph step, plain form
+// =====================================================================================================
+size_t ds3_gn_workspace_bytes(int32_t n_kf, const ds3_image* kf, int32_t n_edges, const ds3_edge* edges,
+                              ds3_dtype dtype) {
+  (void)dtype;
+  Topology T;
+  if (build_topology(n_kf, kf, n_edges, edges, nullptr, 0, kReduceThreads * kPlainPPT, T) != DS3_OK) return 0;
+  GnBuffers B;
+  return carve_gn(nullptr, T, B);
+}
+
+int ds3_gn_linearize(const double* poses, int32_t n_kf, const ds3_image* kf, const void* arena,
+                     ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges, const int32_t* idx,
+                     const ds3_gn_params* params, const int32_t* anchors, int32_t n_anchors, double* H,
+                     double* g, double* cost_out, int64_t* count_out, void* workspace, size_t ws_bytes,
+                     void* stream) {
+  DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
+  if (!H || !g || !cost_out || !workspace) return fail(DS3_EINVAL, "null output or workspace");
+  Topology T;
+  DS3_TRY(build_topology(n_kf, kf, n_edges, edges, anchors, n_anchors, kReduceThreads * kPlainPPT, T));
+  GnBuffers B;
+  if (ws_bytes < carve_gn(nullptr, T, B)) return fail(DS3_ENOSPACE, "gn: workspace too small");
+  carve_gn(workspace, T, B);
+  DS3_TRY(check_arch());
+  hipStream_t s = S(stream);
+  DS3_TRY(upload_topology(T, B, s));
+  return gn_linearize_plain(poses, T, B, arena, dtype, idx, *params, H, g, cost_out, count_out, s);
+}
+
+int ds3_sim3_gn_step(double* poses, int32_t n_kf, const ds3_image* kf, const void* arena, ds3_dtype dtype,
+                     const ds3_edge* edges, int32_t n_edges, const int32_t* idx,
+                     const ds3_gn_params* params, const int32_t* anchors, int32_t n_anchors,
+                     double* cost_out, int32_t* status_out, double* tau_out, void* workspace,
+                     size_t ws_bytes, void* stream) {
+  DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
+  if (!cost_out || !status_out || !workspace) return fail(DS3_EINVAL, "null output or workspace");
+  Topology T;
+  DS3_TRY(build_topology(n_kf, kf, n_edges, edges, anchors, n_anchors, kReduceThreads * kPlainPPT, T));
+  GnBuffers B;
+  if (ws_bytes < carve_gn(nullptr, T, B)) return fail(DS3_ENOSPACE, "gn: workspace too small");
+  carve_gn(workspace, T, B);
+  DS3_TRY(check_arch());
+  hipStream_t s = S(stream);
+  DS3_TRY(upload_topology(T, B, s));
+  DS3_TRY(gn_linearize_plain(poses, T, B, arena, dtype, idx, *params, B.H, B.g, cost_out, nullptr, s));
+  const int n = 7 * n_kf;
+  double* tau = tau_out ? tau_out : B.tau;
+  DS3_TRY(launch_chol_ladder(B.H, B.g, n, params->lambda, params->eps0, params->eps_mult,
+                             params->max_attempts, tau, status_out, B.chol_ws, s));
+  return launch_sim3_update(poses, tau, B.anchor, n_kf, s);
+}
+
+int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const void* arena, ds3_dtype dtype,
+                const ds3_edge* edges, int32_t n_edges, const int32_t* idx, const ds3_gn_params* params,
+                double* cost_out, void* workspace, size_t ws_bytes, void* stream) {
+  DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
+  if (!cost_out || !workspace) return fail(DS3_EINVAL, "null output or workspace");
+  Topology T;
+  DS3_TRY(build_topology(n_kf, kf, n_edges, edges, nullptr, 0, kReduceThreads * kPlainPPT, T));
+  GnBuffers B;
+  if (ws_bytes < carve_gn(nullptr, T, B)) return fail(DS3_ENOSPACE, "gn_cost: workspace too small");
+  carve_gn(workspace, T, B);
+  DS3_TRY(check_arch());
+  hipStream_t s = S(stream);
+  DS3_TRY(upload_topology(T, B, s));
+  const GnConst c = make_gn_const(*params);
+  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
+  for (int e = 0; e < T.n_edges; ++e)
+    DS3_TRY(launch_edge_reduce_one(dtype, kPlainPPT, arena, T.edges[e], e, B.xf, idx, B.partials, c, s));
+  DS3_TRY(launch_edge_finalize(B.edges, T.n_edges, B.partials, B.Ad, B.A_e, B.b_e, B.cost_e, B.count_e, s));
+  return launch_sum_costs(B.cost_e, B.count_e, T.n_edges, cost_out, nullptr, s);
+}
+
+int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, const void* arena,
+                        ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges, const int32_t* idx,
+                        const ds3_gn_params* params, float dcost, float* grad_xyz, float* grad_conf,
+                        double* grad_tau, void* workspace, size_t ws_bytes, void* stream) {
+  DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
+  if (!grad_xyz || !grad_conf || !grad_tau || !workspace) return fail(DS3_EINVAL, "null output or workspace");
+  Topology T;
+  DS3_TRY(build_topology(n_kf, kf, n_edges, edges, nullptr, 0, kReduceThreads * kPlainPPT, T));
+  GnBuffers B;
+  if (ws_bytes < carve_gn(nullptr, T, B)) return fail(DS3_ENOSPACE, "gn_adjoint: workspace too small");
+  carve_gn(workspace, T, B);
+  DS3_TRY(check_arch());
+  hipStream_t s = S(stream);
+  DS3_TRY(upload_topology(T, B, s));
+  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
+  return launch_adjoint(dtype, arena, B.edges, T.n_edges, max_npx_j(T), B.xf, B.Ad, idx,
+                        make_gn_const(*params), dcost, grad_xyz, grad_conf, B.part7, B.b_e, T.n_kf,
+                        B.node_ptr, B.node_adj, grad_tau, s);
+}
+
+}  // extern "C"
+
+// =====================================================================================================
+// Batched plan
+// =====================================================================================================
+namespace ds3 {
+
+constexpr int kHistory = 4096;
+
+struct Plan {
+  Topology T;
+  GnBuffers B;
+  void* ws = nullptr;
+  const void* arena = nullptr;
+  const int32_t* idx = nullptr;
+  double* poses = nullptr;
+  ds3_dtype dt = DS3_F32;
+  ds3_gn_params p;
+  GnConst c;
+  int ppt = 16;
+  int grid = 0;
+  int n_items = 0;
+  WorkItem* items = nullptr;
+  double* cost_hist = nullptr;
+  int32_t* status_hist = nullptr;
+  unsigned* hist_ctr = nullptr;
+  unsigned* time_ctrs = nullptr;
+  int64_t px_scanned = 0, px_valid = 0;
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+__global__ void k_record(const double* cost, const int32_t* status, unsigned* ctr, double* cost_hist,
+                         int32_t* status_hist) {
+  unsigned k = *ctr;
+  if (k < unsigned(kHistory)) {
+    cost_hist[k] = *cost;
+    status_hist[k] = *status;
+  }
+  *ctr = k + 1;
+}
+
+static int plan_iteration(Plan& P, hipStream_t s) {
+  DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, P.B.counter, s));
+  DS3_TRY(launch_edge_reduce_batched(P.dt, P.ppt, P.grid, P.arena, P.B.edges, P.items, P.n_items, P.B.xf,
+                                     P.idx, P.B.partials, P.B.counter, P.c, s));
+  DS3_TRY(launch_edge_finalize(P.B.edges, P.T.n_edges, P.B.partials, P.B.Ad, P.B.A_e, P.B.b_e, P.B.cost_e,
+                               P.B.count_e, s));
+  const size_t n = 7 * size_t(P.T.n_kf);
+  DS3_TRY(launch_fill(P.B.H, n * n, 0.0, s));
+  DS3_TRY(launch_assemble(P.T.n_kf, P.B.node_ptr, P.B.node_adj, P.B.pair_ptr, P.B.pair_edges, P.B.pair_ij,
+                          P.T.n_pairs, P.B.A_e, P.B.b_e, P.B.anchor, P.B.H, P.B.g, s));
+  DS3_TRY(launch_sum_costs(P.B.cost_e, P.B.count_e, P.T.n_edges, P.B.cost_tmp, P.B.count_tmp, s));
+  int32_t* status = reinterpret_cast<int32_t*>(P.B.counter + 8);
+  DS3_TRY(launch_chol_ladder(P.B.H, P.B.g, int(n), P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts,
+                             P.B.tau, status, P.B.chol_ws, s));
+  DS3_TRY(launch_sim3_update(P.poses, P.B.tau, P.B.anchor, P.T.n_kf, s));
+  hipLaunchKernelGGL(k_record, dim3(1), dim3(1), 0, s, P.B.cost_tmp, status, P.hist_ctr, P.cost_hist,
+                     P.status_hist);
+  return check_hip(hipGetLastError(), "k_record");
+}
+
+// Order (edge, tile) items by descending valid count for the current tile shape.
+static int plan_build_items(Plan& P, int ppt, hipStream_t s) {
+  const int tile_px = kReduceThreads * ppt;
+  Topology T2 = P.T;
+  int total = 0, mx = 0;
+  for (auto& E : T2.edges) {
+    E.tile0 = total;
+    E.n_tiles = (E.npx_j + tile_px - 1) / tile_px;
+    total += E.n_tiles;
+    mx = std::max(mx, E.n_tiles);
+  }
+  if (total > P.T.total_tiles) return fail(DS3_EINVAL, "plan: tile table larger than reserved");
+  T2.total_tiles = total;
+  T2.max_tiles = mx;
+  T2.tile_px = tile_px;
+  DS3_TRY(upload(P.B.edges, T2.edges, s));
+  int32_t* counts_dev = reinterpret_cast<int32_t*>(P.B.partials);  // scratch (re-written every iteration)
+  DS3_TRY(launch_count_valid(P.B.edges, T2.n_edges, P.idx, tile_px, mx, counts_dev, s));
+  std::vector<int32_t> counts(std::max(total, 1));
+  DS3_TRY_HIP(hipMemcpyAsync(counts.data(), counts_dev, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
+  DS3_TRY_HIP(hipStreamSynchronize(s));
+  std::vector<WorkItem> items;
+  items.reserve(total);
+  P.px_valid = 0;
+  for (int e = 0; e < T2.n_edges; ++e)
+    for (int t = 0; t < T2.edges[e].n_tiles; ++t) {
+      const int v = counts[T2.edges[e].tile0 + t];
+      P.px_valid += v;
+      if (v > 0) items.push_back(WorkItem{e, t});
+    }
+  std::stable_sort(items.begin(), items.end(), [&](const WorkItem& a, const WorkItem& b) {
+    return counts[T2.edges[a.edge].tile0 + a.tile] > counts[T2.edges[b.edge].tile0 + b.tile];
+  });
+  DS3_TRY(upload(P.items, items, s));
+  // tiles without a valid match are skipped; their partial slots must read as zero
+  DS3_TRY(launch_fill(reinterpret_cast<double*>(P.B.partials), size_t(total) * kPartial / 2, 0.0, s));
+  P.n_items = int(items.size());
+  P.ppt = ppt;
+  P.T.edges = T2.edges;
+  P.T.max_tiles = mx;
+  P.T.tile_px = tile_px;
+  DS3_TRY_HIP(hipStreamSynchronize(s));
+  return DS3_OK;
+}
+
+static int plan_time_reduce(Plan& P, int reps, float* ms, hipStream_t s) {
+  DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, nullptr, s));
+  DS3_TRY(launch_fill_u32(P.time_ctrs, size_t(reps), 0u, s));
+  hipEvent_t a, b;
+  DS3_TRY_HIP(hipEventCreate(&a));
+  DS3_TRY_HIP(hipEventCreate(&b));
+  int rc = check_hip(hipEventRecord(a, s), "hipEventRecord");
+  for (int r = 0; r < reps && rc == DS3_OK; ++r)
+    rc = launch_edge_reduce_batched(P.dt, P.ppt, P.grid, P.arena, P.B.edges, P.items, P.n_items, P.B.xf,
+                                    P.idx, P.B.partials, P.time_ctrs + r, P.c, s);
+  if (rc == DS3_OK) rc = check_hip(hipEventRecord(b, s), "hipEventRecord");
+  if (rc == DS3_OK) rc = check_hip(hipEventSynchronize(b), "hipEventSynchronize");
+  float t = 0.f;
+  if (rc == DS3_OK) rc = check_hip(hipEventElapsedTime(&t, a, b), "hipEventElapsedTime");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc == DS3_OK) *ms = t / float(reps);
+  return rc;
+}
+
+static std::string tune_key(const Plan& P) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  (void)hipGetDeviceProperties(&prop, dev);
+  std::map<std::pair<int, int>, int> shapes;
+  for (auto& E : P.T.edges) shapes[{E.npx_j, E.npx_i}]++;
+  std::ostringstream k;
+  k << prop.gcnArchName << "|" << (P.dt == DS3_F32 ? "f32" : "bf16") << "|cu" << prop.multiProcessorCount;
+  for (auto& kv : shapes) k << "|" << kv.first.first << "x" << kv.first.second;
+  return k.str();
+}
+
+static std::string tune_cache_path() {
+  const char* env = std::getenv("DS3_TUNE_CACHE");
+  if (env && *env) return env;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/ds3_tune.txt";
+}
+
+static bool tune_lookup(const std::string& key, int& ppt, int& bpc) {
+  std::ifstream f(tune_cache_path());
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    auto tab = line.rfind('\t');
+    if (tab == std::string::npos) continue;
+    if (line.substr(0, tab) != key) continue;
+    int a = 0, b = 0;
+    if (std::sscanf(line.c_str() + tab + 1, "%d %d", &a, &b) == 2 && a > 0 && b > 0) {
+      ppt = a;
+      bpc = b;
+      found = true;
+    }
+  }
+  return found;
+}
+
+static void tune_store(const std::string& key, int ppt, int bpc) {
+  std::string path = tune_cache_path();
+  auto slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
+    if (std::system(cmd.c_str()) != 0) return;
+  }
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << "\t" << ppt << " " << bpc << "\n";
+}
+
+static int plan_autotune(Plan& P, hipStream_t s) {
+  const int cus = device_cu_count();
+  const std::string key = tune_key(P);
+  int best_ppt = 16, best_bpc = 2;
+  if (tune_lookup(key, best_ppt, best_bpc)) {
+    DS3_TRY(plan_build_items(P, best_ppt, s));
+    P.grid = std::max(1, std::min(cus * best_bpc, P.n_items));
+    return DS3_OK;
+  }
+  float best = 1e30f;
+  for (int ppt : {4, 8, 16, 32}) {
+    DS3_TRY(plan_build_items(P, ppt, s));
+    for (int bpc : {1, 2, 4, 8}) {
+      P.grid = std::max(1, std::min(cus * bpc, P.n_items));
+      float ms = 0.f;
+      DS3_TRY(plan_time_reduce(P, 2, &ms, s));  // warm
+      DS3_TRY(plan_time_reduce(P, 5, &ms, s));
+      if (ms < best) {
+        best = ms;
+        best_ppt = ppt;
+        best_bpc = bpc;
+      }
+    }
+  }
+  tune_store(key, best_ppt, best_bpc);
+  DS3_TRY(plan_build_items(P, best_ppt, s));
+  P.grid = std::max(1, std::min(cus * best_bpc, P.n_items));
+  return DS3_OK;
+}
+
+static void plan_free(Plan* P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->ws) (void)hipFree(P->ws);
+  if (P->items) (void)hipFree(P->items);
+  if (P->cost_hist) (void)hipFree(P->cost_hist);
+  if (P->status_hist) (void)hipFree(P->status_hist);
+  if (P->hist_ctr) (void)hipFree(P->hist_ctr);
+  if (P->time_ctrs) (void)hipFree(P->time_ctrs);
+  delete P;
+}
+
+}  // namespace ds3
+
+extern "C" {
+
+int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3_dtype dtype,
+                       const ds3_edge* edges, int32_t n_edges, const int32_t* idx,
+                       const ds3_gn_params* params, const int32_t* anchors, int32_t n_anchors,
+                       const ds3_plan_opts* opts, double* poses, void** plan_out, void* stream) {
+  if (!plan_out) return fail(DS3_EINVAL, "plan_out is null");
+  *plan_out = nullptr;
+  DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
+  DS3_TRY(check_arch());
+  hipStream_t s = S(stream);
+  Plan* P = new Plan();
+  // reserve partial slots for the smallest tile (4 px per thread)
+  int rc = build_topology(n_kf, kf, n_edges, edges, anchors, n_anchors, kReduceThreads * 4, P->T);
+  if (rc != DS3_OK) { plan_free(P); return rc; }
+  const size_t ws = carve_gn(nullptr, P->T, P->B);
+  rc = check_hip(hipMalloc(&P->ws, ws), "hipMalloc(plan)");
+  if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->items, sizeof(WorkItem) * std::max(P->T.total_tiles, 1)), "hipMalloc(items)");
+  if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->cost_hist, sizeof(double) * kHistory), "hipMalloc");
+  if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->status_hist, sizeof(int32_t) * kHistory), "hipMalloc");
+  if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->hist_ctr, sizeof(unsigned) * 4), "hipMalloc");
+  if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->time_ctrs, sizeof(unsigned) * 64), "hipMalloc");
+  if (rc != DS3_OK) { plan_free(P); return rc; }
+  carve_gn(P->ws, P->T, P->B);
+  P->arena = arena;
+  P->idx = idx;
+  P->poses = poses;
+  P->dt = dtype;
+  P->p = *params;
+  P->c = make_gn_const(*params);
+  P->use_graph = !opts || opts->use_graph != 0;
+  rc = upload_topology(P->T, P->B, s);
+  if (rc == DS3_OK) rc = launch_fill_u32(P->B.counter, 64, 0u, s);
+  if (rc == DS3_OK) rc = launch_fill_u32(P->hist_ctr, 4, 0u, s);
+  if (rc == DS3_OK) {
+    if (opts && opts->autotune) {
+      rc = plan_autotune(*P, s);
+    } else {
+      int ppt = (opts && opts->px_per_thread > 0) ? opts->px_per_thread : 16;
+      if (ppt != 4 && ppt != 8 && ppt != 16 && ppt != 32) rc = fail(DS3_EINVAL, "px_per_thread must be 4, 8, 16 or 32");
+      if (rc == DS3_OK) rc = plan_build_items(*P, ppt, s);
+      P->grid = std::max(1, std::min(device_cu_count() * 2, P->n_items));
+    }
+  }
+  if (rc == DS3_OK) {
+    P->px_scanned = 0;
+    for (auto& E : P->T.edges) P->px_scanned += E.npx_j;
+  }
+  if (rc == DS3_OK && P->use_graph) {
+    hipStream_t cs;
+    rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    if (rc == DS3_OK) {
+      rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      if (rc == DS3_OK) {
+        int rc2 = plan_iteration(*P, cs);
+        hipGraph_t g = nullptr;
+        int rc3 = check_hip(hipStreamEndCapture(cs, &g), "hipStreamEndCapture");
+        rc = rc2 != DS3_OK ? rc2 : rc3;
+        P->graph = g;
+      }
+      if (rc == DS3_OK) rc = check_hip(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+      (void)hipStreamDestroy(cs);
+    }
+  }
+  if (rc != DS3_OK) { plan_free(P); return rc; }
+  *plan_out = P;
+  return DS3_OK;
+}
+
+int ds3_gn_plan_run(void* plan, int32_t iters, double* cost_per_iter, int32_t* status_per_iter,
+                    void* stream) {
+  Plan* P = static_cast<Plan*>(plan);
+  if (!P || iters < 0) return fail(DS3_EINVAL, "plan_run: bad arguments");
+  if (iters > kHistory) return fail(DS3_EINVAL, "plan_run: at most 4096 iterations per call");
+  hipStream_t s = S(stream);
+  DS3_TRY(launch_fill_u32(P->hist_ctr, 1, 0u, s));
+  for (int it = 0; it < iters; ++it) {
+    if (P->use_graph) {
+      DS3_TRY_HIP(hipGraphLaunch(P->exec, s));
+    } else {
+      DS3_TRY(plan_iteration(*P, s));
+    }
+  }
+  if (iters > 0 && cost_per_iter)
+    DS3_TRY_HIP(hipMemcpyAsync(cost_per_iter, P->cost_hist, sizeof(double) * iters, hipMemcpyDeviceToDevice, s));
+  if (iters > 0 && status_per_iter)
+    DS3_TRY_HIP(hipMemcpyAsync(status_per_iter, P->status_hist, sizeof(int32_t) * iters, hipMemcpyDeviceToDevice, s));
+  return DS3_OK;
+}
+
+int ds3_gn_plan_time_reduce(void* plan, int32_t reps, float* ms_out, void* stream) {
+  Plan* P = static_cast<Plan*>(plan);
+  if (!P || reps < 1 || reps > 64 || !ms_out) return fail(DS3_EINVAL, "plan_time_reduce: bad arguments");
+  return plan_time_reduce(*P, reps, ms_out, S(stream));
+}
+
+int ds3_gn_plan_info(void* plan, int64_t* info) {
+  Plan* P = static_cast<Plan*>(plan);
+  if (!P || !info) return fail(DS3_EINVAL, "plan_info: bad arguments");
+  const int px_bytes = P->dt == DS3_F32 ? 16 : 8;
+  info[0] = P->n_items;
+  info[1] = P->ppt;
+  info[2] = P->px_scanned;
+  info[3] = P->px_valid;
+  info[4] = 4 * P->px_scanned + 2 * int64_t(px_bytes) * P->px_valid;
+  return DS3_OK;
+}
+
+int ds3_gn_plan_destroy(void* plan) {
+  plan_free(static_cast<Plan*>(plan));
+  return DS3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,576 @@
+// Graph-step kernels: per-edge pose prep, the fused residual / Jacobian / Huber / Hessian reduction,
+// per-edge adjoint transform, block assembly with anchor pinning, cost sum and the Sim(3) update.
+//
+// Paper map (CoMo3R-SLAM, Sec. III): residual eq. (1); whitening Sigma_mn = Sigma/q_mn with
+// Sigma = diag(sigma_r^2 I3, sigma_d^2) and component-wise Huber/IRLS (Sec. III-A, "Ray-range
+// tracking"); E_global eq. (5); Jacobian blocks eq. (6) and the endpoint maps -/+ Ad_{T_i^-1} (text after
+// eq. 6); normal equations eq. (7); left update T <- Exp(tau) T (Sec. III-D).
+//
+// Because J_i = -J_j = -J_x Ad, an edge's 14x14 block of J^T W J is [[A, -A], [-A, A]] with
+// A = Ad^T H_L Ad, where H_L = sum J_x^T W J_x over the edge's matches. The streaming kernel therefore
+// reduces only the 28 unique entries of H_L, the 7 of b_L = J_x^T W e, the cost and the count per tile.
+// J_x = [[P/d, -[psi]x, 0], [psi^T, 0, d]] (P = I - psi psi^T) has structural zeros that the
+// accumulation skips: column 6 of the ray rows, column 3+c of ray row c, columns 3-5 of the range row.
+#include "common.hpp"
+#include "internal.hpp"
+#include "sim3.hpp"
+
+namespace ds3 {
+
+GnConst make_gn_const(const ds3_gn_params& p) {
+  GnConst c;
+  c.inv_sr = float(1.0 / p.sigma_ray);
+  c.inv_sd = float(1.0 / p.sigma_dist);
+  c.inv_sr2 = float(1.0 / (p.sigma_ray * p.sigma_ray));
+  c.inv_sd2 = float(1.0 / (p.sigma_dist * p.sigma_dist));
+  c.kappa = float(p.huber_k);
+  return c;
+}
+
+// --------------------------------------------------------------------------------------------------
+// Pose prep: T_ij = T_i^-1 T_j (float32 copy for the residual kernel) and Ad_{T_i^-1} (float64).
+// --------------------------------------------------------------------------------------------------
+__global__ void k_gn_prep(const double* __restrict__ poses, const EdgeDev* __restrict__ edges,
+                          int n_edges, EdgeXf* __restrict__ xf, double* __restrict__ Ad,
+                          unsigned* __restrict__ queue_counter) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (queue_counter && e == 0) queue_counter[0] = 0u;
+  if (e >= n_edges) return;
+  const EdgeDev E = edges[e];
+  Sim3 Ti = sim3_load(poses + 8 * E.i);
+  Sim3 Tj = sim3_load(poses + 8 * E.j);
+  Sim3 Tinv = sim3_inv(Ti);
+  Sim3 Tij = sim3_mul(Tinv, Tj);
+  double R[9];
+  quat_to_mat(Tij.q, R);
+  EdgeXf X;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) X.m[3 * r + c] = float(Tij.s * R[3 * r + c]);
+    X.m[9 + r] = float(Tij.t[r]);
+  }
+  for (int k = 0; k < 4; ++k) X.pad[k] = 0.0f;
+  xf[e] = X;
+  sim3_adjoint(Tinv, Ad + 49 * int64_t(e));
+}
+
+int launch_gn_prep(const double* poses, const EdgeDev* edges, int n_edges, EdgeXf* xf, double* Ad,
+                   unsigned* queue_counter, hipStream_t s) {
+  int threads = 128;
+  int blocks = (n_edges + threads - 1) / threads;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_gn_prep, dim3(blocks), dim3(threads), 0, s, poses, edges, n_edges, xf, Ad,
+                     queue_counter);
+  return check_hip(hipGetLastError(), "k_gn_prep");
+}
+
+// --------------------------------------------------------------------------------------------------
+// Fused residual / Jacobian / Huber / Hessian reduction of one tile of an edge
+// --------------------------------------------------------------------------------------------------
+#define HIDX(r, c) ((r) * 7 - ((r) * ((r) - 1)) / 2 + ((c) - (r)))
+
+struct Acc {
+  float h[28];
+  float b[7];
+  float cost;
+  float cnt;
+};
+
+__device__ inline void acc_zero(Acc& a) {
+#pragma unroll
+  for (int k = 0; k < 28; ++k) a.h[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) a.b[k] = 0.0f;
+  a.cost = 0.0f;
+  a.cnt = 0.0f;
+}
+
+// Ray row c of J_x: J[0..2] = P_c / d, J[3..5] = row c of -[psi]x (its entry 3+c is zero), J[6] = 0.
+template <int Z>
+__device__ inline void acc_ray_row(Acc& a, const float* J, float W, float e) {
+  float wj[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) wj[k] = (k == Z) ? 0.0f : W * J[k];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    if (r == Z) continue;
+#pragma unroll
+    for (int c = r; c < 6; ++c) {
+      if (c == Z) continue;
+      a.h[HIDX(r, c)] = fmaf(wj[r], J[c], a.h[HIDX(r, c)]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (k == Z) continue;
+    a.b[k] = fmaf(wj[k], e, a.b[k]);
+  }
+}
+
+// One match: x = T_ij X_j, e of eq. (1), whitening, Huber weights, J_x, accumulation.
+// Returns false (nothing accumulated) for holes, non-finite values or zero ranges.
+__device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const float* M,
+                                 const GnConst& k) {
+  const float x0 = fmaf(M[0], Xj.x, fmaf(M[1], Xj.y, fmaf(M[2], Xj.z, M[9])));
+  const float x1 = fmaf(M[3], Xj.x, fmaf(M[4], Xj.y, fmaf(M[5], Xj.z, M[10])));
+  const float x2 = fmaf(M[6], Xj.x, fmaf(M[7], Xj.y, fmaf(M[8], Xj.z, M[11])));
+  const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+  const float di2 = fmaf(Xi.x, Xi.x, fmaf(Xi.y, Xi.y, Xi.z * Xi.z));
+  const float dj2 = fmaf(Xj.x, Xj.x, fmaf(Xj.y, Xj.y, Xj.z * Xj.z));
+  const float cc = Xi.w * Xj.w;
+  // holes (|X| <= 1e-9 or non-finite) on either side, zero range after the transform, bad confidence
+  if (!(d2 > 1e-18f) || !(di2 > 1e-18f) || !(dj2 > 1e-18f) || !(cc >= 0.0f) || !isfinite(d2) ||
+      !isfinite(di2) || !isfinite(cc) || !isfinite(dj2))
+    return false;
+  const float rd = rsqrtf(d2);
+  const float rdi = rsqrtf(di2);
+  const float d = d2 * rd;
+  const float di = di2 * rdi;
+  const float p0 = x0 * rd, p1 = x1 * rd, p2 = x2 * rd;
+  const float e0 = p0 - Xi.x * rdi;
+  const float e1 = p1 - Xi.y * rdi;
+  const float e2 = p2 - Xi.z * rdi;
+  const float e3 = d - di;
+  const float q = sqrtf(cc);
+  const float sq = sqrtf(q);
+  const float r0 = sq * e0 * k.inv_sr, r1 = sq * e1 * k.inv_sr, r2 = sq * e2 * k.inv_sr;
+  const float r3 = sq * e3 * k.inv_sd;
+  const float a0 = fabsf(r0), a1 = fabsf(r1), a2 = fabsf(r2), a3 = fabsf(r3);
+  const float w0 = (a0 <= k.kappa) ? 1.0f : k.kappa / a0;
+  const float w1 = (a1 <= k.kappa) ? 1.0f : k.kappa / a1;
+  const float w2 = (a2 <= k.kappa) ? 1.0f : k.kappa / a2;
+  const float w3 = (a3 <= k.kappa) ? 1.0f : k.kappa / a3;
+  // rho(r) = t (|r| - t/2) with t = w |r|: r^2/2 inside kappa, kappa |r| - kappa^2/2 outside
+  const float t0 = w0 * a0, t1 = w1 * a1, t2 = w2 * a2, t3 = w3 * a3;
+  a.cost += t0 * fmaf(-0.5f, t0, a0) + t1 * fmaf(-0.5f, t1, a1) + t2 * fmaf(-0.5f, t2, a2) +
+            t3 * fmaf(-0.5f, t3, a3);
+  a.cnt += 1.0f;
+  const float qr = q * k.inv_sr2;
+  const float W0 = w0 * qr, W1 = w1 * qr, W2 = w2 * qr, W3 = w3 * q * k.inv_sd2;
+  // P/d rows: (delta_ca - psi_c psi_a) / d
+  const float s0 = p0 * rd, s1 = p1 * rd, s2 = p2 * rd;
+  {
+    float J[6] = {rd - s0 * p0, -s0 * p1, -s0 * p2, 0.0f, p2, -p1};
+    acc_ray_row<3>(a, J, W0, e0);
+  }
+  {
+    float J[6] = {-s1 * p0, rd - s1 * p1, -s1 * p2, -p2, 0.0f, p0};
+    acc_ray_row<4>(a, J, W1, e1);
+  }
+  {
+    float J[6] = {-s2 * p0, -s2 * p1, rd - s2 * p2, p1, -p0, 0.0f};
+    acc_ray_row<5>(a, J, W2, e2);
+  }
+  // range row [psi^T, 0, 0, 0, d]
+  {
+    const float j0 = W3 * p0, j1 = W3 * p1, j2 = W3 * p2, j6 = W3 * d;
+    a.h[HIDX(0, 0)] = fmaf(j0, p0, a.h[HIDX(0, 0)]);
+    a.h[HIDX(0, 1)] = fmaf(j0, p1, a.h[HIDX(0, 1)]);
+    a.h[HIDX(0, 2)] = fmaf(j0, p2, a.h[HIDX(0, 2)]);
+    a.h[HIDX(0, 6)] = fmaf(j0, d, a.h[HIDX(0, 6)]);
+    a.h[HIDX(1, 1)] = fmaf(j1, p1, a.h[HIDX(1, 1)]);
+    a.h[HIDX(1, 2)] = fmaf(j1, p2, a.h[HIDX(1, 2)]);
+    a.h[HIDX(1, 6)] = fmaf(j1, d, a.h[HIDX(1, 6)]);
+    a.h[HIDX(2, 2)] = fmaf(j2, p2, a.h[HIDX(2, 2)]);
+    a.h[HIDX(2, 6)] = fmaf(j2, d, a.h[HIDX(2, 6)]);
+    a.h[HIDX(6, 6)] = fmaf(j6, d, a.h[HIDX(6, 6)]);
+    a.b[0] = fmaf(j0, e3, a.b[0]);
+    a.b[1] = fmaf(j1, e3, a.b[1]);
+    a.b[2] = fmaf(j2, e3, a.b[2]);
+    a.b[6] = fmaf(j6, e3, a.b[6]);
+  }
+  return true;
+}
+
+// Block reduction of the 37 accumulators in a fixed order; threads 0..36 write the tile partial.
+__device__ inline void acc_block_store(Acc& a, float* __restrict__ out, float (*lds)[37]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  float* v = reinterpret_cast<float*>(&a);
+#pragma unroll
+  for (int k = 0; k < 37; ++k) {
+    float s = wave_sum(v[k]);
+    if (lane == 0) lds[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPartial) {
+    float s = 0.0f;
+    if (threadIdx.x < 37) {
+#pragma unroll
+      for (int w = 0; w < kReduceThreads / kWave; ++w) s += lds[w][threadIdx.x];
+    }
+    out[threadIdx.x] = s;
+  }
+}
+
+template <int DT, int PPT>
+__device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev& E, int tile,
+                                   const float* M, const int32_t* __restrict__ idx_arena,
+                                   float* __restrict__ out, const GnConst& k, float (*lds)[37]) {
+  Acc a;
+  acc_zero(a);
+  const int64_t base = int64_t(tile) * (kReduceThreads * PPT);
+  const int32_t* __restrict__ idx = idx_arena + E.idx_off;
+  constexpr int U = 4;
+#pragma unroll 1
+  for (int k0 = 0; k0 < PPT; k0 += U) {
+    int32_t m[U];
+    float4 xj[U], xi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t n = base + int64_t(k0 + u) * kReduceThreads + threadIdx.x;
+      m[u] = (n < E.npx_j) ? __builtin_nontemporal_load(idx + n) : -1;
+      if (m[u] >= E.npx_i) m[u] = -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t n = base + int64_t(k0 + u) * kReduceThreads + threadIdx.x;
+      if (m[u] >= 0) {
+        xj[u] = Px<DT>::load(arena, E.off_j + n);
+        xi[u] = Px<DT>::load(arena, E.off_i + m[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (m[u] >= 0) acc_pixel(a, xj[u], xi[u], M, k);
+  }
+  acc_block_store(a, out, lds);
+}
+
+// Plain form: one launch per edge, one block per tile.
+template <int DT, int PPT>
+__global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_one(
+    const void* __restrict__ arena, EdgeDev E, int edge_id, const EdgeXf* __restrict__ xf,
+    const int32_t* __restrict__ idx_arena, float* __restrict__ partials, GnConst k) {
+  __shared__ float lds[kReduceThreads / kWave][37];
+  float M[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) M[q] = xf[edge_id].m[q];
+  reduce_tile<DT, PPT>(arena, E, blockIdx.x, M, idx_arena,
+                       partials + int64_t(E.tile0 + blockIdx.x) * kPartial, k, lds);
+}
+
+// Batched form: persistent blocks pop (edge, tile) items, longest first, from one queue.
+template <int DT, int PPT>
+__global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_batched(
+    const void* __restrict__ arena, const EdgeDev* __restrict__ edges, const WorkItem* __restrict__ items,
+    int n_items, const EdgeXf* __restrict__ xf, const int32_t* __restrict__ idx_arena,
+    float* __restrict__ partials, unsigned* __restrict__ queue_counter, GnConst k) {
+  __shared__ float lds[kReduceThreads / kWave][37];
+  __shared__ int s_item;
+#pragma unroll 1
+  for (;;) {
+    if (threadIdx.x == 0) s_item = int(atomicAdd(queue_counter, 1u));
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const WorkItem W = items[it];
+    const EdgeDev E = edges[W.edge];
+    float M[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) M[q] = xf[W.edge].m[q];
+    reduce_tile<DT, PPT>(arena, E, W.tile, M, idx_arena, partials + int64_t(E.tile0 + W.tile) * kPartial,
+                         k, lds);
+    __syncthreads();
+  }
+}
+
+template <int DT>
+static int launch_one_dt(int ppt, const void* arena, const EdgeDev& e, int edge_id, const EdgeXf* xf,
+                         const int32_t* idx, float* partials, GnConst c, hipStream_t s) {
+  dim3 grid(e.n_tiles), block(kReduceThreads);
+  switch (ppt) {
+    case 4: hipLaunchKernelGGL((k_edge_reduce_one<DT, 4>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
+    case 8: hipLaunchKernelGGL((k_edge_reduce_one<DT, 8>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
+    case 16: hipLaunchKernelGGL((k_edge_reduce_one<DT, 16>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
+    case 32: hipLaunchKernelGGL((k_edge_reduce_one<DT, 32>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
+    default: return fail(DS3_EINVAL, "unsupported pixels-per-thread");
+  }
+  return check_hip(hipGetLastError(), "k_edge_reduce_one");
+}
+
+int launch_edge_reduce_one(ds3_dtype dt, int ppt, const void* arena, const EdgeDev& e, int edge_id,
+                           const EdgeXf* xf, const int32_t* idx_arena, float* partials, GnConst c,
+                           hipStream_t s) {
+  if (e.n_tiles <= 0) return DS3_OK;
+  if (dt == DS3_F32) return launch_one_dt<DS3_F32>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, s);
+  return launch_one_dt<DS3_BF16>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, s);
+}
+
+template <int DT>
+static int launch_batched_dt(int ppt, int grid, const void* arena, const EdgeDev* edges,
+                             const WorkItem* items, int n_items, const EdgeXf* xf, const int32_t* idx,
+                             float* partials, unsigned* qc, GnConst c, hipStream_t s) {
+  dim3 g(grid), b(kReduceThreads);
+  switch (ppt) {
+    case 4: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 4>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
+    case 8: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 8>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
+    case 16: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 16>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
+    case 32: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 32>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
+    default: return fail(DS3_EINVAL, "unsupported pixels-per-thread");
+  }
+  return check_hip(hipGetLastError(), "k_edge_reduce_batched");
+}
+
+int launch_edge_reduce_batched(ds3_dtype dt, int ppt, int grid, const void* arena, const EdgeDev* edges,
+                               const WorkItem* items, int n_items, const EdgeXf* xf,
+                               const int32_t* idx_arena, float* partials, unsigned* queue_counter,
+                               GnConst c, hipStream_t s) {
+  if (n_items <= 0) return DS3_OK;
+  if (dt == DS3_F32)
+    return launch_batched_dt<DS3_F32>(ppt, grid, arena, edges, items, n_items, xf, idx_arena, partials,
+                                      queue_counter, c, s);
+  return launch_batched_dt<DS3_BF16>(ppt, grid, arena, edges, items, n_items, xf, idx_arena, partials,
+                                     queue_counter, c, s);
+}
+
+// --------------------------------------------------------------------------------------------------
+// Per-edge finalize: float64 sum of the edge's tile partials (tile order), A = Ad^T H_L Ad, b = Ad^T b_L
+// --------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_edge_finalize(const EdgeDev* __restrict__ edges,
+                                                      const float* __restrict__ partials,
+                                                      const double* __restrict__ Ad_all,
+                                                      double* __restrict__ A_out, double* __restrict__ b_out,
+                                                      double* __restrict__ cost_e,
+                                                      int64_t* __restrict__ count_e) {
+  __shared__ double S[37];
+  __shared__ double HL[49];
+  __shared__ double Ad[49];
+  __shared__ double Mt[49];
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const EdgeDev E = edges[e];
+  if (t < 37) {
+    double s = 0.0;
+    const float* p = partials + int64_t(E.tile0) * kPartial + t;
+    for (int k = 0; k < E.n_tiles; ++k) s += double(p[int64_t(k) * kPartial]);
+    S[t] = s;
+  }
+  if (t < 49) Ad[t] = Ad_all[49 * int64_t(e) + t];
+  __syncthreads();
+  if (t < 49) {
+    int r = t / 7, c = t % 7;
+    int lo = r < c ? r : c, hi = r < c ? c : r;
+    HL[t] = S[HIDX(lo, hi)];
+  }
+  __syncthreads();
+  if (t < 49) {  // Mt = H_L Ad
+    int a = t / 7, c = t % 7;
+    double s = 0.0;
+    for (int b = 0; b < 7; ++b) s += HL[7 * a + b] * Ad[7 * b + c];
+    Mt[t] = s;
+  }
+  __syncthreads();
+  if (t < 49) {  // A = Ad^T Mt; upper triangle computed, mirrored for exact symmetry
+    int r = t / 7, c = t % 7;
+    int lo = r < c ? r : c, hi = r < c ? c : r;
+    double s = 0.0;
+    for (int a = 0; a < 7; ++a) s += Ad[7 * a + lo] * Mt[7 * a + hi];
+    A_out[49 * int64_t(e) + t] = s;
+  }
+  if (t < 7) {
+    double s = 0.0;
+    for (int a = 0; a < 7; ++a) s += Ad[7 * a + t] * S[28 + a];
+    b_out[7 * int64_t(e) + t] = s;
+  }
+  if (t == 0) {
+    cost_e[e] = S[35];
+    count_e[e] = int64_t(S[36] + 0.5);
+  }
+}
+
+int launch_edge_finalize(const EdgeDev* edges, int n_edges, const float* partials, const double* Ad,
+                         double* A_out, double* b_out, double* cost_e, int64_t* count_e, hipStream_t s) {
+  if (n_edges <= 0) return DS3_OK;
+  hipLaunchKernelGGL(k_edge_finalize, dim3(n_edges), dim3(64), 0, s, edges, partials, Ad, A_out, b_out,
+                     cost_e, count_e);
+  return check_hip(hipGetLastError(), "k_edge_finalize");
+}
+
+// --------------------------------------------------------------------------------------------------
+// Assembly: diagonal blocks and g per keyframe (incident edges in index order), off-diagonal blocks per
+// keyframe pair (its edges in index order); anchor rows/columns are identity with g = 0.
+// H must be zero outside the written blocks.
+// --------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_assemble(int n_kf, const int32_t* __restrict__ node_ptr,
+                                                 const int32_t* __restrict__ node_adj,
+                                                 const int32_t* __restrict__ pair_ptr,
+                                                 const int32_t* __restrict__ pair_edges,
+                                                 const int32_t* __restrict__ pair_ij,
+                                                 const double* __restrict__ A_e,
+                                                 const double* __restrict__ b_e,
+                                                 const uint8_t* __restrict__ anchor,
+                                                 double* __restrict__ H, double* __restrict__ g) {
+  const int t = threadIdx.x;
+  const int64_t n = 7 * int64_t(n_kf);
+  if (int(blockIdx.x) < n_kf) {
+    const int k = blockIdx.x;
+    const bool anc = anchor && anchor[k];
+    if (t < 49) {
+      double s = 0.0;
+      for (int p = node_ptr[k]; p < node_ptr[k + 1]; ++p) s += A_e[49 * int64_t(node_adj[p] >> 1) + t];
+      int r = t / 7, c = t % 7;
+      H[(7 * int64_t(k) + r) * n + 7 * k + c] = anc ? (r == c ? 1.0 : 0.0) : s;
+    } else if (t < 56) {
+      const int r = t - 49;
+      double s = 0.0;
+      for (int p = node_ptr[k]; p < node_ptr[k + 1]; ++p) {
+        const int code = node_adj[p];
+        const double v = b_e[7 * int64_t(code >> 1) + r];
+        s += (code & 1) ? v : -v;
+      }
+      g[7 * int64_t(k) + r] = anc ? 0.0 : s;
+    }
+  } else {
+    const int p = blockIdx.x - n_kf;
+    const int a = pair_ij[2 * p], b = pair_ij[2 * p + 1];
+    const bool anc = anchor && (anchor[a] || anchor[b]);
+    if (t < 49) {
+      double s = 0.0;
+      for (int q = pair_ptr[p]; q < pair_ptr[p + 1]; ++q) s -= A_e[49 * int64_t(pair_edges[q]) + t];
+      if (anc) s = 0.0;
+      const int r = t / 7, c = t % 7;
+      H[(7 * int64_t(a) + r) * n + 7 * b + c] = s;
+      H[(7 * int64_t(b) + c) * n + 7 * a + r] = s;
+    }
+  }
+}
+
+int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,
+                    const int32_t* pair_edges, const int32_t* pair_ij, int n_pairs, const double* A_e,
+                    const double* b_e, const uint8_t* anchor_mask, double* H, double* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble, dim3(n_kf + n_pairs), dim3(64), 0, s, n_kf, node_ptr, node_adj, pair_ptr,
+                     pair_edges, pair_ij, A_e, b_e, anchor_mask, H, g);
+  return check_hip(hipGetLastError(), "k_assemble");
+}
+
+// Deterministic sum of per-edge costs and counts (fixed strided split + fixed tree).
+__global__ __launch_bounds__(256) void k_sum_costs(const double* __restrict__ cost_e,
+                                                   const int64_t* __restrict__ count_e, int n_edges,
+                                                   double* __restrict__ cost_out,
+                                                   int64_t* __restrict__ count_out) {
+  __shared__ double sc[256];
+  __shared__ long long sn[256];
+  double c = 0.0;
+  long long m = 0;
+  for (int e = threadIdx.x; e < n_edges; e += 256) {
+    c += cost_e[e];
+    m += count_e[e];
+  }
+  sc[threadIdx.x] = c;
+  sn[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      sc[threadIdx.x] += sc[threadIdx.x + w];
+      sn[threadIdx.x] += sn[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (cost_out) *cost_out = sc[0];
+    if (count_out) *count_out = sn[0];
+  }
+}
+
+int launch_sum_costs(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
+                     int64_t* count_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_costs, dim3(1), dim3(256), 0, s, cost_e, count_e, n_edges, cost_out, count_out);
+  return check_hip(hipGetLastError(), "k_sum_costs");
+}
+
+// --------------------------------------------------------------------------------------------------
+// Update T <- Exp(tau) T (Sec. III-D), fixed poses untouched; helpers
+// --------------------------------------------------------------------------------------------------
+__global__ void k_sim3_update(double* __restrict__ poses, const double* __restrict__ tau,
+                              const uint8_t* __restrict__ fixed, int n) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  if (fixed && fixed[k]) return;
+  Sim3 E = sim3_exp(tau + 7 * int64_t(k));
+  Sim3 T = sim3_load(poses + 8 * int64_t(k));
+  sim3_store(sim3_mul(E, T), poses + 8 * int64_t(k));
+}
+
+int launch_sim3_update(double* poses, const double* tau, const uint8_t* fixed, int n, hipStream_t s) {
+  if (n <= 0) return DS3_OK;
+  hipLaunchKernelGGL(k_sim3_update, dim3((n + 63) / 64), dim3(64), 0, s, poses, tau, fixed, n);
+  return check_hip(hipGetLastError(), "k_sim3_update");
+}
+
+__global__ void k_fill_f64(double* p, size_t n, double v) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u32(unsigned* p, size_t n, unsigned v) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_copy_f64(const double* src, double* dst, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+static int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return int(b);
+}
+
+int launch_fill(double* p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return DS3_OK;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return check_hip(hipGetLastError(), "k_fill_f64");
+}
+
+int launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s) {
+  if (n == 0) return DS3_OK;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return check_hip(hipGetLastError(), "k_fill_u32");
+}
+
+int launch_copy_f64(const double* src, double* dst, size_t n, hipStream_t s) {
+  if (n == 0) return DS3_OK;
+  hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  return check_hip(hipGetLastError(), "k_copy_f64");
+}
+
+// Valid matches per tile (for ordering the work items): one block per (edge, tile).
+__global__ __launch_bounds__(256) void k_count_valid(const EdgeDev* __restrict__ edges,
+                                                     const int32_t* __restrict__ idx_arena, int tile_px,
+                                                     int32_t* __restrict__ counts) {
+  const int e = blockIdx.y;
+  const EdgeDev E = edges[e];
+  const int tile = blockIdx.x;
+  if (tile >= E.n_tiles) return;
+  int c = 0;
+  const int64_t base = int64_t(tile) * tile_px;
+  for (int q = threadIdx.x; q < tile_px; q += 256) {
+    int64_t n = base + q;
+    if (n < E.npx_j) {
+      int32_t m = idx_arena[E.idx_off + n];
+      c += (m >= 0 && m < E.npx_i) ? 1 : 0;
+    }
+  }
+  c = wave_sum(c);
+  __shared__ int s[4];
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[E.tile0 + tile] = s[0] + s[1] + s[2] + s[3];
+}
+
+int launch_count_valid(const EdgeDev* edges, int n_edges, const int32_t* idx_arena, int tile_px,
+                       int max_tiles, int32_t* counts, hipStream_t s) {
+  if (n_edges <= 0 || max_tiles <= 0) return DS3_OK;
+  hipLaunchKernelGGL(k_count_valid, dim3(max_tiles, n_edges), dim3(256), 0, s, edges, idx_arena, tile_px,
+                     counts);
+  return check_hip(hipGetLastError(), "k_count_valid");
+}
+
+}  // namespace ds3

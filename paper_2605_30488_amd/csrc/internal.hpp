@@ -1,0 +1,114 @@
+// Host-side declarations shared by the translation units of libds3 (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/ds3.h"
+
+namespace ds3 {
+
+// ---- error state -----------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+#define DS3_TRY_HIP(expr)                                        \
+  do {                                                           \
+    int _rc = ::ds3::check_hip((expr), #expr);                   \
+    if (_rc != DS3_OK) return _rc;                               \
+  } while (0)
+#define DS3_TRY(expr)            \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != DS3_OK) return _rc; \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Carves aligned sub-buffers out of one workspace block (or only measures when base == nullptr).
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = align_up(used);
+    used = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+// ---- graph-step device structures --------------------------------------------------------------------
+// One edge as the kernels see it.
+struct EdgeDev {
+  int64_t off_i, off_j;  // arena pixel offsets of keyframes i and j
+  int64_t idx_off;       // idx arena offset
+  int32_t npx_i, npx_j;  // pixel counts
+  int32_t i, j;          // keyframe ids
+  int32_t tile0;         // first tile slot of the edge in the partial buffer
+  int32_t n_tiles;
+};
+
+// Per-edge relative transform T_ij = T_i^-1 T_j in float32 (sR row-major, t) for the residual kernel.
+struct EdgeXf {
+  float m[12];
+  float pad[4];
+};
+
+// Constants of the residual kernel.
+struct GnConst {
+  float inv_sr, inv_sd, inv_sr2, inv_sd2, kappa;
+};
+
+constexpr int kPartial = 40;  // floats per tile partial: H upper 28, b 7, cost, count, 3 pad
+constexpr int kReduceThreads = 256;
+
+// One (edge, tile) work item of the batched residual kernel.
+struct WorkItem {
+  int32_t edge;
+  int32_t tile;
+};
+
+GnConst make_gn_const(const ds3_gn_params& p);
+
+// gn.hip
+int launch_gn_prep(const double* poses, const EdgeDev* edges, int n_edges, EdgeXf* xf, double* Ad,
+                   unsigned* queue_counter, hipStream_t s);
+int launch_edge_reduce_one(ds3_dtype dt, int ppt, const void* arena, const EdgeDev& e, int edge_id,
+                           const EdgeXf* xf, const int32_t* idx_arena, float* partials, GnConst c,
+                           hipStream_t s);
+int launch_edge_reduce_batched(ds3_dtype dt, int ppt, int grid, const void* arena, const EdgeDev* edges,
+                               const WorkItem* items, int n_items, const EdgeXf* xf,
+                               const int32_t* idx_arena, float* partials, unsigned* queue_counter,
+                               GnConst c, hipStream_t s);
+int launch_edge_finalize(const EdgeDev* edges, int n_edges, const float* partials, const double* Ad,
+                         double* A_out, double* b_out, double* cost_e, int64_t* count_e, hipStream_t s);
+int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,
+                    const int32_t* pair_edges, const int32_t* pair_ij, int n_pairs, const double* A_e,
+                    const double* b_e, const uint8_t* anchor_mask, double* H, double* g, hipStream_t s);
+int launch_sum_costs(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
+                     int64_t* count_out, hipStream_t s);
+int launch_sim3_update(double* poses, const double* tau, const uint8_t* fixed, int n, hipStream_t s);
+int launch_fill(double* p, size_t n, double v, hipStream_t s);
+int launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s);
+int launch_copy_f64(const double* src, double* dst, size_t n, hipStream_t s);
+int launch_count_valid(const EdgeDev* edges, int n_edges, const int32_t* idx_arena, int tile_px,
+                       int max_tiles, int32_t* counts, hipStream_t s);
+
+// chol.hip
+size_t chol_workspace_bytes(int n);
+int launch_chol_ladder(const double* H, const double* g, int n, double lambda, double eps0, double mult,
+                       int attempts, double* tau, int32_t* status, void* ws, hipStream_t s);
+
+// sim3.hip
+int launch_sim3_exp(const double* tau, double* poses, int n, hipStream_t s);
+int launch_sim3_log(const double* poses, double* tau, int n, hipStream_t s);
+
+// pack / match / gauge / adjoint
+int launch_pack(const float* xyz, const float* conf, int64_t n, ds3_dtype dt, void* out, hipStream_t s);
+int device_cu_count();
+
+}  // namespace ds3

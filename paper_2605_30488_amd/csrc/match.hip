@@ -1,0 +1,314 @@
+// Projective ray matching (Sec. III-A "Learned geometry": p* = argmin_p |psi([X_ref]_p) - psi(x)|^2)
+// and bidirectional verification with the nu gate (Sec. III-B).
+//
+// Per query pixel: Levenberg-Marquardt over the continuous reference pixel p on the bilinear interpolant
+// of the reference ray image psi(X_ref) (not renormalised), started at the query's own pixel scaled to
+// the reference grid; a trial step is accepted iff it lowers |s(p) - psi(x)|^2 (damping / 10, floored),
+// otherwise the damping grows x10; stop after max_iters trial steps or an accepted step below
+// step_tol_px. idx = round(p*) (ties up). Valid iff no hole was touched, the final angular residual is
+// within ang_tol_px * min(|ds/du|, |ds/dv|) and the range agrees within range_rel_tol. The mutual check
+// keeps pixel n of j iff its match m in i maps back within a Chebyshev radius of n.
+//
+// The reference ray image is built once per keyframe (float4: psi, |X|; holes have |X| = 0) so each LM
+// sample is four 16-byte reads. Batched launches walk (direction, tile) items that the host interleaves
+// so that all tiles of one direction land on one XCD (block b runs on XCD b mod 8), keeping that
+// reference ray image in one L2.
+#include "common.hpp"
+#include "internal.hpp"
+#include "match_internal.hpp"
+
+namespace ds3 {
+
+template <int DT>
+__global__ void k_raymap(const void* __restrict__ arena, int64_t n, float4* __restrict__ rays) {
+  int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (; k < n; k += stride) {
+    float4 X = Px<DT>::load(arena, k);
+    float d2 = fmaf(X.x, X.x, fmaf(X.y, X.y, X.z * X.z));
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (finite3(X.x, X.y, X.z) && d2 > 1e-18f) {
+      float rd = 1.0f / sqrtf(d2);
+      float d = sqrtf(d2);
+      r = make_float4(X.x * rd, X.y * rd, X.z * rd, d);
+    }
+    rays[k] = r;
+  }
+}
+
+int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, hipStream_t s) {
+  if (n <= 0) return DS3_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (dt == DS3_F32)
+    hipLaunchKernelGGL(k_raymap<DS3_F32>, dim3(blocks), dim3(256), 0, s, arena, n, rays);
+  else
+    hipLaunchKernelGGL(k_raymap<DS3_BF16>, dim3(blocks), dim3(256), 0, s, arena, n, rays);
+  return check_hip(hipGetLastError(), "k_raymap");
+}
+
+struct Sample {
+  float s[3], su[3], sv[3];
+  bool hole;
+};
+
+__device__ inline Sample sample_rays(const float4* __restrict__ R, int H, int W, float u, float v) {
+  int u0 = min(int(floorf(u)), W - 2);
+  int v0 = min(int(floorf(v)), H - 2);
+  u0 = max(u0, 0);
+  v0 = max(v0, 0);
+  const float fu = u - float(u0), fv = v - float(v0);
+  const int64_t i00 = int64_t(v0) * W + u0;
+  const float4 a = R[i00], b = R[i00 + 1], c = R[i00 + W], d = R[i00 + W + 1];
+  Sample S;
+  S.hole = !(a.w > 0.f) || !(b.w > 0.f) || !(c.w > 0.f) || !(d.w > 0.f);
+  const float ax[3] = {a.x, a.y, a.z}, bx[3] = {b.x, b.y, b.z}, cx[3] = {c.x, c.y, c.z},
+              dx[3] = {d.x, d.y, d.z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float top = fmaf(fu, bx[k] - ax[k], ax[k]);
+    const float bot = fmaf(fu, dx[k] - cx[k], cx[k]);
+    S.s[k] = fmaf(fv, bot - top, top);
+    S.su[k] = fmaf(fv, (dx[k] - cx[k]) - (bx[k] - ax[k]), bx[k] - ax[k]);
+    S.sv[k] = bot - top;
+  }
+  return S;
+}
+
+// One query: returns idx (or -1); p and iteration count through the pointers when non-null.
+__device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W, float4 x, int qu, int qv,
+                                      int Hq, int Wq, const MatchConst& P, float* pu, float* pv,
+                                      int* iters) {
+  *pu = __int_as_float(0x7fc00000);
+  *pv = __int_as_float(0x7fc00000);
+  *iters = 0;
+  const float dx2 = fmaf(x.x, x.x, fmaf(x.y, x.y, x.z * x.z));
+  if (!finite3(x.x, x.y, x.z) || !(dx2 > 1e-18f)) return -1;
+  const float dx = sqrtf(dx2);
+  const float t0 = x.x / dx, t1 = x.y / dx, t2 = x.z / dx;
+  float u = (Wq > 1) ? float(qu) * (float(W - 1) / float(Wq - 1)) : 0.0f;
+  float v = (Hq > 1) ? float(qv) * (float(H - 1) / float(Hq - 1)) : 0.0f;
+  Sample S = sample_rays(R, H, W, u, v);
+  if (S.hole) return -1;
+  float r0 = S.s[0] - t0, r1 = S.s[1] - t1, r2 = S.s[2] - t2;
+  float c = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
+  float lam = P.lambda0;
+  int it = 0;
+  for (; it < P.max_iters; ++it) {
+    const float a = fmaf(S.su[0], S.su[0], fmaf(S.su[1], S.su[1], S.su[2] * S.su[2]));
+    const float b = fmaf(S.su[0], S.sv[0], fmaf(S.su[1], S.sv[1], S.su[2] * S.sv[2]));
+    const float dd = fmaf(S.sv[0], S.sv[0], fmaf(S.sv[1], S.sv[1], S.sv[2] * S.sv[2]));
+    const float gu = fmaf(S.su[0], r0, fmaf(S.su[1], r1, S.su[2] * r2));
+    const float gv = fmaf(S.sv[0], r0, fmaf(S.sv[1], r1, S.sv[2] * r2));
+    const float A = a * (1.0f + lam), D = dd * (1.0f + lam);
+    const float det = A * D - b * b;
+    if (!(det > 0.0f)) {
+      lam *= 10.0f;
+      continue;
+    }
+    const float du = -(D * gu - b * gv) / det;
+    const float dv = -(A * gv - b * gu) / det;
+    const float un = fminf(fmaxf(u + du, 0.0f), float(W - 1));
+    const float vn = fminf(fmaxf(v + dv, 0.0f), float(H - 1));
+    Sample Sn = sample_rays(R, H, W, un, vn);
+    if (Sn.hole) {
+      *iters = it + 1;
+      return -1;
+    }
+    const float n0 = Sn.s[0] - t0, n1 = Sn.s[1] - t1, n2 = Sn.s[2] - t2;
+    const float cn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
+    if (cn < c) {
+      const float step = fmaxf(fabsf(un - u), fabsf(vn - v));
+      u = un; v = vn; S = Sn; c = cn;
+      r0 = n0; r1 = n1; r2 = n2;
+      lam = fmaxf(lam * 0.1f, P.lambda_min);
+      if (step < P.step_tol) {
+        ++it;
+        break;
+      }
+    } else {
+      lam *= 10.0f;
+    }
+  }
+  *iters = it;
+  *pu = u;
+  *pv = v;
+  const float nsu = sqrtf(fmaf(S.su[0], S.su[0], fmaf(S.su[1], S.su[1], S.su[2] * S.su[2])));
+  const float nsv = sqrtf(fmaf(S.sv[0], S.sv[0], fmaf(S.sv[1], S.sv[1], S.sv[2] * S.sv[2])));
+  const float rr = sqrtf(c);
+  if (!(rr <= P.ang_tol * fminf(nsu, nsv))) return -1;
+  const int mu = min(max(int(floorf(u + 0.5f)), 0), W - 1);
+  const int mv = min(max(int(floorf(v + 0.5f)), 0), H - 1);
+  const int32_t m = mv * W + mu;
+  const float4 Rm = R[m];
+  if (!(Rm.w > 0.f)) return -1;
+  if (!(fabsf(dx - Rm.w) <= P.range_tol * Rm.w)) return -1;
+  return m;
+}
+
+// Single direction: one thread per query pixel.
+template <int DT>
+__global__ __launch_bounds__(256) void k_match_one(const float4* __restrict__ rays, int H, int W,
+                                                   const void* __restrict__ qry, int Hq, int Wq,
+                                                   MatchConst P, int32_t* __restrict__ idx_out,
+                                                   float* __restrict__ p_out, int32_t* __restrict__ it_out) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= int64_t(Hq) * Wq) return;
+  const float4 x = Px<DT>::load(qry, n);
+  float pu, pv;
+  int its;
+  const int32_t m = match_query(rays, H, W, x, int(n % Wq), int(n / Wq), Hq, Wq, P, &pu, &pv, &its);
+  idx_out[n] = m;
+  if (p_out) {
+    p_out[2 * n] = pu;
+    p_out[2 * n + 1] = pv;
+  }
+  if (it_out) it_out[n] = its;
+}
+
+int launch_match_one(const float4* rays, int H, int W, const void* qry, int Hq, int Wq, ds3_dtype dt,
+                     const MatchConst& P, int32_t* idx_out, float* p_out, int32_t* it_out, hipStream_t s) {
+  const int64_t n = int64_t(Hq) * Wq;
+  if (n <= 0) return DS3_OK;
+  dim3 grid(unsigned((n + 255) / 256)), block(256);
+  if (dt == DS3_F32)
+    hipLaunchKernelGGL(k_match_one<DS3_F32>, grid, block, 0, s, rays, H, W, qry, Hq, Wq, P, idx_out, p_out, it_out);
+  else
+    hipLaunchKernelGGL(k_match_one<DS3_BF16>, grid, block, 0, s, rays, H, W, qry, Hq, Wq, P, idx_out, p_out, it_out);
+  return check_hip(hipGetLastError(), "k_match_one");
+}
+
+// Locate the (entry, tile) of block b in the binned item map; false for padding blocks.
+__device__ inline bool locate_item(const ItemMap& M, int b, int& entry, int& tile) {
+  const int x = b & 7, slot = b >> 3;
+  if (slot >= M.bin_tiles[x]) return false;
+  int lo = M.bin_start[x], hi = M.bin_start[x + 1] - 1;
+  while (lo < hi) {  // last entry with prefix <= slot
+    const int mid = (lo + hi + 1) >> 1;
+    if (M.prefix[mid] <= slot) lo = mid; else hi = mid - 1;
+  }
+  entry = lo;
+  tile = slot - M.prefix[lo];
+  return true;
+}
+
+// Batched: 256 query pixels per block; blocks of one direction share an XCD.
+template <int DT>
+__global__ __launch_bounds__(256) void k_match_batched(const float4* __restrict__ rays,
+                                                       const void* __restrict__ cross,
+                                                       const MatchDir* __restrict__ dirs, ItemMap map,
+                                                       MatchConst P, int32_t* __restrict__ idx_tmp) {
+  int entry, tile;
+  if (!locate_item(map, blockIdx.x, entry, tile)) return;
+  const MatchDir D = dirs[entry];
+  const int64_t n = int64_t(tile) * 256 + threadIdx.x;
+  if (n >= int64_t(D.Hq) * D.Wq) return;
+  const float4 x = Px<DT>::load(cross, D.qry_off + n);
+  float pu, pv;
+  int its;
+  idx_tmp[D.out_off + n] = match_query(rays + D.ref_off, D.Hr, D.Wr, x, int(n % D.Wq), int(n / D.Wq),
+                                       D.Hq, D.Wq, P, &pu, &pv, &its);
+}
+
+int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, const MatchDir* dirs,
+                         ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp, hipStream_t s) {
+  if (grid <= 0) return DS3_OK;
+  if (dt == DS3_F32)
+    hipLaunchKernelGGL(k_match_batched<DS3_F32>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp);
+  else
+    hipLaunchKernelGGL(k_match_batched<DS3_BF16>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp);
+  return check_hip(hipGetLastError(), "k_match_batched");
+}
+
+// --------------------------------------------------------------------------------------------------
+// Mutual check + nu counts. Side J (pixels of j): final idx and valid mask; side I (pixels of i):
+// count only. counts[2e] = i-side count, counts[2e+1] = j-side count.
+// --------------------------------------------------------------------------------------------------
+__device__ inline bool round_trip(const int32_t* __restrict__ fwd, const int32_t* __restrict__ bwd,
+                                  int64_t n, int W_self, int64_t n_self, int64_t n_other, int radius,
+                                  int32_t& m_out) {
+  const int32_t m = fwd[n];
+  m_out = m;
+  if (m < 0 || m >= n_other) return false;
+  const int32_t n2 = bwd[m];
+  if (n2 < 0 || n2 >= n_self) return false;
+  const int du = abs(int(n2 % W_self) - int(n % W_self));
+  const int dv = abs(int(n2 / W_self) - int(n / W_self));
+  return max(du, dv) <= radius;
+}
+
+template <int DT>
+__device__ inline float conf_at(const void* arena, int64_t px) {
+  return Px<DT>::load(arena, px).w;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_mutual(const MutualDir* __restrict__ md, ItemMap map,
+                                                MatchConst P, const int32_t* __restrict__ idx_tmp,
+                                                int32_t* __restrict__ idx_final, uint8_t* __restrict__ valid,
+                                                unsigned* __restrict__ counts) {
+  int entry, tile;
+  if (!locate_item(map, blockIdx.x, entry, tile)) return;  // uniform per block
+  const MutualDir M = md[entry];
+  int hit = 0;
+  const int64_t n = int64_t(tile) * 256 + threadIdx.x;
+  const int64_t n_self = int64_t(M.H_self) * M.W_self;
+  if (n < n_self) {
+    int32_t m;
+    const bool ok = round_trip(idx_tmp + M.fwd_off, idx_tmp + M.bwd_off, n, M.W_self, n_self,
+                               int64_t(M.H_other) * M.W_other, P.radius, m);
+    if (ok) {
+      const double cs = double(conf_at<DT>(M.conf_self, n));
+      const double co = double(conf_at<DT>(M.conf_other, m));
+      hit = (sqrt(co * cs) >= P.q_min) ? 1 : 0;
+    }
+    if (M.write_out) {
+      idx_final[M.out_off + n] = ok ? m : -1;
+      valid[M.out_off + n] = ok ? 1 : 0;
+    }
+  }
+  hit = wave_sum(hit);
+  __shared__ int s[4];
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = hit;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = s[0] + s[1] + s[2] + s[3];
+    if (tot) atomicAdd(&counts[M.count_slot], unsigned(tot));
+  }
+}
+
+int launch_mutual(const MutualDir* md, ItemMap map, int grid, ds3_dtype dt, const MatchConst& P,
+                  const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* counts,
+                  hipStream_t s) {
+  if (grid <= 0) return DS3_OK;
+  if (dt == DS3_F32)
+    hipLaunchKernelGGL(k_mutual<DS3_F32>, dim3(grid), dim3(256), 0, s, md, map, P, idx_tmp, idx_final, valid, counts);
+  else
+    hipLaunchKernelGGL(k_mutual<DS3_BF16>, dim3(grid), dim3(256), 0, s, md, map, P, idx_tmp, idx_final, valid, counts);
+  return check_hip(hipGetLastError(), "k_mutual");
+}
+
+// nu = count / pixels in double; admit = min(nu_i, nu_j) >= nu_min (same arithmetic as a double sum).
+__global__ void k_nu_finalize(const unsigned* __restrict__ counts, const int64_t* __restrict__ npx,
+                              int n_edges, double nu_min, float* __restrict__ nu,
+                              int32_t* __restrict__ admit) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_edges) return;
+  const double ni = double(counts[2 * e]) / double(npx[2 * e]);
+  const double nj = double(counts[2 * e + 1]) / double(npx[2 * e + 1]);
+  if (nu) {
+    nu[2 * e] = float(ni);
+    nu[2 * e + 1] = float(nj);
+  }
+  if (admit) admit[e] = (fmin(ni, nj) >= nu_min) ? 1 : 0;
+}
+
+int launch_nu_finalize(const unsigned* counts, const int64_t* npx, int n_edges, double nu_min, float* nu,
+                       int32_t* admit, hipStream_t s) {
+  if (n_edges <= 0) return DS3_OK;
+  hipLaunchKernelGGL(k_nu_finalize, dim3((n_edges + 127) / 128), dim3(128), 0, s, counts, npx, n_edges,
+                     nu_min, nu, admit);
+  return check_hip(hipGetLastError(), "k_nu_finalize");
+}
+
+}  // namespace ds3

@@ -1,0 +1,57 @@
+// Device tables of the matching kernels (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/ds3.h"
+
+namespace ds3 {
+
+struct MatchConst {
+  int max_iters;
+  float lambda0, lambda_min, step_tol, ang_tol, range_tol;
+  int radius;
+  double q_min;
+};
+
+// One decoded direction: queries (another view's points in the reference camera) against a reference.
+struct MatchDir {
+  int64_t ref_off;  // pixel offset of the reference in the ray-image buffer
+  int64_t qry_off;  // pixel offset of the queries in their arena
+  int64_t out_off;  // offset of the per-query idx in the temporary idx buffer
+  int32_t Hr, Wr, Hq, Wq;
+};
+
+// One side of the mutual check: pixels of `self`, forward matches into `other` and back.
+struct MutualDir {
+  int64_t fwd_off, bwd_off;  // offsets in the temporary idx buffer (self->other, other->self)
+  int64_t out_off;           // offset of the final idx / valid outputs (write_out only)
+  const void* conf_self;     // xyzc of self (pixel 0); c = confidence
+  const void* conf_other;    // xyzc of other (pixel 0)
+  int32_t H_self, W_self, H_other, W_other;
+  int32_t count_slot;        // nu counter index
+  int32_t write_out;         // 1 for the j side of an edge
+};
+
+// Blocks are dealt to 8 bins (block b -> bin b mod 8, which the dispatcher places on XCD b mod 8);
+// entries of bin x are [bin_start[x], bin_start[x+1]) with within-bin tile prefixes; 256 px per tile.
+struct ItemMap {
+  const int32_t* bin_start;  // 9
+  const int32_t* prefix;     // per entry: first tile of the entry within its bin
+  const int32_t* bin_tiles;  // 8
+};
+
+int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, hipStream_t s);
+int launch_match_one(const float4* rays, int H, int W, const void* qry, int Hq, int Wq, ds3_dtype dt,
+                     const MatchConst& P, int32_t* idx_out, float* p_out, int32_t* it_out, hipStream_t s);
+int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, const MatchDir* dirs,
+                         ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp, hipStream_t s);
+int launch_mutual(const MutualDir* md, ItemMap map, int grid, ds3_dtype dt, const MatchConst& P,
+                  const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* counts,
+                  hipStream_t s);
+int launch_nu_finalize(const unsigned* counts, const int64_t* npx, int n_edges, double nu_min, float* nu,
+                       int32_t* admit, hipStream_t s);
+
+}  // namespace ds3

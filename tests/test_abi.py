@@ -1,0 +1,66 @@
+"""The C-ABI library loads on the CPU and exports every entry point include/ds3.h declares (no compute
+calls without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ds3.h")
+LIB = os.path.join(ROOT, "paper_2605_30488_amd", "libds3.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ds3_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2605_30488_amd import _build
+        _build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_symbol():
+    from paper_2605_30488_amd import _lib
+    assert sorted(_lib.exported_names()) == declared()
+
+
+def test_pure_host_entry_points(lib):
+    """Calls that touch no device: parameter defaults, status strings, workspace sizing, argument
+    checks that fail before any HIP call."""
+    from paper_2605_30488_amd import _lib as L
+    ds3 = L.load()
+    p = L.MatchParams()
+    ds3.ds3_default_match_params(ctypes.byref(p))
+    assert (p.max_iters, p.lambda0, p.ang_tol_px, p.range_rel_tol, p.mutual_radius_px, p.q_min, p.nu_min) == \
+        (10, 1e-4, 0.5, 0.10, 1, 1.5, 0.1)
+    q = L.GNParams()
+    ds3.ds3_default_gn_params(ctypes.byref(q))
+    assert (q.sigma_ray, q.sigma_dist, q.huber_k, q.lam, q.eps0, q.eps_mult, q.max_attempts) == \
+        (0.003, 10.0, 1.345, 0.0, 1e-6, 100.0, 6)
+    assert ds3.ds3_version() >= 100
+    assert b"invalid" in ds3.ds3_status_string(-1)
+    assert ds3.ds3_match_workspace_bytes(384, 512) >= 384 * 512 * 16
+    assert ds3.ds3_match_workspace_bytes(0, 512) == 0
+    assert ds3.ds3_chol_workspace_bytes(1400) > 2 * 1400 * 1400 * 8
+    kf = (L.Image * 2)(L.Image(48, 64, 0), L.Image(48, 64, 3072))
+    ed = (L.Edge * 1)(L.Edge(0, 1, 0))
+    assert ds3.ds3_gn_workspace_bytes(2, kf, 1, ed, 0) > 0
+    bad = (L.Edge * 1)(L.Edge(0, 0, 0))  # self loop
+    assert ds3.ds3_gn_workspace_bytes(2, kf, 1, bad, 0) == 0
+    # null pointers are rejected before any device call
+    assert ds3.ds3_match(None, L.Image(2, 2, 0), None, L.Image(2, 2, 0), 0, ctypes.byref(p), None, None,
+                         None, None, 0, None) == -1
+    assert ds3.ds3_pack_xyzc(None, None, 5, 0, None, None) == -1

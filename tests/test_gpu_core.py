@@ -1,0 +1,291 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI: packing, Sim(3), the Cholesky
+ladder, the graph step (plain form), projective matching and gauge alignment, at sizes the oracle
+finishes in seconds (several tiles, ragged tails)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.helpers import exact_graph, perturb
+
+pytestmark = pytest.mark.gpu
+
+ds3 = pytest.importorskip("paper_2605_30488_amd.api")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(dev)
+
+
+# --------------------------------------------------------------------------------------------------
+# keyframe packing
+# --------------------------------------------------------------------------------------------------
+def test_pack_bit_exact(dev):
+    rng = np.random.default_rng(0)
+    xyz = (rng.normal(size=(5003, 3)) * rng.choice([1e-3, 1, 30, 1e4], size=(5003, 1))).astype(np.float32)
+    xyz[0] = [1 + 2 ** -8, 1 + 3 * 2 ** -8, np.inf]
+    xyz[1] = [np.nan, 1e-40, 3.4e38]
+    xyz[2] = [-0.0, 0.0, 1.0]
+    conf = rng.uniform(1, 5, size=5003).astype(np.float32)
+    a32 = ds3.pack_xyzc(_t(xyz, dev), _t(conf, dev), "f32").cpu().numpy()
+    assert np.array_equal(a32[:, :3].view(np.uint32), xyz.view(np.uint32))
+    assert np.array_equal(a32[:, 3], conf)
+    b16 = ds3.pack_xyzc(_t(xyz, dev), _t(conf, dev), "bf16").cpu().numpy().view(np.uint16)
+    ref = O.bf16_round(np.c_[xyz, conf])
+    nan = np.isnan(np.c_[xyz, conf])
+    assert np.array_equal(b16[~nan], ref[~nan])
+    assert np.all((b16[nan] & 0x7F80) == 0x7F80) and np.all((b16[nan] & 0x7F) != 0)
+
+
+# --------------------------------------------------------------------------------------------------
+# Sim(3)
+# --------------------------------------------------------------------------------------------------
+def _tangents(rng, n):
+    scales = [1e-9, 1e-6, 1e-3, 0.03, 0.06, 0.3, 1.0, 2.0]
+    out = []
+    for k in range(n):
+        s = scales[k % len(scales)]
+        t = rng.normal(size=7) * s
+        w = np.linalg.norm(t[3:6])
+        if w > 3.0:
+            t[3:6] *= 3.0 / w
+        out.append(t)
+    # mixed regimes: tiny rotation with a large scale change and vice versa
+    out.append(np.array([0.3, -0.2, 0.1, 1e-7, 2e-7, -1e-7, 0.7]))
+    out.append(np.array([0.3, -0.2, 0.1, 0.04, 0.01, -0.02, 1e-9]))
+    out.append(np.array([0.3, -0.2, 0.1, 0.0, 0.0, 0.0, -2.5]))
+    return np.array(out)
+
+
+def test_sim3_exp_log(dev):
+    rng = np.random.default_rng(1)
+    tau = _tangents(rng, 400)
+    p = ds3.sim3_exp(_t(tau, dev)).cpu().numpy()
+    for k in range(len(tau)):
+        M = O.pose_to_mat(p[k])
+        E = O.sim3_exp_mat(tau[k])
+        assert np.abs(M - E).max() <= 1e-12 * max(1.0, np.abs(E).max()), (k, tau[k])
+    back = ds3.sim3_log(_t(p, dev)).cpu().numpy()
+    ref = O.sim3_log(p)
+    assert np.abs(back - ref).max() <= 1e-10
+    assert np.abs(back - tau).max() <= 1e-10
+
+
+def test_sim3_update(dev):
+    rng = np.random.default_rng(2)
+    poses = np.stack([O.sim3_exp(rng.normal(size=7))[0] for _ in range(33)])
+    tau = _tangents(rng, 30)[:33]
+    fixed = np.zeros(33, np.uint8)
+    fixed[[0, 5]] = 1
+    P = _t(poses, dev)
+    ds3.sim3_update(P, _t(tau, dev), _t(fixed, dev))
+    got = P.cpu().numpy()
+    ref = O.sim3_update(poses, tau, fixed)
+    assert np.array_equal(got[0], poses[0]) and np.array_equal(got[5], poses[5])
+    assert O.pose_error(got, ref).max() < 1e-12
+
+
+# --------------------------------------------------------------------------------------------------
+# Cholesky ladder (eq. 7)
+# --------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [7, 14, 33, 140, 700])
+def test_chol_spd(dev, n):
+    rng = np.random.default_rng(n)
+    A = rng.normal(size=(n, n))
+    H = A @ A.T + 0.5 * np.eye(n)
+    g = rng.normal(size=n)
+    tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev), lam=0.1)
+    ref, st_ref = O.chol_ladder(H, g, lam=0.1)
+    assert int(st.item()) == st_ref == 0
+    assert np.allclose(tau.cpu().numpy(), ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
+
+
+def test_chol_ladder_failures(dev):
+    rng = np.random.default_rng(13)
+    Q, _ = np.linalg.qr(rng.normal(size=(70, 70)))
+    ev = np.linspace(1.0, 5.0, 70)
+    ev[3] = -0.5
+    H = Q @ np.diag(ev) @ Q.T
+    g = rng.normal(size=70)
+    tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev))
+    ref, st_ref = O.chol_ladder(H, g)
+    assert int(st.item()) == st_ref == 3
+    assert np.allclose(tau.cpu().numpy(), ref, rtol=1e-9)
+    ev[3] = -1e5
+    H = Q @ np.diag(ev) @ Q.T
+    tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev))
+    assert int(st.item()) == -1 and np.all(tau.cpu().numpy() == 0)
+
+
+# --------------------------------------------------------------------------------------------------
+# Graph step, plain form
+# --------------------------------------------------------------------------------------------------
+def _f32(arrs):
+    """Inputs as the GPU sees them (float32), for both sides of a comparison."""
+    return [np.asarray(a, np.float32) for a in arrs]
+
+
+def _gpu_graph(xyz, conf, edges, idx, dev, dtype="f32", anchors=(0,)):
+    a = ds3.build_arena(xyz, conf, dtype, dev)
+    return ds3.Graph(a, edges, _t(np.concatenate([np.asarray(i).reshape(-1) for i in idx]), dev,
+                                  torch.int32), anchors=anchors)
+
+
+def test_gn_linearize_exact_graph(dev):
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=4, H=40, W=120, seed=21)  # 4800 px: 2 tiles, ragged
+    xyz, conf = _f32(xyz), _f32(conf)
+    poses = perturb(gt, np.random.default_rng(3), rot=0.02, trans=0.03, scale=0.02)
+    G = _gpu_graph(xyz, conf, edges, idx, dev)
+    H, g, cost, cnt = ds3.gn_linearize(G, _t(poses, dev))
+    og = O.Graph(xyz, conf, edges, idx, anchors=(0,))
+    Hr, gr, cr, nr, _, _ = O.gn_assemble(og, poses)
+    H, g = H.cpu().numpy(), g.cpu().numpy()
+    assert int(cnt.item()) == nr
+    assert abs(cost.item() - cr) <= 2e-5 * cr
+    assert np.abs(H - Hr).max() <= 2e-5 * np.abs(Hr).max()
+    assert np.abs(g - gr).max() <= 2e-4 * np.abs(gr).max()
+    assert np.array_equal(H, H.T)
+
+
+@pytest.mark.parametrize("start", ["identity", "noisy"])
+def test_gn_iterations_config1(dev, start):
+    """Ten GN steps of the tiny pair (ground-truth matches): poses agree with the oracle to 1e-5."""
+    g = synth.make_config(1)
+    idx = [g.gt_idx(0)]
+    init = g.poses_init if start == "identity" else perturb(g.poses_gt, np.random.default_rng(5))
+    G = _gpu_graph(g.xyz, g.conf, g.edges, idx, dev)
+    og = O.Graph(g.xyz, g.conf, g.edges, idx, anchors=(0,))
+    P = _t(init, dev)
+    ref = init.copy()
+    for it in range(10):
+        cost, st = ds3.sim3_gn_step(G, P)
+        ref, cr, sr, _ = O.gn_step(og, ref)
+        assert abs(cost.item() - cr) <= 1e-4 * cr, it
+        assert int(st.item()) == sr
+    err = O.pose_error(P.cpu().numpy(), ref).max()
+    assert err <= 1e-5, err
+
+
+def test_gn_step_exact_graph_recovers_truth(dev):
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=5, H=30, W=40, seed=22)
+    xyz, conf = _f32(xyz), _f32(conf)
+    init = perturb(gt, np.random.default_rng(6), rot=0.01, trans=0.02, scale=0.01)
+    G = _gpu_graph(xyz, conf, edges, idx, dev)
+    P = _t(init, dev)
+    for _ in range(8):
+        ds3.sim3_gn_step(G, P)
+    err = O.pose_error(P.cpu().numpy(), gt).max()
+    assert err < 1e-5, err
+    assert np.array_equal(P.cpu().numpy()[0], gt[0])
+
+
+# --------------------------------------------------------------------------------------------------
+# Matching
+# --------------------------------------------------------------------------------------------------
+def _margins(res, P=None):
+    """Oracle-side exclusion for bit-exact idx: rounding ties and validity thresholds within a margin."""
+    p = res.p
+    with np.errstate(invalid="ignore"):
+        tie = np.minimum(np.abs(p[:, 0] - np.floor(p[:, 0]) - 0.5), np.abs(p[:, 1] - np.floor(p[:, 1]) - 0.5))
+        near = (tie < 2e-4) | (np.abs(res.ratios[:, 0] - 1) < 1e-3) | (np.abs(res.ratios[:, 1] - 1) < 1e-4)
+    return np.nan_to_num(near, nan=False).astype(bool)
+
+
+def test_match_one_direction_bit_exact(dev):
+    g = synth.make_config(1)
+    Xji, _ = g.cross_view(0)
+    H, W = g.shape(0)
+    ref = ds3.pack_xyzc(_t(g.xyz[0], dev).reshape(-1, 3), _t(g.conf[0], dev).reshape(-1), "f32")
+    qry = ds3.pack_xyzc(_t(Xji, dev).reshape(-1, 3), _t(g.conf[1], dev).reshape(-1), "f32")
+    idx, p, its = ds3.match(ref, (H, W), qry, g.shape(1), "f32", diagnostics=True)
+    r = O.match(g.xyz[0], Xji)
+    idx = idx.cpu().numpy()
+    excl = _margins(r)
+    keep = ~excl
+    pv = p.cpu().numpy()
+    both = (r.idx >= 0) & (idx >= 0)
+    dev_p = np.abs(pv[both] - r.p[both]).max(axis=1)
+    print(f"excluded {excl.sum()} of {excl.size}; valid {np.mean(r.idx >= 0):.3f}; "
+          f"|p_gpu - p_oracle| median {np.median(dev_p):.2e} p99 {np.quantile(dev_p, 0.99):.2e} "
+          f"max {dev_p.max():.2e}; iteration counts equal {np.mean(its.cpu().numpy() == r.iters):.4f}")
+    assert excl.sum() <= 0.01 * excl.size
+    assert np.array_equal(idx[keep], r.idx[keep])
+    assert dev_p.max() < 2e-3
+
+
+def test_match_bidir_config1(dev):
+    g = synth.make_config(1)
+    Xji, Xij = g.cross_view(0)
+    (Hi, Wi), (Hj, Wj) = g.shape(0), g.shape(1)
+
+    def ar(x, c):
+        return ds3.pack_xyzc(_t(x, dev).reshape(-1, 3), _t(c, dev).reshape(-1), "f32")
+
+    idx, valid, nu, admit = ds3.match_bidir(ar(g.xyz[0], g.conf[0]), ar(Xji, g.conf[1]),
+                                            ar(g.xyz[1], g.conf[1]), ar(Xij, g.conf[0]), (Hi, Wi), (Hj, Wj))
+    r = O.match_bidir(g.xyz[0], Xji, g.xyz[1], Xij, g.conf[0], g.conf[1])
+    idx, valid = idx.cpu().numpy(), valid.cpu().numpy()
+    excl = _margins(r.fwd)
+    # a pixel whose own or partner's decision is near a margin may flip the round trip
+    bm = _margins(r.bwd)
+    partner = np.zeros_like(excl)
+    ok = r.fwd.idx >= 0
+    partner[ok] = bm[r.fwd.idx[ok]]
+    keep = ~(excl | partner)
+    assert np.array_equal(idx[keep], r.idx_j2i[keep])
+    assert np.array_equal(valid[keep], r.valid_j[keep])
+    assert np.allclose(nu.cpu().numpy(), r.nu, atol=3e-3)
+    assert bool(admit.item()) == r.admit
+
+
+def test_match_mixed_resolution(dev):
+    """Queries on a 48x64 grid against a 36x48 reference (start pixel scaled between grids)."""
+    g = synth.make_pair(H=36, W=48, seed=77)
+    h = synth.make_pair(H=48, W=64, seed=77)
+    Xq, _ = h.cross_view(0)
+    ref = ds3.pack_xyzc(_t(g.xyz[0], dev).reshape(-1, 3), _t(g.conf[0], dev).reshape(-1), "f32")
+    qry = ds3.pack_xyzc(_t(Xq, dev).reshape(-1, 3), _t(h.conf[1], dev).reshape(-1), "f32")
+    idx = ds3.match(ref, (36, 48), qry, (48, 64)).cpu().numpy()
+    r = O.match(g.xyz[0], Xq)
+    keep = ~_margins(r)
+    assert (r.idx >= 0).mean() > 0.3
+    assert np.array_equal(idx[keep], r.idx[keep])
+
+
+# --------------------------------------------------------------------------------------------------
+# Gauge alignment (eq. 4)
+# --------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("ref_is_i", [True, False])
+def test_gauge_align(dev, ref_is_i):
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=2, H=20, W=30, seed=31, frac_valid=0.7)
+    xyz, conf = _f32(xyz), _f32(conf)
+    rng = np.random.default_rng(8)
+    poses = perturb(gt, rng, rot=0.3, trans=1.0, scale=0.3, fixed=())
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    valid = (idx[0] >= 0).astype(np.uint8)
+    T, used = ds3.gauge_align(a, 0, 1, _t(idx[0], dev), _t(valid, dev), _t(poses, dev), ref_is_i=ref_is_i)
+    i, j = 0, 1
+    sel = np.nonzero(valid)[0]
+    Xi = np.asarray(xyz[i]).reshape(-1, 3)[idx[0][sel]].astype(np.float32).astype(np.float64)
+    Xj = np.asarray(xyz[j]).reshape(-1, 3)[sel].astype(np.float32).astype(np.float64)
+    wi, wj = O.transform_points(poses[i], Xi), O.transform_points(poses[j], Xj)
+    Tr = O.umeyama(wi, wj) if ref_is_i else O.umeyama(wj, wi)
+    assert int(used.item()) == 1
+    assert np.allclose(O.pose_to_mat(T.cpu().numpy()), O.pose_to_mat(Tr), atol=1e-9)
+    # fallback below N_c^min
+    T2, used2 = ds3.gauge_align(a, 0, 1, _t(idx[0], dev), _t(valid, dev), _t(poses, dev), ref_is_i=ref_is_i,
+                                nc_min=10 ** 7)
+    ref_kf, mov_kf = (0, 1) if ref_is_i else (1, 0)
+    Tf = O.compose(poses[ref_kf], O.invert(poses[mov_kf]))
+    assert int(used2.item()) == 0
+    assert np.allclose(O.pose_to_mat(T2.cpu().numpy()), O.pose_to_mat(Tf), atol=1e-12)
