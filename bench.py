@@ -1,0 +1,313 @@
+#!/usr/bin/env python3
+"""Benchmark of the dense Sim(3) back-end on one MI355X.
+
+Metric: edge-pixels/s per Sim(3) GN step + matched px/s, plain vs batched-BF16.
+
+Workload (default): the batched multi-agent graph in BF16 -- 4 agents x 50 keyframes (agents 0/2 at
+512x384, 1/3 at 512x288), 800 edges (196 sequential, 604 inter-agent), per-edge valid bands U(0.3, 1),
+independent per-agent Sim(3) gauges; synthetic seeded scenes. One step = one pass of the whole path on
+inputs resident in HBM:
+  1. bidirectional projective matching of every edge (one batched launch set),
+  2. gauge synchronisation of the agents' map components (host component tracker, device Umeyama),
+  3. GN_ITERS batched Gauss-Newton iterations (each one captured hipGraph: pose prep, persistent fused
+     residual/Hessian reduction, assembly, Cholesky ladder, Sim(3) update).
+`value` = valid edge-pixels linearised per second by the GN iterations (batched, BF16 pointmaps, FP32
+accumulation, FP64 solve); `matched_px_per_s` = query pixels through the bidirectional match per
+second. The plain form (FP32, one residual launch per edge, no graph) is timed on the same graph.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4|3|2] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "edge-pixels/s per Sim(3) GN step + matched px/s, plain vs batched-BF16"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+VALU_FP32_PEAK_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz, non-packed FP32 FMA
+MATCH_FLOP_PER_STEP = 120        # LM trial step: 5 dot products, 2x2 solve, bilinear sample, cost
+MATCH_FLOP_PER_QUERY = 70        # ray of the query, start pixel, validity tests
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------------------------------------------
+# workload on the device
+# --------------------------------------------------------------------------------------------------
+class Workload:
+    pass
+
+
+def build_workload(g, dtype, dev, with_cross=True):
+    import torch
+
+    from paper_2605_30488_amd import api as ds3
+    W = Workload()
+    W.g = g
+    W.dtype = dtype
+    W.arena = ds3.build_arena(g.xyz, g.conf, dtype, dev)
+    W.edges = [(int(i), int(j)) for i, j in g.edges]
+    W.idx_offsets, off = [], 0
+    for i, j in W.edges:
+        W.idx_offsets.append(off)
+        H, Wd = g.shape(j)
+        off += H * Wd
+    W.idx_total = off
+    W.idx = torch.full((off,), -1, dtype=torch.int32, device=dev)
+    W.valid = torch.zeros(off, dtype=torch.uint8, device=dev)
+    W.poses_init = torch.as_tensor(g.poses_init).to(dev)
+    W.poses = W.poses_init.clone()
+    W.agent = [int(a) for a in g.agent]
+    W.query_px = 0
+    if with_cross:
+        W.cross_off, coff = [], 0
+        for i, j in W.edges:
+            nj = g.shape(j)[0] * g.shape(j)[1]
+            ni = g.shape(i)[0] * g.shape(i)[1]
+            W.cross_off += [coff, coff + nj]
+            coff += nj + ni
+        W.query_px = coff
+        W.cross = torch.empty((coff, 4), dtype=torch.float32 if dtype == "f32" else torch.int16, device=dev)
+        for e, (i, j) in enumerate(W.edges):
+            Xji, Xij = g.cross_view(e)
+            a, b = W.cross_off[2 * e], W.cross_off[2 * e + 1]
+            nj, ni = Xji.shape[0] * Xji.shape[1], Xij.shape[0] * Xij.shape[1]
+            ds3.pack_xyzc(torch.from_numpy(Xji.reshape(-1, 3)).to(dev),
+                          torch.from_numpy(g.conf[j].reshape(-1)).to(dev), dtype, out=W.cross[a:a + nj])
+            ds3.pack_xyzc(torch.from_numpy(Xij.reshape(-1, 3)).to(dev),
+                          torch.from_numpy(g.conf[i].reshape(-1)).to(dev), dtype, out=W.cross[b:b + ni])
+        W.mws = ds3.match_batch_workspace(W.arena, W.edges, W.idx_offsets)
+    W.graph = ds3.Graph(W.arena, W.edges, W.idx, W.idx_offsets, anchors=(0,))
+    return W
+
+
+def match_all(W, lm_steps=None):
+    from paper_2605_30488_amd import api as ds3
+    return ds3.match_batch(W.arena, W.cross, W.cross_off, W.edges, W.idx_offsets, W.idx_total,
+                           idx_out=W.idx, valid_out=W.valid, ws=W.mws, lm_steps=lm_steps)
+
+
+# --------------------------------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the same workload
+# --------------------------------------------------------------------------------------------------
+def cpu_baseline(g, n_edges_gn=None, n_edges_match=32):
+    """About 10-30 s of oracle work: one FP64 GN step over (a sample of) the edges and the bidirectional
+    matching of a sample of edges, scaled to per-second rates."""
+    import oracle as O
+    E = len(g.edges)
+    n_edges_gn = E if n_edges_gn is None else n_edges_gn
+    pick = list(range(0, E, max(1, E // n_edges_gn)))[:n_edges_gn]
+    kfs = sorted({int(v) for e in pick for v in g.edges[e]})
+    remap = {k: n for n, k in enumerate(kfs)}
+    idx = [g.gt_idx(e) for e in pick]
+    og = O.Graph([g.xyz[k] for k in kfs], [g.conf[k] for k in kfs],
+                 [(remap[int(g.edges[e][0])], remap[int(g.edges[e][1])]) for e in pick], idx, anchors=(0,))
+    poses = g.poses_init[kfs]
+    valid = int(sum((i >= 0).sum() for i in idx))
+    t0 = time.perf_counter()
+    O.gn_step(og, poses)
+    t_gn = time.perf_counter() - t0
+    q_px = 0
+    t0 = time.perf_counter()
+    for e in pick[::max(1, len(pick) // n_edges_match)][:n_edges_match]:
+        i, j = (int(v) for v in g.edges[e])
+        Xji, Xij = g.cross_view(e)
+        O.match_bidir(g.xyz[i], Xji, g.xyz[j], Xij, g.conf[i], g.conf[j])
+        q_px += Xji.shape[0] * Xji.shape[1] + Xij.shape[0] * Xij.shape[1]
+    t_m = time.perf_counter() - t0
+    return {"value": valid / t_gn, "unit": "edge-px/s", "cores": O.num_threads(), "kind": "oracle",
+            "matched_px_per_s": q_px / t_m,
+            "sample": f"one FP64 GN step (assembly + dense Cholesky ladder + update) over {len(pick)} of {E} "
+                      f"edges ({valid} valid edge-pixels, {len(kfs)} keyframes) in {t_gn:.2f} s; "
+                      f"bidirectional matching of {n_edges_match} edges ({q_px} query px) in {t_m:.2f} s"}
+
+
+# --------------------------------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4])
+    ap.add_argument("--gn-iters", type=int, default=20)
+    ap.add_argument("--plain-iters", type=int, default=3)
+    ap.add_argument("--plain-match-edges", type=int, default=40)
+    ap.add_argument("--quick", action="store_true", help="skip the plain form and the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2605_30488_amd import api as ds3
+    ds3.version()  # fails loudly without the HIP library
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    dtype = "bf16" if args.config == 4 else "f32"
+    t0 = time.time()
+    g = synth.make_config(3 if args.config in (3, 4) else 2)
+    log(f"generated config {args.config}: {g.n_kf} keyframes, {len(g.edges)} edges in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    W = build_workload(g, dtype, dev)
+    torch.cuda.synchronize()
+    log(f"workload on device in {time.time() - t0:.1f}s: arena {tuple(W.arena.data.shape)}, "
+        f"cross {tuple(W.cross.shape)}")
+
+    lm = torch.zeros(1, dtype=torch.int64, device=dev)
+    match_all(W, lm)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plan = ds3.GNPlan(W.graph, W.poses, autotune=not args.no_autotune)
+    torch.cuda.synchronize()
+    info = plan.info()
+    log(f"plan: {info} (created in {time.time() - t0:.1f}s)")
+
+    def step(ev):
+        W.poses.copy_(W.poses_init)
+        ev[0].record()
+        _, _, nu, admit = match_all(W, lm)
+        ev[1].record()
+        ds3.gauge_sync(W.poses, W.agent, W.arena, W.edges, W.idx_offsets, W.idx, W.valid, admit)
+        ev[2].record()
+        cost, st = plan.run(args.gn_iters)
+        ev[3].record()
+        return cost, st, admit
+
+    for k in range(args.warmup):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        step(ev)
+        torch.cuda.synchronize()
+        log(f"warmup step {k} done")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for k in range(args.steps):
+        cost, st, admit = step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    t_match = np.mean([evs[k][0].elapsed_time(evs[k][1]) for k in range(args.steps)])
+    t_gauge = np.mean([evs[k][1].elapsed_time(evs[k][2]) for k in range(args.steps)])
+    t_gn = np.mean([evs[k][2].elapsed_time(evs[k][3]) for k in range(args.steps)])
+    ms_step = wall * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step (match {t_match:.2f}, gauge {t_gauge:.2f}, "
+        f"GN x{args.gn_iters} {t_gn:.2f})")
+    costs = cost.cpu().numpy()
+    statuses = st.cpu().numpy()
+    n_admit = int(admit.sum().item())
+    lm_steps = int(lm.item())
+
+    px_valid, px_scanned = info["px_valid"], info["px_scanned"]
+    edge_px_s = px_valid * args.gn_iters / (t_gn * 1e-3)
+    matched_px_s = W.query_px / (t_match * 1e-3)
+
+    # dominant kernels: the fused residual/Hessian reduction (per launch) and the matching pass
+    k4_ms = plan.time_reduce(20)
+    k4_bytes = info["bytes_streaming"]
+    k4_gbs = k4_bytes / (k4_ms * 1e-3) / 1e9
+    roof_k4 = {"kernel": "k_edge_reduce_batched", "bound": "hbm", "achieved": round(k4_gbs, 1),
+               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(k4_gbs / HBM_PEAK_GBS, 4),
+               "traffic": None, "launch_ms": round(k4_ms, 4), "bytes_per_launch": k4_bytes}
+    match_flop = MATCH_FLOP_PER_STEP * lm_steps + MATCH_FLOP_PER_QUERY * W.query_px
+    match_tflops = match_flop / (t_match * 1e-3) / 1e12
+    roof_match = {"kernel": "k_match_batched (whole matching pass)", "bound": "alu",
+                  "achieved": round(match_tflops, 3), "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                  "frac": round(match_tflops / VALU_FP32_PEAK_TFLOPS, 4), "traffic": None,
+                  "lm_steps_per_query": round(lm_steps / W.query_px, 3)}
+    k4_share = k4_ms * args.gn_iters
+    roofline, secondary = (roof_k4, roof_match) if k4_share >= t_match else (roof_match, roof_k4)
+
+    out = {"metric": METRIC, "value": round(edge_px_s, 1), "unit": "edge-px/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic",
+           "config": {"workload": ("batched multi-agent graph, 4 agents x 50 keyframes (512x384 / 512x288), "
+                                   f"800 edges, {dtype} xyzc, {args.gn_iters} GN iterations per step")
+                      if args.config in (3, 4) else
+                      f"single agent, 20 keyframes 512x384, 40 edges, {args.gn_iters} GN iterations",
+                      "n_kf": g.n_kf, "n_edges": len(g.edges), "gn_iters": args.gn_iters,
+                      "edge_px_scanned": px_scanned, "edge_px_valid": px_valid, "query_px": W.query_px,
+                      "admitted_edges": n_admit},
+           "matched_px_per_s": round(matched_px_s, 1),
+           "breakdown_ms": {"match": round(t_match, 3), "gauge": round(t_gauge, 3),
+                            "gn_iters_total": round(t_gn, 3), "gn_iter": round(t_gn / args.gn_iters, 4),
+                            "k_edge_reduce_launch": round(k4_ms, 4)},
+           "roofline": roofline, "roofline_secondary": secondary,
+           "gn_cost_first_last": [float(costs[0]), float(costs[-1])],
+           "ladder_status_max": int(statuses.max()), "plan": info}
+
+    if not args.quick:
+        # plain form: FP32, one residual launch per edge, no graph, on the same matches
+        W32 = W if dtype == "f32" else build_workload(g, "f32", dev, with_cross=False)
+        W32.idx = W.idx
+        graph32 = ds3.Graph(W32.arena, W.edges, W.idx, W.idx_offsets, anchors=(0,))
+        P = W.poses_init.clone()
+        ds3.sim3_gn_step(graph32, P)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.plain_iters):
+            ds3.sim3_gn_step(graph32, P)
+        b.record()
+        torch.cuda.synchronize()
+        t_plain = a.elapsed_time(b) / args.plain_iters
+        # plain matching: one bidirectional call per edge on a sample of edges
+        ne = min(args.plain_match_edges, len(W.edges))
+        pxb = 0
+        a.record()
+        for e in range(ne):
+            i, j = W.edges[e]
+            (Hi, Wi, oi), (Hj, Wj, oj) = W.arena.images[i], W.arena.images[j]
+            ca, cb = W.cross_off[2 * e], W.cross_off[2 * e + 1]
+            ds3.match_bidir(W.arena.data[oi:oi + Hi * Wi], W.cross[ca:ca + Hj * Wj],
+                            W.arena.data[oj:oj + Hj * Wj], W.cross[cb:cb + Hi * Wi], (Hi, Wi), (Hj, Wj), dtype)
+            pxb += Hi * Wi + Hj * Wj
+        b.record()
+        torch.cuda.synchronize()
+        t_pm = a.elapsed_time(b)
+        out["plain"] = {"dtype": "f32", "edge_px_per_s": round(px_valid / (t_plain * 1e-3), 1),
+                        "gn_step_ms": round(t_plain, 3),
+                        "matched_px_per_s": round(pxb / (t_pm * 1e-3), 1), "match_sample_edges": ne}
+        out["speedup_vs_plain"] = round(edge_px_s / (px_valid / (t_plain * 1e-3)), 2)
+        log(f"plain: GN step {t_plain:.2f} ms, matching {t_pm:.1f} ms for {ne} edges")
+        if not args.no_cpu_baseline:
+            t0 = time.time()
+            out["cpu_baseline"] = cpu_baseline(g)
+            log(f"cpu baseline in {time.time() - t0:.1f}s")
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * n * 4
+
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -128,14 +128,15 @@ int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const 
  *   cross_arena (device): per edge e two cross-view pointmaps, X^j_i (H_j*W_j px) at cross_off[2e] and
  *   X^i_j (H_i*W_i px) at cross_off[2e+1] (host int64 pixel offsets).
  *   edges (host): (i, j, idx_offset) per edge; outputs written at idx_offset of idx_arena (int32) and
- *   valid_arena (uint8); nu (device float32, 2 per edge), admit (device int32, 1 per edge).
+ *   valid_arena (uint8); nu (device float32, 2 per edge), admit (device int32, 1 per edge);
+ *   lm_steps (device uint64, may be NULL) receives the total number of LM trial steps taken.
  * Workspace from ds3_match_batch_workspace_bytes. */
 size_t ds3_match_batch_workspace_bytes(int32_t n_kf, const ds3_image* kf, int32_t n_edges,
                                        const ds3_edge* edges);
 int ds3_match_batch(const void* kf_arena, const ds3_image* kf, int32_t n_kf, const void* cross_arena,
                     const int64_t* cross_off, const ds3_edge* edges, int32_t n_edges, ds3_dtype dtype,
                     const ds3_match_params* params, int32_t* idx_arena, uint8_t* valid_arena, float* nu,
-                    int32_t* admit, void* workspace, size_t ws_bytes, void* stream);
+                    int32_t* admit, uint64_t* lm_steps, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------------------
  * Gauge synchronisation (Sec. III-C)
@@ -218,7 +219,8 @@ int ds3_chol_ladder_solve(const double* H, const double* g, int32_t n, double la
                           size_t ws_bytes, void* stream);
 
 /* Batched form: one plan per graph topology. Creation uploads the topology, counts valid matches per
- * tile, orders (edge, tile) items longest first, picks tile shapes (opts->autotune: timed candidates,
+ * tile, orders (edge, tile) items longest first (an ordering hint only: every tile is processed, so the
+ * plan stays valid when the idx arena is rewritten, e.g. by a new matching pass), picks tile shapes (opts->autotune: timed candidates,
  * cached per device, dtype and shape mix; synchronises) and captures one GN iteration in a hipGraph.
  * The plan owns its device buffers and graph; the keyframe arena, idx arena and poses stay the
  * caller's and must outlive the plan. ds3_gn_plan_run replays the iteration `iters` times on `stream`

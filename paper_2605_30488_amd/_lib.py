@@ -55,7 +55,7 @@ _SIGS = {
                                   vp, vp, vp, sz, vp]),
     "ds3_match_batch_workspace_bytes": (sz, [i32, P_img, i32, P_edge]),
     "ds3_match_batch": (C.c_int, [vp, P_img, i32, vp, P_i64, P_edge, i32, C.c_int,
-                                  C.POINTER(MatchParams), vp, vp, vp, vp, vp, sz, vp]),
+                                  C.POINTER(MatchParams), vp, vp, vp, vp, vp, vp, sz, vp]),
     "ds3_gauge_workspace_bytes": (sz, [i32]),
     "ds3_gauge_align": (C.c_int, [vp, Image, vp, Image, C.c_int, vp, vp, vp, i32, i32, i32, i32, vp, vp,
                                   vp, sz, vp]),

@@ -159,10 +159,11 @@ def match_bidir(X_ii, X_ji, X_jj, X_ij, hw_i, hw_j, dtype="f32", params=None):
 
 
 def match_batch(arena: Arena, cross: torch.Tensor, cross_off, edges, idx_offsets, idx_total, params=None,
-                idx_out=None, valid_out=None, ws=None):
+                idx_out=None, valid_out=None, ws=None, lm_steps=None):
     """Batched bidirectional matching of every edge (ds3_match_batch). cross: xyzc arena of the
     cross-view pointmaps; cross_off[2e], cross_off[2e+1] their pixel offsets (X^j_i, X^i_j).
-    Returns (idx arena int32, valid arena uint8, nu (E, 2) float32, admit (E,) int32)."""
+    Returns (idx arena int32, valid arena uint8, nu (E, 2) float32, admit (E,) int32); lm_steps, a
+    device int64 tensor of one element, receives the number of LM trial steps when given."""
     _need_cuda(arena.data, cross)
     P = params or default_match_params()
     dev = arena.data.device
@@ -178,8 +179,8 @@ def match_batch(arena: Arena, cross: torch.Tensor, cross_off, edges, idx_offsets
     if ws is None or ws.numel() < nb:
         ws = _ws(nb, dev)
     call("ds3_match_batch", _ptr(arena.data), kf, len(arena.images), _ptr(cross), off, et, ne,
-         _dt(arena.dtype), C.byref(P), _ptr(idx), _ptr(valid), _ptr(nu), _ptr(admit), _ptr(ws), ws.numel(),
-         _stream())
+         _dt(arena.dtype), C.byref(P), _ptr(idx), _ptr(valid), _ptr(nu), _ptr(admit), _ptr(lm_steps), _ptr(ws),
+         ws.numel(), _stream())
     return idx, valid, nu, admit
 
 

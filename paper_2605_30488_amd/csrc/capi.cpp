@@ -515,16 +515,13 @@ static int plan_build_items(Plan& P, int ppt, hipStream_t s) {
   P.px_valid = 0;
   for (int e = 0; e < T2.n_edges; ++e)
     for (int t = 0; t < T2.edges[e].n_tiles; ++t) {
-      const int v = counts[T2.edges[e].tile0 + t];
-      P.px_valid += v;
-      if (v > 0) items.push_back(WorkItem{e, t});
+      P.px_valid += counts[T2.edges[e].tile0 + t];
+      items.push_back(WorkItem{e, t});  // every tile: the plan stays valid when the matches change
     }
   std::stable_sort(items.begin(), items.end(), [&](const WorkItem& a, const WorkItem& b) {
     return counts[T2.edges[a.edge].tile0 + a.tile] > counts[T2.edges[b.edge].tile0 + b.tile];
   });
   DS3_TRY(upload(P.items, items, s));
-  // tiles without a valid match are skipped; their partial slots must read as zero
-  DS3_TRY(launch_fill(reinterpret_cast<double*>(P.B.partials), size_t(total) * kPartial / 2, 0.0, s));
   P.n_items = int(items.size());
   P.ppt = ppt;
   P.T.edges = T2.edges;

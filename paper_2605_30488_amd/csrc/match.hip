@@ -197,26 +197,33 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_match_batched(const float4* __restrict__ rays,
                                                        const void* __restrict__ cross,
                                                        const MatchDir* __restrict__ dirs, ItemMap map,
-                                                       MatchConst P, int32_t* __restrict__ idx_tmp) {
+                                                       MatchConst P, int32_t* __restrict__ idx_tmp,
+                                                       unsigned long long* __restrict__ lm_steps) {
   int entry, tile;
-  if (!locate_item(map, blockIdx.x, entry, tile)) return;
+  if (!locate_item(map, blockIdx.x, entry, tile)) return;  // uniform per block
   const MatchDir D = dirs[entry];
   const int64_t n = int64_t(tile) * 256 + threadIdx.x;
-  if (n >= int64_t(D.Hq) * D.Wq) return;
-  const float4 x = Px<DT>::load(cross, D.qry_off + n);
-  float pu, pv;
-  int its;
-  idx_tmp[D.out_off + n] = match_query(rays + D.ref_off, D.Hr, D.Wr, x, int(n % D.Wq), int(n / D.Wq),
-                                       D.Hq, D.Wq, P, &pu, &pv, &its);
+  int its = 0;
+  if (n < int64_t(D.Hq) * D.Wq) {
+    const float4 x = Px<DT>::load(cross, D.qry_off + n);
+    float pu, pv;
+    idx_tmp[D.out_off + n] = match_query(rays + D.ref_off, D.Hr, D.Wr, x, int(n % D.Wq), int(n / D.Wq),
+                                         D.Hq, D.Wq, P, &pu, &pv, &its);
+  }
+  if (lm_steps) {
+    its = wave_sum(its);
+    if ((threadIdx.x & 63) == 0 && its) atomicAdd(lm_steps, (unsigned long long)its);
+  }
 }
 
 int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, const MatchDir* dirs,
-                         ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp, hipStream_t s) {
+                         ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp,
+                         unsigned long long* lm_steps, hipStream_t s) {
   if (grid <= 0) return DS3_OK;
   if (dt == DS3_F32)
-    hipLaunchKernelGGL(k_match_batched<DS3_F32>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp);
+    hipLaunchKernelGGL(k_match_batched<DS3_F32>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp, lm_steps);
   else
-    hipLaunchKernelGGL(k_match_batched<DS3_BF16>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp);
+    hipLaunchKernelGGL(k_match_batched<DS3_BF16>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp, lm_steps);
   return check_hip(hipGetLastError(), "k_match_batched");
 }
 

@@ -47,7 +47,8 @@ int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, hipS
 int launch_match_one(const float4* rays, int H, int W, const void* qry, int Hq, int Wq, ds3_dtype dt,
                      const MatchConst& P, int32_t* idx_out, float* p_out, int32_t* it_out, hipStream_t s);
 int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, const MatchDir* dirs,
-                         ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp, hipStream_t s);
+                         ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp,
+                         unsigned long long* lm_steps, hipStream_t s);
 int launch_mutual(const MutualDir* md, ItemMap map, int grid, ds3_dtype dt, const MatchConst& P,
                   const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* counts,
                   hipStream_t s);

@@ -26,6 +26,27 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+try:  # ray casting runs on torch when present (multi-threaded CPU or a GPU); numpy otherwise
+    import torch
+except ImportError:  # pragma: no cover
+    torch = None
+
+_DEVICE = None
+
+
+def set_device(dev):
+    """Device for the bulk ray casting ('cpu', 'cuda', ...); None picks cuda when available."""
+    global _DEVICE
+    _DEVICE = dev
+
+
+def _device():
+    if torch is None:
+        return None
+    if _DEVICE is not None:
+        return torch.device(_DEVICE)
+    return torch.device("cuda") if torch.cuda.is_available() else torch.device("cpu")
+
 __all__ = ["SynthGraph", "make_config", "make_pair", "rot_to_quat", "quat_to_rot"]
 
 
@@ -115,6 +136,46 @@ class Scene:
 
     def cast(self, o: np.ndarray, d: np.ndarray) -> np.ndarray:
         """Distance along unit directions d (n, 3) from origin o (3,) to the nearest surface."""
+        dev = _device()
+        if dev is not None:
+            return self._cast_torch(o, d, dev)
+        return self._cast_np(o, d)
+
+    def _cast_torch(self, o, d, dev) -> np.ndarray:
+        D = torch.as_tensor(d, dtype=torch.float64, device=dev)
+        O = torch.as_tensor(np.asarray(o, np.float64), device=dev)
+        best = torch.full((D.shape[0],), float("inf"), dtype=torch.float64, device=dev)
+        inf = torch.tensor(float("inf"), dtype=torch.float64, device=dev)
+        for nrm, off in self.planes:
+            n = torch.as_tensor(nrm, dtype=torch.float64, device=dev)
+            den = D @ n
+            t = (off - O @ n) / den
+            t = torch.where(torch.isfinite(t) & (t > 1e-6), t, inf)
+            best = torch.minimum(best, t)
+        for bc, half, yaw in self.boxes:
+            Ry = torch.tensor([[math.cos(yaw), 0, math.sin(yaw)], [0, 1, 0], [-math.sin(yaw), 0, math.cos(yaw)]],
+                              dtype=torch.float64, device=dev)
+            ol = Ry.T @ (O - torch.as_tensor(bc, dtype=torch.float64, device=dev))
+            dl = D @ Ry
+            h = torch.as_tensor(half, dtype=torch.float64, device=dev)
+            inv = 1.0 / dl
+            t1 = (-h - ol) * inv
+            t2 = (h - ol) * inv
+            tmin = torch.nan_to_num(torch.minimum(t1, t2), nan=-float("inf")).max(dim=1).values
+            tmax = torch.nan_to_num(torch.maximum(t1, t2), nan=float("inf")).min(dim=1).values
+            hit = (tmax >= tmin) & (tmax > 1e-6)
+            t = torch.where(tmin > 1e-6, tmin, tmax)
+            best = torch.minimum(best, torch.where(hit, t, inf))
+        sc, sr = self.sphere
+        oc = O - torch.as_tensor(sc, dtype=torch.float64, device=dev)
+        b = D @ oc
+        cc = oc @ oc - sr * sr
+        disc = b * b - cc
+        t = -b + torch.sqrt(torch.clamp(disc, min=0.0))
+        best = torch.minimum(best, torch.where(disc < 0, inf, t))
+        return best.cpu().numpy()
+
+    def _cast_np(self, o: np.ndarray, d: np.ndarray) -> np.ndarray:
         n = d.shape[0]
         best = np.full(n, np.inf)
         for nrm, off in self.planes:
@@ -348,17 +409,33 @@ def _build(name, scene, cams, agent, path, rng, scales):
 
 
 def _overlap_matrix(cams, poses, world, dist, stride=16):
+    """O[i, j]: fraction of a subsampled grid of j's pixels that i sees (projection inside i's image and
+    i's own surface at that pixel within 5%)."""
     n = len(cams)
     subs = []
     for k in range(n):
         H, W = cams[k].H, cams[k].W
         v, u = np.mgrid[0:H:stride, 0:W:stride]
         subs.append(world[k][(v * W + u).reshape(-1)])
+    counts = np.array([s.shape[0] for s in subs])
+    allp = np.concatenate(subs)
+    owner = np.repeat(np.arange(n), counts)
     O = np.zeros((n, n))
     for i in range(n):
-        for j in range(n):
-            if i != j:
-                O[i, j] = _overlap(cams[i], poses[i], subs[j], dist[i])
+        cam = cams[i]
+        R, t, _ = pose_parts(poses[i])
+        X = (allp - t) @ R
+        z = X[:, 2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u = cam.f * X[:, 0] / z + cam.cx
+            v = cam.f * X[:, 1] / z + cam.cy
+        ok = (z > 0.05) & (u > -0.5) & (u < cam.W - 0.5) & (v > -0.5) & (v < cam.H - 0.5)
+        mu = np.clip(np.floor(np.nan_to_num(u) + 0.5), 0, cam.W - 1).astype(np.int64)
+        mv = np.clip(np.floor(np.nan_to_num(v) + 0.5), 0, cam.H - 1).astype(np.int64)
+        m = mv * cam.W + mu
+        ok &= np.abs(dist[i][m] - np.linalg.norm(X, axis=1)) <= 0.05 * dist[i][m]
+        O[i] = np.bincount(owner, weights=ok, minlength=n) / counts
+        O[i, i] = 0.0
     return O
 
 
@@ -413,7 +490,7 @@ def make_config(k: int, seed: int | None = None, n_agents=None, kf_per_agent=Non
         # retrieval stand-in: each keyframe keeps its top-k overlapping keyframes of other agents
         cand = {}
         for q in range(n):
-            others = [o for o in np.argsort(-O[q]) if agent[o] != agent[q]][:4]
+            others = [o for o in np.argsort(-O[q]) if agent[o] != agent[q]][:8]
             for o in others:
                 key = (min(q, o), max(q, o))
                 cand[key] = max(cand.get(key, 0.0), min(O[q, o], O[o, q]))

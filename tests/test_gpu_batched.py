@@ -1,0 +1,239 @@
+"""GPU parity of the batched form (persistent residual launch under a hipGraph), of batched matching
+and gauge synchronisation, and of the cost adjoint, against the FP64 oracle and the plain form."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.helpers import exact_graph, perturb
+
+pytestmark = pytest.mark.gpu
+
+ds3 = pytest.importorskip("paper_2605_30488_amd.api")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(dev)
+
+
+@pytest.fixture(scope="module")
+def single(dev):
+    """Config 2 (20 keyframes 512x384, 40 edges) with ground-truth matches."""
+    g = synth.make_config(2)
+    idx = g.gt_idx_all()
+    return g, idx
+
+
+def _graph(g, idx, dtype, dev):
+    a = ds3.build_arena(g.xyz, g.conf, dtype, dev)
+    return ds3.Graph(a, g.edges, _t(np.concatenate(idx), dev, torch.int32), anchors=(0,))
+
+
+def _bf16_inputs(g):
+    """The values a BF16 arena holds, as float64 for the oracle."""
+    xyz = [O.bf16_to_f32(O.bf16_round(x)).reshape(x.shape).astype(np.float64) for x in g.xyz]
+    conf = [O.bf16_to_f32(O.bf16_round(c)).reshape(c.shape).astype(np.float64) for c in g.conf]
+    return xyz, conf
+
+
+@pytest.mark.parametrize("ppt", [4, 16, 32])
+def test_plan_equals_plain_form(dev, single, ppt):
+    """Batched plan (graph replay) and plain per-edge steps give the same poses (same FP32 math, tile
+    sums in a different order) for every tile shape."""
+    g, idx = single
+    G = _graph(g, idx, "f32", dev)
+    P1 = _t(g.poses_init, dev)
+    P2 = _t(g.poses_init, dev)
+    plan = ds3.GNPlan(G, P2, px_per_thread=ppt)
+    costs, st = plan.run(3)
+    c_plain = []
+    for _ in range(3):
+        c, s = ds3.sim3_gn_step(G, P1)
+        c_plain.append(c.item())
+    err = O.pose_error(P2.cpu().numpy(), P1.cpu().numpy()).max()
+    assert err < 2e-6, err
+    assert np.allclose(costs.cpu().numpy(), c_plain, rtol=1e-5)
+    assert np.all(st.cpu().numpy() == 0)
+    plan.close()
+
+
+def test_plan_f32_matches_oracle(dev, single):
+    """Three iterations of config 2 from its noisy start: poses within 1e-5 of the FP64 oracle."""
+    g, idx = single
+    G = _graph(g, idx, "f32", dev)
+    P = _t(g.poses_init, dev)
+    plan = ds3.GNPlan(G, P)
+    costs, _ = plan.run(3)
+    og = O.Graph(g.xyz, g.conf, g.edges, idx, anchors=(0,))
+    ref = g.poses_init.copy()
+    rc = []
+    for _ in range(3):
+        ref, c, _, _ = O.gn_step(og, ref)
+        rc.append(c)
+    err = O.pose_error(P.cpu().numpy(), ref)
+    print(f"f32 plan vs oracle: max pose error {err.max():.2e}; costs {costs.cpu().numpy()} vs {rc}")
+    assert err.max() <= 1e-5
+    assert np.allclose(costs.cpu().numpy(), rc, rtol=1e-4)
+    plan.close()
+
+
+def test_plan_bf16_matches_oracle_on_rounded_inputs(dev, single):
+    """BF16 storage, FP32 accumulation: against the oracle on the same BF16-rounded inputs (the
+    arithmetic-only error) within 1e-5, and against the FP32 inputs (total error) within 1e-4."""
+    g, idx = single
+    G = _graph(g, idx, "bf16", dev)
+    P = _t(g.poses_init, dev)
+    plan = ds3.GNPlan(G, P)
+    plan.run(3)
+    xb, cb = _bf16_inputs(g)
+    ref_b = g.poses_init.copy()
+    ref_f = g.poses_init.copy()
+    ob = O.Graph(xb, cb, g.edges, idx, anchors=(0,))
+    of = O.Graph(g.xyz, g.conf, g.edges, idx, anchors=(0,))
+    for _ in range(3):
+        ref_b, *_ = O.gn_step(ob, ref_b)
+        ref_f, *_ = O.gn_step(of, ref_f)
+    got = P.cpu().numpy()
+    e_arith = O.pose_error(got, ref_b).max()
+    e_total = O.pose_error(got, ref_f).max()
+    print(f"bf16 plan: arithmetic error {e_arith:.2e}, total error {e_total:.2e}")
+    assert e_arith <= 1e-5
+    assert e_total <= 1e-4
+    plan.close()
+
+
+def test_graph_replays_match_direct_launches(dev, single):
+    """Each replay of the captured iteration equals the same launches issued directly (bit for bit),
+    with eager work and synchronisation between replays."""
+    g, idx = single
+    G = _graph(g, idx, "f32", dev)
+    Pa = _t(g.poses_init, dev)
+    Pb = _t(g.poses_init, dev)
+    pa = ds3.GNPlan(G, Pa, use_graph=True)
+    pb = ds3.GNPlan(G, Pb, use_graph=False)
+    for _ in range(4):
+        ca, _ = pa.run(1)
+        torch.cuda.synchronize()
+        _ = torch.zeros(1000, device=dev).sum()  # unrelated eager work between replays
+        cb, _ = pb.run(1)
+        torch.cuda.synchronize()
+        assert torch.equal(Pa, Pb)
+        assert torch.equal(ca, cb)
+    pa.close()
+    pb.close()
+
+
+def test_match_batch_equals_single_and_oracle(dev, single):
+    """Batched matching of all 40 edges equals per-edge bidirectional calls bit for bit, and the oracle
+    on >= 99.9% of valid pixels of sampled edges (full 512x384 size)."""
+    import bench
+    g, _ = single
+    W = bench.build_workload(g, "f32", dev)
+    idx, valid, nu, admit = bench.match_all(W)
+    idx, valid = idx.cpu().numpy(), valid.cpu().numpy()
+    for e in (0, 17, 33):
+        i, j = W.edges[e]
+        (Hi, Wi, oi), (Hj, Wj, oj) = W.arena.images[i], W.arena.images[j]
+        ca, cb = W.cross_off[2 * e], W.cross_off[2 * e + 1]
+        one = ds3.match_bidir(W.arena.data[oi:oi + Hi * Wi], W.cross[ca:ca + Hj * Wj],
+                              W.arena.data[oj:oj + Hj * Wj], W.cross[cb:cb + Hi * Wi], (Hi, Wi), (Hj, Wj))
+        sl = slice(W.idx_offsets[e], W.idx_offsets[e] + Hj * Wj)
+        assert np.array_equal(one[0].cpu().numpy(), idx[sl])
+        assert np.array_equal(one[1].cpu().numpy(), valid[sl])
+        assert np.array_equal(one[2].cpu().numpy(), nu[e].cpu().numpy())
+        Xji, Xij = g.cross_view(e)
+        r = O.match_bidir(g.xyz[i], Xji, g.xyz[j], Xij, g.conf[i], g.conf[j])
+        either = (r.idx_j2i >= 0) | (idx[sl] >= 0)
+        agree = (r.idx_j2i == idx[sl])[either].mean()
+        print(f"edge {e}: agreement {agree:.5f} over {either.sum()} pixels; nu {nu[e].cpu().numpy()} vs {r.nu}")
+        assert agree >= 0.999
+        assert np.allclose(nu[e].cpu().numpy(), r.nu, atol=2e-3)
+        assert bool(admit[e].item()) == r.admit
+
+
+def test_gauge_sync_matches_oracle(dev):
+    """Three agents in foreign gauges joined by inter-agent edges (exact matches)."""
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=6, H=24, W=32, seed=41, frac_valid=0.9,
+                                            edges=[(0, 1), (2, 3), (4, 5), (3, 1), (5, 2), (4, 0)])
+    xyz = [np.asarray(x, np.float32) for x in xyz]
+    conf = [np.asarray(c, np.float32) for c in conf]
+    agent = [0, 0, 1, 1, 2, 2]
+    rng = np.random.default_rng(9)
+    init = gt.copy()
+    for a in (1, 2):
+        G = O.sim3_exp(rng.normal(size=7) * np.array([2, 2, 2, 1, 1, 1, 0.3]))[0]
+        for k in (2 * a, 2 * a + 1):
+            init[k] = O.compose(G, gt[k])
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    offs = [0]
+    for e in range(len(edges) - 1):
+        offs.append(offs[-1] + 24 * 32)
+    idx_all = _t(np.concatenate(idx), dev, torch.int32)
+    valid_all = _t(np.concatenate([(i >= 0).astype(np.uint8) for i in idx]), dev)
+    admit = _t(np.ones(len(edges), np.int32), dev)
+    P = _t(init, dev)
+    links = ds3.gauge_sync(P, agent, a, edges, offs, idx_all, valid_all, admit)
+    ref, rl = O.gauge_sync(init, np.array(agent), edges, [True] * len(edges),
+                           [(i, (i >= 0).astype(np.uint8)) for i in idx], xyz)
+    assert links == len(rl) == 2
+    assert O.pose_error(P.cpu().numpy(), ref).max() < 1e-9
+    assert O.pose_error(P.cpu().numpy(), gt).max() < 1e-5
+
+
+def test_cost_and_adjoint_match_oracle(dev):
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=4, H=20, W=24, seed=51, frac_valid=0.8)
+    xyz = [np.asarray(x, np.float32) for x in xyz]
+    conf = [np.asarray(c, np.float32) for c in conf]
+    poses = perturb(gt, np.random.default_rng(10), rot=0.01, trans=0.01, scale=0.01, fixed=())
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    G = ds3.Graph(a, edges, _t(np.concatenate(idx), dev, torch.int32), anchors=(0,))
+    P = _t(poses, dev)
+    cost = ds3.gn_cost(G, P).item()
+    gx, gc, gt_ = ds3.gn_cost_adjoint(G, P, dcost=2.0)
+    og = O.Graph(xyz, conf, edges, idx, anchors=())
+    E, rx, rc, rt = O.cost_grad(og, poses)
+    assert abs(cost - E) <= 1e-5 * E
+    gx, gc, gt_ = gx.cpu().numpy(), gc.cpu().numpy(), gt_.cpu().numpy()
+    assert np.abs(gx - 2 * rx).max() <= 2e-4 * np.abs(2 * rx).max()
+    assert np.abs(gc - 2 * rc).max() <= 2e-4 * np.abs(2 * rc).max()
+    assert np.abs(gt_ - 2 * rt).max() <= 2e-4 * np.abs(2 * rt).max()
+    # dE/dtau equals the Gauss-Newton gradient g (no anchor): same numbers through another path
+    og2 = O.Graph(xyz, conf, edges, idx, anchors=())
+    _, g_ref, *_ = O.gn_assemble(og2, poses)
+    assert np.abs(gt_.reshape(-1) - 2 * g_ref).max() <= 2e-4 * np.abs(2 * g_ref).max()
+
+
+def test_autograd_function_finite_differences(dev):
+    """DenseSim3Cost: backward vs central differences of its own forward in float64-safe steps."""
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=3, H=12, W=16, seed=61, frac_valid=0.8)
+    xyz = [np.asarray(x, np.float32) for x in xyz]
+    conf = [np.asarray(c, np.float32) for c in conf]
+    poses = perturb(gt, np.random.default_rng(11), rot=0.01, trans=0.01, scale=0.01, fixed=())
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    G = ds3.Graph(a, edges, _t(np.concatenate(idx), dev, torch.int32), anchors=())
+    X = _t(np.concatenate([x.reshape(-1, 3) for x in xyz]), dev).requires_grad_(True)
+    Cf = _t(np.concatenate([c.reshape(-1) for c in conf]), dev).requires_grad_(True)
+    tau = torch.zeros((3, 7), dtype=torch.float64, device=dev, requires_grad=True)
+    P0 = _t(poses, dev)
+    E = ds3.DenseSim3Cost.apply(X, Cf, tau, G, P0)
+    E.backward()
+    og = O.Graph(xyz, conf, edges, idx, anchors=())
+    _, rx, rc, rt = O.cost_grad(og, poses)
+    assert np.abs(tau.grad.cpu().numpy() - rt).max() <= 2e-4 * np.abs(rt).max()
+    assert np.abs(X.grad.cpu().numpy() - rx).max() <= 2e-4 * np.abs(rx).max()
+    # pose tangents by central differences of the oracle cost (FP64)
+    h = 1e-6
+    for k in range(3):
+        for c in range(7):
+            d = np.zeros((3, 7))
+            d[k, c] = h
+            fd = (O.cost(og, O.sim3_update(poses, d)) - O.cost(og, O.sim3_update(poses, -d))) / (2 * h)
+            assert abs(fd - tau.grad[k, c].item()) <= 3e-4 * np.abs(rt).max()
