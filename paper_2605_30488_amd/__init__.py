@@ -10,6 +10,6 @@ __all__ = ["DS3Error", "exported_names", "load", "api"]
 
 def __getattr__(name):
     if name == "api":
-        from . import api
-        return api
+        import importlib
+        return importlib.import_module(__name__ + ".api")
     raise AttributeError(name)

@@ -2,13 +2,16 @@
 //   (H + lambda diag H + eps_r I) tau = -g,  eps_r = eps0 * mult^r,  r = 0 .. attempts-1,
 // and a zero update (status -1) when every factorisation fails.
 //
-// One persistent launch: a right-looking blocked Cholesky over 32x32 float64 tiles with one grid barrier
-// per panel. In step k every workgroup owns trailing tiles (i, j), k < j <= i; it forms L_ik = A_ik
-// L_kk^-T (and L_jk) itself from the stored inverse of the diagonal factor, so the panel solve and the
-// trailing update need no separate phase. The owner of (k+1, k+1) factors it right after its update;
-// the owner of each (i, k+1) stores L_ik and carries the forward substitution of -g. Back substitution
-// runs as a dataflow wave over per-block ready flags. Every wait is bounded: on a spin timeout the kernel
-// records an error and all workgroups leave.
+// Right-looking blocked Cholesky over 32x32 float64 tiles, one kernel per panel so that kernel
+// boundaries order the steps (no in-kernel grid barriers, no device-wide cache maintenance):
+//   init      copy + regularise the lower tiles; the owner of tile (0, 0) factors it, inverts the factor
+//             and starts the forward substitution of -g;
+//   panel k   every workgroup owns one trailing tile (i, j), k < j <= i: it forms L_ik = A_ik L_kk^-T
+//             (and L_jk) from the stored inverse, updates A_ij -= L_ik L_jk^T, stores L_ik and carries
+//             the forward substitution when j = k+1, and the owner of (k+1, k+1) factors it right away;
+//   backsub   one workgroup solves L^T x = y block by block.
+// Attempt 0 runs this way; only when it fails does a persistent fallback kernel run attempts 1.. with its
+// own bounded grid barriers (the common case never pays for the ladder).
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -34,10 +37,256 @@ struct CholArgs {
   double* b;    // np: -g after forward elimination
   double* y;    // np: L^-1 (-g) per block
   double* x;    // np: solution blocks
-  unsigned* sync;  // [0] barrier count, [1] generation, [2] error, [3] pad,
+  unsigned* sync;  // [0] barrier count, [1] generation, [2] error, [3] attempt-0 failed,
                    // [4 .. 4 + attempts*nt) failure of diagonal tile s in attempt r, then nt ready flags
 };
 
+// ---------------------------------------------------------------------------------------------------
+// Tile helpers (32x32, lower triangular factors, LDS row stride LDT)
+// ---------------------------------------------------------------------------------------------------
+__device__ inline double rsqrt_full(double d) {
+  double y = __builtin_amdgcn_rsq(d);  // hardware estimate, refined by two Newton steps
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
+__device__ inline void tile_load(double* T, const double* src, int ld) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) T[(e / NB) * LDT + e % NB] = src[int64_t(e / NB) * ld + e % NB];
+}
+
+__device__ inline void tile_store(const double* T, double* dst, int ld) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) dst[int64_t(e / NB) * ld + e % NB] = T[(e / NB) * LDT + e % NB];
+}
+
+// Lower Cholesky of the LDS tile in place (upper part zeroed); false on a non-positive or non-finite
+// pivot. 256 threads; thread t owns column t % 32 of rows t / 32 + 8q. Two barriers per column.
+__device__ bool tile_potrf(double* T) {
+  const int s = threadIdx.x % NB;
+  const int r0 = threadIdx.x / NB;
+  for (int c = 0; c < NB; ++c) {
+    __syncthreads();
+    const double d = T[c * LDT + c];
+    if (!(d > 0.0) || !isfinite(d)) return false;  // uniform: every thread read the same pivot
+    const double y = rsqrt_full(d);
+    const double ls = T[s * LDT + c] * y;
+    double lr[NB * NB / kCholThreads];
+#pragma unroll
+    for (int q = 0; q < NB * NB / kCholThreads; ++q) lr[q] = T[(r0 + 8 * q) * LDT + c] * y;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB * NB / kCholThreads; ++q) {
+      const int r = r0 + 8 * q;
+      if (s == c && r >= c) T[r * LDT + c] = lr[q];  // r == c: d / sqrt(d) = sqrt(d)
+      if (s > c && r >= s) T[r * LDT + s] = fma(-lr[q], ls, T[r * LDT + s]);
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads)
+    if (e % NB > e / NB) T[(e / NB) * LDT + e % NB] = 0.0;
+  __syncthreads();
+  return true;
+}
+
+// X = L^-1 (lower): column c solved by thread c with the column kept in registers (x_t = 0 for t < c,
+// so the dot products can run over every t < r).
+__device__ void tile_trinv(const double* Lt, double* X) {
+  if (threadIdx.x < NB) {
+    const int c = threadIdx.x;
+    double x[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < r; ++t) {
+        if (t & 1) s1 = fma(Lt[r * LDT + t], x[t], s1);
+        else s0 = fma(Lt[r * LDT + t], x[t], s0);
+      }
+      x[r] = (r >= c) ? (((r == c) ? 1.0 : 0.0) - (s0 + s1)) / Lt[r * LDT + r] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) X[r * LDT + c] = x[r];
+  }
+  __syncthreads();
+}
+
+// T <- T * Inv^T (Inv lower triangular): the panel solve L_ik = A_ik L_kk^-T.
+__device__ inline void tile_mul_invT(double* T, const double* Inv) {
+  double acc[NB * NB / kCholThreads];
+  int q = 0;
+  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) {
+    const int r = e / NB, c = e % NB;
+    double s = 0.0;
+    for (int t = 0; t <= c; ++t) s = fma(T[r * LDT + t], Inv[c * LDT + t], s);
+    acc[q] = s;
+  }
+  __syncthreads();
+  q = 0;
+  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) T[(e / NB) * LDT + e % NB] = acc[q];
+  __syncthreads();
+}
+
+// ydst = Inv * bsrc (32 threads)
+__device__ inline void tile_gemv_store(const double* Inv, const double* bsrc, double* ydst) {
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    const int r = threadIdx.x;
+    double s = 0.0;
+    for (int t = 0; t <= r; ++t) s = fma(Inv[r * LDT + t], bsrc[t], s);
+    ydst[r] = s;
+  }
+  __syncthreads();
+}
+
+// Copy + regularise one lower tile of H into T (LDS); identity on padding.
+__device__ inline void tile_from_H(const CholArgs& a, int i, int j, double eps, double* T) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int rr = i * NB + e / NB, cc = j * NB + e % NB;
+    double v;
+    if (rr < a.n && cc < a.n) {
+      v = a.H[int64_t(rr) * a.n + cc];
+      if (rr == cc) v += a.lambda * v + eps;
+    } else {
+      v = (rr == cc) ? 1.0 : 0.0;
+    }
+    T[(e / NB) * LDT + e % NB] = v;
+  }
+}
+
+// Factor a diagonal tile in S1: L -> L buffer, inverse -> Inv buffer, y_i = Inv (b_i). False on failure.
+__device__ bool factor_diag(const CholArgs& a, int i, double* S1, double* S2) {
+  __syncthreads();
+  if (!tile_potrf(S1)) return false;
+  tile_store(S1, a.L + int64_t(i) * NB * a.np + i * NB, a.np);
+  tile_trinv(S1, S2);
+  tile_store(S2, a.Inv + int64_t(i) * NB * NB, NB);
+  tile_gemv_store(S2, a.b + i * NB, a.y + i * NB);
+  return true;
+}
+
+__device__ inline void tile_index(int tt, int& i, int& j) {
+  i = 0;
+  while ((i + 1) * (i + 2) / 2 <= tt) ++i;
+  j = tt - i * (i + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Attempt 0: init, panels, back substitution
+// ---------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kCholThreads) void k_chol_init(CholArgs a) {
+  __shared__ double S1[NB * LDT];
+  __shared__ double S2[NB * LDT];
+  int i, j;
+  tile_index(blockIdx.x, i, j);
+  tile_from_H(a, i, j, a.eps0, S1);
+  if (j == 0 && threadIdx.x < NB) {
+    const int rr = i * NB + threadIdx.x;
+    a.b[rr] = (rr < a.n) ? -a.g[rr] : 0.0;
+  }
+  __syncthreads();
+  if (i == 0) {
+    const bool ok = factor_diag(a, 0, S1, S2);
+    if (threadIdx.x == 0) {
+      a.sync[3] = ok ? 0u : 1u;
+      *a.status = -2;  // replaced by the back substitution or the fallback
+    }
+  } else {
+    tile_store(S1, a.Wm + int64_t(i) * NB * a.np + j * NB, a.np);
+  }
+}
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_panel(CholArgs a, int k) {
+  if (a.sync[3] != 0u) return;  // attempt 0 already failed (uniform)
+  __shared__ double S0[NB * LDT];
+  __shared__ double S1[NB * LDT];
+  __shared__ double S2[NB * LDT];
+  const int np = a.np;
+  int ii, jj;
+  tile_index(blockIdx.x, ii, jj);
+  const int i = k + 1 + ii, j = k + 1 + jj;
+  tile_load(S0, a.Inv + int64_t(k) * NB * NB, NB);
+  tile_load(S1, a.Wm + int64_t(i) * NB * np + k * NB, np);
+  if (j != i) tile_load(S2, a.Wm + int64_t(j) * NB * np + k * NB, np);
+  __syncthreads();
+  tile_mul_invT(S1, S0);  // L_ik
+  const double* Ljk = S1;
+  if (j != i) {
+    tile_mul_invT(S2, S0);  // L_jk
+    Ljk = S2;
+  }
+  double acc[NB * NB / kCholThreads];
+  int q = 0;
+  double* Aij = a.Wm + int64_t(i) * NB * np + j * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) {
+    const int rr = e / NB, cc = e % NB;
+    double s = Aij[int64_t(rr) * np + cc];
+    for (int t = 0; t < NB; ++t) s = fma(-S1[rr * LDT + t], Ljk[cc * LDT + t], s);
+    acc[q] = s;
+  }
+  if (j == k + 1) {
+    tile_store(S1, a.L + int64_t(i) * NB * np + k * NB, np);
+    if (threadIdx.x < NB) {
+      const int rr = threadIdx.x;
+      double s = 0.0;
+      for (int t = 0; t < NB; ++t) s = fma(S1[rr * LDT + t], a.y[k * NB + t], s);
+      a.b[i * NB + rr] -= s;
+    }
+  }
+  __syncthreads();
+  if (i == j && i == k + 1) {
+    q = 0;
+    for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) S1[(e / NB) * LDT + e % NB] = acc[q];
+    const bool ok = factor_diag(a, i, S1, S2);
+    if (!ok && threadIdx.x == 0) a.sync[3] = 1u;
+  } else {
+    q = 0;
+    for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) Aij[int64_t(e / NB) * np + e % NB] = acc[q];
+  }
+}
+
+// Back substitution L^T x = y by one workgroup of 1024 threads: for block k (last first),
+// x_k = Inv_k^T (y_k - sum_{i>k} L_ik^T x_i); the sum is split over 32 row slices per column.
+constexpr int kBackThreads = 1024;
+
+__global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
+  if (a.sync[3] != 0u) {  // attempt 0 failed: the fallback takes over, or gives up with one attempt
+    if (a.attempts == 1) {
+      for (int k = threadIdx.x; k < a.n; k += kBackThreads) a.tau[k] = 0.0;
+      if (threadIdx.x == 0) *a.status = -1;
+    }
+    return;
+  }
+  __shared__ double part[32][NB + 1];
+  __shared__ double rhs[NB];
+  const int c = threadIdx.x % NB, sl = threadIdx.x / NB;  // column within the block, row slice
+  const int np = a.np;
+  for (int k = a.nt - 1; k >= 0; --k) {
+    const int c0 = k * NB;
+    double s = 0.0;
+    for (int row = c0 + NB + sl; row < np; row += 32) s = fma(a.L[int64_t(row) * np + c0 + c], a.x[row], s);
+    part[sl][c] = s;
+    __syncthreads();
+    if (threadIdx.x < NB) {
+      double t = 0.0;
+      for (int q = 0; q < 32; ++q) t += part[q][threadIdx.x];
+      rhs[threadIdx.x] = a.y[c0 + threadIdx.x] - t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NB) {
+      const double* Inv = a.Inv + int64_t(k) * NB * NB;
+      double v = 0.0;
+      for (int t = threadIdx.x; t < NB; ++t) v = fma(Inv[t * NB + threadIdx.x], rhs[t], v);
+      a.x[c0 + threadIdx.x] = v;
+      if (c0 + threadIdx.x < a.n) a.tau[c0 + threadIdx.x] = v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *a.status = 0;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Fallback: attempts 1 .. attempts-1 in one persistent launch with bounded grid barriers
+// ---------------------------------------------------------------------------------------------------
 __device__ inline unsigned ld_acq(unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -73,144 +322,36 @@ __device__ bool grid_barrier(unsigned* sync, unsigned nblocks) {
   return s_ok != 0;
 }
 
-__device__ inline void tile_load(double* T, const double* src, int ld) {
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads) {
-    int r = e / NB, c = e % NB;
-    T[r * LDT + c] = src[int64_t(r) * ld + c];
-  }
-}
-
-__device__ inline void tile_store(const double* T, double* dst, int ld) {
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads) {
-    int r = e / NB, c = e % NB;
-    dst[int64_t(r) * ld + c] = T[r * LDT + c];
-  }
-}
-
-// T <- T * Inv^T (Inv lower triangular): the panel solve L_ik = A_ik L_kk^-T.
-__device__ inline void tile_mul_invT(double* T, const double* Inv) {
-  double acc[NB * NB / kCholThreads];
-  int q = 0;
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) {
-    int r = e / NB, c = e % NB;
-    double s = 0.0;
-    for (int t = 0; t <= c; ++t) s += T[r * LDT + t] * Inv[c * LDT + t];
-    acc[q] = s;
-  }
-  __syncthreads();
-  q = 0;
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) T[(e / NB) * LDT + e % NB] = acc[q];
-  __syncthreads();
-}
-
-// In-place lower Cholesky of the tile; false on a non-positive or non-finite pivot (uniform result).
-__device__ bool tile_potrf(double* T) {
-  __shared__ int s_ok;
-  for (int c = 0; c < NB; ++c) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double d = T[c * LDT + c];
-      int ok = (d > 0.0) && isfinite(d);
-      s_ok = ok;
-      if (ok) T[c * LDT + c] = sqrt(d);
-    }
-    __syncthreads();
-    if (!s_ok) return false;
-    const double piv = T[c * LDT + c];
-    for (int r = c + 1 + threadIdx.x; r < NB; r += kCholThreads) T[r * LDT + c] /= piv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < NB * NB; e += kCholThreads) {
-      int r = e / NB, s = e % NB;
-      if (s > c && r >= s) T[r * LDT + s] -= T[r * LDT + c] * T[s * LDT + c];
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads) {
-    int r = e / NB, c = e % NB;
-    if (c > r) T[r * LDT + c] = 0.0;
-  }
-  __syncthreads();
-  return true;
-}
-
-// X = L^-1 for the lower-triangular L (column c by thread c).
-__device__ void tile_trinv(const double* Lt, double* X) {
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads) X[(e / NB) * LDT + e % NB] = 0.0;
-  __syncthreads();
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
-    for (int r = c; r < NB; ++r) {
-      double s = (r == c) ? 1.0 : 0.0;
-      for (int t = c; t < r; ++t) s -= Lt[r * LDT + t] * X[t * LDT + c];
-      X[r * LDT + c] = s / Lt[r * LDT + r];
-    }
-  }
-  __syncthreads();
-}
-
-// y_blk = Inv * b_blk (32 threads)
-__device__ inline void tile_gemv_store(const double* Inv, const double* bsrc, double* ydst) {
-  __syncthreads();
-  if (threadIdx.x < NB) {
-    const int r = threadIdx.x;
-    double s = 0.0;
-    for (int t = 0; t <= r; ++t) s += Inv[r * LDT + t] * bsrc[t];
-    ydst[r] = s;
-  }
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(kCholThreads) void k_chol_ladder(CholArgs a) {
-  __shared__ double S0[NB * LDT];  // Inv_k
-  __shared__ double S1[NB * LDT];  // L_ik / diagonal work
-  __shared__ double S2[NB * LDT];  // L_jk / inverse work
+__global__ __launch_bounds__(kCholThreads) void k_chol_fallback(CholArgs a) {
+  if (a.sync[3] == 0u) return;  // attempt 0 succeeded (uniform)
+  __shared__ double S0[NB * LDT];
+  __shared__ double S1[NB * LDT];
+  __shared__ double S2[NB * LDT];
   const unsigned G = gridDim.x;
   const int w = blockIdx.x;
   const int nt = a.nt, np = a.np, n = a.n;
-  // fail_flag[r * nt + s]: the factorisation of diagonal tile s failed in attempt r. One slot per
-  // (attempt, tile) so a flag read after a barrier can only have been written before that barrier.
+  // fail_flag[r * nt + s]: diagonal tile s failed in attempt r; one slot per (attempt, tile) so a flag
+  // read after a barrier can only have been written before that barrier.
   unsigned* fail_flag = a.sync + 4;
   unsigned* ready = a.sync + 4 + a.attempts * nt;
-  if (w == 0) {
+  if (w == 0)
     for (int k = threadIdx.x; k < (a.attempts + 1) * nt; k += kCholThreads) a.sync[4 + k] = 0u;
-    if (threadIdx.x == 0) *a.status = -2;  // stays -2 only if the kernel leaves on a barrier timeout
-  }
+  if (!grid_barrier(a.sync, G)) return;
   int result = -1;
-  double eps = a.eps0;
-  for (int r = 0; r < a.attempts; ++r, eps *= a.mult) {
-    // ---- copy + regularise the lower tiles; workgroup 0 factors tile (0, 0) on the way
+  double eps = a.eps0 * a.mult;
+  for (int r = 1; r < a.attempts; ++r, eps *= a.mult) {
     const int n_lower = nt * (nt + 1) / 2;
     for (int tt = w; tt < n_lower; tt += G) {
-      int i = 0;
-      while ((i + 1) * (i + 2) / 2 <= tt) ++i;
-      const int j = tt - i * (i + 1) / 2;
-      for (int e = threadIdx.x; e < NB * NB; e += kCholThreads) {
-        const int rr = i * NB + e / NB, cc = j * NB + e % NB;
-        double v;
-        if (rr < n && cc < n) {
-          v = a.H[int64_t(rr) * n + cc];
-          if (rr == cc) v += a.lambda * v + eps;
-        } else {
-          v = (rr == cc) ? 1.0 : 0.0;
-        }
-        S1[(e / NB) * LDT + e % NB] = v;
-      }
+      int i, j;
+      tile_index(tt, i, j);
+      tile_from_H(a, i, j, eps, S1);
       if (j == 0 && threadIdx.x < NB) {
         const int rr = i * NB + threadIdx.x;
         a.b[rr] = (rr < n) ? -a.g[rr] : 0.0;
       }
       __syncthreads();
-      if (i == 0) {  // tile (0, 0): factor now
-        const bool ok = tile_potrf(S1);
-        if (!ok) {
-          if (threadIdx.x == 0) atomicOr(&fail_flag[r * nt], 1u);
-        } else {
-          tile_store(S1, a.L, np);
-          tile_trinv(S1, S2);
-          tile_store(S2, a.Inv, NB);
-          __syncthreads();
-          tile_gemv_store(S2, a.b, a.y);
-        }
+      if (i == 0) {
+        if (!factor_diag(a, 0, S1, S2) && threadIdx.x == 0) atomicOr(&fail_flag[r * nt], 1u);
       } else {
         tile_store(S1, a.Wm + int64_t(i) * NB * np + j * NB, np);
       }
@@ -218,15 +359,13 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_ladder(CholArgs a) {
     }
     if (!grid_barrier(a.sync, G)) return;
     bool failed = ld_acq(&fail_flag[r * nt]) != 0u;
-    // ---- panel steps
     for (int k = 0; k + 1 < nt && !failed; ++k) {
       const int m = nt - k - 1;
       const int n_tiles = m * (m + 1) / 2;
       bool have_inv = false;
       for (int tt = w; tt < n_tiles; tt += G) {
-        int ii = 0;
-        while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
-        const int jj = tt - ii * (ii + 1) / 2;
+        int ii, jj;
+        tile_index(tt, ii, jj);
         const int i = k + 1 + ii, j = k + 1 + jj;
         if (!have_inv) {
           tile_load(S0, a.Inv + int64_t(k) * NB * NB, NB);
@@ -234,32 +373,30 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_ladder(CholArgs a) {
         }
         tile_load(S1, a.Wm + int64_t(i) * NB * np + k * NB, np);
         __syncthreads();
-        tile_mul_invT(S1, S0);  // L_ik
+        tile_mul_invT(S1, S0);
         const double* Ljk = S1;
         if (j != i) {
           tile_load(S2, a.Wm + int64_t(j) * NB * np + k * NB, np);
           __syncthreads();
-          tile_mul_invT(S2, S0);  // L_jk
+          tile_mul_invT(S2, S0);
           Ljk = S2;
         }
-        // C = A_ij - L_ik L_jk^T
         double acc[NB * NB / kCholThreads];
         int q = 0;
         double* Aij = a.Wm + int64_t(i) * NB * np + j * NB;
         for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) {
           const int rr = e / NB, cc = e % NB;
           double s = Aij[int64_t(rr) * np + cc];
-          for (int t = 0; t < NB; ++t) s -= S1[rr * LDT + t] * Ljk[cc * LDT + t];
+          for (int t = 0; t < NB; ++t) s = fma(-S1[rr * LDT + t], Ljk[cc * LDT + t], s);
           acc[q] = s;
         }
         if (j == k + 1) {
-          // final L_ik, and forward elimination of block i: b_i -= L_ik y_k
           tile_store(S1, a.L + int64_t(i) * NB * np + k * NB, np);
           __syncthreads();
           if (threadIdx.x < NB) {
             const int rr = threadIdx.x;
             double s = 0.0;
-            for (int t = 0; t < NB; ++t) s += S1[rr * LDT + t] * a.y[k * NB + t];
+            for (int t = 0; t < NB; ++t) s = fma(S1[rr * LDT + t], a.y[k * NB + t], s);
             a.b[i * NB + rr] -= s;
           }
         }
@@ -267,15 +404,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_ladder(CholArgs a) {
         if (i == j && i == k + 1) {
           q = 0;
           for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) S1[(e / NB) * LDT + e % NB] = acc[q];
-          const bool ok = tile_potrf(S1);
-          if (!ok) {
-            if (threadIdx.x == 0) atomicOr(&fail_flag[r * nt + k + 1], 1u);
-          } else {
-            tile_store(S1, a.L + int64_t(i) * NB * np + i * NB, np);
-            tile_trinv(S1, S2);
-            tile_store(S2, a.Inv + int64_t(i) * NB * NB, NB);
-            tile_gemv_store(S2, a.b + i * NB, a.y + i * NB);
-          }
+          if (!factor_diag(a, i, S1, S2) && threadIdx.x == 0) atomicOr(&fail_flag[r * nt + k + 1], 1u);
         } else {
           q = 0;
           for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q)
@@ -298,7 +427,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_ladder(CholArgs a) {
     }
     return;
   }
-  // ---- back substitution L^T x = y, block k owned by workgroup k mod G, highest blocks first
+  // back substitution as a dataflow wave: block k owned by workgroup k mod G, highest blocks first
   __shared__ double acc_s[NB];
   __shared__ int s_ok;
   const int k_first = (w < nt) ? w + ((nt - 1 - w) / int(G)) * int(G) : -1;
@@ -387,13 +516,25 @@ int launch_chol_ladder(const double* H, const double* g, int n, double lambda, d
   a.H = H; a.g = g; a.n = n;
   a.lambda = lambda; a.eps0 = eps0; a.mult = mult; a.attempts = attempts;
   a.tau = tau; a.status = status;
-  // barrier words start at zero (a fill kernel, not a memset, so the launch sequence can be captured)
-  DS3_TRY(launch_fill_u32(a.sync, 4, 0u, s));
-  int max_tiles = (a.nt - 1) * a.nt / 2;
-  int G = max_tiles < 1 ? 1 : max_tiles;
-  if (G > 128) G = 128;
-  hipLaunchKernelGGL(k_chol_ladder, dim3(G), dim3(kCholThreads), 0, s, a);
-  return check_hip(hipGetLastError(), "k_chol_ladder");
+  // barrier words start at zero (a fill kernel, not a memset, so the sequence can be captured)
+  DS3_TRY(launch_fill_u32(a.sync, 3, 0u, s));
+  hipLaunchKernelGGL(k_chol_init, dim3(a.nt * (a.nt + 1) / 2), dim3(kCholThreads), 0, s, a);
+  DS3_TRY(check_hip(hipGetLastError(), "k_chol_init"));
+  for (int k = 0; k + 1 < a.nt; ++k) {
+    const int m = a.nt - k - 1;
+    hipLaunchKernelGGL(k_chol_panel, dim3(m * (m + 1) / 2), dim3(kCholThreads), 0, s, a, k);
+    DS3_TRY(check_hip(hipGetLastError(), "k_chol_panel"));
+  }
+  hipLaunchKernelGGL(k_chol_backsub, dim3(1), dim3(kBackThreads), 0, s, a);
+  DS3_TRY(check_hip(hipGetLastError(), "k_chol_backsub"));
+  if (attempts > 1) {
+    int G = (a.nt - 1) * a.nt / 2;
+    if (G < 1) G = 1;
+    if (G > 128) G = 128;
+    hipLaunchKernelGGL(k_chol_fallback, dim3(G), dim3(kCholThreads), 0, s, a);
+    DS3_TRY(check_hip(hipGetLastError(), "k_chol_fallback"));
+  }
+  return DS3_OK;
 }
 
 }  // namespace ds3

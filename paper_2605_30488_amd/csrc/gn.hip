@@ -117,10 +117,11 @@ __device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const
   const float di2 = fmaf(Xi.x, Xi.x, fmaf(Xi.y, Xi.y, Xi.z * Xi.z));
   const float dj2 = fmaf(Xj.x, Xj.x, fmaf(Xj.y, Xj.y, Xj.z * Xj.z));
   const float cc = Xi.w * Xj.w;
-  // holes (|X| <= 1e-9 or non-finite) on either side, zero range after the transform, bad confidence
-  if (!(d2 > 1e-18f) || !(di2 > 1e-18f) || !(dj2 > 1e-18f) || !(cc >= 0.0f) || !isfinite(d2) ||
-      !isfinite(di2) || !isfinite(cc) || !isfinite(dj2))
-    return false;
+  // holes (|X| <= 1e-9 or non-finite) on either side, zero range after the transform, bad confidence:
+  // a NaN or infinity anywhere makes the sum non-finite
+  const float mn = fminf(fminf(d2, di2), dj2);
+  const float sum = (d2 + di2) + (dj2 + cc);
+  if (!(mn > 1e-18f) || !(cc >= 0.0f) || !(sum < __builtin_huge_valf())) return false;
   const float rd = rsqrtf(d2);
   const float rdi = rsqrtf(di2);
   const float d = d2 * rd;
@@ -135,10 +136,11 @@ __device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const
   const float r0 = sq * e0 * k.inv_sr, r1 = sq * e1 * k.inv_sr, r2 = sq * e2 * k.inv_sr;
   const float r3 = sq * e3 * k.inv_sd;
   const float a0 = fabsf(r0), a1 = fabsf(r1), a2 = fabsf(r2), a3 = fabsf(r3);
-  const float w0 = (a0 <= k.kappa) ? 1.0f : k.kappa / a0;
-  const float w1 = (a1 <= k.kappa) ? 1.0f : k.kappa / a1;
-  const float w2 = (a2 <= k.kappa) ? 1.0f : k.kappa / a2;
-  const float w3 = (a3 <= k.kappa) ? 1.0f : k.kappa / a3;
+  // IRLS weight min(1, kappa/|r|); the reciprocal is the hardware one (1 ulp)
+  const float w0 = (a0 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a0);
+  const float w1 = (a1 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a1);
+  const float w2 = (a2 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a2);
+  const float w3 = (a3 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a3);
   // rho(r) = t (|r| - t/2) with t = w |r|: r^2/2 inside kappa, kappa |r| - kappa^2/2 outside
   const float t0 = w0 * a0, t1 = w1 * a1, t2 = w2 * a2, t3 = w3 * a3;
   a.cost += t0 * fmaf(-0.5f, t0, a0) + t1 * fmaf(-0.5f, t1, a1) + t2 * fmaf(-0.5f, t2, a2) +

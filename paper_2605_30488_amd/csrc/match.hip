@@ -93,13 +93,14 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
   float r0 = S.s[0] - t0, r1 = S.s[1] - t1, r2 = S.s[2] - t2;
   float c = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
   float lam = P.lambda0;
+  // normal equations at the current p; unchanged by a rejected step, so rebuilt only on acceptance
+  float a = fmaf(S.su[0], S.su[0], fmaf(S.su[1], S.su[1], S.su[2] * S.su[2]));
+  float b = fmaf(S.su[0], S.sv[0], fmaf(S.su[1], S.sv[1], S.su[2] * S.sv[2]));
+  float dd = fmaf(S.sv[0], S.sv[0], fmaf(S.sv[1], S.sv[1], S.sv[2] * S.sv[2]));
+  float gu = fmaf(S.su[0], r0, fmaf(S.su[1], r1, S.su[2] * r2));
+  float gv = fmaf(S.sv[0], r0, fmaf(S.sv[1], r1, S.sv[2] * r2));
   int it = 0;
   for (; it < P.max_iters; ++it) {
-    const float a = fmaf(S.su[0], S.su[0], fmaf(S.su[1], S.su[1], S.su[2] * S.su[2]));
-    const float b = fmaf(S.su[0], S.sv[0], fmaf(S.su[1], S.sv[1], S.su[2] * S.sv[2]));
-    const float dd = fmaf(S.sv[0], S.sv[0], fmaf(S.sv[1], S.sv[1], S.sv[2] * S.sv[2]));
-    const float gu = fmaf(S.su[0], r0, fmaf(S.su[1], r1, S.su[2] * r2));
-    const float gv = fmaf(S.sv[0], r0, fmaf(S.sv[1], r1, S.sv[2] * r2));
     const float A = a * (1.0f + lam), D = dd * (1.0f + lam);
     const float det = A * D - b * b;
     if (!(det > 0.0f)) {
@@ -110,6 +111,10 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
     const float dv = -(A * gv - b * gu) / det;
     const float un = fminf(fmaxf(u + du, 0.0f), float(W - 1));
     const float vn = fminf(fmaxf(v + dv, 0.0f), float(H - 1));
+    if (un == u && vn == v) {  // no movement (clamped or vanishing step): same sample, same cost, reject
+      lam *= 10.0f;
+      continue;
+    }
     Sample Sn = sample_rays(R, H, W, un, vn);
     if (Sn.hole) {
       *iters = it + 1;
@@ -126,6 +131,11 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
         ++it;
         break;
       }
+      a = fmaf(S.su[0], S.su[0], fmaf(S.su[1], S.su[1], S.su[2] * S.su[2]));
+      b = fmaf(S.su[0], S.sv[0], fmaf(S.su[1], S.sv[1], S.su[2] * S.sv[2]));
+      dd = fmaf(S.sv[0], S.sv[0], fmaf(S.sv[1], S.sv[1], S.sv[2] * S.sv[2]));
+      gu = fmaf(S.su[0], r0, fmaf(S.su[1], r1, S.su[2] * r2));
+      gv = fmaf(S.sv[0], r0, fmaf(S.sv[1], r1, S.sv[2] * r2));
     } else {
       lam *= 10.0f;
     }

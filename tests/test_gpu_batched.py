@@ -86,25 +86,27 @@ def test_plan_f32_matches_oracle(dev, single):
 
 
 def test_plan_bf16_matches_oracle_on_rounded_inputs(dev, single):
-    """BF16 storage, FP32 accumulation: against the oracle on the same BF16-rounded inputs (the
-    arithmetic-only error) within 1e-5, and against the FP32 inputs (total error) within 1e-4."""
+    """BF16 storage, FP32 accumulation, 10 iterations from the noisy start: against the oracle on the
+    same BF16-rounded inputs (the arithmetic-only error) within 1e-5, and against the oracle on the
+    FP32 inputs (arithmetic + quantisation) within 1e-4."""
     g, idx = single
     G = _graph(g, idx, "bf16", dev)
     P = _t(g.poses_init, dev)
     plan = ds3.GNPlan(G, P)
-    plan.run(3)
+    iters = 10
+    plan.run(iters)
     xb, cb = _bf16_inputs(g)
     ref_b = g.poses_init.copy()
     ref_f = g.poses_init.copy()
     ob = O.Graph(xb, cb, g.edges, idx, anchors=(0,))
     of = O.Graph(g.xyz, g.conf, g.edges, idx, anchors=(0,))
-    for _ in range(3):
+    for _ in range(iters):
         ref_b, *_ = O.gn_step(ob, ref_b)
         ref_f, *_ = O.gn_step(of, ref_f)
     got = P.cpu().numpy()
     e_arith = O.pose_error(got, ref_b).max()
     e_total = O.pose_error(got, ref_f).max()
-    print(f"bf16 plan: arithmetic error {e_arith:.2e}, total error {e_total:.2e}")
+    print(f"bf16 plan after {iters} iterations: arithmetic error {e_arith:.2e}, total error {e_total:.2e}")
     assert e_arith <= 1e-5
     assert e_total <= 1e-4
     plan.close()
