@@ -20,9 +20,14 @@ struct Px;
 template <>
 struct Px<DS3_F32> {
   static constexpr int bytes = 16;
+  using raw_t = float4;
   __device__ static inline float4 load(const void* base, int64_t px) {
     return reinterpret_cast<const float4*>(base)[px];
   }
+  __device__ static inline raw_t load_raw(const void* base, int64_t px) {
+    return reinterpret_cast<const float4*>(base)[px];
+  }
+  __device__ static inline float4 unpack(raw_t r) { return r; }
 };
 
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
@@ -31,8 +36,15 @@ __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0
 template <>
 struct Px<DS3_BF16> {
   static constexpr int bytes = 8;
+  using raw_t = uint2;
   __device__ static inline float4 load(const void* base, int64_t px) {
     uint2 w = reinterpret_cast<const uint2*>(base)[px];
+    return make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y));
+  }
+  __device__ static inline raw_t load_raw(const void* base, int64_t px) {
+    return reinterpret_cast<const uint2*>(base)[px];
+  }
+  __device__ static inline float4 unpack(raw_t w) {
     return make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y));
   }
 };

@@ -212,11 +212,15 @@ __device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev
   acc_zero(a);
   const int64_t base = int64_t(tile) * (kReduceThreads * PPT);
   const int32_t* __restrict__ idx = idx_arena + E.idx_off;
-  constexpr int U = 4;
+  // U pixels in flight per thread: idx loads, then the raw pointmap loads of the valid ones, then the
+  // math, so the waits for the gathers come after all of them were issued
+  constexpr int U = (DT == DS3_BF16) ? (PPT < 8 ? PPT : 8) : 4;
+  static_assert(PPT % U == 0, "pixels per thread must be a multiple of the unroll");
+  using raw_t = typename Px<DT>::raw_t;
 #pragma unroll 1
   for (int k0 = 0; k0 < PPT; k0 += U) {
     int32_t m[U];
-    float4 xj[U], xi[U];
+    raw_t rj[U], ri[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t n = base + int64_t(k0 + u) * kReduceThreads + threadIdx.x;
@@ -227,13 +231,13 @@ __device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev
     for (int u = 0; u < U; ++u) {
       const int64_t n = base + int64_t(k0 + u) * kReduceThreads + threadIdx.x;
       if (m[u] >= 0) {
-        xj[u] = Px<DT>::load(arena, E.off_j + n);
-        xi[u] = Px<DT>::load(arena, E.off_i + m[u]);
+        rj[u] = Px<DT>::load_raw(arena, E.off_j + n);
+        ri[u] = Px<DT>::load_raw(arena, E.off_i + m[u]);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (m[u] >= 0) acc_pixel(a, xj[u], xi[u], M, k);
+      if (m[u] >= 0) acc_pixel(a, Px<DT>::unpack(rj[u]), Px<DT>::unpack(ri[u]), M, k);
   }
   acc_block_store(a, out, lds);
 }
