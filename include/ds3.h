@@ -210,9 +210,9 @@ int ds3_sim3_gn_step(double* poses, int32_t n_kf, const ds3_image* kf, const voi
                      size_t ws_bytes, void* stream);
 
 /* Solve (H + lambda diag(H) + eps_r I) tau = -g for a symmetric n x n H (device, row-major, float64;
- * only the lower triangle is read) with eps_r = eps0 * mult^r, r = 0 .. attempts-1; tau (device, n) = 0
- * and status (device int32) = -1 when every factorisation fails, else status = r. Workspace from
- * ds3_chol_workspace_bytes(n). */
+ * only the lower triangle is read; 1 <= n <= 8192, else DS3_EINVAL) with eps_r = eps0 * mult^r,
+ * r = 0 .. attempts-1 (attempts <= 16); tau (device, n) = 0 and status (device int32) = -1 when every
+ * factorisation fails, else status = r. Workspace from ds3_chol_workspace_bytes(n). */
 size_t ds3_chol_workspace_bytes(int32_t n);
 int ds3_chol_ladder_solve(const double* H, const double* g, int32_t n, double lambda, double eps0,
                           double mult, int32_t attempts, double* tau, int32_t* status, void* workspace,

@@ -4,24 +4,29 @@
 //
 // Right-looking blocked Cholesky over 32x32 float64 tiles, one kernel per panel so that kernel
 // boundaries order the steps (no in-kernel grid barriers, no device-wide cache maintenance):
-//   init      copy + regularise the lower tiles; the owner of tile (0, 0) factors it, inverts the factor
-//             and starts the forward substitution of -g;
+//   init      copy + regularise the lower tiles; the owner of tile (0, 0) factors it;
 //   panel k   every workgroup owns one trailing tile (i, j), k < j <= i: it forms L_ik = A_ik L_kk^-T
 //             (and L_jk) from the stored inverse, updates A_ij -= L_ik L_jk^T, stores L_ik and carries
 //             the forward substitution when j = k+1, and the owner of (k+1, k+1) factors it right away;
-//   backsub   one workgroup solves L^T x = y block by block.
+//   backsub   one workgroup solves L^T x = y, streaming the factor row block by row block.
+// A diagonal factorisation produces L_kk, its inverse and y_k = L_kk^-1 b_k together: the inverse is
+// accumulated by the same rank-one column updates that form L, with one barrier per column.
 // Attempt 0 runs this way; only when it fails does a persistent fallback kernel run attempts 1.. with its
 // own bounded grid barriers (the common case never pays for the ladder).
+//
+// Tile products run on the float64 MFMA; LDS tiles use row stride NB + 4.
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace ds3 {
 
 constexpr int NB = 32;
-constexpr int LDT = NB + 1;
+constexpr int LDT = NB + 4;
 constexpr int kCholThreads = 256;
 constexpr long kSpinLimit = 1L << 24;
 constexpr int kMaxAttempts = 16;
+constexpr int kBackThreads = 512;
+constexpr int kMaxN = 8192;  // back substitution keeps at most 16 columns per thread
 
 struct CholArgs {
   const double* H;
@@ -33,139 +38,263 @@ struct CholArgs {
   int32_t* status;
   double* Wm;   // np x np working copy (lower tiles)
   double* L;    // np x np factor (lower tiles)
-  double* Inv;  // nt tiles: inverse of each diagonal factor
+  double* Inv;  // nt tiles: inverse of each diagonal factor (row-major 32x32, zero above the diagonal)
   double* b;    // np: -g after forward elimination
   double* y;    // np: L^-1 (-g) per block
-  double* x;    // np: solution blocks
+  double* x;    // np: solution blocks (fallback back substitution)
   unsigned* sync;  // [0] barrier count, [1] generation, [2] error, [3] attempt-0 failed,
                    // [4 .. 4 + attempts*nt) failure of diagonal tile s in attempt r, then nt ready flags
 };
 
+// LDS scratch of one diagonal factorisation: double-buffered pairs of published columns of T and rows
+// of X (8 x 32), then the block of b (32).
+constexpr int kFactorScratch = 9 * NB;
+
 // ---------------------------------------------------------------------------------------------------
-// Tile helpers (32x32, lower triangular factors, LDS row stride LDT)
+// Fragment helpers. The 256 threads hold a 32x32 tile in the accumulator layout of the float64 MFMA
+// (16x16x4): wave w owns quadrant (w/2, w%2); lane l holds column 16 (w%2) + l%16 of rows
+// 16 (w/2) + l/16 + 4 v, v = 0..3 (accumulator register v of this instruction holds rows l/16 + 4 v).
 // ---------------------------------------------------------------------------------------------------
-__device__ inline double rsqrt_full(double d) {
-  double y = __builtin_amdgcn_rsq(d);  // hardware estimate, refined by two Newton steps
-  y = y * fma(-0.5 * d * y, y, 1.5);
-  y = y * fma(-0.5 * d * y, y, 1.5);
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int fcol() { return 16 * ((threadIdx.x >> 6) & 1) + (threadIdx.x & 15); }
+__device__ inline int frow(int v) { return 16 * (threadIdx.x >> 7) + ((threadIdx.x >> 4) & 3) + 4 * v; }
+
+__device__ inline void frag_load(f64x4& q, const double* src, int64_t ld) {
+  const int c = fcol();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) q[v] = src[int64_t(frow(v)) * ld + c];
+}
+
+__device__ inline void frag_store(const f64x4& q, double* dst, int64_t ld) {
+  const int c = fcol();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) dst[int64_t(frow(v)) * ld + c] = q[v];
+}
+
+__device__ inline void frag_to_lds(const f64x4& q, double* S) {
+  const int c = fcol();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) S[frow(v) * LDT + c] = q[v];
+}
+
+// acc (+/-)= (A B^T) restricted to this wave's quadrant, A and B LDS tiles: eight MFMA steps over t.
+template <bool SUB>
+__device__ inline void frag_gemm_abt(const double* A, const double* B, f64x4& acc) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const double* a = A + (16 * (w >> 1) + (l & 15)) * LDT + (l >> 4);
+  const double* b = B + (16 * (w & 1) + (l & 15)) * LDT + (l >> 4);
+#pragma unroll
+  for (int t0 = 0; t0 < NB; t0 += 4) {
+    const double x = SUB ? -a[t0] : a[t0];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, b[t0], acc, 0, 0, 0);
+  }
+}
+
+// 1/d from the hardware estimate refined by two Newton steps.
+__device__ inline double recip(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  y = fma(y, fma(-d, y, 1.0), y);
+  y = fma(y, fma(-d, y, 1.0), y);
   return y;
 }
 
-__device__ inline void tile_load(double* T, const double* src, int ld) {
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) T[(e / NB) * LDT + e % NB] = src[int64_t(e / NB) * ld + e % NB];
-}
+__device__ inline bool pivot_ok(double d) { return (d > 0.0) && isfinite(d); }
 
-__device__ inline void tile_store(const double* T, double* dst, int ld) {
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) dst[int64_t(e / NB) * ld + e % NB] = T[(e / NB) * LDT + e % NB];
-}
-
-// Lower Cholesky of the LDS tile in place (upper part zeroed); false on a non-positive or non-finite
-// pivot. 256 threads; thread t owns column t % 32 of rows t / 32 + 8q. Two barriers per column.
-__device__ bool tile_potrf(double* T) {
-  const int s = threadIdx.x % NB;
-  const int r0 = threadIdx.x / NB;
-  for (int c = 0; c < NB; ++c) {
-    __syncthreads();
-    const double d = T[c * LDT + c];
-    if (!(d > 0.0) || !isfinite(d)) return false;  // uniform: every thread read the same pivot
-    const double y = rsqrt_full(d);
-    const double ls = T[s * LDT + c] * y;
-    double lr[NB * NB / kCholThreads];
+// Cholesky of the SPD tile held as a fragment (lower triangle used), together with its inverse, two
+// columns per barrier. Columns c, c+1 of T and rows c, c+1 of the inverse accumulator X (identity at
+// the start) are published in LDS before the pair; every thread then forms the 2x2 pivot block
+//   d0 = T[c][c],  t = T[c+1][c],  d1 = T[c+1][c+1] - t^2 / d0,
+// the step-c value of column c+1 (b' = T[.][c+1] - T[.][c] t / d0) and of row c+1 of X, and applies
+//   T[r][s] -= T[r][c] T[s][c] / d0 + b'_r b'_s / d1                     (c+1 < s <= r),
+//   X[r][j] -= T[r][c] X[c][j] / d0 + b'_r X'[c+1][j] / d1               (r > c+1),
+// with row c+1 of X taking only the first term. At the end L[r][s] = T[r][s] / sqrt(d_s) and
+// L^-1[r][j] = X[r][j] / sqrt(d_r). Returns false (uniformly) on a non-positive or non-finite pivot.
+__device__ bool factor_frag(f64x4& T, double* fb, f64x4& Lq, f64x4& Xq) {
+  const int s = fcol();
+  f64x4 X;
+  double dc = 1.0, dr[4] = {1.0, 1.0, 1.0, 1.0};
 #pragma unroll
-    for (int q = 0; q < NB * NB / kCholThreads; ++q) lr[q] = T[(r0 + 8 * q) * LDT + c] * y;
-    __syncthreads();
+  for (int v = 0; v < 4; ++v) X[v] = (frow(v) == s) ? 1.0 : 0.0;
+  // publish columns 0, 1 and rows 0, 1 into buffer 0: fb[par * 4 NB + {0: col c, 1: col c+1, 2: row c,
+  // 3: row c+1} * NB]
+  if (s < 2)
 #pragma unroll
-    for (int q = 0; q < NB * NB / kCholThreads; ++q) {
-      const int r = r0 + 8 * q;
-      if (s == c && r >= c) T[r * LDT + c] = lr[q];  // r == c: d / sqrt(d) = sqrt(d)
-      if (s > c && r >= s) T[r * LDT + s] = fma(-lr[q], ls, T[r * LDT + s]);
+    for (int v = 0; v < 4; ++v) fb[s * NB + frow(v)] = T[v];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (frow(v) < 2) fb[(2 + frow(v)) * NB + s] = X[v];
+  __syncthreads();
+  for (int c = 0; c < NB; c += 2) {
+    const double* P = fb + ((c >> 1) & 1) * 4 * NB;
+    const double d0 = P[c];
+    const double t10 = P[c + 1];
+    if (!pivot_ok(d0)) return false;  // every thread read the same pivots
+    const double i0 = recip(d0);
+    const double d1 = fma(-t10 * i0, t10, P[NB + c + 1]);
+    if (!pivot_ok(d1)) return false;
+    const double i1 = recip(d1);
+    const double g = t10 * i0;
+    const double as = P[s], bs = fma(-as, g, P[NB + s]);
+    const double x0s = P[2 * NB + s], x1s = fma(-g, x0s, P[3 * NB + s]);
+    if (s == c) dc = d0;
+    if (s == c + 1) dc = d1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = frow(v);
+      const double av = P[r];
+      const double bv = fma(-av, g, P[NB + r]);
+      if (r == c) dr[v] = d0;
+      if (r == c + 1) dr[v] = d1;
+      if (r > c + 1) {
+        if (s > c + 1 && s <= r) T[v] -= fma(av * i0, as, bv * i1 * bs);
+        X[v] -= fma(av * i0, x0s, bv * i1 * x1s);
+      } else if (r == c + 1) {
+        X[v] -= av * i0 * x0s;
+      }
+      if (s == c + 1 && r >= c + 1) T[v] = bv;
     }
+    if (c + 2 < NB) {
+      double* Q = fb + (((c >> 1) + 1) & 1) * 4 * NB;
+      if (s == c + 2 || s == c + 3)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Q[(s - c - 2) * NB + frow(v)] = T[v];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (frow(v) == c + 2 || frow(v) == c + 3) Q[(frow(v) - c) * NB + s] = X[v];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads)
-    if (e % NB > e / NB) T[(e / NB) * LDT + e % NB] = 0.0;
-  __syncthreads();
+  const double rsc = 1.0 / sqrt(dc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const bool low = s <= frow(v);
+    Lq[v] = low ? T[v] * rsc : 0.0;
+    Xq[v] = low ? X[v] / sqrt(dr[v]) : 0.0;
+  }
   return true;
 }
 
-// X = L^-1 (lower): column c solved by thread c with the column kept in registers (x_t = 0 for t < c,
-// so the dot products can run over every t < r).
-__device__ void tile_trinv(const double* Lt, double* X) {
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
-    double x[NB];
-#pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int t = 0; t < r; ++t) {
-        if (t & 1) s1 = fma(Lt[r * LDT + t], x[t], s1);
-        else s0 = fma(Lt[r * LDT + t], x[t], s0);
-      }
-      x[r] = (r >= c) ? (((r == c) ? 1.0 : 0.0) - (s0 + s1)) / Lt[r * LDT + r] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < NB; ++r) X[r * LDT + c] = x[r];
-  }
-  __syncthreads();
-}
-
-// T <- T * Inv^T (Inv lower triangular): the panel solve L_ik = A_ik L_kk^-T.
-__device__ inline void tile_mul_invT(double* T, const double* Inv) {
-  double acc[NB * NB / kCholThreads];
-  int q = 0;
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) {
-    const int r = e / NB, c = e % NB;
-    double s = 0.0;
-    for (int t = 0; t <= c; ++t) s = fma(T[r * LDT + t], Inv[c * LDT + t], s);
-    acc[q] = s;
-  }
-  __syncthreads();
-  q = 0;
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) T[(e / NB) * LDT + e % NB] = acc[q];
-  __syncthreads();
-}
-
-// ydst = Inv * bsrc (32 threads)
-__device__ inline void tile_gemv_store(const double* Inv, const double* bsrc, double* ydst) {
+// Stores L_ii and its inverse, and y_i = L_ii^-1 b_i (b_i in LDS sb). S: a free LDS tile.
+__device__ void store_diag(const CholArgs& a, int i, const f64x4& Lq, const f64x4& Xq, double* S,
+                           const double* sb) {
+  frag_store(Lq, a.L + int64_t(i) * NB * a.np + i * NB, a.np);
+  frag_store(Xq, a.Inv + int64_t(i) * NB * NB, NB);
+  frag_to_lds(Xq, S);
   __syncthreads();
   if (threadIdx.x < NB) {
     const int r = threadIdx.x;
-    double s = 0.0;
-    for (int t = 0; t <= r; ++t) s = fma(Inv[r * LDT + t], bsrc[t], s);
-    ydst[r] = s;
-  }
-  __syncthreads();
-}
-
-// Copy + regularise one lower tile of H into T (LDS); identity on padding.
-__device__ inline void tile_from_H(const CholArgs& a, int i, int j, double eps, double* T) {
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int rr = i * NB + e / NB, cc = j * NB + e % NB;
-    double v;
-    if (rr < a.n && cc < a.n) {
-      v = a.H[int64_t(rr) * a.n + cc];
-      if (rr == cc) v += a.lambda * v + eps;
-    } else {
-      v = (rr == cc) ? 1.0 : 0.0;
+    double s0 = 0.0, s1 = 0.0;
+    for (int t = 0; t <= r; t += 2) {
+      s0 = fma(S[r * LDT + t], sb[t], s0);
+      if (t + 1 <= r) s1 = fma(S[r * LDT + t + 1], sb[t + 1], s1);
     }
-    T[(e / NB) * LDT + e % NB] = v;
+    a.y[i * NB + r] = s0 + s1;
   }
 }
 
-// Factor a diagonal tile in S1: L -> L buffer, inverse -> Inv buffer, y_i = Inv (b_i). False on failure.
-__device__ bool factor_diag(const CholArgs& a, int i, double* S1, double* S2) {
+// Regularised lower tile (i, j) of H as a fragment; identity on padding, zero above the diagonal.
+__device__ inline void frag_from_H(const CholArgs& a, int i, int j, double eps, f64x4& q) {
+  const int cc = j * NB + fcol();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = i * NB + frow(v);
+    double x;
+    if (rr < a.n && cc < a.n) {
+      x = (cc <= rr) ? a.H[int64_t(rr) * a.n + cc] : 0.0;
+      if (rr == cc) x += a.lambda * x + eps;
+    } else {
+      x = (rr == cc) ? 1.0 : 0.0;
+    }
+    q[v] = x;
+  }
+}
+
+// Init of one lower tile for regularisation eps. The owner of (0, 0) factors it; returns its success
+// (true for every other tile).
+__device__ bool init_tile(const CholArgs& a, int i, int j, double eps, double* S, double* fb) {
+  f64x4 q;
+  frag_from_H(a, i, j, eps, q);
+  double* sb = fb + 8 * NB;
+  if (j == 0 && threadIdx.x < NB) {
+    const int rr = i * NB + threadIdx.x;
+    const double bv = (rr < a.n) ? -a.g[rr] : 0.0;
+    a.b[rr] = bv;
+    if (i == 0) sb[threadIdx.x] = bv;
+  }
+  if (i != 0) {
+    frag_store(q, a.Wm + int64_t(i) * NB * a.np + j * NB, a.np);
+    return true;
+  }
   __syncthreads();
-  if (!tile_potrf(S1)) return false;
-  tile_store(S1, a.L + int64_t(i) * NB * a.np + i * NB, a.np);
-  tile_trinv(S1, S2);
-  tile_store(S2, a.Inv + int64_t(i) * NB * NB, NB);
-  tile_gemv_store(S2, a.b + i * NB, a.y + i * NB);
+  f64x4 Lq, Xq;
+  if (!factor_frag(q, fb, Lq, Xq)) return false;
+  store_diag(a, 0, Lq, Xq, S, sb);
   return true;
 }
 
+// Trailing tile (i, j) of panel k. Returns false only for the next diagonal tile (i = j = k+1) when its
+// factorisation fails.
+__device__ bool panel_tile(const CholArgs& a, int k, int i, int j, double* S0, double* S1, double* S2,
+                           double* fb) {
+  const int np = a.np;
+  const bool offd = (j != i);
+  const bool col = (j == k + 1);  // this workgroup stores L_ik and eliminates b_i
+  f64x4 qinv, qi, qj, qa;
+  frag_load(qinv, a.Inv + int64_t(k) * NB * NB, NB);
+  frag_load(qi, a.Wm + int64_t(i) * NB * np + k * NB, np);
+  if (offd) frag_load(qj, a.Wm + int64_t(j) * NB * np + k * NB, np);
+  frag_load(qa, a.Wm + int64_t(i) * NB * np + j * NB, np);
+  double yk = 0.0, bi = 0.0;
+  if (col && threadIdx.x < NB) {
+    yk = a.y[k * NB + threadIdx.x];
+    bi = a.b[i * NB + threadIdx.x];
+  }
+  __syncthreads();  // previous users of S0..S2 and fb (fallback loop) are done
+  frag_to_lds(qinv, S0);
+  frag_to_lds(qi, S1);
+  if (offd) frag_to_lds(qj, S2);
+  double* sy = fb + 4 * NB;  // y_k while the factor scratch is unused
+  double* sb = fb + 8 * NB;
+  if (col && threadIdx.x < NB) sy[threadIdx.x] = yk;
+  __syncthreads();
+  f64x4 li = {0.0, 0.0, 0.0, 0.0}, lj = {0.0, 0.0, 0.0, 0.0};
+  frag_gemm_abt<false>(S1, S0, li);  // L_ik = A_ik Inv_k^T
+  if (offd) frag_gemm_abt<false>(S2, S0, lj);
+  __syncthreads();
+  frag_to_lds(li, S1);
+  if (offd) frag_to_lds(lj, S2);
+  __syncthreads();
+  frag_gemm_abt<true>(S1, offd ? S2 : S1, qa);  // A_ij -= L_ik L_jk^T
+  if (col) {
+    frag_store(li, a.L + int64_t(i) * NB * np + k * NB, np);
+    if (threadIdx.x < NB) {  // forward elimination b_i -= L_ik y_k
+      const int r = threadIdx.x;
+      double s0 = 0.0, s1 = 0.0;
+      for (int t = 0; t < NB; t += 2) {
+        s0 = fma(S1[r * LDT + t], sy[t], s0);
+        s1 = fma(S1[r * LDT + t + 1], sy[t + 1], s1);
+      }
+      const double bv = bi - (s0 + s1);
+      a.b[i * NB + r] = bv;
+      sb[r] = bv;
+    }
+  }
+  if (i == j && i == k + 1) {
+    __syncthreads();
+    f64x4 Lq, Xq;
+    if (!factor_frag(qa, fb, Lq, Xq)) return false;
+    store_diag(a, i, Lq, Xq, S0, sb);
+    return true;
+  }
+  frag_store(qa, a.Wm + int64_t(i) * NB * np + j * NB, np);
+  return true;
+}
+
+// Lower-triangle tile number tt -> (i, j), j <= i, row by row.
 __device__ inline void tile_index(int tt, int& i, int& j) {
-  i = 0;
+  i = int((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > tt) --i;
   while ((i + 1) * (i + 2) / 2 <= tt) ++i;
   j = tt - i * (i + 1) / 2;
 }
@@ -174,24 +303,14 @@ __device__ inline void tile_index(int tt, int& i, int& j) {
 // Attempt 0: init, panels, back substitution
 // ---------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kCholThreads) void k_chol_init(CholArgs a) {
-  __shared__ double S1[NB * LDT];
-  __shared__ double S2[NB * LDT];
+  __shared__ double S[NB * LDT];
+  __shared__ double fb[kFactorScratch];
   int i, j;
   tile_index(blockIdx.x, i, j);
-  tile_from_H(a, i, j, a.eps0, S1);
-  if (j == 0 && threadIdx.x < NB) {
-    const int rr = i * NB + threadIdx.x;
-    a.b[rr] = (rr < a.n) ? -a.g[rr] : 0.0;
-  }
-  __syncthreads();
-  if (i == 0) {
-    const bool ok = factor_diag(a, 0, S1, S2);
-    if (threadIdx.x == 0) {
-      a.sync[3] = ok ? 0u : 1u;
-      *a.status = -2;  // replaced by the back substitution or the fallback
-    }
-  } else {
-    tile_store(S1, a.Wm + int64_t(i) * NB * a.np + j * NB, a.np);
+  const bool ok = init_tile(a, i, j, a.eps0, S, fb);
+  if (i == 0 && threadIdx.x == 0) {
+    a.sync[3] = ok ? 0u : 1u;
+    *a.status = -2;  // replaced by the back substitution or the fallback
   }
 }
 
@@ -200,54 +319,17 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_panel(CholArgs a, int k) 
   __shared__ double S0[NB * LDT];
   __shared__ double S1[NB * LDT];
   __shared__ double S2[NB * LDT];
-  const int np = a.np;
+  __shared__ double fb[kFactorScratch];
   int ii, jj;
   tile_index(blockIdx.x, ii, jj);
-  const int i = k + 1 + ii, j = k + 1 + jj;
-  tile_load(S0, a.Inv + int64_t(k) * NB * NB, NB);
-  tile_load(S1, a.Wm + int64_t(i) * NB * np + k * NB, np);
-  if (j != i) tile_load(S2, a.Wm + int64_t(j) * NB * np + k * NB, np);
-  __syncthreads();
-  tile_mul_invT(S1, S0);  // L_ik
-  const double* Ljk = S1;
-  if (j != i) {
-    tile_mul_invT(S2, S0);  // L_jk
-    Ljk = S2;
-  }
-  double acc[NB * NB / kCholThreads];
-  int q = 0;
-  double* Aij = a.Wm + int64_t(i) * NB * np + j * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) {
-    const int rr = e / NB, cc = e % NB;
-    double s = Aij[int64_t(rr) * np + cc];
-    for (int t = 0; t < NB; ++t) s = fma(-S1[rr * LDT + t], Ljk[cc * LDT + t], s);
-    acc[q] = s;
-  }
-  if (j == k + 1) {
-    tile_store(S1, a.L + int64_t(i) * NB * np + k * NB, np);
-    if (threadIdx.x < NB) {
-      const int rr = threadIdx.x;
-      double s = 0.0;
-      for (int t = 0; t < NB; ++t) s = fma(S1[rr * LDT + t], a.y[k * NB + t], s);
-      a.b[i * NB + rr] -= s;
-    }
-  }
-  __syncthreads();
-  if (i == j && i == k + 1) {
-    q = 0;
-    for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) S1[(e / NB) * LDT + e % NB] = acc[q];
-    const bool ok = factor_diag(a, i, S1, S2);
-    if (!ok && threadIdx.x == 0) a.sync[3] = 1u;
-  } else {
-    q = 0;
-    for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) Aij[int64_t(e / NB) * np + e % NB] = acc[q];
-  }
+  if (!panel_tile(a, k, k + 1 + ii, k + 1 + jj, S0, S1, S2, fb) && threadIdx.x == 0) a.sync[3] = 1u;
 }
 
-// Back substitution L^T x = y by one workgroup of 1024 threads: for block k (last first),
-// x_k = Inv_k^T (y_k - sum_{i>k} L_ik^T x_i); the sum is split over 32 row slices per column.
-constexpr int kBackThreads = 1024;
-
+// Back substitution L^T x = y by one workgroup, right-looking: for block k (last first)
+//   x_k = Inv_k^T (y_k - acc_k),  then acc_j += sum_r L[32k + r][j] x_k[r] for every column j < 32k,
+// where thread t keeps acc for columns t + 512 m in registers. The first RC rows of block k are loaded
+// before x_k is solved, and Inv_{k-1} one block ahead, so that the loads overlap the solve.
+template <int CPT, int RC>
 __global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
   if (a.sync[3] != 0u) {  // attempt 0 failed: the fallback takes over, or gives up with one attempt
     if (a.attempts == 1) {
@@ -256,32 +338,70 @@ __global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
     }
     return;
   }
-  __shared__ double part[32][NB + 1];
+  constexpr int kInvPer = NB * NB / kBackThreads;
+  __shared__ double sinv[NB * NB];
   __shared__ double rhs[NB];
-  const int c = threadIdx.x % NB, sl = threadIdx.x / NB;  // column within the block, row slice
-  const int np = a.np;
+  __shared__ double xs[NB];
+  const int t = threadIdx.x;
+  const int64_t np = a.np;
+  double acc[CPT];
+#pragma unroll
+  for (int m = 0; m < CPT; ++m) acc[m] = 0.0;
+  double inv[kInvPer];
+#pragma unroll
+  for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(a.nt - 1) * NB * NB + t + e * kBackThreads];
   for (int k = a.nt - 1; k >= 0; --k) {
     const int c0 = k * NB;
-    double s = 0.0;
-    for (int row = c0 + NB + sl; row < np; row += 32) s = fma(a.L[int64_t(row) * np + c0 + c], a.x[row], s);
-    part[sl][c] = s;
-    __syncthreads();
-    if (threadIdx.x < NB) {
-      double t = 0.0;
-      for (int q = 0; q < 32; ++q) t += part[q][threadIdx.x];
-      rhs[threadIdx.x] = a.y[c0 + threadIdx.x] - t;
+    double buf[RC][CPT];
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+#pragma unroll
+      for (int m = 0; m < CPT; ++m) {
+        const int j = t + kBackThreads * m;
+        buf[r][m] = (j < c0) ? a.L[(c0 + r) * np + j] : 0.0;
+      }
+#pragma unroll
+    for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBackThreads] = inv[e];
+    if (k > 0)
+#pragma unroll
+      for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(k - 1) * NB * NB + t + e * kBackThreads];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      const int j = t + kBackThreads * m;
+      if (j >= c0 && j < c0 + NB) rhs[j - c0] = a.y[j] - acc[m];
     }
     __syncthreads();
-    if (threadIdx.x < NB) {
-      const double* Inv = a.Inv + int64_t(k) * NB * NB;
-      double v = 0.0;
-      for (int t = threadIdx.x; t < NB; ++t) v = fma(Inv[t * NB + threadIdx.x], rhs[t], v);
-      a.x[c0 + threadIdx.x] = v;
-      if (c0 + threadIdx.x < a.n) a.tau[c0 + threadIdx.x] = v;
+    if (t < NB) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int u = t; u < NB; u += 2) {
+        s0 = fma(sinv[u * NB + t], rhs[u], s0);
+        if (u + 1 < NB) s1 = fma(sinv[(u + 1) * NB + t], rhs[u + 1], s1);
+      }
+      xs[t] = s0 + s1;
+      if (c0 + t < a.n) a.tau[c0 + t] = s0 + s1;
     }
     __syncthreads();
+#pragma unroll 1
+    for (int rr = 0; rr < NB; rr += RC) {
+      if (rr > 0) {
+#pragma unroll
+        for (int r = 0; r < RC; ++r)
+#pragma unroll
+          for (int m = 0; m < CPT; ++m) {
+            const int j = t + kBackThreads * m;
+            buf[r][m] = (j < c0) ? a.L[(c0 + rr + r) * np + j] : 0.0;
+          }
+      }
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        const double xr = xs[rr + r];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) acc[m] = fma(buf[r][m], xr, acc[m]);
+      }
+    }
+    __syncthreads();  // sinv, rhs and xs are rewritten by the next block
   }
-  if (threadIdx.x == 0) *a.status = 0;
+  if (t == 0) *a.status = 0;
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -327,6 +447,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_fallback(CholArgs a) {
   __shared__ double S0[NB * LDT];
   __shared__ double S1[NB * LDT];
   __shared__ double S2[NB * LDT];
+  __shared__ double fb[kFactorScratch];
   const unsigned G = gridDim.x;
   const int w = blockIdx.x;
   const int nt = a.nt, np = a.np, n = a.n;
@@ -344,17 +465,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_fallback(CholArgs a) {
     for (int tt = w; tt < n_lower; tt += G) {
       int i, j;
       tile_index(tt, i, j);
-      tile_from_H(a, i, j, eps, S1);
-      if (j == 0 && threadIdx.x < NB) {
-        const int rr = i * NB + threadIdx.x;
-        a.b[rr] = (rr < n) ? -a.g[rr] : 0.0;
-      }
       __syncthreads();
-      if (i == 0) {
-        if (!factor_diag(a, 0, S1, S2) && threadIdx.x == 0) atomicOr(&fail_flag[r * nt], 1u);
-      } else {
-        tile_store(S1, a.Wm + int64_t(i) * NB * np + j * NB, np);
-      }
+      if (!init_tile(a, i, j, eps, S0, fb) && threadIdx.x == 0) atomicOr(&fail_flag[r * nt], 1u);
       __syncthreads();
     }
     if (!grid_barrier(a.sync, G)) return;
@@ -362,54 +474,11 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_fallback(CholArgs a) {
     for (int k = 0; k + 1 < nt && !failed; ++k) {
       const int m = nt - k - 1;
       const int n_tiles = m * (m + 1) / 2;
-      bool have_inv = false;
       for (int tt = w; tt < n_tiles; tt += G) {
         int ii, jj;
         tile_index(tt, ii, jj);
-        const int i = k + 1 + ii, j = k + 1 + jj;
-        if (!have_inv) {
-          tile_load(S0, a.Inv + int64_t(k) * NB * NB, NB);
-          have_inv = true;
-        }
-        tile_load(S1, a.Wm + int64_t(i) * NB * np + k * NB, np);
-        __syncthreads();
-        tile_mul_invT(S1, S0);
-        const double* Ljk = S1;
-        if (j != i) {
-          tile_load(S2, a.Wm + int64_t(j) * NB * np + k * NB, np);
-          __syncthreads();
-          tile_mul_invT(S2, S0);
-          Ljk = S2;
-        }
-        double acc[NB * NB / kCholThreads];
-        int q = 0;
-        double* Aij = a.Wm + int64_t(i) * NB * np + j * NB;
-        for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) {
-          const int rr = e / NB, cc = e % NB;
-          double s = Aij[int64_t(rr) * np + cc];
-          for (int t = 0; t < NB; ++t) s = fma(-S1[rr * LDT + t], Ljk[cc * LDT + t], s);
-          acc[q] = s;
-        }
-        if (j == k + 1) {
-          tile_store(S1, a.L + int64_t(i) * NB * np + k * NB, np);
-          __syncthreads();
-          if (threadIdx.x < NB) {
-            const int rr = threadIdx.x;
-            double s = 0.0;
-            for (int t = 0; t < NB; ++t) s = fma(S1[rr * LDT + t], a.y[k * NB + t], s);
-            a.b[i * NB + rr] -= s;
-          }
-        }
-        __syncthreads();
-        if (i == j && i == k + 1) {
-          q = 0;
-          for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q) S1[(e / NB) * LDT + e % NB] = acc[q];
-          if (!factor_diag(a, i, S1, S2) && threadIdx.x == 0) atomicOr(&fail_flag[r * nt + k + 1], 1u);
-        } else {
-          q = 0;
-          for (int e = threadIdx.x; e < NB * NB; e += kCholThreads, ++q)
-            Aij[int64_t(e / NB) * np + e % NB] = acc[q];
-        }
+        if (!panel_tile(a, k, k + 1 + ii, k + 1 + jj, S0, S1, S2, fb) && threadIdx.x == 0)
+          atomicOr(&fail_flag[r * nt + k + 1], 1u);
         __syncthreads();
       }
       if (!grid_barrier(a.sync, G)) return;
@@ -499,9 +568,30 @@ size_t chol_workspace_bytes(int n) {
   return c.used;
 }
 
+// Back substitution launch with the smallest instantiated column count per thread covering np.
+static int launch_backsub(const CholArgs& a, hipStream_t s) {
+  const int need = (a.np + kBackThreads - 1) / kBackThreads;
+#define DS3_BACKSUB(C, R)                                                             \
+  if (need <= C) {                                                                    \
+    hipLaunchKernelGGL((k_chol_backsub<C, R>), dim3(1), dim3(kBackThreads), 0, s, a); \
+    return check_hip(hipGetLastError(), "k_chol_backsub");                            \
+  }
+  DS3_BACKSUB(1, 32)
+  DS3_BACKSUB(2, 32)
+  DS3_BACKSUB(3, 32)
+  DS3_BACKSUB(4, 16)
+  DS3_BACKSUB(6, 8)
+  DS3_BACKSUB(8, 8)
+  DS3_BACKSUB(12, 4)
+  DS3_BACKSUB(16, 4)
+#undef DS3_BACKSUB
+  return fail(DS3_EINVAL, "chol: n too large");
+}
+
 int launch_chol_ladder(const double* H, const double* g, int n, double lambda, double eps0, double mult,
                        int attempts, double* tau, int32_t* status, void* ws, hipStream_t s) {
   if (n <= 0 || !H || !g || !tau || !status || !ws) return fail(DS3_EINVAL, "chol: bad arguments");
+  if (n > kMaxN) return fail(DS3_EINVAL, "chol: n above 8192");
   if (attempts < 1 || attempts > kMaxAttempts) return fail(DS3_EINVAL, "chol: attempts out of range");
   CholArgs a;
   chol_dims(n, a.nt, a.np);
@@ -525,8 +615,7 @@ int launch_chol_ladder(const double* H, const double* g, int n, double lambda, d
     hipLaunchKernelGGL(k_chol_panel, dim3(m * (m + 1) / 2), dim3(kCholThreads), 0, s, a, k);
     DS3_TRY(check_hip(hipGetLastError(), "k_chol_panel"));
   }
-  hipLaunchKernelGGL(k_chol_backsub, dim3(1), dim3(kBackThreads), 0, s, a);
-  DS3_TRY(check_hip(hipGetLastError(), "k_chol_backsub"));
+  DS3_TRY(launch_backsub(a, s));
   if (attempts > 1) {
     int G = (a.nt - 1) * a.nt / 2;
     if (G < 1) G = 1;

@@ -85,7 +85,8 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
   const float dx2 = fmaf(x.x, x.x, fmaf(x.y, x.y, x.z * x.z));
   if (!finite3(x.x, x.y, x.z) || !(dx2 > 1e-18f)) return -1;
   const float dx = sqrtf(dx2);
-  const float t0 = x.x / dx, t1 = x.y / dx, t2 = x.z / dx;
+  const float rdx = 1.0f / dx;
+  const float t0 = x.x * rdx, t1 = x.y * rdx, t2 = x.z * rdx;
   float u = (Wq > 1) ? float(qu) * (float(W - 1) / float(Wq - 1)) : 0.0f;
   float v = (Hq > 1) ? float(qv) * (float(H - 1) / float(Hq - 1)) : 0.0f;
   Sample S = sample_rays(R, H, W, u, v);
@@ -107,8 +108,9 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
       lam *= 10.0f;
       continue;
     }
-    const float du = -(D * gu - b * gv) / det;
-    const float dv = -(A * gv - b * gu) / det;
+    const float idet = __builtin_amdgcn_rcpf(det);  // hardware reciprocal (1 ulp)
+    const float du = -(D * gu - b * gv) * idet;
+    const float dv = -(A * gv - b * gu) * idet;
     const float un = fminf(fmaxf(u + du, 0.0f), float(W - 1));
     const float vn = fminf(fmaxf(v + dv, 0.0f), float(H - 1));
     if (un == u && vn == v) {  // no movement (clamped or vanishing step): same sample, same cost, reject

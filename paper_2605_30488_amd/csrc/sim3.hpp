@@ -95,11 +95,15 @@ __device__ __host__ inline Sim3 sim3_inv(const Sim3& A) {
 __device__ __host__ inline void exp_moments(double z, double* I) {
   if (fabs(z) <= 2.0) {
     // sum_n z^n / (n! (n + k + 1)); 40 terms reach double precision for |z| <= 2
+    // (fully unrolled so that every reciprocal below is a compile-time constant)
+#pragma unroll
     for (int k = 0; k <= 10; ++k) I[k] = 0.0;
     double term = 1.0;  // z^n / n!
+#pragma unroll
     for (int n = 0; n < 40; ++n) {
-      for (int k = 0; k <= 10; ++k) I[k] += term / double(n + k + 1);
-      term *= z / double(n + 1);
+#pragma unroll
+      for (int k = 0; k <= 10; ++k) I[k] = fma(term, 1.0 / double(n + k + 1), I[k]);
+      term *= z * (1.0 / double(n + 1));
     }
   } else {
     double ez = exp(z);
@@ -115,15 +119,18 @@ __device__ __host__ inline void sim3_V_coeffs(double zeta, double theta, double&
   const double rho2 = zeta * zeta + th2;
   if (rho2 < 0.05 * 0.05) {
     // double series, total degree n + 2m <= 12
+    // (fully unrolled: the factorial denominators fold into constant reciprocals)
     A = 0.0; B = 0.0; C = 0.0;
     double zn = 1.0, nfact = 1.0;
+#pragma unroll
     for (int n = 0; n <= 12; ++n) {
-      A += zn / (nfact * (n + 1));
+      A += zn * (1.0 / (nfact * (n + 1)));
       double tm = 1.0, f1 = 1.0, f2 = 2.0;  // theta^{2m}, (2m+1)!, (2m+2)!
       double sgn = 1.0;
+#pragma unroll
       for (int m = 0; n + 2 * m <= 12; ++m) {
-        B += sgn * zn * tm / (nfact * f1 * (n + 2 * m + 2));
-        C += sgn * zn * tm / (nfact * f2 * (n + 2 * m + 3));
+        B += zn * tm * (sgn / (nfact * f1 * (n + 2 * m + 2)));
+        C += zn * tm * (sgn / (nfact * f2 * (n + 2 * m + 3)));
         tm *= th2;
         f1 *= double(2 * m + 2) * double(2 * m + 3);
         f2 *= double(2 * m + 3) * double(2 * m + 4);
@@ -140,9 +147,10 @@ __device__ __host__ inline void sim3_V_coeffs(double zeta, double theta, double&
     exp_moments(zeta, I);
     B = 0.0; C = 0.0;
     double tm = 1.0, f1 = 1.0, f2 = 2.0, sgn = 1.0;
+#pragma unroll
     for (int m = 0; m <= 4; ++m) {
-      B += sgn * tm / f1 * I[2 * m + 1];
-      C += sgn * tm / f2 * I[2 * m + 2];
+      B += tm * (sgn / f1) * I[2 * m + 1];
+      C += tm * (sgn / f2) * I[2 * m + 2];
       tm *= th2;
       f1 *= double(2 * m + 2) * double(2 * m + 3);
       f2 *= double(2 * m + 3) * double(2 * m + 4);

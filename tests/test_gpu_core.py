@@ -98,7 +98,7 @@ def test_sim3_update(dev):
 # --------------------------------------------------------------------------------------------------
 # Cholesky ladder (eq. 7)
 # --------------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("n", [7, 14, 33, 140, 700])
+@pytest.mark.parametrize("n", [7, 14, 33, 140, 700, 1400, 2100])
 def test_chol_spd(dev, n):
     rng = np.random.default_rng(n)
     A = rng.normal(size=(n, n))
@@ -125,6 +125,35 @@ def test_chol_ladder_failures(dev):
     H = Q @ np.diag(ev) @ Q.T
     tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev))
     assert int(st.item()) == -1 and np.all(tau.cpu().numpy() == 0)
+
+
+def test_chol_ladder_fallback_many_tiles(dev):
+    """The ladder beyond attempt 0 with more tiles than fallback workgroups (22 tiles of 32)."""
+    rng = np.random.default_rng(17)
+    n = 700
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = np.linspace(1.0, 5.0, n)
+    ev[11] = -0.005
+    H = Q @ np.diag(ev) @ Q.T
+    g = rng.normal(size=n)
+    tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev))
+    ref, st_ref = O.chol_ladder(H, g)
+    assert int(st.item()) == st_ref == 2
+    assert np.allclose(tau.cpu().numpy(), ref, rtol=1e-8, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [3600, 5000])
+def test_chol_large_against_direct_solve(dev, n):
+    """Sizes whose back substitution keeps 8 and 12 columns per thread, against a direct dense solve
+    of the same regularised system (lambda = 0, eps = 1e-6)."""
+    rng = np.random.default_rng(n)
+    A = rng.normal(size=(n, n)) / np.sqrt(n)
+    H = A @ A.T + np.eye(n)
+    g = rng.normal(size=n)
+    tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev), lam=0.0)
+    ref = np.linalg.solve(H + 1e-6 * np.eye(n), -g)
+    assert int(st.item()) == 0
+    assert np.allclose(tau.cpu().numpy(), ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
 
 
 # --------------------------------------------------------------------------------------------------
