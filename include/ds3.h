@@ -123,20 +123,32 @@ int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const 
                     int32_t* idx_j2i, uint8_t* valid_j, float* nu, int32_t* admit, void* workspace,
                     size_t ws_bytes, void* stream);
 
+/* Kernel timer: two HIP events (timing enabled, created on the current device) that a library call
+ * records on its stream immediately before and after one kernel launch, so that the caller can read that
+ * kernel's duration without a profiler. Calls that would record it inside a stream capture fail with
+ * DS3_ENOTSUP. ds3_timer_elapsed_ms waits for the second event and returns the time between the last
+ * recorded pair in *ms (host); DS3_EINVAL if nothing was recorded yet. */
+typedef struct ds3_timer ds3_timer;
+int ds3_timer_create(ds3_timer** out);
+int ds3_timer_elapsed_ms(ds3_timer* timer, float* ms);
+int ds3_timer_destroy(ds3_timer* timer);
+
 /* Batched bidirectional matching of many edges in few launches.
  *   kf_arena (device) + kf (host, n_kf images): canonical pointmaps.
  *   cross_arena (device): per edge e two cross-view pointmaps, X^j_i (H_j*W_j px) at cross_off[2e] and
  *   X^i_j (H_i*W_i px) at cross_off[2e+1] (host int64 pixel offsets).
  *   edges (host): (i, j, idx_offset) per edge; outputs written at idx_offset of idx_arena (int32) and
  *   valid_arena (uint8); nu (device float32, 2 per edge), admit (device int32, 1 per edge);
- *   lm_steps (device uint64, may be NULL) receives the total number of LM trial steps taken.
+ *   lm_steps (device uint64, may be NULL) receives the total number of LM trial steps taken;
+ *   match_timer (may be NULL) is recorded around the one launch that runs every LM query.
  * Workspace from ds3_match_batch_workspace_bytes. */
 size_t ds3_match_batch_workspace_bytes(int32_t n_kf, const ds3_image* kf, int32_t n_edges,
                                        const ds3_edge* edges);
 int ds3_match_batch(const void* kf_arena, const ds3_image* kf, int32_t n_kf, const void* cross_arena,
                     const int64_t* cross_off, const ds3_edge* edges, int32_t n_edges, ds3_dtype dtype,
                     const ds3_match_params* params, int32_t* idx_arena, uint8_t* valid_arena, float* nu,
-                    int32_t* admit, uint64_t* lm_steps, void* workspace, size_t ws_bytes, void* stream);
+                    int32_t* admit, uint64_t* lm_steps, ds3_timer* match_timer, void* workspace,
+                    size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------------------
  * Gauge synchronisation (Sec. III-C)
@@ -230,6 +242,9 @@ typedef struct {
   int32_t autotune;        /* 1: time candidate tile shapes at creation */
   int32_t px_per_thread;   /* tile shape when not autotuning (0 = default) */
   int32_t use_graph;       /* 1: capture the iteration in a hipGraph (default), 0: direct launches */
+  ds3_timer* reduce_timer; /* may be NULL: recorded around the fused residual/Hessian launch of the last
+                              iteration of every ds3_gn_plan_run, which then runs as direct launches
+                              instead of a graph replay (same kernels, same results) */
 } ds3_plan_opts;
 
 int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena, ds3_dtype dtype,

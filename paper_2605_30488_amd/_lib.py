@@ -33,7 +33,8 @@ class GNParams(C.Structure):
 
 
 class PlanOpts(C.Structure):
-    _fields_ = [("autotune", C.c_int32), ("px_per_thread", C.c_int32), ("use_graph", C.c_int32)]
+    _fields_ = [("autotune", C.c_int32), ("px_per_thread", C.c_int32), ("use_graph", C.c_int32),
+                ("reduce_timer", C.c_void_p)]
 
 
 _lib = None
@@ -55,7 +56,10 @@ _SIGS = {
                                   vp, vp, vp, sz, vp]),
     "ds3_match_batch_workspace_bytes": (sz, [i32, P_img, i32, P_edge]),
     "ds3_match_batch": (C.c_int, [vp, P_img, i32, vp, P_i64, P_edge, i32, C.c_int,
-                                  C.POINTER(MatchParams), vp, vp, vp, vp, vp, vp, sz, vp]),
+                                  C.POINTER(MatchParams), vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+    "ds3_timer_create": (C.c_int, [C.POINTER(vp)]),
+    "ds3_timer_elapsed_ms": (C.c_int, [vp, C.POINTER(C.c_float)]),
+    "ds3_timer_destroy": (C.c_int, [vp]),
     "ds3_gauge_workspace_bytes": (sz, [i32]),
     "ds3_gauge_align": (C.c_int, [vp, Image, vp, Image, C.c_int, vp, vp, vp, i32, i32, i32, i32, vp, vp,
                                   vp, sz, vp]),

@@ -159,11 +159,12 @@ def match_bidir(X_ii, X_ji, X_jj, X_ij, hw_i, hw_j, dtype="f32", params=None):
 
 
 def match_batch(arena: Arena, cross: torch.Tensor, cross_off, edges, idx_offsets, idx_total, params=None,
-                idx_out=None, valid_out=None, ws=None, lm_steps=None):
+                idx_out=None, valid_out=None, ws=None, lm_steps=None, timer=None):
     """Batched bidirectional matching of every edge (ds3_match_batch). cross: xyzc arena of the
     cross-view pointmaps; cross_off[2e], cross_off[2e+1] their pixel offsets (X^j_i, X^i_j).
     Returns (idx arena int32, valid arena uint8, nu (E, 2) float32, admit (E,) int32); lm_steps, a
-    device int64 tensor of one element, receives the number of LM trial steps when given."""
+    device int64 tensor of one element, receives the number of LM trial steps when given; timer (a
+    KernelTimer) is recorded around the launch that runs the LM queries."""
     _need_cuda(arena.data, cross)
     P = params or default_match_params()
     dev = arena.data.device
@@ -179,8 +180,8 @@ def match_batch(arena: Arena, cross: torch.Tensor, cross_off, edges, idx_offsets
     if ws is None or ws.numel() < nb:
         ws = _ws(nb, dev)
     call("ds3_match_batch", _ptr(arena.data), kf, len(arena.images), _ptr(cross), off, et, ne,
-         _dt(arena.dtype), C.byref(P), _ptr(idx), _ptr(valid), _ptr(nu), _ptr(admit), _ptr(lm_steps), _ptr(ws),
-         ws.numel(), _stream())
+         _dt(arena.dtype), C.byref(P), _ptr(idx), _ptr(valid), _ptr(nu), _ptr(admit), _ptr(lm_steps),
+         timer.handle if timer is not None else None, _ptr(ws), ws.numel(), _stream())
     return idx, valid, nu, admit
 
 
@@ -330,15 +331,45 @@ def chol_ladder_solve(H, g, lam=0.0, eps0=1e-6, mult=100.0, attempts=6):
     return tau, st
 
 
+class KernelTimer:
+    """ds3_timer: HIP events that a library call records around one kernel launch on its stream."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        call("ds3_timer_create", C.byref(h))
+        self.handle = h
+
+    def ms(self) -> float:
+        """Duration of the last recorded launch (waits for it)."""
+        v = C.c_float()
+        call("ds3_timer_elapsed_ms", self.handle, C.byref(v))
+        return v.value
+
+    def close(self):
+        if self.handle:
+            L.load().ds3_timer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class GNPlan:
     """Batched form (ds3_gn_plan_*): one persistent residual launch per iteration, captured with the
-    rest of the iteration in a hipGraph. Binds to `poses`, which every run updates in place."""
+    rest of the iteration in a hipGraph. Binds to `poses`, which every run updates in place.
+    reduce_timer (a KernelTimer, kept alive by the plan) is recorded around the residual launch."""
 
-    def __init__(self, graph: Graph, poses, params=None, autotune=False, px_per_thread=0, use_graph=True):
+    def __init__(self, graph: Graph, poses, params=None, autotune=False, px_per_thread=0, use_graph=True,
+                 reduce_timer=None):
         self.graph = graph
         self.poses = poses
+        self.reduce_timer = reduce_timer
         P = params or default_gn_params()
-        opts = L.PlanOpts(int(autotune), int(px_per_thread), int(use_graph))
+        opts = L.PlanOpts(int(autotune), int(px_per_thread), int(use_graph),
+                          reduce_timer.handle if reduce_timer is not None else None)
         h = C.c_void_p()
         call("ds3_gn_plan_create", graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
              len(graph.edges), _ptr(graph.idx), C.byref(P), graph.an, len(graph.anchors), C.byref(opts),

@@ -455,6 +455,7 @@ struct Plan {
   unsigned* time_ctrs = nullptr;
   int64_t px_scanned = 0, px_valid = 0;
   bool use_graph = true;
+  ds3_timer* timer = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -469,10 +470,13 @@ __global__ void k_record(const double* cost, const int32_t* status, unsigned* ct
   *ctr = k + 1;
 }
 
-static int plan_iteration(Plan& P, hipStream_t s) {
+// One GN iteration; `timed` records the plan's timer around the residual launch (never inside a capture).
+static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
   DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, P.B.counter, s));
+  if (timed) DS3_TRY(timer_record(P.timer, true, s));
   DS3_TRY(launch_edge_reduce_batched(P.dt, P.ppt, P.grid, P.arena, P.B.edges, P.items, P.n_items, P.B.xf,
                                      P.idx, P.B.partials, P.B.counter, P.c, s));
+  if (timed) DS3_TRY(timer_record(P.timer, false, s));
   DS3_TRY(launch_edge_finalize(P.B.edges, P.T.n_edges, P.B.partials, P.B.Ad, P.B.A_e, P.B.b_e, P.B.cost_e,
                                P.B.count_e, s));
   const size_t n = 7 * size_t(P.T.n_kf);
@@ -644,9 +648,51 @@ static void plan_free(Plan* P) {
   delete P;
 }
 
+int timer_record(ds3_timer* t, bool begin, hipStream_t s) {
+  if (!t) return DS3_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  DS3_TRY_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(DS3_ENOTSUP, "timer: not recordable inside a capture");
+  DS3_TRY_HIP(hipEventRecord(t->ev[begin ? 0 : 1], s));
+  if (!begin) t->recorded = true;
+  return DS3_OK;
+}
+
 }  // namespace ds3
 
 extern "C" {
+
+int ds3_timer_create(ds3_timer** out) {
+  if (!out) return fail(DS3_EINVAL, "timer: out is null");
+  *out = nullptr;
+  ds3_timer* t = new ds3_timer();
+  for (int k = 0; k < 2; ++k) {
+    const int rc = check_hip(hipEventCreate(&t->ev[k]), "hipEventCreate");
+    if (rc != DS3_OK) {
+      if (k == 1) (void)hipEventDestroy(t->ev[0]);
+      delete t;
+      return rc;
+    }
+  }
+  *out = t;
+  return DS3_OK;
+}
+
+int ds3_timer_elapsed_ms(ds3_timer* t, float* ms) {
+  if (!t || !ms) return fail(DS3_EINVAL, "timer: bad arguments");
+  if (!t->recorded) return fail(DS3_EINVAL, "timer: nothing recorded yet");
+  DS3_TRY_HIP(hipEventSynchronize(t->ev[1]));
+  DS3_TRY_HIP(hipEventElapsedTime(ms, t->ev[0], t->ev[1]));
+  return DS3_OK;
+}
+
+int ds3_timer_destroy(ds3_timer* t) {
+  if (!t) return DS3_OK;
+  (void)hipEventDestroy(t->ev[0]);
+  (void)hipEventDestroy(t->ev[1]);
+  delete t;
+  return DS3_OK;
+}
 
 int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3_dtype dtype,
                        const ds3_edge* edges, int32_t n_edges, const int32_t* idx,
@@ -677,6 +723,7 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
   P->p = *params;
   P->c = make_gn_const(*params);
   P->use_graph = !opts || opts->use_graph != 0;
+  P->timer = opts ? opts->reduce_timer : nullptr;
   rc = upload_topology(P->T, P->B, s);
   if (rc == DS3_OK) rc = launch_fill_u32(P->B.counter, 64, 0u, s);
   if (rc == DS3_OK) rc = launch_fill_u32(P->hist_ctr, 4, 0u, s);
@@ -700,7 +747,7 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
     if (rc == DS3_OK) {
       rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
       if (rc == DS3_OK) {
-        int rc2 = plan_iteration(*P, cs);
+        int rc2 = plan_iteration(*P, cs, false);
         hipGraph_t g = nullptr;
         int rc3 = check_hip(hipStreamEndCapture(cs, &g), "hipStreamEndCapture");
         rc = rc2 != DS3_OK ? rc2 : rc3;
@@ -723,10 +770,13 @@ int ds3_gn_plan_run(void* plan, int32_t iters, double* cost_per_iter, int32_t* s
   hipStream_t s = S(stream);
   DS3_TRY(launch_fill_u32(P->hist_ctr, 1, 0u, s));
   for (int it = 0; it < iters; ++it) {
-    if (P->use_graph) {
+    // with a timer, the last iteration runs as direct launches so that the events bracket its residual
+    // launch (event records are not captured into the graph)
+    const bool timed = P->timer && it == iters - 1;
+    if (P->use_graph && !timed) {
       DS3_TRY_HIP(hipGraphLaunch(P->exec, s));
     } else {
-      DS3_TRY(plan_iteration(*P, s));
+      DS3_TRY(plan_iteration(*P, s, timed));
     }
   }
   if (iters > 0 && cost_per_iter)

@@ -143,7 +143,7 @@ struct EdgeSpec {
 
 static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dtype dt, const MatchConst& C,
                      double nu_min, MatchWs& W, int32_t* idx_out, uint8_t* valid_out, float* nu,
-                     int32_t* admit, uint64_t* lm_steps, hipStream_t s) {
+                     int32_t* admit, uint64_t* lm_steps, ds3_timer* timer, hipStream_t s) {
   const int ne = int(es.size());
   std::vector<MatchDir> dirs;
   std::vector<int32_t> dtiles;
@@ -186,8 +186,10 @@ static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dty
   DS3_TRY(upload(W.npx, npx, s));
   DS3_TRY(launch_fill_u32(W.counts, 2 * size_t(ne), 0u, s));
   if (lm_steps) DS3_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(lm_steps), 2, 0u, s));
+  DS3_TRY(timer_record(timer, true, s));
   DS3_TRY(launch_match_batched(W.rays, cross, dt, W.dirs, as_map(W.map_m), grid_m, C, W.idx_tmp,
                                reinterpret_cast<unsigned long long*>(lm_steps), s));
+  DS3_TRY(timer_record(timer, false, s));
   DS3_TRY(launch_mutual(W.md, as_map(W.map_u), grid_u, dt, C, W.idx_tmp, idx_out, valid_out, W.counts, s));
   return launch_nu_finalize(W.counts, W.npx, ne, nu_min, nu, admit, s);
 }
@@ -311,7 +313,8 @@ size_t ds3_match_batch_workspace_bytes(int32_t n_kf, const ds3_image* kf, int32_
 int ds3_match_batch(const void* kf_arena, const ds3_image* kf, int32_t n_kf, const void* cross_arena,
                     const int64_t* cross_off, const ds3_edge* edges, int32_t n_edges, ds3_dtype dtype,
                     const ds3_match_params* params, int32_t* idx_arena, uint8_t* valid_arena, float* nu,
-                    int32_t* admit, uint64_t* lm_steps, void* workspace, size_t ws_bytes, void* stream) {
+                    int32_t* admit, uint64_t* lm_steps, ds3_timer* match_timer, void* workspace,
+                    size_t ws_bytes, void* stream) {
   if (!kf_arena || !kf || !cross_arena || !cross_off || !edges || !idx_arena || !valid_arena || !workspace)
     return fail(DS3_EINVAL, "match_batch: null pointer");
   if (n_kf <= 0 || n_edges <= 0) return fail(DS3_EINVAL, "match_batch: empty graph");
@@ -351,7 +354,7 @@ int ds3_match_batch(const void* kf_arena, const ds3_image* kf, int32_t n_kf, con
   carve_match(workspace, ray_px, tmp, 2 * n_edges, 2 * n_edges, n_edges, W);
   DS3_TRY(launch_raymap(kf_arena, ray_px, dtype, W.rays, s));
   return run_match(es, cross_arena, dtype, make_match_const(*params), params->nu_min, W, idx_arena,
-                   valid_arena, nu, admit, lm_steps, s);
+                   valid_arena, nu, admit, lm_steps, match_timer, s);
 }
 
 // ---- gauge -------------------------------------------------------------------------------------------

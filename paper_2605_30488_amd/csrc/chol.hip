@@ -9,8 +9,8 @@
 //             (and L_jk) from the stored inverse, updates A_ij -= L_ik L_jk^T, stores L_ik and carries
 //             the forward substitution when j = k+1, and the owner of (k+1, k+1) factors it right away;
 //   backsub   one workgroup solves L^T x = y, streaming the factor row block by row block.
-// A diagonal factorisation produces L_kk, its inverse and y_k = L_kk^-1 b_k together: the inverse is
-// accumulated by the same rank-one column updates that form L, with one barrier per column.
+// A diagonal factorisation produces the inverse of L_kk and y_k = L_kk^-1 b_k: the inverse is accumulated
+// by the same column updates that form L, two columns per barrier; L_kk itself is never stored.
 // Attempt 0 runs this way; only when it fails does a persistent fallback kernel run attempts 1.. with its
 // own bounded grid barriers (the common case never pays for the ladder).
 //
@@ -101,21 +101,25 @@ __device__ inline double recip(double d) {
 
 __device__ inline bool pivot_ok(double d) { return (d > 0.0) && isfinite(d); }
 
-// Cholesky of the SPD tile held as a fragment (lower triangle used), together with its inverse, two
-// columns per barrier. Columns c, c+1 of T and rows c, c+1 of the inverse accumulator X (identity at
-// the start) are published in LDS before the pair; every thread then forms the 2x2 pivot block
+// Cholesky of the SPD tile held as a fragment (lower triangle used), producing the inverse of its
+// factor, two columns per barrier. Columns c, c+1 of T and rows c, c+1 of the inverse accumulator X
+// (identity at the start) are published in LDS before the pair; every thread then forms the 2x2 pivot
+// block
 //   d0 = T[c][c],  t = T[c+1][c],  d1 = T[c+1][c+1] - t^2 / d0,
 // the step-c value of column c+1 (b' = T[.][c+1] - T[.][c] t / d0) and of row c+1 of X, and applies
 //   T[r][s] -= T[r][c] T[s][c] / d0 + b'_r b'_s / d1                     (c+1 < s <= r),
 //   X[r][j] -= T[r][c] X[c][j] / d0 + b'_r X'[c+1][j] / d1               (r > c+1),
-// with row c+1 of X taking only the first term. At the end L[r][s] = T[r][s] / sqrt(d_s) and
-// L^-1[r][j] = X[r][j] / sqrt(d_r). Returns false (uniformly) on a non-positive or non-finite pivot.
-__device__ bool factor_frag(f64x4& T, double* fb, f64x4& Lq, f64x4& Xq) {
+// with row c+1 of X taking only the first term. At the end L^-1[r][j] = X[r][j] / sqrt(d_r) (the factor
+// itself, T[r][s] / sqrt(d_s), is not needed). Returns false (uniformly) on a non-positive or
+// non-finite pivot.
+__device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
   const int s = fcol();
-  f64x4 X;
-  double dc = 1.0, dr[4] = {1.0, 1.0, 1.0, 1.0};
+  double T[4], X[4], dr[4] = {1.0, 1.0, 1.0, 1.0};
 #pragma unroll
-  for (int v = 0; v < 4; ++v) X[v] = (frow(v) == s) ? 1.0 : 0.0;
+  for (int v = 0; v < 4; ++v) {
+    T[v] = Tf[v];
+    X[v] = (frow(v) == s) ? 1.0 : 0.0;
+  }
   // publish columns 0, 1 and rows 0, 1 into buffer 0: fb[par * 4 NB + {0: col c, 1: col c+1, 2: row c,
   // 3: row c+1} * NB]
   if (s < 2)
@@ -131,28 +135,26 @@ __device__ bool factor_frag(f64x4& T, double* fb, f64x4& Lq, f64x4& Xq) {
     const double t10 = P[c + 1];
     if (!pivot_ok(d0)) return false;  // every thread read the same pivots
     const double i0 = recip(d0);
-    const double d1 = fma(-t10 * i0, t10, P[NB + c + 1]);
+    const double g = t10 * i0;
+    const double d1 = fma(-g, t10, P[NB + c + 1]);
     if (!pivot_ok(d1)) return false;
     const double i1 = recip(d1);
-    const double g = t10 * i0;
     const double as = P[s], bs = fma(-as, g, P[NB + s]);
     const double x0s = P[2 * NB + s], x1s = fma(-g, x0s, P[3 * NB + s]);
-    if (s == c) dc = d0;
-    if (s == c + 1) dc = d1;
+    // branch-free update of the four rows: T below the pair, column c+1 set to its step-c value, X
+    const bool s_trail = s > c + 1;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = frow(v);
       const double av = P[r];
       const double bv = fma(-av, g, P[NB + r]);
-      if (r == c) dr[v] = d0;
-      if (r == c + 1) dr[v] = d1;
-      if (r > c + 1) {
-        if (s > c + 1 && s <= r) T[v] -= fma(av * i0, as, bv * i1 * bs);
-        X[v] -= fma(av * i0, x0s, bv * i1 * x1s);
-      } else if (r == c + 1) {
-        X[v] -= av * i0 * x0s;
-      }
-      if (s == c + 1 && r >= c + 1) T[v] = bv;
+      const double f0 = av * i0, f1 = bv * i1;
+      dr[v] = (r == c) ? d0 : ((r == c + 1) ? d1 : dr[v]);
+      const double t_upd = fma(-f0, as, fma(-f1, bs, T[v]));
+      const double x_two = fma(-f0, x0s, fma(-f1, x1s, X[v]));
+      const double x_one = fma(-f0, x0s, X[v]);
+      T[v] = (s_trail && s <= r) ? t_upd : ((s == c + 1 && r > c) ? bv : T[v]);
+      X[v] = (r > c + 1) ? x_two : ((r == c + 1) ? x_one : X[v]);
     }
     if (c + 2 < NB) {
       double* Q = fb + (((c >> 1) + 1) & 1) * 4 * NB;
@@ -165,32 +167,26 @@ __device__ bool factor_frag(f64x4& T, double* fb, f64x4& Lq, f64x4& Xq) {
     }
     __syncthreads();
   }
-  const double rsc = 1.0 / sqrt(dc);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const bool low = s <= frow(v);
-    Lq[v] = low ? T[v] * rsc : 0.0;
-    Xq[v] = low ? X[v] / sqrt(dr[v]) : 0.0;
-  }
+  for (int v = 0; v < 4; ++v) Xq[v] = (s <= frow(v)) ? X[v] / sqrt(dr[v]) : 0.0;
   return true;
 }
 
-// Stores L_ii and its inverse, and y_i = L_ii^-1 b_i (b_i in LDS sb). S: a free LDS tile.
-__device__ void store_diag(const CholArgs& a, int i, const f64x4& Lq, const f64x4& Xq, double* S,
-                           const double* sb) {
-  frag_store(Lq, a.L + int64_t(i) * NB * a.np + i * NB, a.np);
+// Stores the inverse of the diagonal factor and y_i = L_ii^-1 b_i (b_i in LDS sb). S: a free LDS tile.
+// (The diagonal factor itself is not needed afterwards: the panels and both substitutions use its
+// inverse.) The product runs on 8 threads per row, reduced with lane shuffles.
+__device__ void store_diag(const CholArgs& a, int i, const f64x4& Xq, double* S, const double* sb) {
   frag_store(Xq, a.Inv + int64_t(i) * NB * NB, NB);
   frag_to_lds(Xq, S);
   __syncthreads();
-  if (threadIdx.x < NB) {
-    const int r = threadIdx.x;
-    double s0 = 0.0, s1 = 0.0;
-    for (int t = 0; t <= r; t += 2) {
-      s0 = fma(S[r * LDT + t], sb[t], s0);
-      if (t + 1 <= r) s1 = fma(S[r * LDT + t + 1], sb[t + 1], s1);
-    }
-    a.y[i * NB + r] = s0 + s1;
-  }
+  const int r = threadIdx.x >> 3, p = threadIdx.x & 7;
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB / 8; ++q) acc = fma(S[r * LDT + p + 8 * q], sb[p + 8 * q], acc);
+  acc += __shfl_xor(acc, 1, 8);
+  acc += __shfl_xor(acc, 2, 8);
+  acc += __shfl_xor(acc, 4, 8);
+  if (p == 0) a.y[i * NB + r] = acc;
 }
 
 // Regularised lower tile (i, j) of H as a fragment; identity on padding, zero above the diagonal.
@@ -227,9 +223,9 @@ __device__ bool init_tile(const CholArgs& a, int i, int j, double eps, double* S
     return true;
   }
   __syncthreads();
-  f64x4 Lq, Xq;
-  if (!factor_frag(q, fb, Lq, Xq)) return false;
-  store_diag(a, 0, Lq, Xq, S, sb);
+  f64x4 Xq;
+  if (!factor_frag(q, fb, Xq)) return false;
+  store_diag(a, 0, Xq, S, sb);
   return true;
 }
 
@@ -240,6 +236,9 @@ __device__ bool panel_tile(const CholArgs& a, int k, int i, int j, double* S0, d
   const int np = a.np;
   const bool offd = (j != i);
   const bool col = (j == k + 1);  // this workgroup stores L_ik and eliminates b_i
+  // the next diagonal tile is on the critical path of the whole factorisation: its waves get issue
+  // priority over the other workgroups sharing their compute unit
+  if (i == j && i == k + 1) __builtin_amdgcn_s_setprio(3);
   f64x4 qinv, qi, qj, qa;
   frag_load(qinv, a.Inv + int64_t(k) * NB * NB, NB);
   frag_load(qi, a.Wm + int64_t(i) * NB * np + k * NB, np);
@@ -282,9 +281,9 @@ __device__ bool panel_tile(const CholArgs& a, int k, int i, int j, double* S0, d
   }
   if (i == j && i == k + 1) {
     __syncthreads();
-    f64x4 Lq, Xq;
-    if (!factor_frag(qa, fb, Lq, Xq)) return false;
-    store_diag(a, i, Lq, Xq, S0, sb);
+    f64x4 Xq;
+    if (!factor_frag(qa, fb, Xq)) return false;
+    store_diag(a, i, Xq, S0, sb);
     return true;
   }
   frag_store(qa, a.Wm + int64_t(i) * NB * np + j * NB, np);
@@ -327,8 +326,9 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_panel(CholArgs a, int k) 
 
 // Back substitution L^T x = y by one workgroup, right-looking: for block k (last first)
 //   x_k = Inv_k^T (y_k - acc_k),  then acc_j += sum_r L[32k + r][j] x_k[r] for every column j < 32k,
-// where thread t keeps acc for columns t + 512 m in registers. The first RC rows of block k are loaded
-// before x_k is solved, and Inv_{k-1} one block ahead, so that the loads overlap the solve.
+// where thread t keeps acc for columns t + 512 m in registers. y sits in LDS; the first RC rows of block
+// k are loaded before x_k is solved and Inv_{k-1} one block ahead, so that the solve never waits for
+// global memory.
 template <int CPT, int RC>
 __global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
   if (a.sync[3] != 0u) {  // attempt 0 failed: the fallback takes over, or gives up with one attempt
@@ -339,11 +339,13 @@ __global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
     return;
   }
   constexpr int kInvPer = NB * NB / kBackThreads;
+  extern __shared__ double sy[];  // np
   __shared__ double sinv[NB * NB];
   __shared__ double rhs[NB];
   __shared__ double xs[NB];
   const int t = threadIdx.x;
   const int64_t np = a.np;
+  for (int e = t; e < a.np; e += kBackThreads) sy[e] = a.y[e];
   double acc[CPT];
 #pragma unroll
   for (int m = 0; m < CPT; ++m) acc[m] = 0.0;
@@ -352,6 +354,8 @@ __global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
   for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(a.nt - 1) * NB * NB + t + e * kBackThreads];
   for (int k = a.nt - 1; k >= 0; --k) {
     const int c0 = k * NB;
+#pragma unroll
+    for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBackThreads] = inv[e];
     double buf[RC][CPT];
 #pragma unroll
     for (int r = 0; r < RC; ++r)
@@ -360,25 +364,31 @@ __global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
         const int j = t + kBackThreads * m;
         buf[r][m] = (j < c0) ? a.L[(c0 + r) * np + j] : 0.0;
       }
-#pragma unroll
-    for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBackThreads] = inv[e];
     if (k > 0)
 #pragma unroll
       for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(k - 1) * NB * NB + t + e * kBackThreads];
+    __syncthreads();  // sy (first block) and sinv written
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       const int j = t + kBackThreads * m;
-      if (j >= c0 && j < c0 + NB) rhs[j - c0] = a.y[j] - acc[m];
+      if (j >= c0 && j < c0 + NB) rhs[j - c0] = sy[j] - acc[m];
     }
     __syncthreads();
-    if (t < NB) {
-      double s0 = 0.0, s1 = 0.0;
-      for (int u = t; u < NB; u += 2) {
-        s0 = fma(sinv[u * NB + t], rhs[u], s0);
-        if (u + 1 < NB) s1 = fma(sinv[(u + 1) * NB + t], rhs[u + 1], s1);
+    if (t < 8 * NB) {  // x_k[c] = sum_{u >= c} Inv_k[u][c] rhs[u], eight threads per c
+      const int c = t >> 3, p = t & 7;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NB / 8; ++q) {
+        const int u = p + 8 * q;
+        v = fma(sinv[u * NB + c], rhs[u], v);  // Inv_k is zero above its diagonal
       }
-      xs[t] = s0 + s1;
-      if (c0 + t < a.n) a.tau[c0 + t] = s0 + s1;
+      v += __shfl_xor(v, 1, 8);
+      v += __shfl_xor(v, 2, 8);
+      v += __shfl_xor(v, 4, 8);
+      if (p == 0) {
+        xs[c] = v;
+        if (c0 + c < a.n) a.tau[c0 + c] = v;
+      }
     }
     __syncthreads();
 #pragma unroll 1
@@ -571,10 +581,14 @@ size_t chol_workspace_bytes(int n) {
 // Back substitution launch with the smallest instantiated column count per thread covering np.
 static int launch_backsub(const CholArgs& a, hipStream_t s) {
   const int need = (a.np + kBackThreads - 1) / kBackThreads;
-#define DS3_BACKSUB(C, R)                                                             \
-  if (need <= C) {                                                                    \
-    hipLaunchKernelGGL((k_chol_backsub<C, R>), dim3(1), dim3(kBackThreads), 0, s, a); \
-    return check_hip(hipGetLastError(), "k_chol_backsub");                            \
+  const size_t lds = size_t(a.np) * sizeof(double);  // y
+#define DS3_BACKSUB(C, R)                                                                          \
+  if (need <= C) {                                                                                 \
+    if (lds > 48 * 1024)                                                                           \
+      DS3_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backsub<C, R>),        \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));      \
+    hipLaunchKernelGGL((k_chol_backsub<C, R>), dim3(1), dim3(kBackThreads), lds, s, a);            \
+    return check_hip(hipGetLastError(), "k_chol_backsub");                                         \
   }
   DS3_BACKSUB(1, 32)
   DS3_BACKSUB(2, 32)

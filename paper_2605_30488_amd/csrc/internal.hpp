@@ -9,6 +9,11 @@
 
 #include "../../include/ds3.h"
 
+struct ds3_timer {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool recorded = false;
+};
+
 namespace ds3 {
 
 // ---- error state -----------------------------------------------------------------------------------
@@ -27,6 +32,10 @@ int check_hip(hipError_t e, const char* what);
   } while (0)
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Records the begin (or end) event of a kernel timer on s; inside a stream capture the record becomes an
+// event node of the graph. A null timer records nothing.
+int timer_record(ds3_timer* t, bool begin, hipStream_t s);
 
 // Carves aligned sub-buffers out of one workspace block (or only measures when base == nullptr).
 struct Carver {

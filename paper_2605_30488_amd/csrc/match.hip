@@ -100,47 +100,48 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
   float dd = fmaf(S.sv[0], S.sv[0], fmaf(S.sv[1], S.sv[1], S.sv[2] * S.sv[2]));
   float gu = fmaf(S.su[0], r0, fmaf(S.su[1], r1, S.su[2] * r2));
   float gv = fmaf(S.sv[0], r0, fmaf(S.sv[1], r1, S.sv[2] * r2));
+  // The trial loop is written with selects rather than branches so that a wave's divergent lanes cost
+  // few exec-mask instructions: every active lane samples once per trial (at the current point when the
+  // step does not move), and lanes leave through `active`.
   int it = 0;
+  bool active = true, hole = false;
   for (; it < P.max_iters; ++it) {
+    if (!active) break;
     const float A = a * (1.0f + lam), D = dd * (1.0f + lam);
     const float det = A * D - b * b;
-    if (!(det > 0.0f)) {
-      lam *= 10.0f;
-      continue;
-    }
+    const bool det_ok = det > 0.0f;
     const float idet = __builtin_amdgcn_rcpf(det);  // hardware reciprocal (1 ulp)
     const float du = -(D * gu - b * gv) * idet;
     const float dv = -(A * gv - b * gu) * idet;
-    const float un = fminf(fmaxf(u + du, 0.0f), float(W - 1));
-    const float vn = fminf(fmaxf(v + dv, 0.0f), float(H - 1));
-    if (un == u && vn == v) {  // no movement (clamped or vanishing step): same sample, same cost, reject
-      lam *= 10.0f;
-      continue;
-    }
-    Sample Sn = sample_rays(R, H, W, un, vn);
-    if (Sn.hole) {
-      *iters = it + 1;
-      return -1;
+    const float un = det_ok ? fminf(fmaxf(u + du, 0.0f), float(W - 1)) : u;
+    const float vn = det_ok ? fminf(fmaxf(v + dv, 0.0f), float(H - 1)) : v;
+    // no movement (singular system, clamped or vanishing step): same sample, same cost, reject
+    const bool moved = (un != u) || (vn != v);
+    const Sample Sn = sample_rays(R, H, W, un, vn);
+    if (moved && Sn.hole) {
+      hole = true;
+      active = false;
+      continue;  // `it` advances past this trial
     }
     const float n0 = Sn.s[0] - t0, n1 = Sn.s[1] - t1, n2 = Sn.s[2] - t2;
     const float cn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
-    if (cn < c) {
-      const float step = fmaxf(fabsf(un - u), fabsf(vn - v));
+    const bool acc = moved && (cn < c);
+    const float step = fmaxf(fabsf(un - u), fabsf(vn - v));
+    lam = acc ? fmaxf(lam * 0.1f, P.lambda_min) : lam * 10.0f;
+    if (acc) {
       u = un; v = vn; S = Sn; c = cn;
       r0 = n0; r1 = n1; r2 = n2;
-      lam = fmaxf(lam * 0.1f, P.lambda_min);
-      if (step < P.step_tol) {
-        ++it;
-        break;
-      }
       a = fmaf(S.su[0], S.su[0], fmaf(S.su[1], S.su[1], S.su[2] * S.su[2]));
       b = fmaf(S.su[0], S.sv[0], fmaf(S.su[1], S.sv[1], S.su[2] * S.sv[2]));
       dd = fmaf(S.sv[0], S.sv[0], fmaf(S.sv[1], S.sv[1], S.sv[2] * S.sv[2]));
       gu = fmaf(S.su[0], r0, fmaf(S.su[1], r1, S.su[2] * r2));
       gv = fmaf(S.sv[0], r0, fmaf(S.sv[1], r1, S.sv[2] * r2));
-    } else {
-      lam *= 10.0f;
+      if (step < P.step_tol) active = false;  // converged: `it` advances past this trial
     }
+  }
+  if (hole) {
+    *iters = it;
+    return -1;
   }
   *iters = it;
   *pu = u;
