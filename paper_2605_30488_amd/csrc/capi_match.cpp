@@ -114,6 +114,7 @@ struct MatchWs {
   ItemMapBufs map_m, map_u;
   unsigned* counts;
   int64_t* npx;
+  unsigned* step_stripes;
 };
 
 static size_t carve_match(void* base, int64_t ray_px, int64_t tmp_idx, int n_dirs, int n_sides, int n_edges,
@@ -127,6 +128,7 @@ static size_t carve_match(void* base, int64_t ray_px, int64_t tmp_idx, int n_dir
   carve_map(c, n_sides, W.map_u);
   W.counts = c.take<unsigned>(2 * size_t(std::max(n_edges, 1)));
   W.npx = c.take<int64_t>(2 * size_t(std::max(n_edges, 1)));
+  W.step_stripes = c.take<unsigned>(size_t(kStepStripes) * kStripeStride);
   return c.used;
 }
 
@@ -185,11 +187,12 @@ static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dty
   DS3_TRY(upload(W.map_u.bin_tiles, bt2, s));
   DS3_TRY(upload(W.npx, npx, s));
   DS3_TRY(launch_fill_u32(W.counts, 2 * size_t(ne), 0u, s));
-  if (lm_steps) DS3_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(lm_steps), 2, 0u, s));
+  unsigned* stripes = lm_steps ? W.step_stripes : nullptr;
+  if (stripes) DS3_TRY(launch_fill_u32(stripes, size_t(kStepStripes) * kStripeStride, 0u, s));
   DS3_TRY(timer_record(timer, true, s));
-  DS3_TRY(launch_match_batched(W.rays, cross, dt, W.dirs, as_map(W.map_m), grid_m, C, W.idx_tmp,
-                               reinterpret_cast<unsigned long long*>(lm_steps), s));
+  DS3_TRY(launch_match_batched(W.rays, cross, dt, W.dirs, as_map(W.map_m), grid_m, C, W.idx_tmp, stripes, s));
   DS3_TRY(timer_record(timer, false, s));
+  if (stripes) DS3_TRY(launch_sum_stripes(stripes, reinterpret_cast<unsigned long long*>(lm_steps), s));
   DS3_TRY(launch_mutual(W.md, as_map(W.map_u), grid_u, dt, C, W.idx_tmp, idx_out, valid_out, W.counts, s));
   return launch_nu_finalize(W.counts, W.npx, ne, nu_min, nu, admit, s);
 }

@@ -8,9 +8,10 @@
 //   panel k   every workgroup owns one trailing tile (i, j), k < j <= i: it forms L_ik = A_ik L_kk^-T
 //             (and L_jk) from the stored inverse, updates A_ij -= L_ik L_jk^T, stores L_ik and carries
 //             the forward substitution when j = k+1, and the owner of (k+1, k+1) factors it right away;
-//   backsub   one workgroup solves L^T x = y, streaming the factor row block by row block.
+//   backsub   ceil(nt / 8) workgroups solve L^T x = y, each owning eight diagonal blocks and passing
+//             the solved blocks down through flags.
 // A diagonal factorisation produces the inverse of L_kk and y_k = L_kk^-1 b_k: the inverse is accumulated
-// by the same column updates that form L, two columns per barrier; L_kk itself is never stored.
+// by the same column updates that form L, four columns per barrier; L_kk itself is never stored.
 // Attempt 0 runs this way; only when it fails does a persistent fallback kernel run attempts 1.. with its
 // own bounded grid barriers (the common case never pays for the ladder).
 //
@@ -25,8 +26,7 @@ constexpr int LDT = NB + 4;
 constexpr int kCholThreads = 256;
 constexpr long kSpinLimit = 1L << 24;
 constexpr int kMaxAttempts = 16;
-constexpr int kBackThreads = 512;
-constexpr int kMaxN = 8192;  // back substitution keeps at most 16 columns per thread
+constexpr int kMaxN = 8192;
 
 struct CholArgs {
   const double* H;
@@ -44,11 +44,16 @@ struct CholArgs {
   double* x;    // np: solution blocks (fallback back substitution)
   unsigned* sync;  // [0] barrier count, [1] generation, [2] error, [3] attempt-0 failed,
                    // [4 .. 4 + attempts*nt) failure of diagonal tile s in attempt r, then nt ready flags
+                   // of the fallback; from 4 + 17 nt the nt ready flags of the back substitution
 };
 
-// LDS scratch of one diagonal factorisation: double-buffered pairs of published columns of T and rows
-// of X (8 x 32), then the block of b (32).
-constexpr int kFactorScratch = 9 * NB;
+// Ready flags of the back substitution's blocks, after the fallback's flags.
+__device__ inline unsigned* bs_ready(const CholArgs& a) { return a.sync + 4 + (kMaxAttempts + 1) * a.nt; }
+
+// Columns per barrier of the diagonal factorisation, and its LDS scratch: double-buffered groups of kFw
+// published columns of T and kFw rows of X, then the block of b.
+constexpr int kFw = 4;
+constexpr int kFactorScratch = 4 * kFw * NB + NB;
 
 // ---------------------------------------------------------------------------------------------------
 // Fragment helpers. The 256 threads hold a 32x32 tile in the accumulator layout of the float64 MFMA
@@ -102,16 +107,17 @@ __device__ inline double recip(double d) {
 __device__ inline bool pivot_ok(double d) { return (d > 0.0) && isfinite(d); }
 
 // Cholesky of the SPD tile held as a fragment (lower triangle used), producing the inverse of its
-// factor, two columns per barrier. Columns c, c+1 of T and rows c, c+1 of the inverse accumulator X
-// (identity at the start) are published in LDS before the pair; every thread then forms the 2x2 pivot
-// block
-//   d0 = T[c][c],  t = T[c+1][c],  d1 = T[c+1][c+1] - t^2 / d0,
-// the step-c value of column c+1 (b' = T[.][c+1] - T[.][c] t / d0) and of row c+1 of X, and applies
-//   T[r][s] -= T[r][c] T[s][c] / d0 + b'_r b'_s / d1                     (c+1 < s <= r),
-//   X[r][j] -= T[r][c] X[c][j] / d0 + b'_r X'[c+1][j] / d1               (r > c+1),
-// with row c+1 of X taking only the first term. At the end L^-1[r][j] = X[r][j] / sqrt(d_r) (the factor
-// itself, T[r][s] / sqrt(d_s), is not needed). Returns false (uniformly) on a non-positive or
-// non-finite pivot.
+// factor, kFw columns per barrier. Before a step, columns c .. c+kFw-1 of T and rows c .. c+kFw-1 of the
+// inverse accumulator X (identity at the start) are published in LDS. Every thread factors the kFw x kFw
+// pivot block D (unscaled: pivots d_q, multipliers g_pq = D'[p][q] / d_q, which is the one sequential
+// chain of the step), brings its rows' and its column's entries of the published columns and rows up to
+// date within the block,
+//   a_q(r) = T[r][c+q] - sum_{p<q} a_p(r) g_qp,   x_q(j) = X[c+q][j] - sum_{p<q} g_qp x_p(j),
+// and applies the rank-kFw update
+//   T[r][s] -= sum_q a_q(r) a_q(s) / d_q   (c+kFw <= s <= r),   X[r][j] -= sum_q a_q(r) x_q(j) / d_q (r >= c+kFw),
+// while the block's own columns and rows take their step values a_q and x_q. At the end
+// L^-1[r][j] = X[r][j] / sqrt(d_r) (the factor itself, T[r][s] / sqrt(d_s), is not needed).
+// Returns false (uniformly) on a non-positive or non-finite pivot.
 __device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
   const int s = fcol();
   double T[4], X[4], dr[4] = {1.0, 1.0, 1.0, 1.0};
@@ -120,53 +126,92 @@ __device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
     T[v] = Tf[v];
     X[v] = (frow(v) == s) ? 1.0 : 0.0;
   }
-  // publish columns 0, 1 and rows 0, 1 into buffer 0: fb[par * 4 NB + {0: col c, 1: col c+1, 2: row c,
-  // 3: row c+1} * NB]
-  if (s < 2)
+  // buffer layout per parity: kFw columns of T, then kFw rows of X, NB doubles each
+  constexpr int kBuf = 2 * kFw * NB;
+  if (s < kFw)
 #pragma unroll
     for (int v = 0; v < 4; ++v) fb[s * NB + frow(v)] = T[v];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    if (frow(v) < 2) fb[(2 + frow(v)) * NB + s] = X[v];
+    if (frow(v) < kFw) fb[(kFw + frow(v)) * NB + s] = X[v];
   __syncthreads();
-  for (int c = 0; c < NB; c += 2) {
-    const double* P = fb + ((c >> 1) & 1) * 4 * NB;
-    const double d0 = P[c];
-    const double t10 = P[c + 1];
-    if (!pivot_ok(d0)) return false;  // every thread read the same pivots
-    const double i0 = recip(d0);
-    const double g = t10 * i0;
-    const double d1 = fma(-g, t10, P[NB + c + 1]);
-    if (!pivot_ok(d1)) return false;
-    const double i1 = recip(d1);
-    const double as = P[s], bs = fma(-as, g, P[NB + s]);
-    const double x0s = P[2 * NB + s], x1s = fma(-g, x0s, P[3 * NB + s]);
-    // branch-free update of the four rows: T below the pair, column c+1 set to its step-c value, X
-    const bool s_trail = s > c + 1;
+  bool ok = true;
+  for (int c = 0; c < NB; c += kFw) {
+    const double* P = fb + ((c / kFw) & 1) * kBuf;
+    // every LDS read of the step first
+    double D[kFw][kFw], as[kFw], xs[kFw], av[4][kFw];
+#pragma unroll
+    for (int p = 0; p < kFw; ++p)
+#pragma unroll
+      for (int q = 0; q <= p; ++q) D[p][q] = P[q * NB + c + p];
+#pragma unroll
+    for (int q = 0; q < kFw; ++q) {
+      as[q] = P[q * NB + s];
+      xs[q] = P[(kFw + q) * NB + s];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) av[v][q] = P[q * NB + frow(v)];
+    }
+    // pivot block (identical in every thread, so the verdict is uniform)
+    double dq[kFw], iq[kFw], g[kFw][kFw];
+#pragma unroll
+    for (int q = 0; q < kFw; ++q) {
+      dq[q] = D[q][q];
+      ok = ok && pivot_ok(dq[q]);
+      iq[q] = recip(dq[q]);
+#pragma unroll
+      for (int p = q + 1; p < kFw; ++p) g[p][q] = D[p][q] * iq[q];
+#pragma unroll
+      for (int p = q + 1; p < kFw; ++p)
+#pragma unroll
+        for (int r = q + 1; r <= p; ++r) D[p][r] = fma(-g[p][q], D[r][q], D[p][r]);
+    }
+    // bring the published entries up to date within the block
+#pragma unroll
+    for (int q = 1; q < kFw; ++q)
+#pragma unroll
+      for (int p = 0; p < q; ++p) {
+        as[q] = fma(-as[p], g[q][p], as[q]);
+        xs[q] = fma(-g[q][p], xs[p], xs[q]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) av[v][q] = fma(-av[v][p], g[q][p], av[v][q]);
+      }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = frow(v);
-      const double av = P[r];
-      const double bv = fma(-av, g, P[NB + r]);
-      const double f0 = av * i0, f1 = bv * i1;
-      dr[v] = (r == c) ? d0 : ((r == c + 1) ? d1 : dr[v]);
-      const double t_upd = fma(-f0, as, fma(-f1, bs, T[v]));
-      const double x_two = fma(-f0, x0s, fma(-f1, x1s, X[v]));
-      const double x_one = fma(-f0, x0s, X[v]);
-      T[v] = (s_trail && s <= r) ? t_upd : ((s == c + 1 && r > c) ? bv : T[v]);
-      X[v] = (r > c + 1) ? x_two : ((r == c + 1) ? x_one : X[v]);
+      double t_upd = T[v], x_upd = X[v];
+#pragma unroll
+      for (int q = 0; q < kFw; ++q) {
+        const double f = av[v][q] * iq[q];
+        t_upd = fma(-f, as[q], t_upd);
+        x_upd = fma(-f, xs[q], x_upd);
+      }
+      const int qr = r - c, qs = s - c;  // position inside the block (in [0, kFw) when inside)
+#pragma unroll
+      for (int q = 0; q < kFw; ++q) dr[v] = (qr == q) ? dq[q] : dr[v];
+      double t_col = T[v], x_row = X[v];
+#pragma unroll
+      for (int q = 1; q < kFw; ++q) {
+        t_col = (qs == q) ? av[v][q] : t_col;
+        x_row = (qr == q) ? xs[q] : x_row;
+      }
+      T[v] = (qs >= kFw && s <= r) ? t_upd : ((qs > 0 && qs < kFw && r >= s) ? t_col : T[v]);
+      X[v] = (qr >= kFw) ? x_upd : ((qr > 0 && qr < kFw) ? x_row : X[v]);
     }
-    if (c + 2 < NB) {
-      double* Q = fb + (((c >> 1) + 1) & 1) * 4 * NB;
-      if (s == c + 2 || s == c + 3)
+    if (c + kFw < NB) {
+      double* Q = fb + ((c / kFw + 1) & 1) * kBuf;
+      const int qs = s - c - kFw;
+      if (qs >= 0 && qs < kFw)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Q[(s - c - 2) * NB + frow(v)] = T[v];
+        for (int v = 0; v < 4; ++v) Q[qs * NB + frow(v)] = T[v];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (frow(v) == c + 2 || frow(v) == c + 3) Q[(frow(v) - c) * NB + s] = X[v];
+      for (int v = 0; v < 4; ++v) {
+        const int qr = frow(v) - c - kFw;
+        if (qr >= 0 && qr < kFw) Q[(kFw + qr) * NB + s] = X[v];
+      }
     }
     __syncthreads();
   }
+  if (!ok) return false;
 #pragma unroll
   for (int v = 0; v < 4; ++v) Xq[v] = (s <= frow(v)) ? X[v] / sqrt(dr[v]) : 0.0;
   return true;
@@ -211,7 +256,7 @@ __device__ inline void frag_from_H(const CholArgs& a, int i, int j, double eps, 
 __device__ bool init_tile(const CholArgs& a, int i, int j, double eps, double* S, double* fb) {
   f64x4 q;
   frag_from_H(a, i, j, eps, q);
-  double* sb = fb + 8 * NB;
+  double* sb = fb + 4 * kFw * NB;
   if (j == 0 && threadIdx.x < NB) {
     const int rr = i * NB + threadIdx.x;
     const double bv = (rr < a.n) ? -a.g[rr] : 0.0;
@@ -253,8 +298,8 @@ __device__ bool panel_tile(const CholArgs& a, int k, int i, int j, double* S0, d
   frag_to_lds(qinv, S0);
   frag_to_lds(qi, S1);
   if (offd) frag_to_lds(qj, S2);
-  double* sy = fb + 4 * NB;  // y_k while the factor scratch is unused
-  double* sb = fb + 8 * NB;
+  double* sy = fb + 2 * kFw * NB;  // y_k while the factor scratch is unused (parity-1 buffer)
+  double* sb = fb + 4 * kFw * NB;
   if (col && threadIdx.x < NB) sy[threadIdx.x] = yk;
   __syncthreads();
   f64x4 li = {0.0, 0.0, 0.0, 0.0}, lj = {0.0, 0.0, 0.0, 0.0};
@@ -306,6 +351,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_init(CholArgs a) {
   __shared__ double fb[kFactorScratch];
   int i, j;
   tile_index(blockIdx.x, i, j);
+  if (i == 0)  // flags of the back substitution start at zero
+    for (int k = threadIdx.x; k < a.nt; k += blockDim.x) bs_ready(a)[k] = 0u;
   const bool ok = init_tile(a, i, j, a.eps0, S, fb);
   if (i == 0 && threadIdx.x == 0) {
     a.sync[3] = ok ? 0u : 1u;
@@ -324,102 +371,130 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_panel(CholArgs a, int k) 
   if (!panel_tile(a, k, k + 1 + ii, k + 1 + jj, S0, S1, S2, fb) && threadIdx.x == 0) a.sync[3] = 1u;
 }
 
-// Back substitution L^T x = y by one workgroup, right-looking: for block k (last first)
-//   x_k = Inv_k^T (y_k - acc_k),  then acc_j += sum_r L[32k + r][j] x_k[r] for every column j < 32k,
-// where thread t keeps acc for columns t + 512 m in registers. y sits in LDS; the first RC rows of block
-// k are loaded before x_k is solved and Inv_{k-1} one block ahead, so that the solve never waits for
-// global memory.
-template <int CPT, int RC>
-__global__ __launch_bounds__(kBackThreads) void k_chol_backsub(CholArgs a) {
+__device__ inline unsigned ld_acq(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Back substitution L^T x = y over ceil(nt / 8) workgroups. Workgroup w owns the eight diagonal blocks
+// [8w, 8w + 8) and keeps, per owned column j, acc_j = sum over the rows below its block of L[row][j] x[row]
+// (thread = column slot x half of the 32 rows of a block row). It walks the block rows from the last one
+// down: a block row above its range is applied once its owner has published x_i (flag ready[i], agent
+// scope), a block row of its own is first solved, x_i = Inv_i^T (y_i - acc_i), and published. The factor
+// rows and Inv of the next own block are prefetched one block row ahead (after a publish, so that its
+// release does not wait for them); y of the own blocks sits in LDS.
+// Every wait is bounded; a timeout sets sync[2], zeroes the workgroup's part of tau and ends in status -2.
+constexpr int kBsBlocks = 8;
+constexpr int kBsCols = kBsBlocks * NB;  // 256
+constexpr int kBsThreads = 2 * kBsCols;  // 512
+constexpr int kBsRows = NB / 2;          // rows of a block row per thread
+
+__global__ __launch_bounds__(kBsThreads) void k_chol_backsub(CholArgs a) {
+  const int nt = a.nt, w = blockIdx.x;
+  const int b0 = w * kBsBlocks, b1 = min(nt, b0 + kBsBlocks);
   if (a.sync[3] != 0u) {  // attempt 0 failed: the fallback takes over, or gives up with one attempt
     if (a.attempts == 1) {
-      for (int k = threadIdx.x; k < a.n; k += kBackThreads) a.tau[k] = 0.0;
-      if (threadIdx.x == 0) *a.status = -1;
+      for (int k = b0 * NB + threadIdx.x; k < min(a.n, b1 * NB); k += kBsThreads) a.tau[k] = 0.0;
+      if (w == 0 && threadIdx.x == 0) *a.status = -1;
     }
     return;
   }
-  constexpr int kInvPer = NB * NB / kBackThreads;
-  extern __shared__ double sy[];  // np
   __shared__ double sinv[NB * NB];
-  __shared__ double rhs[NB];
+  __shared__ double ys[kBsCols];
+  __shared__ double red[2][kBsCols];
   __shared__ double xs[NB];
+  __shared__ int s_ok;
   const int t = threadIdx.x;
+  const int cs = t & (kBsCols - 1), h = t >> 8;
+  const int col = b0 * NB + cs;
+  const bool has_col = col < b1 * NB;
   const int64_t np = a.np;
-  for (int e = t; e < a.np; e += kBackThreads) sy[e] = a.y[e];
-  double acc[CPT];
+  unsigned* ready = bs_ready(a);
+  if (t < kBsCols) ys[t] = has_col ? a.y[col] : 0.0;
+  double cur[kBsRows], nxt[kBsRows];
+  auto load_rows = [&](int i, double* buf) {
 #pragma unroll
-  for (int m = 0; m < CPT; ++m) acc[m] = 0.0;
+    for (int r = 0; r < kBsRows; ++r)
+      buf[r] = (has_col && col < i * NB) ? a.L[int64_t(i * NB + kBsRows * h + r) * np + col] : 0.0;
+  };
+  constexpr int kInvPer = NB * NB / kBsThreads;
   double inv[kInvPer];
 #pragma unroll
-  for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(a.nt - 1) * NB * NB + t + e * kBackThreads];
-  for (int k = a.nt - 1; k >= 0; --k) {
-    const int c0 = k * NB;
-#pragma unroll
-    for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBackThreads] = inv[e];
-    double buf[RC][CPT];
-#pragma unroll
-    for (int r = 0; r < RC; ++r)
-#pragma unroll
-      for (int m = 0; m < CPT; ++m) {
-        const int j = t + kBackThreads * m;
-        buf[r][m] = (j < c0) ? a.L[(c0 + r) * np + j] : 0.0;
-      }
-    if (k > 0)
-#pragma unroll
-      for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(k - 1) * NB * NB + t + e * kBackThreads];
-    __syncthreads();  // sy (first block) and sinv written
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-      const int j = t + kBackThreads * m;
-      if (j >= c0 && j < c0 + NB) rhs[j - c0] = sy[j] - acc[m];
-    }
-    __syncthreads();
-    if (t < 8 * NB) {  // x_k[c] = sum_{u >= c} Inv_k[u][c] rhs[u], eight threads per c
-      const int c = t >> 3, p = t & 7;
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < NB / 8; ++q) {
-        const int u = p + 8 * q;
-        v = fma(sinv[u * NB + c], rhs[u], v);  // Inv_k is zero above its diagonal
-      }
-      v += __shfl_xor(v, 1, 8);
-      v += __shfl_xor(v, 2, 8);
-      v += __shfl_xor(v, 4, 8);
-      if (p == 0) {
-        xs[c] = v;
-        if (c0 + c < a.n) a.tau[c0 + c] = v;
-      }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int rr = 0; rr < NB; rr += RC) {
-      if (rr > 0) {
-#pragma unroll
-        for (int r = 0; r < RC; ++r)
-#pragma unroll
-          for (int m = 0; m < CPT; ++m) {
-            const int j = t + kBackThreads * m;
-            buf[r][m] = (j < c0) ? a.L[(c0 + rr + r) * np + j] : 0.0;
+  for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(b1 - 1) * NB * NB + t + e * kBsThreads];
+  load_rows(nt - 1, cur);
+  double acc = 0.0;
+  bool ok = true;
+  for (int i = nt - 1; i >= b0; --i) {
+    if (i >= b1) {  // block row of a later workgroup: wait for its x_i
+      if (i - 1 >= b0) load_rows(i - 1, nxt);
+      if (t == 0) {
+        long spins = 0;
+        int good = 1;
+        while (ld_acq(&ready[i]) == 0u) {
+          if (ld_acq(&a.sync[2]) != 0u || ++spins > kSpinLimit) {
+            atomicOr(&a.sync[2], 1u);
+            good = 0;
+            break;
           }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        s_ok = good;
       }
+      __syncthreads();
+      if (!s_ok) {
+        ok = false;
+        break;
+      }
+      if (t < NB) xs[t] = __hip_atomic_load(&a.x[i * NB + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+    } else {  // own block: solve and publish
 #pragma unroll
-      for (int r = 0; r < RC; ++r) {
-        const double xr = xs[rr + r];
+      for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBsThreads] = inv[e];
+      red[h][cs] = acc;
+      __syncthreads();
+      if (t < 8 * NB) {  // x_i[c] = sum_{u >= c} Inv_i[u][c] (y_i[u] - acc_i[u]), eight threads per c
+        const int c = t >> 3, p = t & 7, base = (i - b0) * NB;
+        double v = 0.0;
 #pragma unroll
-        for (int m = 0; m < CPT; ++m) acc[m] = fma(buf[r][m], xr, acc[m]);
+        for (int q = 0; q < NB / 8; ++q) {
+          const int u = p + 8 * q;  // Inv_i is zero above its diagonal
+          v = fma(sinv[u * NB + c], ys[base + u] - (red[0][base + u] + red[1][base + u]), v);
+        }
+        v += __shfl_xor(v, 1, 8);
+        v += __shfl_xor(v, 2, 8);
+        v += __shfl_xor(v, 4, 8);
+        if (p == 0) {
+          xs[c] = v;
+          if (i * NB + c < a.n) a.tau[i * NB + c] = v;
+          __hip_atomic_store(&a.x[i * NB + c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __threadfence();
+        }
+      }
+      __syncthreads();
+      if (t == 0) __hip_atomic_store(&ready[i], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      // the next block's loads go out only now, so that the release above never waits for them
+      if (i - 1 >= b0) {
+        load_rows(i - 1, nxt);
+#pragma unroll
+        for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(i - 1) * NB * NB + t + e * kBsThreads];
       }
     }
-    __syncthreads();  // sinv, rhs and xs are rewritten by the next block
+#pragma unroll
+    for (int r = 0; r < kBsRows; ++r) acc = fma(cur[r], xs[kBsRows * h + r], acc);
+#pragma unroll
+    for (int r = 0; r < kBsRows; ++r) cur[r] = nxt[r];
+    __syncthreads();  // xs, red and sinv are rewritten by the next block row
   }
-  if (t == 0) *a.status = 0;
+  if (!ok) {
+    for (int k = b0 * NB + t; k < min(a.n, b1 * NB); k += kBsThreads) a.tau[k] = 0.0;
+    if (w == 0 && t == 0) *a.status = -2;
+    return;
+  }
+  if (w == 0 && t == 0) *a.status = (ld_acq(&a.sync[2]) != 0u) ? -2 : 0;
 }
 
 // ---------------------------------------------------------------------------------------------------
 // Fallback: attempts 1 .. attempts-1 in one persistent launch with bounded grid barriers
 // ---------------------------------------------------------------------------------------------------
-__device__ inline unsigned ld_acq(unsigned* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Grid-wide barrier; false when the wait timed out or another workgroup reported an error.
 __device__ bool grid_barrier(unsigned* sync, unsigned nblocks) {
@@ -574,32 +649,14 @@ size_t chol_workspace_bytes(int n) {
   c.take<double>(np);
   c.take<double>(np);
   c.take<double>(np);
-  c.take<unsigned>(4 + (kMaxAttempts + 1) * nt);
+  c.take<unsigned>(4 + (kMaxAttempts + 2) * nt);
   return c.used;
 }
 
-// Back substitution launch with the smallest instantiated column count per thread covering np.
 static int launch_backsub(const CholArgs& a, hipStream_t s) {
-  const int need = (a.np + kBackThreads - 1) / kBackThreads;
-  const size_t lds = size_t(a.np) * sizeof(double);  // y
-#define DS3_BACKSUB(C, R)                                                                          \
-  if (need <= C) {                                                                                 \
-    if (lds > 48 * 1024)                                                                           \
-      DS3_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_backsub<C, R>),        \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));      \
-    hipLaunchKernelGGL((k_chol_backsub<C, R>), dim3(1), dim3(kBackThreads), lds, s, a);            \
-    return check_hip(hipGetLastError(), "k_chol_backsub");                                         \
-  }
-  DS3_BACKSUB(1, 32)
-  DS3_BACKSUB(2, 32)
-  DS3_BACKSUB(3, 32)
-  DS3_BACKSUB(4, 16)
-  DS3_BACKSUB(6, 8)
-  DS3_BACKSUB(8, 8)
-  DS3_BACKSUB(12, 4)
-  DS3_BACKSUB(16, 4)
-#undef DS3_BACKSUB
-  return fail(DS3_EINVAL, "chol: n too large");
+  const int groups = (a.nt + kBsBlocks - 1) / kBsBlocks;
+  hipLaunchKernelGGL(k_chol_backsub, dim3(groups), dim3(kBsThreads), 0, s, a);
+  return check_hip(hipGetLastError(), "k_chol_backsub");
 }
 
 int launch_chol_ladder(const double* H, const double* g, int n, double lambda, double eps0, double mult,
@@ -616,7 +673,7 @@ int launch_chol_ladder(const double* H, const double* g, int n, double lambda, d
   a.b = c.take<double>(a.np);
   a.y = c.take<double>(a.np);
   a.x = c.take<double>(a.np);
-  a.sync = c.take<unsigned>(4 + (kMaxAttempts + 1) * a.nt);
+  a.sync = c.take<unsigned>(4 + (kMaxAttempts + 2) * a.nt);
   a.H = H; a.g = g; a.n = n;
   a.lambda = lambda; a.eps0 = eps0; a.mult = mult; a.attempts = attempts;
   a.tau = tau; a.status = status;

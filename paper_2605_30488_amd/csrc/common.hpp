@@ -28,6 +28,9 @@ struct Px<DS3_F32> {
     return reinterpret_cast<const float4*>(base)[px];
   }
   __device__ static inline float4 unpack(raw_t r) { return r; }
+  __device__ static inline float conf(const void* base, int64_t px) {
+    return reinterpret_cast<const float*>(base)[4 * px + 3];
+  }
 };
 
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
@@ -46,6 +49,9 @@ struct Px<DS3_BF16> {
   }
   __device__ static inline float4 unpack(raw_t w) {
     return make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y));
+  }
+  __device__ static inline float conf(const void* base, int64_t px) {
+    return bf16_hi(reinterpret_cast<const uint32_t*>(base)[2 * px + 1]);
   }
 };
 

@@ -52,24 +52,47 @@ struct Sample {
   bool hole;
 };
 
-__device__ inline Sample sample_rays(const float4* __restrict__ R, int H, int W, float u, float v) {
-  int u0 = min(int(floorf(u)), W - 2);
-  int v0 = min(int(floorf(v)), H - 2);
-  u0 = max(u0, 0);
-  v0 = max(v0, 0);
-  const float fu = u - float(u0), fv = v - float(v0);
+// The four texels of the last cell a query sampled: a trial that stays in the same cell (the common case
+// once the steps are sub-pixel, and for every damped retry that moves a little) reuses them instead of
+// gathering again.
+struct Cell {
+  int u0, v0;
+  float a[3], b[3], c[3], d[3];
+  bool hole;
+};
+
+__device__ inline void cell_origin(int H, int W, float u, float v, int& u0, int& v0) {
+  u0 = max(min(int(floorf(u)), W - 2), 0);
+  v0 = max(min(int(floorf(v)), H - 2), 0);
+}
+
+__device__ inline void fetch_cell(const float4* __restrict__ R, int W, int u0, int v0, Cell& C) {
   const int64_t i00 = int64_t(v0) * W + u0;
   const float4 a = R[i00], b = R[i00 + 1], c = R[i00 + W], d = R[i00 + W + 1];
+  C.u0 = u0;
+  C.v0 = v0;
+  C.hole = !(a.w > 0.f) || !(b.w > 0.f) || !(c.w > 0.f) || !(d.w > 0.f);
+  C.a[0] = a.x; C.a[1] = a.y; C.a[2] = a.z;
+  C.b[0] = b.x; C.b[1] = b.y; C.b[2] = b.z;
+  C.c[0] = c.x; C.c[1] = c.y; C.c[2] = c.z;
+  C.d[0] = d.x; C.d[1] = d.y; C.d[2] = d.z;
+}
+
+// Bilinear sample of the ray image and its in-cell derivatives at (u, v); gathers only when the cell
+// differs from the cached one.
+__device__ inline Sample sample_rays(const float4* __restrict__ R, int H, int W, float u, float v, Cell& C) {
+  int u0, v0;
+  cell_origin(H, W, u, v, u0, v0);
+  if (u0 != C.u0 || v0 != C.v0) fetch_cell(R, W, u0, v0, C);
+  const float fu = u - float(u0), fv = v - float(v0);
   Sample S;
-  S.hole = !(a.w > 0.f) || !(b.w > 0.f) || !(c.w > 0.f) || !(d.w > 0.f);
-  const float ax[3] = {a.x, a.y, a.z}, bx[3] = {b.x, b.y, b.z}, cx[3] = {c.x, c.y, c.z},
-              dx[3] = {d.x, d.y, d.z};
+  S.hole = C.hole;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float top = fmaf(fu, bx[k] - ax[k], ax[k]);
-    const float bot = fmaf(fu, dx[k] - cx[k], cx[k]);
+    const float top = fmaf(fu, C.b[k] - C.a[k], C.a[k]);
+    const float bot = fmaf(fu, C.d[k] - C.c[k], C.c[k]);
     S.s[k] = fmaf(fv, bot - top, top);
-    S.su[k] = fmaf(fv, (dx[k] - cx[k]) - (bx[k] - ax[k]), bx[k] - ax[k]);
+    S.su[k] = fmaf(fv, (C.d[k] - C.c[k]) - (C.b[k] - C.a[k]), C.b[k] - C.a[k]);
     S.sv[k] = bot - top;
   }
   return S;
@@ -89,7 +112,10 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
   const float t0 = x.x * rdx, t1 = x.y * rdx, t2 = x.z * rdx;
   float u = (Wq > 1) ? float(qu) * (float(W - 1) / float(Wq - 1)) : 0.0f;
   float v = (Hq > 1) ? float(qv) * (float(H - 1) / float(Hq - 1)) : 0.0f;
-  Sample S = sample_rays(R, H, W, u, v);
+  Cell C;
+  C.u0 = -1;
+  C.v0 = -1;
+  Sample S = sample_rays(R, H, W, u, v, C);
   if (S.hole) return -1;
   float r0 = S.s[0] - t0, r1 = S.s[1] - t1, r2 = S.s[2] - t2;
   float c = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
@@ -117,7 +143,7 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
     const float vn = det_ok ? fminf(fmaxf(v + dv, 0.0f), float(H - 1)) : v;
     // no movement (singular system, clamped or vanishing step): same sample, same cost, reject
     const bool moved = (un != u) || (vn != v);
-    const Sample Sn = sample_rays(R, H, W, un, vn);
+    const Sample Sn = sample_rays(R, H, W, un, vn, C);
     if (moved && Sn.hole) {
       hole = true;
       active = false;
@@ -205,13 +231,16 @@ __device__ inline bool locate_item(const ItemMap& M, int b, int& entry, int& til
   return true;
 }
 
-// Batched: 256 query pixels per block; blocks of one direction share an XCD.
+// Batched: 256 query pixels per block; blocks of one direction share an XCD. The LM trial-step count is
+// summed per block and added to one of kStepStripes counters 128 B apart (block b to stripe b mod
+// kStepStripes): a single counter hit by every wave becomes a hot spot of one L2 channel that stalls the
+// whole launch.
 template <int DT>
 __global__ __launch_bounds__(256) void k_match_batched(const float4* __restrict__ rays,
                                                        const void* __restrict__ cross,
                                                        const MatchDir* __restrict__ dirs, ItemMap map,
                                                        MatchConst P, int32_t* __restrict__ idx_tmp,
-                                                       unsigned long long* __restrict__ lm_steps) {
+                                                       unsigned* __restrict__ step_stripes) {
   int entry, tile;
   if (!locate_item(map, blockIdx.x, entry, tile)) return;  // uniform per block
   const MatchDir D = dirs[entry];
@@ -223,21 +252,45 @@ __global__ __launch_bounds__(256) void k_match_batched(const float4* __restrict_
     idx_tmp[D.out_off + n] = match_query(rays + D.ref_off, D.Hr, D.Wr, x, int(n % D.Wq), int(n / D.Wq),
                                          D.Hq, D.Wq, P, &pu, &pv, &its);
   }
-  if (lm_steps) {
+  if (step_stripes) {
+    __shared__ int s[4];
     its = wave_sum(its);
-    if ((threadIdx.x & 63) == 0 && its) atomicAdd(lm_steps, (unsigned long long)its);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = its;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int tot = s[0] + s[1] + s[2] + s[3];
+      if (tot) atomicAdd(&step_stripes[(blockIdx.x % kStepStripes) * kStripeStride], unsigned(tot));
+    }
   }
+}
+
+__global__ void k_sum_stripes(const unsigned* __restrict__ step_stripes, unsigned long long* __restrict__ out) {
+  unsigned long long v = 0;
+  for (int k = threadIdx.x; k < kStepStripes; k += blockDim.x) v += step_stripes[k * kStripeStride];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  __shared__ unsigned long long part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
 }
 
 int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, const MatchDir* dirs,
                          ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp,
-                         unsigned long long* lm_steps, hipStream_t s) {
+                         unsigned* step_stripes, hipStream_t s) {
   if (grid <= 0) return DS3_OK;
   if (dt == DS3_F32)
-    hipLaunchKernelGGL(k_match_batched<DS3_F32>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp, lm_steps);
+    hipLaunchKernelGGL(k_match_batched<DS3_F32>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp,
+                       step_stripes);
   else
-    hipLaunchKernelGGL(k_match_batched<DS3_BF16>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp, lm_steps);
+    hipLaunchKernelGGL(k_match_batched<DS3_BF16>, dim3(grid), dim3(256), 0, s, rays, cross, dirs, map, P, idx_tmp,
+                       step_stripes);
   return check_hip(hipGetLastError(), "k_match_batched");
+}
+
+int launch_sum_stripes(const unsigned* step_stripes, unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_stripes, dim3(1), dim3(256), 0, s, step_stripes, out);
+  return check_hip(hipGetLastError(), "k_sum_stripes");
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -259,7 +312,7 @@ __device__ inline bool round_trip(const int32_t* __restrict__ fwd, const int32_t
 
 template <int DT>
 __device__ inline float conf_at(const void* arena, int64_t px) {
-  return Px<DT>::load(arena, px).w;
+  return Px<DT>::conf(arena, px);  // the confidence word only
 }
 
 template <int DT>

@@ -46,9 +46,14 @@ struct ItemMap {
 int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, hipStream_t s);
 int launch_match_one(const float4* rays, int H, int W, const void* qry, int Hq, int Wq, ds3_dtype dt,
                      const MatchConst& P, int32_t* idx_out, float* p_out, int32_t* it_out, hipStream_t s);
+// LM step counting of the batched launch: per-block sums spread over kStepStripes counters, 128 B apart.
+constexpr int kStepStripes = 256;
+constexpr int kStripeStride = 32;
+// step_stripes may be NULL (no counting); it must start at zero.
 int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, const MatchDir* dirs,
                          ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp,
-                         unsigned long long* lm_steps, hipStream_t s);
+                         unsigned* step_stripes, hipStream_t s);
+int launch_sum_stripes(const unsigned* step_stripes, unsigned long long* out, hipStream_t s);
 int launch_mutual(const MutualDir* md, ItemMap map, int grid, ds3_dtype dt, const MatchConst& P,
                   const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* counts,
                   hipStream_t s);
