@@ -173,12 +173,94 @@ def cpu_baseline(g, n_edges_gn=None, n_edges_match=32):
 
 
 # --------------------------------------------------------------------------------------------------
+# Long horizon: forward cost + hand-written adjoint over 4 agents x 250 keyframes, 4000 edges (BF16)
+# --------------------------------------------------------------------------------------------------
+def cpu_baseline_adjoint(g, idx_all, n_edges=400):
+    """The oracle's cost and gradient over a sample of edges (about ten seconds on 16 cores), scaled to
+    edge-px/s."""
+    import oracle as O
+    pick = list(range(0, len(g.edges), len(g.edges) // n_edges))[:n_edges]
+    kfs = sorted({int(v) for e in pick for v in g.edges[e]})
+    remap = {k: n for n, k in enumerate(kfs)}
+    idx = [idx_all[e] for e in pick]
+    og = O.Graph([g.xyz[k] for k in kfs], [g.conf[k] for k in kfs],
+                 [(remap[int(g.edges[e][0])], remap[int(g.edges[e][1])]) for e in pick], idx, anchors=())
+    valid = int(sum((i >= 0).sum() for i in idx))
+    t0 = time.perf_counter()
+    O.cost_grad(og, g.poses_init[kfs])
+    t = time.perf_counter() - t0
+    return {"value": valid / t, "unit": "edge-px/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"FP64 cost and gradient over {len(pick)} of {len(g.edges)} edges ({valid} valid edge-pixels) "
+                      f"in {t:.2f} s"}
+
+
+def run_long_horizon(args, dev):
+    import torch
+
+    import synth
+    from paper_2605_30488_amd import api as ds3
+    t0 = time.time()
+    g = synth.make_config(5)
+    idx = g.gt_idx_all_torch(dev)
+    log(f"generated config 5: {g.n_kf} keyframes, {len(g.edges)} edges in {time.time() - t0:.1f}s")
+    arena = ds3.build_arena(g.xyz, g.conf, "bf16", dev)
+    edges = [(int(i), int(j)) for i, j in g.edges]
+    G = ds3.Graph(arena, edges, idx, anchors=(0,))
+    P = torch.as_tensor(g.poses_init).to(dev)
+    timer = ds3.KernelTimer()
+    px_scanned = int(idx.numel())
+    px_valid = int((idx >= 0).sum().item())
+
+    def step():
+        c = ds3.gn_cost(G, P)
+        _, _, gt = ds3.gn_cost_adjoint(G, P, timer=timer)
+        return c, gt
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    kms = []
+    for _ in range(args.steps):
+        c, gt = step()
+        kms.append(timer.ms())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = wall * 1e3 / args.steps
+    k_ms = float(np.mean(kms))
+    # per launch: the forward streaming bytes (4 B idx per scanned pixel, both 8 B pointmap entries per
+    # valid pixel), 16 B of gradient written per valid query pixel and 16 B scattered per matched pixel
+    adj_bytes = 4 * px_scanned + 16 * px_valid + 16 * px_valid + 16 * px_valid
+    gbs = adj_bytes / (k_ms * 1e-3) / 1e9
+    out = {"metric": METRIC, "value": round(px_valid / (ms_step * 1e-3), 1), "unit": "edge-px/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": "long horizon: 4 agents x 250 keyframes 512x384, 4000 edges, bf16 xyzc; one "
+                                  "step = forward cost + hand-written adjoint (dE/dxyz, dE/dconf, dE/dtau)",
+                      "n_kf": g.n_kf, "n_edges": len(edges), "edge_px_scanned": px_scanned,
+                      "edge_px_valid": px_valid},
+           "roofline": {"kernel": "k_edge_adjoint", "bound": "hbm", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                        "launch_ms": round(k_ms, 4), "bytes_per_launch": adj_bytes},
+           "cost": float(c.item()), "grad_tau_norm": float(gt.norm().item())}
+    if not args.no_cpu_baseline and not args.quick:
+        idx_np = idx.cpu().numpy()
+        offs = np.cumsum([0] + [g.shape(j)[0] * g.shape(j)[1] for _, j in edges])
+        out["cpu_baseline"] = cpu_baseline_adjoint(g, [idx_np[offs[e]:offs[e + 1]] for e in range(len(edges))])
+    timer.close()
+    print(json.dumps(out), flush=True)
+
+
+# --------------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4])
+    ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4, 5],
+                    help="4 (default): batched graph in BF16; 3: the same in FP32; 2: single agent; "
+                         "5: long horizon, forward cost + hand-written adjoint")
     ap.add_argument("--gn-iters", type=int, default=20)
     ap.add_argument("--plain-iters", type=int, default=3)
     ap.add_argument("--plain-match-edges", type=int, default=40)
@@ -203,6 +285,9 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.config == 5:
+        run_long_horizon(args, dev)
+        return
     dtype = "bf16" if args.config == 4 else "f32"
     t0 = time.time()
     g = synth.make_config(3 if args.config in (3, 4) else 2)

@@ -275,12 +275,12 @@ int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const vo
 /* dE/dX and dE/dC per arena pixel (device float32, 3 resp. 1 per pixel, ACCUMULATED into the caller's
  * buffers: zero them first) and dE/dtau per keyframe (device float64 n_kf x 7, overwritten), all scaled
  * by dcost (host float). The per-pixel scatter onto the gathered side uses float atomics, so those sums
- * are not bitwise reproducible. */
+ * are not bitwise reproducible. adjoint_timer (may be NULL) is recorded around the per-pixel launch. */
 int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, const void* xyzc_arena,
                         ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges,
                         const int32_t* idx_arena, const ds3_gn_params* params, float dcost,
-                        float* grad_xyz, float* grad_conf, double* grad_tau, void* workspace,
-                        size_t ws_bytes, void* stream);
+                        float* grad_xyz, float* grad_conf, double* grad_tau, ds3_timer* adjoint_timer,
+                        void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

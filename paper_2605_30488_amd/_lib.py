@@ -85,7 +85,7 @@ _SIGS = {
     "ds3_gn_cost": (C.c_int, [vp, i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams), vp, vp,
                               sz, vp]),
     "ds3_gn_cost_adjoint": (C.c_int, [vp, i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams),
-                                      f32, vp, vp, vp, vp, sz, vp]),
+                                      f32, vp, vp, vp, vp, vp, sz, vp]),
 }
 
 

@@ -419,8 +419,9 @@ def gn_cost(graph: Graph, poses, params=None):
     return cost
 
 
-def gn_cost_adjoint(graph: Graph, poses, dcost=1.0, params=None):
-    """(dE/dxyz (P, 3) float32, dE/dconf (P,) float32, dE/dtau (N, 7) float64), scaled by dcost."""
+def gn_cost_adjoint(graph: Graph, poses, dcost=1.0, params=None, timer=None):
+    """(dE/dxyz (P, 3) float32, dE/dconf (P,) float32, dE/dtau (N, 7) float64), scaled by dcost; timer (a
+    KernelTimer) is recorded around the per-pixel adjoint launch."""
     P = params or default_gn_params()
     dev = poses.device
     npx = graph.arena.data.shape[0]
@@ -430,7 +431,7 @@ def gn_cost_adjoint(graph: Graph, poses, dcost=1.0, params=None):
     ws = graph.workspace()
     call("ds3_gn_cost_adjoint", _ptr(poses), graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype,
          graph.et, len(graph.edges), _ptr(graph.idx), C.byref(P), float(dcost), _ptr(gx), _ptr(gc), _ptr(gt),
-         _ptr(ws), ws.numel(), _stream())
+         timer.handle if timer is not None else None, _ptr(ws), ws.numel(), _stream())
     return gx, gc, gt
 
 

@@ -151,15 +151,18 @@ int adjoint_part_floats(int n_edges, int max_npx_j) {
 int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
                    const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c, float dcost,
                    float* grad_xyz, float* grad_conf, float* part7, double* b_e, int n_kf,
-                   const int32_t* node_ptr, const int32_t* node_adj, double* grad_tau, hipStream_t s) {
+                   const int32_t* node_ptr, const int32_t* node_adj, double* grad_tau, ds3_timer* timer,
+                   hipStream_t s) {
   const int tiles = (max_npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
   if (n_edges > 0 && tiles > 0) {
     dim3 grid(tiles, n_edges), block(kAdjThreads);
+    DS3_TRY(timer_record(timer, true, s));
     if (dt == DS3_F32)
       hipLaunchKernelGGL(k_edge_adjoint<DS3_F32>, grid, block, 0, s, arena, edges, xf, idx, c, dcost, grad_xyz, grad_conf, part7);
     else
       hipLaunchKernelGGL(k_edge_adjoint<DS3_BF16>, grid, block, 0, s, arena, edges, xf, idx, c, dcost, grad_xyz, grad_conf, part7);
     DS3_TRY(check_hip(hipGetLastError(), "k_edge_adjoint"));
+    DS3_TRY(timer_record(timer, false, s));
     hipLaunchKernelGGL(k_adjoint_edge_finalize, dim3((n_edges + 63) / 64), dim3(64), 0, s, edges, tiles, part7,
                        Ad, b_e, n_edges);
     DS3_TRY(check_hip(hipGetLastError(), "k_adjoint_edge_finalize"));

@@ -163,7 +163,8 @@ int adjoint_part_floats(int n_edges, int max_npx_j);
 int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
                    const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c, float dcost,
                    float* grad_xyz, float* grad_conf, float* part7, double* b_e, int n_kf,
-                   const int32_t* node_ptr, const int32_t* node_adj, double* grad_tau, hipStream_t s);
+                   const int32_t* node_ptr, const int32_t* node_adj, double* grad_tau, ds3_timer* timer,
+                   hipStream_t s);
 
 static int max_npx_j(const Topology& T) {
   int m = 0;
@@ -409,7 +410,8 @@ int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const vo
 int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, const void* arena,
                         ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges, const int32_t* idx,
                         const ds3_gn_params* params, float dcost, float* grad_xyz, float* grad_conf,
-                        double* grad_tau, void* workspace, size_t ws_bytes, void* stream) {
+                        double* grad_tau, ds3_timer* adjoint_timer, void* workspace, size_t ws_bytes,
+                        void* stream) {
   DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
   if (!grad_xyz || !grad_conf || !grad_tau || !workspace) return fail(DS3_EINVAL, "null output or workspace");
   Topology T;
@@ -423,7 +425,7 @@ int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, 
   DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
   return launch_adjoint(dtype, arena, B.edges, T.n_edges, max_npx_j(T), B.xf, B.Ad, idx,
                         make_gn_const(*params), dcost, grad_xyz, grad_conf, B.part7, B.b_e, T.n_kf,
-                        B.node_ptr, B.node_adj, grad_tau, s);
+                        B.node_ptr, B.node_adj, grad_tau, adjoint_timer, s);
 }
 
 }  // extern "C"

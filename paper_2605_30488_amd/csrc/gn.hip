@@ -131,16 +131,20 @@ __device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const
   const float e1 = p1 - Xi.y * rdi;
   const float e2 = p2 - Xi.z * rdi;
   const float e3 = d - di;
-  const float q = sqrtf(cc);
-  const float sq = sqrtf(q);
-  const float r0 = sq * e0 * k.inv_sr, r1 = sq * e1 * k.inv_sr, r2 = sq * e2 * k.inv_sr;
-  const float r3 = sq * e3 * k.inv_sd;
+  // q = sqrt(C_i C_j) and its square root by the hardware square root (1 ulp; cc is a product of
+  // confidences, never denormal here)
+  const float q = __builtin_amdgcn_sqrtf(cc);
+  const float sq = __builtin_amdgcn_sqrtf(q);
+  const float sr = sq * k.inv_sr;
+  const float r0 = sr * e0, r1 = sr * e1, r2 = sr * e2;
+  const float r3 = sq * k.inv_sd * e3;
   const float a0 = fabsf(r0), a1 = fabsf(r1), a2 = fabsf(r2), a3 = fabsf(r3);
   // IRLS weight min(1, kappa/|r|); the reciprocal is the hardware one (1 ulp)
-  const float w0 = (a0 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a0);
-  const float w1 = (a1 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a1);
-  const float w2 = (a2 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a2);
-  const float w3 = (a3 <= k.kappa) ? 1.0f : k.kappa * __builtin_amdgcn_rcpf(a3);
+  // (min(1, kappa * rcp(|r|)): |r| = 0 gives rcp = inf and weight 1)
+  const float w0 = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a0));
+  const float w1 = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a1));
+  const float w2 = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a2));
+  const float w3 = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a3));
   // rho(r) = t (|r| - t/2) with t = w |r|: r^2/2 inside kappa, kappa |r| - kappa^2/2 outside
   const float t0 = w0 * a0, t1 = w1 * a1, t2 = w2 * a2, t3 = w3 * a3;
   a.cost += t0 * fmaf(-0.5f, t0, a0) + t1 * fmaf(-0.5f, t1, a1) + t2 * fmaf(-0.5f, t2, a2) +
@@ -204,41 +208,76 @@ __device__ inline void acc_block_store(Acc& a, float* __restrict__ out, float (*
   }
 }
 
+// Per-wave queue of matched (n, m) pairs in LDS: a ring of kQueue entries that each wave fills from its
+// scanned pixels and drains in rounds of 64, so that every lane of a round computes a valid match
+// (the scanned tile holds holes, unmatched pixels and band edges that would otherwise idle lanes).
+constexpr int kScanU = 4;    // scanned pixels per lane per refill
+constexpr int kRounds = 4;   // rounds of 64 matches per drain batch (2 gathers each in flight per lane)
+constexpr int kQueue = 512;  // >= 64 * (kScanU + kRounds), a power of two
+static_assert(kQueue >= 64 * (kScanU + kRounds) && (kQueue & (kQueue - 1)) == 0, "queue size");
+
+template <int DT>
+__device__ inline void drain_rounds(Acc& a, const void* __restrict__ arena, const EdgeDev& E, const int2* q,
+                                    unsigned& head, unsigned avail, const float* M, const GnConst& k) {
+  using raw_t = typename Px<DT>::raw_t;
+  const int lane = threadIdx.x & (kWave - 1);
+  int2 e[kRounds];
+  raw_t rj[kRounds], ri[kRounds];
+  bool ok[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    ok[r] = unsigned(r * kWave + lane) < avail;
+    e[r] = ok[r] ? q[(head + r * kWave + lane) & (kQueue - 1)] : make_int2(0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r)
+    if (ok[r]) {
+      rj[r] = Px<DT>::load_raw(arena, E.off_j + e[r].x);
+      ri[r] = Px<DT>::load_raw(arena, E.off_i + e[r].y);
+    }
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r)
+    if (ok[r]) acc_pixel(a, Px<DT>::unpack(rj[r]), Px<DT>::unpack(ri[r]), M, k);
+  head += min(avail, unsigned(kRounds * kWave));
+}
+
 template <int DT, int PPT>
 __device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev& E, int tile,
                                    const float* M, const int32_t* __restrict__ idx_arena,
-                                   float* __restrict__ out, const GnConst& k, float (*lds)[37]) {
+                                   float* __restrict__ out, const GnConst& k, float (*lds)[37],
+                                   int2* __restrict__ queue) {
+  static_assert(PPT % kScanU == 0, "pixels per thread must be a multiple of the scan unroll");
   Acc a;
   acc_zero(a);
   const int64_t base = int64_t(tile) * (kReduceThreads * PPT);
   const int32_t* __restrict__ idx = idx_arena + E.idx_off;
-  // U pixels in flight per thread: idx loads, then the raw pointmap loads of the valid ones, then the
-  // math, so the waits for the gathers come after all of them were issued
-  constexpr int U = (DT == DS3_BF16) ? (PPT < 8 ? PPT : 8) : 4;
-  static_assert(PPT % U == 0, "pixels per thread must be a multiple of the unroll");
-  using raw_t = typename Px<DT>::raw_t;
+  int2* q = queue + (threadIdx.x / kWave) * kQueue;
+  unsigned head = 0, tail = 0;  // wave-uniform
 #pragma unroll 1
-  for (int k0 = 0; k0 < PPT; k0 += U) {
-    int32_t m[U];
-    raw_t rj[U], ri[U];
+  for (int k0 = 0; k0 < PPT; k0 += kScanU) {
+    int32_t m[kScanU];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < kScanU; ++u) {
       const int64_t n = base + int64_t(k0 + u) * kReduceThreads + threadIdx.x;
       m[u] = (n < E.npx_j) ? __builtin_nontemporal_load(idx + n) : -1;
       if (m[u] >= E.npx_i) m[u] = -1;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t n = base + int64_t(k0 + u) * kReduceThreads + threadIdx.x;
-      if (m[u] >= 0) {
-        rj[u] = Px<DT>::load_raw(arena, E.off_j + n);
-        ri[u] = Px<DT>::load_raw(arena, E.off_i + m[u]);
+    for (int u = 0; u < kScanU; ++u) {
+      const bool valid = m[u] >= 0;
+      const uint64_t ballot = __ballot(valid);
+      if (valid) {
+        const unsigned below = __builtin_amdgcn_mbcnt_hi(uint32_t(ballot >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo(uint32_t(ballot), 0u));
+        const int n = int(base + int64_t(k0 + u) * kReduceThreads + threadIdx.x);
+        q[(tail + below) & (kQueue - 1)] = make_int2(n, m[u]);
       }
+      tail += unsigned(__popcll(ballot));
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (m[u] >= 0) acc_pixel(a, Px<DT>::unpack(rj[u]), Px<DT>::unpack(ri[u]), M, k);
+    __builtin_amdgcn_wave_barrier();  // the wave's queue writes are ordered before its reads
+    while (tail - head >= unsigned(kRounds * kWave)) drain_rounds<DT>(a, arena, E, q, head, kRounds * kWave, M, k);
   }
+  while (tail != head) drain_rounds<DT>(a, arena, E, q, head, tail - head, M, k);
   acc_block_store(a, out, lds);
 }
 
@@ -248,11 +287,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_one(
     const void* __restrict__ arena, EdgeDev E, int edge_id, const EdgeXf* __restrict__ xf,
     const int32_t* __restrict__ idx_arena, float* __restrict__ partials, GnConst k) {
   __shared__ float lds[kReduceThreads / kWave][37];
+  __shared__ int2 queue[kReduceThreads / kWave * kQueue];
   float M[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) M[q] = xf[edge_id].m[q];
   reduce_tile<DT, PPT>(arena, E, blockIdx.x, M, idx_arena,
-                       partials + int64_t(E.tile0 + blockIdx.x) * kPartial, k, lds);
+                       partials + int64_t(E.tile0 + blockIdx.x) * kPartial, k, lds, queue);
 }
 
 // Batched form: persistent blocks pop (edge, tile) items, longest first, from one queue.
@@ -262,6 +302,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_batched(
     int n_items, const EdgeXf* __restrict__ xf, const int32_t* __restrict__ idx_arena,
     float* __restrict__ partials, unsigned* __restrict__ queue_counter, GnConst k) {
   __shared__ float lds[kReduceThreads / kWave][37];
+  __shared__ int2 queue[kReduceThreads / kWave * kQueue];
   __shared__ int s_item;
 #pragma unroll 1
   for (;;) {
@@ -276,7 +317,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_batched(
 #pragma unroll
     for (int q = 0; q < 12; ++q) M[q] = xf[W.edge].m[q];
     reduce_tile<DT, PPT>(arena, E, W.tile, M, idx_arena, partials + int64_t(E.tile0 + W.tile) * kPartial,
-                         k, lds);
+                         k, lds, queue);
     __syncthreads();
   }
 }

@@ -296,6 +296,38 @@ class SynthGraph:
     def gt_idx_all(self):
         return [self.gt_idx(e) for e in range(len(self.edges))]
 
+    def gt_idx_all_torch(self, dev, rel_tol=0.05):
+        """gt_idx of every edge computed with torch on `dev` (for the long-horizon graph, where the
+        per-edge numpy version takes a minute), concatenated in edge order as one int32 tensor. The
+        projection is written element by element in the same order as gt_idx."""
+        out = []
+        world, dist_i = {}, {}
+        for e in range(len(self.edges)):
+            i, j = (int(v) for v in self.edges[e])
+            if j not in world:
+                world[j] = torch.as_tensor(self.world[j], dtype=torch.float64, device=dev)
+            if i not in dist_i:
+                dist_i[i] = torch.as_tensor(self.dist[i], dtype=torch.float64, device=dev)
+            cam = self.cams[i]
+            R, t, _ = pose_parts(self.poses_gt[i])
+            A = world[j] - torch.as_tensor(t, dtype=torch.float64, device=dev)
+            X = [A[:, 0] * float(R[0, c]) + A[:, 1] * float(R[1, c]) + A[:, 2] * float(R[2, c]) for c in range(3)]
+            z = X[2]
+            u = cam.f * X[0] / z + cam.cx
+            v = cam.f * X[1] / z + cam.cy
+            ok = (z > 0.05) & (u > -0.5) & (u < cam.W - 0.5) & (v > -0.5) & (v < cam.H - 0.5)
+            mu = torch.clamp(torch.floor(u + 0.5), 0, cam.W - 1).to(torch.int64)
+            mv = torch.clamp(torch.floor(v + 0.5), 0, cam.H - 1).to(torch.int64)
+            m = torch.where(ok, mv * cam.W + mu, torch.zeros_like(mu))
+            dist = torch.sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2])
+            di = dist_i[i][m]
+            ok = ok & (torch.abs(di - dist) <= rel_tol * di)
+            col = torch.arange(A.shape[0], device=dev) % self.cams[j].W
+            lo, hi = self.band[e]
+            ok = ok & (col >= lo) & (col < hi)
+            out.append(torch.where(ok, m, torch.full_like(m, -1)).to(torch.int32))
+        return torch.cat(out)
+
 
 # ---------------------------------------------------------------------------------------------
 # Construction helpers

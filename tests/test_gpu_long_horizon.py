@@ -1,0 +1,93 @@
+"""GPU parity of the forward cost and the hand-written adjoint on the long-horizon graph (4 agents x 250
+keyframes at 512x384, 4000 edges, BF16 storage), in the launch configuration the benchmark's
+long-horizon mode times: one ds3_gn_cost and one ds3_gn_cost_adjoint over the whole graph.
+
+The oracle cannot redo the whole graph in seconds, so the full-size outputs are checked on sampled
+keyframes (every edge that touches a sampled keyframe goes into an oracle subgraph, which makes the
+sampled keyframes' pose gradients and per-pixel gradients complete), and through a property that holds
+at any size: the pose tangent gradients sum to zero over the keyframes (gauge invariance of E under a
+common left Sim(3) perturbation)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ds3 = pytest.importorskip("paper_2605_30488_amd.api")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def long_graph(dev):
+    g = synth.make_config(5)
+    idx = g.gt_idx_all_torch(dev)
+    arena = ds3.build_arena(g.xyz, g.conf, "bf16", dev)
+    G = ds3.Graph(arena, [(int(i), int(j)) for i, j in g.edges], idx, anchors=(0,))
+    P = torch.as_tensor(g.poses_init).to(dev)
+    cost = ds3.gn_cost(G, P).item()
+    gx, gc, gt = ds3.gn_cost_adjoint(G, P)
+    torch.cuda.synchronize()
+    return g, G, P, idx, cost, gx, gc, gt
+
+
+def _bf16(a):
+    return O.bf16_to_f32(O.bf16_round(a)).reshape(np.shape(a)).astype(np.float64)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_fullsize_sampled_keyframes(dev, long_graph):
+    """Six seeded keyframes (spread over the agents): their dE/dtau rows, and dE/dxyz and dE/dconf over
+    all their pixels, from the full-graph launch against the FP64 oracle on every edge incident to them
+    (same BF16-rounded inputs, same matches); FP32 arithmetic error only."""
+    g, G, P, idx, cost, gx, gc, gt = long_graph
+    assert np.isfinite(cost) and cost > 0
+    rng = np.random.default_rng(55)
+    sample = sorted(rng.choice(g.n_kf, size=6, replace=False).tolist())
+    pick = [e for e, (i, j) in enumerate(G.edges) if i in sample or j in sample]
+    kfs = sorted({v for e in pick for v in G.edges[e]})
+    remap = {k: n for n, k in enumerate(kfs)}
+    idx_np = idx.cpu().numpy()
+    sub_idx = [idx_np[G.idx_offsets[e]:G.idx_offsets[e] + g.shape(G.edges[e][1])[0] * g.shape(G.edges[e][1])[1]]
+               for e in pick]
+    og = O.Graph([_bf16(g.xyz[k]) for k in kfs], [_bf16(g.conf[k]) for k in kfs],
+                 [(remap[G.edges[e][0]], remap[G.edges[e][1]]) for e in pick], sub_idx, anchors=())
+    E_ref, rx, rc, rt = O.cost_grad(og, g.poses_init[kfs])
+    # the same kernels on the subgraph's edges (full arena, idx offsets into the full idx arena)
+    Gs = ds3.Graph(G.arena, [G.edges[e] for e in pick], idx, [G.idx_offsets[e] for e in pick], anchors=())
+    E_sub = ds3.gn_cost(Gs, P).item()
+    print(f"sampled keyframes {sample}: {len(pick)} incident edges; subgraph cost {E_sub:.6e} vs {E_ref:.6e}")
+    assert abs(E_sub - E_ref) <= 1e-5 * E_ref
+    gx_np, gc_np, gt_np = gx.cpu().numpy(), gc.cpu().numpy(), gt.cpu().numpy()
+    px_off = np.cumsum([0] + [g.shape(k)[0] * g.shape(k)[1] for k in range(g.n_kf)])
+    sub_off = np.cumsum([0] + [g.shape(k)[0] * g.shape(k)[1] for k in kfs])
+    for k in sample:
+        a, b = px_off[k], px_off[k + 1]
+        s = remap[k]
+        sa, sb = sub_off[s], sub_off[s + 1]
+        ex = np.abs(gx_np[a:b] - rx[sa:sb]).max() / np.abs(rx[sa:sb]).max()
+        ec = np.abs(gc_np[a:b] - rc[sa:sb]).max() / np.abs(rc[sa:sb]).max()
+        et = np.abs(gt_np[k] - rt[s]).max() / np.abs(rt[s]).max()
+        print(f"kf {k}: rel err dE/dxyz {ex:.2e} dE/dconf {ec:.2e} dE/dtau {et:.2e}")
+        assert ex <= 2e-4 and ec <= 2e-4 and et <= 1e-3
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_fullsize_pose_gradients_sum_to_zero(dev, long_graph):
+    """Gauge invariance at full size: sum over the 1000 keyframes of dE/dtau vanishes to FP32
+    accumulation error relative to the sum of magnitudes."""
+    g, G, P, idx, cost, gx, gc, gt = long_graph
+    gt_np = gt.cpu().numpy()
+    assert np.all(np.isfinite(gt_np)) and np.all(np.isfinite(gx.cpu().numpy()))
+    s = np.abs(gt_np.sum(0))
+    m = np.abs(gt_np).sum(0)
+    print(f"|sum_k dE/dtau_k| {s} vs sum_k |dE/dtau_k| {m}")
+    assert np.all(s <= 1e-4 * m)

@@ -243,3 +243,14 @@ def test_cost_gradient_matches_finite_differences():
         em = O.cost(g, poses)
         g.conf[flat] = save
         assert abs((ep - em) / (2 * h) - gc[flat]) <= 1e-5 * max(1.0, abs(gc[flat]))
+
+
+def test_pose_gradient_sums_to_zero():
+    """E depends on the poses only through T_i^-1 T_j, so a common left perturbation Exp(xi) of every
+    pose leaves it unchanged: with the left update the pose tangent gradients sum to zero over the
+    keyframes (all seven components, scale included)."""
+    g, gt = _graph(seed=17, n_kf=4)
+    poses = perturb(gt, np.random.default_rng(18), rot=0.03, trans=0.03, scale=0.03, fixed=())
+    _, _, _, gt_tau = O.cost_grad(g, poses)
+    assert np.abs(gt_tau).max() > 1e-3
+    assert np.abs(gt_tau.sum(0)).max() <= 1e-9 * np.abs(gt_tau).sum(0).max()
