@@ -240,7 +240,7 @@ def run_long_horizon(args, dev):
                                   "step = forward cost + hand-written adjoint (dE/dxyz, dE/dconf, dE/dtau)",
                       "n_kf": g.n_kf, "n_edges": len(edges), "edge_px_scanned": px_scanned,
                       "edge_px_valid": px_valid},
-           "roofline": {"kernel": "k_edge_adjoint", "bound": "hbm", "achieved": round(gbs, 1),
+           "roofline": {"kernel": "k_adjoint_gather_j + k_adjoint_scatter_i", "bound": "hbm", "achieved": round(gbs, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                         "launch_ms": round(k_ms, 4), "bytes_per_launch": adj_bytes},
            "cost": float(c.item()), "grad_tau_norm": float(gt.norm().item())}

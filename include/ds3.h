@@ -266,16 +266,20 @@ int ds3_gn_plan_destroy(void* plan);
  * Cost and its adjoint (gradient of eq. 5 with the matches held fixed)
  * ------------------------------------------------------------------------------------------------- */
 
-/* E_global at poses (device float64 scalar); per-edge recomputation, no stored Jacobians. */
+/* E_global at poses (device float64 scalar): one launch over every (edge, tile) pair evaluates the Huber
+ * cost of each valid match (float32 per block, float64 per edge, fixed summation order, so the result
+ * is reproducible), no Jacobians. */
 int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const void* xyzc_arena,
                 ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges, const int32_t* idx_arena,
                 const ds3_gn_params* params, double* cost_out, void* workspace, size_t ws_bytes,
                 void* stream);
 
-/* dE/dX and dE/dC per arena pixel (device float32, 3 resp. 1 per pixel, ACCUMULATED into the caller's
- * buffers: zero them first) and dE/dtau per keyframe (device float64 n_kf x 7, overwritten), all scaled
- * by dcost (host float). The per-pixel scatter onto the gathered side uses float atomics, so those sums
- * are not bitwise reproducible. adjoint_timer (may be NULL) is recorded around the per-pixel launch. */
+/* dE/dX and dE/dC per arena pixel (device float32, 3 resp. 1 per pixel) and dE/dtau per keyframe (device
+ * float64 n_kf x 7), all scaled by dcost (host float) and all OVERWRITTEN for every pixel of every
+ * keyframe in kf (arena pixels outside the keyframes are left untouched). Two per-pixel launches: the
+ * query side is gathered per keyframe and stored, then the gathered side adds its terms with float
+ * atomics, so the per-pixel sums are not bitwise reproducible. adjoint_timer (may be NULL) is recorded
+ * around the two per-pixel launches. */
 int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, const void* xyzc_arena,
                         ds3_dtype dtype, const ds3_edge* edges, int32_t n_edges,
                         const int32_t* idx_arena, const ds3_gn_params* params, float dcost,

@@ -421,12 +421,13 @@ def gn_cost(graph: Graph, poses, params=None):
 
 def gn_cost_adjoint(graph: Graph, poses, dcost=1.0, params=None, timer=None):
     """(dE/dxyz (P, 3) float32, dE/dconf (P,) float32, dE/dtau (N, 7) float64), scaled by dcost; timer (a
-    KernelTimer) is recorded around the per-pixel adjoint launch."""
+    KernelTimer) is recorded around the two per-pixel adjoint launches. The arena is assumed to hold only
+    the graph's keyframes (every pixel is written)."""
     P = params or default_gn_params()
     dev = poses.device
     npx = graph.arena.data.shape[0]
-    gx = torch.zeros((npx, 3), dtype=torch.float32, device=dev)
-    gc = torch.zeros(npx, dtype=torch.float32, device=dev)
+    gx = torch.empty((npx, 3), dtype=torch.float32, device=dev)
+    gc = torch.empty(npx, dtype=torch.float32, device=dev)
     gt = torch.empty((graph.n_kf, 7), dtype=torch.float64, device=dev)
     ws = graph.workspace()
     call("ds3_gn_cost_adjoint", _ptr(poses), graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype,

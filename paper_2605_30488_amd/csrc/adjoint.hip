@@ -9,8 +9,10 @@
 //   dE/dC = sum_c w_c r_c^2 / (4 C) for both endpoint confidences (r_c scales with (C_i C_j)^(1/4)),
 //   dE/dtau_j = Ad^T [dE/dx; x x dE/dx; x . dE/dx] summed over the edge,  dE/dtau_i = -(the same)
 //   (the chain of eq. 6 and the -/+Ad endpoint maps; equal to the Gauss-Newton gradient g).
-// The pointmap / confidence scatter uses float atomics (many matches of one edge can land on one pixel
-// of i, and keyframes belong to several edges).
+// Two passes: the query side of every pixel is gathered over the edges that end in its keyframe and
+// stored once (no atomics, which also clears the outputs); the gathered side then adds its terms with
+// float atomics, since several matches of one edge can land on one pixel of i and a keyframe is the
+// gathered side of several edges.
 #include "common.hpp"
 #include "internal.hpp"
 #include "sim3.hpp"
@@ -20,11 +22,146 @@ namespace ds3 {
 constexpr int kAdjThreads = 256;
 constexpr int kAdjPPT = 8;
 
+// Forward pass and cotangents of one match (n of j, m of i), scaled by dcost. Returns false for the
+// pixels the cost skips (holes, zero ranges, bad confidences, non-finite values).
+struct AdjPix {
+  float x[3];    // T_ij X_j[n]
+  float gx[3];   // dE/dx
+  float gam[4];  // dE/de
+  float pi[3];   // psi(X_i[m])
+  float rdi;     // 1 / |X_i[m]|
+  float dc;      // sum_c w_c r_c^2
+};
+
+__device__ inline bool adj_pixel(const float4 Xj, const float4 Xi, const float* M, const GnConst& k, float dcost,
+                                 AdjPix& o) {
+  const float x0 = fmaf(M[0], Xj.x, fmaf(M[1], Xj.y, fmaf(M[2], Xj.z, M[9])));
+  const float x1 = fmaf(M[3], Xj.x, fmaf(M[4], Xj.y, fmaf(M[5], Xj.z, M[10])));
+  const float x2 = fmaf(M[6], Xj.x, fmaf(M[7], Xj.y, fmaf(M[8], Xj.z, M[11])));
+  const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+  const float di2 = fmaf(Xi.x, Xi.x, fmaf(Xi.y, Xi.y, Xi.z * Xi.z));
+  const float dj2 = fmaf(Xj.x, Xj.x, fmaf(Xj.y, Xj.y, Xj.z * Xj.z));
+  const float cc = Xi.w * Xj.w;
+  const float mn = fminf(fminf(d2, di2), dj2);
+  const float sum = (d2 + di2) + (dj2 + cc);
+  if (!(mn > 1e-18f) || !(cc >= 0.0f) || !(sum < __builtin_huge_valf())) return false;
+  const float rd = rsqrtf(d2), rdi = rsqrtf(di2);
+  const float d = d2 * rd, di = di2 * rdi;
+  const float p[3] = {x0 * rd, x1 * rd, x2 * rd};
+  o.pi[0] = Xi.x * rdi;
+  o.pi[1] = Xi.y * rdi;
+  o.pi[2] = Xi.z * rdi;
+  o.rdi = rdi;
+  const float e4[4] = {p[0] - o.pi[0], p[1] - o.pi[1], p[2] - o.pi[2], d - di};
+  const float sq = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(cc));
+  const float isg[4] = {k.inv_sr, k.inv_sr, k.inv_sr, k.inv_sd};
+  float dc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float r = sq * e4[c] * isg[c];
+    const float w = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(fabsf(r)));
+    o.gam[c] = w * r * sq * isg[c] * dcost;
+    dc = fmaf(w * r, r, dc);
+  }
+  o.dc = dc * dcost;
+  const float pg = p[0] * o.gam[0] + p[1] * o.gam[1] + p[2] * o.gam[2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o.gx[a] = (o.gam[a] - p[a] * pg) * rd + o.gam[3] * p[a];
+  o.x[0] = x0;
+  o.x[1] = x1;
+  o.x[2] = x2;
+  return true;
+}
+
+// Query side, gathered: block (tile, k) owns 2048 pixels of keyframe k and walks the edges that end in
+// k (j = k). Per pixel it sums dE/dX_k = (s_ij R_ij)^T dE/dx and the j half of dE/dC over those edges in
+// registers and stores them once (zeros where nothing contributes); per (edge, tile) it leaves the
+// seven pose-tangent pieces [g; x cross g; x . g] in part7 (row stride `stride` tiles).
 template <int DT>
-__global__ __launch_bounds__(kAdjThreads) void k_edge_adjoint(
+__global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather_j(
+    const void* __restrict__ arena, const EdgeDev* __restrict__ edges, const EdgeXf* __restrict__ xf,
+    const int32_t* __restrict__ idx_arena, const int64_t* __restrict__ kf_off, const int32_t* __restrict__ kf_npx,
+    const int32_t* __restrict__ node_ptr, const int32_t* __restrict__ node_adj, GnConst k, float dcost,
+    float* __restrict__ grad_xyz, float* __restrict__ grad_conf, float* __restrict__ part7, int stride) {
+  const int kf = blockIdx.y;
+  const int tile = blockIdx.x;
+  const int npx = kf_npx[kf];
+  if (tile * kAdjThreads * kAdjPPT >= npx) return;  // uniform per block
+  const int64_t off = kf_off[kf];
+  typename Px<DT>::raw_t xr[kAdjPPT];
+  float acc[kAdjPPT][4];
+#pragma unroll
+  for (int u = 0; u < kAdjPPT; ++u) {
+    const int n = tile * kAdjThreads * kAdjPPT + u * kAdjThreads + threadIdx.x;
+    xr[u] = Px<DT>::load_raw(arena, off + (n < npx ? n : 0));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[u][c] = 0.0f;
+  }
+  __shared__ float red[kAdjThreads / kWave][8];
+  for (int q = node_ptr[kf]; q < node_ptr[kf + 1]; ++q) {
+    const int code = node_adj[q];
+    if (!(code & 1)) continue;  // this keyframe is the gathered side of that edge
+    const int e = code >> 1;
+    const EdgeDev E = edges[e];
+    float M[12];
+#pragma unroll
+    for (int r = 0; r < 12; ++r) M[r] = xf[e].m[r];
+    const int32_t* idx = idx_arena + E.idx_off;
+    float g7[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < kAdjPPT; ++u) {
+      const int n = tile * kAdjThreads * kAdjPPT + u * kAdjThreads + threadIdx.x;
+      const int32_t m = (n < npx) ? idx[n] : -1;
+      if (m < 0 || m >= E.npx_i) continue;
+      const float4 Xj = Px<DT>::unpack(xr[u]);
+      const float4 Xi = Px<DT>::load(arena, E.off_i + m);
+      AdjPix o;
+      if (!adj_pixel(Xj, Xi, M, k, dcost, o)) continue;
+      acc[u][0] += M[0] * o.gx[0] + M[3] * o.gx[1] + M[6] * o.gx[2];
+      acc[u][1] += M[1] * o.gx[0] + M[4] * o.gx[1] + M[7] * o.gx[2];
+      acc[u][2] += M[2] * o.gx[0] + M[5] * o.gx[1] + M[8] * o.gx[2];
+      acc[u][3] += o.dc / (4.0f * Xj.w);
+      g7[0] += o.gx[0];
+      g7[1] += o.gx[1];
+      g7[2] += o.gx[2];
+      g7[3] += o.x[1] * o.gx[2] - o.x[2] * o.gx[1];
+      g7[4] += o.x[2] * o.gx[0] - o.x[0] * o.gx[2];
+      g7[5] += o.x[0] * o.gx[1] - o.x[1] * o.gx[0];
+      g7[6] += o.x[0] * o.gx[0] + o.x[1] * o.gx[1] + o.x[2] * o.gx[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      const float v = wave_sum(g7[c]);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+      float v = 0.0f;
+      for (int w = 0; w < kAdjThreads / kWave; ++w) v += red[w][threadIdx.x];
+      part7[(int64_t(e) * stride + tile) * 8 + threadIdx.x] = v;
+    }
+    __syncthreads();  // red is reused by the next edge
+  }
+#pragma unroll
+  for (int u = 0; u < kAdjPPT; ++u) {
+    const int n = tile * kAdjThreads * kAdjPPT + u * kAdjThreads + threadIdx.x;
+    if (n >= npx) continue;
+    float* gj = grad_xyz + 3 * (off + n);
+    gj[0] = acc[u][0];
+    gj[1] = acc[u][1];
+    gj[2] = acc[u][2];
+    grad_conf[off + n] = acc[u][3];
+  }
+}
+
+// Gathered side, scattered: the matches of one tile of an edge add dE/dX_i[m] and the i half of dE/dC
+// with float atomics (several matches can land on one pixel of i, and a keyframe is the gathered side of
+// several edges). Runs after k_adjoint_gather_j, whose plain stores it accumulates onto.
+template <int DT>
+__global__ __launch_bounds__(kAdjThreads) void k_adjoint_scatter_i(
     const void* __restrict__ arena, const EdgeDev* __restrict__ edges, const EdgeXf* __restrict__ xf,
     const int32_t* __restrict__ idx_arena, GnConst k, float dcost, float* __restrict__ grad_xyz,
-    float* __restrict__ grad_conf, float* __restrict__ part7) {
+    float* __restrict__ grad_conf) {
   const int e = blockIdx.y;
   const EdgeDev E = edges[e];
   const int tile = blockIdx.x;
@@ -33,8 +170,45 @@ __global__ __launch_bounds__(kAdjThreads) void k_edge_adjoint(
   float M[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) M[q] = xf[e].m[q];
-  float g7[7] = {0, 0, 0, 0, 0, 0, 0};
   const int32_t* idx = idx_arena + E.idx_off;
+#pragma unroll 2
+  for (int u = 0; u < kAdjPPT; ++u) {
+    const int64_t n = int64_t(tile) * kAdjThreads * kAdjPPT + int64_t(u) * kAdjThreads + threadIdx.x;
+    if (n >= E.npx_j) continue;
+    const int32_t m = idx[n];
+    if (m < 0 || m >= E.npx_i) continue;
+    const float4 Xj = Px<DT>::load(arena, E.off_j + n);
+    const float4 Xi = Px<DT>::load(arena, E.off_i + m);
+    AdjPix o;
+    if (!adj_pixel(Xj, Xi, M, k, dcost, o)) continue;
+    const float pgi = o.pi[0] * o.gam[0] + o.pi[1] * o.gam[1] + o.pi[2] * o.gam[2];
+    float* gi = grad_xyz + 3 * (E.off_i + m);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) atomicAdd(gi + a, -((o.gam[a] - o.pi[a] * pgi) * o.rdi + o.gam[3] * o.pi[a]));
+    atomicAdd(grad_conf + E.off_i + m, o.dc / (4.0f * Xi.w));
+  }
+}
+
+// E_global alone (eq. 5), in the same (tile, edge) grid as the adjoint: per pixel the Huber cost of the
+// four whitened residual components, with the validity rules, square roots and weights of the GN
+// reduction; per block one (cost, count) pair in the block's slot of part (stride 8).
+template <int DT>
+__global__ __launch_bounds__(kAdjThreads) void k_edge_cost(const void* __restrict__ arena,
+                                                           const EdgeDev* __restrict__ edges,
+                                                           const EdgeXf* __restrict__ xf,
+                                                           const int32_t* __restrict__ idx_arena, GnConst k,
+                                                           float* __restrict__ part) {
+  const int e = blockIdx.y;
+  const EdgeDev E = edges[e];
+  const int tile = blockIdx.x;
+  const int tiles_e = (E.npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
+  if (tile >= tiles_e) return;  // uniform per block
+  float M[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) M[q] = xf[e].m[q];
+  const int32_t* idx = idx_arena + E.idx_off;
+  float cost = 0.0f, cnt = 0.0f;
+#pragma unroll 2
   for (int u = 0; u < kAdjPPT; ++u) {
     const int64_t n = int64_t(tile) * kAdjThreads * kAdjPPT + int64_t(u) * kAdjThreads + threadIdx.x;
     if (n >= E.npx_j) continue;
@@ -49,64 +223,67 @@ __global__ __launch_bounds__(kAdjThreads) void k_edge_adjoint(
     const float di2 = fmaf(Xi.x, Xi.x, fmaf(Xi.y, Xi.y, Xi.z * Xi.z));
     const float dj2 = fmaf(Xj.x, Xj.x, fmaf(Xj.y, Xj.y, Xj.z * Xj.z));
     const float cc = Xi.w * Xj.w;
-    if (!(d2 > 1e-18f) || !(di2 > 1e-18f) || !(dj2 > 1e-18f) || !(cc >= 0.0f) || !isfinite(d2) ||
-        !isfinite(di2) || !isfinite(cc) || !isfinite(dj2))
-      continue;
+    const float mn = fminf(fminf(d2, di2), dj2);
+    const float sum = (d2 + di2) + (dj2 + cc);
+    if (!(mn > 1e-18f) || !(cc >= 0.0f) || !(sum < __builtin_huge_valf())) continue;
     const float rd = rsqrtf(d2), rdi = rsqrtf(di2);
-    const float d = d2 * rd, di = di2 * rdi;
-    const float p[3] = {x0 * rd, x1 * rd, x2 * rd};
-    const float pi[3] = {Xi.x * rdi, Xi.y * rdi, Xi.z * rdi};
-    const float e4[4] = {p[0] - pi[0], p[1] - pi[1], p[2] - pi[2], d - di};
-    const float q = sqrtf(cc), sq = sqrtf(q);
+    const float e4[4] = {x0 * rd - Xi.x * rdi, x1 * rd - Xi.y * rdi, x2 * rd - Xi.z * rdi, d2 * rd - di2 * rdi};
+    const float sq = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(cc));
     const float isg[4] = {k.inv_sr, k.inv_sr, k.inv_sr, k.inv_sd};
-    float gam[4], dc = 0.0f;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const float r = sq * e4[c] * isg[c];
-      const float a = fabsf(r);
-      const float w = (a <= k.kappa) ? 1.0f : k.kappa / a;
-      gam[c] = w * r * sq * isg[c] * dcost;
-      dc = fmaf(w * r, r, dc);
+      const float a = fabsf(sq * isg[c] * e4[c]);
+      const float t = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a)) * a;  // rho = t (|r| - t/2)
+      cost = fmaf(t, fmaf(-0.5f, t, a), cost);
     }
-    dc *= dcost;
-    // dE/dx
-    const float pg = p[0] * gam[0] + p[1] * gam[1] + p[2] * gam[2];
-    float gx[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) gx[a] = (gam[a] - p[a] * pg) * rd + gam[3] * p[a];
-    // dE/dX_j = (sR)^T gx
-    float* gj = grad_xyz + 3 * (E.off_j + n);
-    atomicAdd(gj + 0, M[0] * gx[0] + M[3] * gx[1] + M[6] * gx[2]);
-    atomicAdd(gj + 1, M[1] * gx[0] + M[4] * gx[1] + M[7] * gx[2]);
-    atomicAdd(gj + 2, M[2] * gx[0] + M[5] * gx[1] + M[8] * gx[2]);
-    // dE/dX_i
-    const float pgi = pi[0] * gam[0] + pi[1] * gam[1] + pi[2] * gam[2];
-    float* gi = grad_xyz + 3 * (E.off_i + m);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) atomicAdd(gi + a, -((gam[a] - pi[a] * pgi) * rdi + gam[3] * pi[a]));
-    atomicAdd(grad_conf + E.off_j + n, dc / (4.0f * Xj.w));
-    atomicAdd(grad_conf + E.off_i + m, dc / (4.0f * Xi.w));
-    // pose tangent pieces [g; x cross g; x . g]
-    g7[0] += gx[0];
-    g7[1] += gx[1];
-    g7[2] += gx[2];
-    g7[3] += x1 * gx[2] - x2 * gx[1];
-    g7[4] += x2 * gx[0] - x0 * gx[2];
-    g7[5] += x0 * gx[1] - x1 * gx[0];
-    g7[6] += x0 * gx[0] + x1 * gx[1] + x2 * gx[2];
+    cnt += 1.0f;
   }
-  __shared__ float red[kAdjThreads / kWave][7];
-#pragma unroll
-  for (int c = 0; c < 7; ++c) {
-    float s = wave_sum(g7[c]);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = s;
+  __shared__ float red[kAdjThreads / kWave][2];
+  cost = wave_sum(cost);
+  cnt = wave_sum(cnt);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = cost;
+    red[threadIdx.x >> 6][1] = cnt;
   }
   __syncthreads();
-  if (threadIdx.x < 7) {
+  if (threadIdx.x < 2) {
     float s = 0.0f;
     for (int w = 0; w < kAdjThreads / kWave; ++w) s += red[w][threadIdx.x];
-    part7[(int64_t(e) * gridDim.x + tile) * 8 + threadIdx.x] = s;
+    part[(int64_t(e) * gridDim.x + tile) * 8 + threadIdx.x] = s;
   }
+}
+
+// Per edge: cost and count from the tile pairs, float64 / int64, in tile order.
+__global__ void k_cost_edge_finalize(const EdgeDev* __restrict__ edges, int tiles_stride,
+                                     const float* __restrict__ part, double* __restrict__ cost_e,
+                                     int64_t* __restrict__ count_e, int n_edges) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_edges) return;
+  const int tiles_e = (edges[e].npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
+  double c = 0.0;
+  int64_t n = 0;
+  for (int t = 0; t < tiles_e; ++t) {
+    c += double(part[(int64_t(e) * tiles_stride + t) * 8]);
+    n += int64_t(part[(int64_t(e) * tiles_stride + t) * 8 + 1]);
+  }
+  cost_e[e] = c;
+  count_e[e] = n;
+}
+
+int launch_cost_batched(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
+                        const EdgeXf* xf, const int32_t* idx, GnConst c, float* part, double* cost_e,
+                        int64_t* count_e, hipStream_t s) {
+  const int tiles = (max_npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
+  if (n_edges <= 0 || tiles <= 0) return 0;
+  dim3 grid(tiles, n_edges), block(kAdjThreads);
+  if (dt == DS3_F32)
+    hipLaunchKernelGGL(k_edge_cost<DS3_F32>, grid, block, 0, s, arena, edges, xf, idx, c, part);
+  else
+    hipLaunchKernelGGL(k_edge_cost<DS3_BF16>, grid, block, 0, s, arena, edges, xf, idx, c, part);
+  DS3_TRY(check_hip(hipGetLastError(), "k_edge_cost"));
+  hipLaunchKernelGGL(k_cost_edge_finalize, dim3((n_edges + 63) / 64), dim3(64), 0, s, edges, tiles, part, cost_e,
+                     count_e, n_edges);
+  return check_hip(hipGetLastError(), "k_cost_edge_finalize");
 }
 
 // Per edge: b_e = Ad^T (sum of tile pieces), float64.
@@ -149,20 +326,35 @@ int adjoint_part_floats(int n_edges, int max_npx_j) {
 }
 
 int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
-                   const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c, float dcost,
-                   float* grad_xyz, float* grad_conf, float* part7, double* b_e, int n_kf,
-                   const int32_t* node_ptr, const int32_t* node_adj, double* grad_tau, ds3_timer* timer,
-                   hipStream_t s) {
+                   int max_npx_kf, const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c,
+                   float dcost, float* grad_xyz, float* grad_conf, float* part7, double* b_e, int n_kf,
+                   const int64_t* kf_off, const int32_t* kf_npx, const int32_t* node_ptr,
+                   const int32_t* node_adj, double* grad_tau, ds3_timer* timer, hipStream_t s) {
   const int tiles = (max_npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
+  const int tiles_kf = (max_npx_kf + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
+  DS3_TRY(timer_record(timer, true, s));
+  if (tiles_kf > 0) {
+    dim3 grid(tiles_kf, n_kf), block(kAdjThreads);
+    if (dt == DS3_F32)
+      hipLaunchKernelGGL(k_adjoint_gather_j<DS3_F32>, grid, block, 0, s, arena, edges, xf, idx, kf_off, kf_npx,
+                         node_ptr, node_adj, c, dcost, grad_xyz, grad_conf, part7, tiles);
+    else
+      hipLaunchKernelGGL(k_adjoint_gather_j<DS3_BF16>, grid, block, 0, s, arena, edges, xf, idx, kf_off, kf_npx,
+                         node_ptr, node_adj, c, dcost, grad_xyz, grad_conf, part7, tiles);
+    DS3_TRY(check_hip(hipGetLastError(), "k_adjoint_gather_j"));
+  }
   if (n_edges > 0 && tiles > 0) {
     dim3 grid(tiles, n_edges), block(kAdjThreads);
-    DS3_TRY(timer_record(timer, true, s));
     if (dt == DS3_F32)
-      hipLaunchKernelGGL(k_edge_adjoint<DS3_F32>, grid, block, 0, s, arena, edges, xf, idx, c, dcost, grad_xyz, grad_conf, part7);
+      hipLaunchKernelGGL(k_adjoint_scatter_i<DS3_F32>, grid, block, 0, s, arena, edges, xf, idx, c, dcost,
+                         grad_xyz, grad_conf);
     else
-      hipLaunchKernelGGL(k_edge_adjoint<DS3_BF16>, grid, block, 0, s, arena, edges, xf, idx, c, dcost, grad_xyz, grad_conf, part7);
-    DS3_TRY(check_hip(hipGetLastError(), "k_edge_adjoint"));
-    DS3_TRY(timer_record(timer, false, s));
+      hipLaunchKernelGGL(k_adjoint_scatter_i<DS3_BF16>, grid, block, 0, s, arena, edges, xf, idx, c, dcost,
+                         grad_xyz, grad_conf);
+    DS3_TRY(check_hip(hipGetLastError(), "k_adjoint_scatter_i"));
+  }
+  DS3_TRY(timer_record(timer, false, s));
+  if (n_edges > 0 && tiles > 0) {
     hipLaunchKernelGGL(k_adjoint_edge_finalize, dim3((n_edges + 63) / 64), dim3(64), 0, s, edges, tiles, part7,
                        Ad, b_e, n_edges);
     DS3_TRY(check_hip(hipGetLastError(), "k_adjoint_edge_finalize"));

@@ -70,7 +70,8 @@ static int upload(T* dst, const std::vector<T>& src, hipStream_t s) {
 struct Topology {
   int n_kf = 0, n_edges = 0, n_pairs = 0, total_tiles = 0, max_tiles = 0, tile_px = 0;
   std::vector<EdgeDev> edges;
-  std::vector<int32_t> node_ptr, node_adj, pair_ptr, pair_edges, pair_ij;
+  std::vector<int64_t> kf_off;
+  std::vector<int32_t> kf_npx, node_ptr, node_adj, pair_ptr, pair_edges, pair_ij;
   std::vector<uint8_t> anchor;
 };
 
@@ -82,9 +83,14 @@ static int build_topology(int n_kf, const ds3_image* kf, int n_edges, const ds3_
   T.n_kf = n_kf;
   T.n_edges = n_edges;
   T.tile_px = tile_px;
-  for (int k = 0; k < n_kf; ++k)
+  T.kf_off.resize(n_kf);
+  T.kf_npx.resize(n_kf);
+  for (int k = 0; k < n_kf; ++k) {
     if (kf[k].H <= 0 || kf[k].W <= 0 || kf[k].px_offset < 0 || int64_t(kf[k].H) * kf[k].W > INT32_MAX)
       return fail(DS3_EINVAL, "bad keyframe image " + std::to_string(k));
+    T.kf_off[k] = kf[k].px_offset;
+    T.kf_npx[k] = kf[k].H * kf[k].W;
+  }
   T.edges.resize(n_edges);
   T.total_tiles = 0;
   T.max_tiles = 0;
@@ -149,7 +155,8 @@ struct GnBuffers {
   float* partials;
   double *A_e, *b_e, *cost_e;
   int64_t* count_e;
-  int32_t *node_ptr, *node_adj, *pair_ptr, *pair_edges, *pair_ij;
+  int64_t* kf_off;
+  int32_t *kf_npx, *node_ptr, *node_adj, *pair_ptr, *pair_edges, *pair_ij;
   uint8_t* anchor;
   double *H, *g, *tau;
   double* cost_tmp;
@@ -161,11 +168,14 @@ struct GnBuffers {
 
 int adjoint_part_floats(int n_edges, int max_npx_j);
 int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
-                   const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c, float dcost,
-                   float* grad_xyz, float* grad_conf, float* part7, double* b_e, int n_kf,
-                   const int32_t* node_ptr, const int32_t* node_adj, double* grad_tau, ds3_timer* timer,
-                   hipStream_t s);
+                   int max_npx_kf, const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c,
+                   float dcost, float* grad_xyz, float* grad_conf, float* part7, double* b_e, int n_kf,
+                   const int64_t* kf_off, const int32_t* kf_npx, const int32_t* node_ptr,
+                   const int32_t* node_adj, double* grad_tau, ds3_timer* timer, hipStream_t s);
 
+int launch_cost_batched(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
+                        const EdgeXf* xf, const int32_t* idx, GnConst c, float* part, double* cost_e,
+                        int64_t* count_e, hipStream_t s);
 static int max_npx_j(const Topology& T) {
   int m = 0;
   for (auto& E : T.edges) m = std::max(m, int(E.npx_j));
@@ -184,6 +194,8 @@ static size_t carve_gn(void* base, const Topology& T, GnBuffers& B) {
   B.b_e = c.take<double>(7 * size_t(E));
   B.cost_e = c.take<double>(E);
   B.count_e = c.take<int64_t>(E);
+  B.kf_off = c.take<int64_t>(T.n_kf);
+  B.kf_npx = c.take<int32_t>(T.n_kf);
   B.node_ptr = c.take<int32_t>(T.n_kf + 1);
   B.node_adj = c.take<int32_t>(2 * size_t(E));
   B.pair_ptr = c.take<int32_t>(size_t(E) + 1);
@@ -203,6 +215,8 @@ static size_t carve_gn(void* base, const Topology& T, GnBuffers& B) {
 
 static int upload_topology(const Topology& T, GnBuffers& B, hipStream_t s) {
   DS3_TRY(upload(B.edges, T.edges, s));
+  DS3_TRY(upload(B.kf_off, T.kf_off, s));
+  DS3_TRY(upload(B.kf_npx, T.kf_npx, s));
   DS3_TRY(upload(B.node_ptr, T.node_ptr, s));
   DS3_TRY(upload(B.node_adj, T.node_adj, s));
   DS3_TRY(upload(B.pair_ptr, T.pair_ptr, s));
@@ -399,11 +413,9 @@ int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const vo
   DS3_TRY(check_arch());
   hipStream_t s = S(stream);
   DS3_TRY(upload_topology(T, B, s));
-  const GnConst c = make_gn_const(*params);
   DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
-  for (int e = 0; e < T.n_edges; ++e)
-    DS3_TRY(launch_edge_reduce_one(dtype, kPlainPPT, arena, T.edges[e], e, B.xf, idx, B.partials, c, s));
-  DS3_TRY(launch_edge_finalize(B.edges, T.n_edges, B.partials, B.Ad, B.A_e, B.b_e, B.cost_e, B.count_e, s));
+  DS3_TRY(launch_cost_batched(dtype, arena, B.edges, T.n_edges, max_npx_j(T), B.xf, idx, make_gn_const(*params),
+                              B.part7, B.cost_e, B.count_e, s));
   return launch_sum_costs(B.cost_e, B.count_e, T.n_edges, cost_out, nullptr, s);
 }
 
@@ -423,9 +435,10 @@ int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, 
   hipStream_t s = S(stream);
   DS3_TRY(upload_topology(T, B, s));
   DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
-  return launch_adjoint(dtype, arena, B.edges, T.n_edges, max_npx_j(T), B.xf, B.Ad, idx,
-                        make_gn_const(*params), dcost, grad_xyz, grad_conf, B.part7, B.b_e, T.n_kf,
-                        B.node_ptr, B.node_adj, grad_tau, adjoint_timer, s);
+  const int max_npx_kf = *std::max_element(T.kf_npx.begin(), T.kf_npx.end());
+  return launch_adjoint(dtype, arena, B.edges, T.n_edges, max_npx_j(T), max_npx_kf, B.xf, B.Ad, idx,
+                        make_gn_const(*params), dcost, grad_xyz, grad_conf, B.part7, B.b_e, T.n_kf, B.kf_off,
+                        B.kf_npx, B.node_ptr, B.node_adj, grad_tau, adjoint_timer, s);
 }
 
 }  // extern "C"
