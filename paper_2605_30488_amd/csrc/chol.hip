@@ -51,9 +51,9 @@ struct CholArgs {
 __device__ inline unsigned* bs_ready(const CholArgs& a) { return a.sync + 4 + (kMaxAttempts + 1) * a.nt; }
 
 // Columns per barrier of the diagonal factorisation, and its LDS scratch: double-buffered groups of kFw
-// published columns of T and kFw rows of X, then the block of b.
+// published columns of T and kFw rows of X, then the block of b, then the NB pivots.
 constexpr int kFw = 4;
-constexpr int kFactorScratch = 4 * kFw * NB + NB;
+constexpr int kFactorScratch = 4 * kFw * NB + 2 * NB;
 
 // ---------------------------------------------------------------------------------------------------
 // Fragment helpers. The 256 threads hold a 32x32 tile in the accumulator layout of the float64 MFMA
@@ -104,52 +104,62 @@ __device__ inline double recip(double d) {
   return y;
 }
 
+// 1/sqrt(d) from the hardware estimate refined by two Newton steps.
+__device__ inline double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 __device__ inline bool pivot_ok(double d) { return (d > 0.0) && isfinite(d); }
 
-// Cholesky of the SPD tile held as a fragment (lower triangle used), producing the inverse of its
-// factor, kFw columns per barrier. Before a step, columns c .. c+kFw-1 of T and rows c .. c+kFw-1 of the
-// inverse accumulator X (identity at the start) are published in LDS. Every thread factors the kFw x kFw
-// pivot block D (unscaled: pivots d_q, multipliers g_pq = D'[p][q] / d_q, which is the one sequential
-// chain of the step), brings its rows' and its column's entries of the published columns and rows up to
-// date within the block,
-//   a_q(r) = T[r][c+q] - sum_{p<q} a_p(r) g_qp,   x_q(j) = X[c+q][j] - sum_{p<q} g_qp x_p(j),
-// and applies the rank-kFw update
-//   T[r][s] -= sum_q a_q(r) a_q(s) / d_q   (c+kFw <= s <= r),   X[r][j] -= sum_q a_q(r) x_q(j) / d_q (r >= c+kFw),
-// while the block's own columns and rows take their step values a_q and x_q. At the end
-// L^-1[r][j] = X[r][j] / sqrt(d_r) (the factor itself, T[r][s] / sqrt(d_s), is not needed).
+// Cholesky of the SPD tile held as a fragment, producing the inverse of its factor, kFw columns per
+// barrier (right-looking LDL^T on the full symmetric tile). Before a step, columns c .. c+kFw-1 of T and
+// rows c .. c+kFw-1 of the inverse accumulator X (identity at the start) are published in LDS. Every
+// thread factors the kFw x kFw pivot block D (pivots d_q, multipliers g_pq = D'[p][q] / d_q: the one
+// sequential chain of the step) and brings the published entries it needs up to date within the block,
+//   a_q(r) = T[r][c+q] - sum_{p<q} a_p(r) g_qp,   x_q(j) = X[c+q][j] - sum_{p<q} g_qp x_p(j).
+// The rank-kFw updates
+//   T[r][s] -= sum_q (a_q(r) / d_q) a_q(s),   X[r][j] -= sum_q (a_q(r) / d_q) x_q(j)   (r >= c+kFw)
+// are one float64 MFMA each per wave (K = kFw): lane l feeds the A operand of row 16 (w/2) + l%16 and
+// pivot q = l/16 (zero for rows above the trailing block, which leaves them untouched) and the B operand
+// of column fcol() and pivot q. Entries of T outside the trailing block pick up terms that are never
+// read again. The block's own rows of X take their step values x_q. At the end
+// L^-1[r][j] = X[r][j] / sqrt(d_r) (the factor itself is not needed).
 // Returns false (uniformly) on a non-positive or non-finite pivot.
 __device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
   const int s = fcol();
-  double T[4], X[4], dr[4] = {1.0, 1.0, 1.0, 1.0};
+  const int l = threadIdx.x & 63;
+  const int rbase = 16 * (threadIdx.x >> 7);  // first row of this wave's quadrant
+  const int ra = rbase + (l & 15);            // A-operand row of this lane
+  const int qa = l >> 4;                      // pivot of both operands; also the lane's row in a group of 4
+  f64x4 X;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    T[v] = Tf[v];
-    X[v] = (frow(v) == s) ? 1.0 : 0.0;
-  }
+  for (int v = 0; v < 4; ++v) X[v] = (frow(v) == s) ? 1.0 : 0.0;
   // buffer layout per parity: kFw columns of T, then kFw rows of X, NB doubles each
   constexpr int kBuf = 2 * kFw * NB;
+  double* piv = fb + 4 * kFw * NB + NB;
   if (s < kFw)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) fb[s * NB + frow(v)] = T[v];
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    if (frow(v) < kFw) fb[(kFw + frow(v)) * NB + s] = X[v];
+    for (int v = 0; v < 4; ++v) fb[s * NB + frow(v)] = Tf[v];
+  if (rbase == 0) fb[(kFw + qa) * NB + s] = X[0];  // rows 0..3: register 0 of the top quadrants
   __syncthreads();
   bool ok = true;
   for (int c = 0; c < NB; c += kFw) {
     const double* P = fb + ((c / kFw) & 1) * kBuf;
     // every LDS read of the step first
-    double D[kFw][kFw], as[kFw], xs[kFw], av[4][kFw];
+    double D[kFw][kFw], ar[kFw], as[kFw], xs[kFw];
 #pragma unroll
     for (int p = 0; p < kFw; ++p)
 #pragma unroll
       for (int q = 0; q <= p; ++q) D[p][q] = P[q * NB + c + p];
 #pragma unroll
     for (int q = 0; q < kFw; ++q) {
+      ar[q] = P[q * NB + ra];
       as[q] = P[q * NB + s];
       xs[q] = P[(kFw + q) * NB + s];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) av[v][q] = P[q * NB + frow(v)];
     }
     // pivot block (identical in every thread, so the verdict is uniform)
     double dq[kFw], iq[kFw], g[kFw][kFw];
@@ -165,55 +175,50 @@ __device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
 #pragma unroll
         for (int r = q + 1; r <= p; ++r) D[p][r] = fma(-g[p][q], D[r][q], D[p][r]);
     }
-    // bring the published entries up to date within the block
 #pragma unroll
     for (int q = 1; q < kFw; ++q)
 #pragma unroll
       for (int p = 0; p < q; ++p) {
+        ar[q] = fma(-ar[p], g[q][p], ar[q]);
         as[q] = fma(-as[p], g[q][p], as[q]);
         xs[q] = fma(-g[q][p], xs[p], xs[q]);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) av[v][q] = fma(-av[v][p], g[q][p], av[v][q]);
       }
+    double aop = -ar[0] * iq[0], bop = as[0], xop = xs[0], dsel = dq[0];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = frow(v);
-      double t_upd = T[v], x_upd = X[v];
-#pragma unroll
-      for (int q = 0; q < kFw; ++q) {
-        const double f = av[v][q] * iq[q];
-        t_upd = fma(-f, as[q], t_upd);
-        x_upd = fma(-f, xs[q], x_upd);
-      }
-      const int qr = r - c, qs = s - c;  // position inside the block (in [0, kFw) when inside)
-#pragma unroll
-      for (int q = 0; q < kFw; ++q) dr[v] = (qr == q) ? dq[q] : dr[v];
-      double t_col = T[v], x_row = X[v];
-#pragma unroll
-      for (int q = 1; q < kFw; ++q) {
-        t_col = (qs == q) ? av[v][q] : t_col;
-        x_row = (qr == q) ? xs[q] : x_row;
-      }
-      T[v] = (qs >= kFw && s <= r) ? t_upd : ((qs > 0 && qs < kFw && r >= s) ? t_col : T[v]);
-      X[v] = (qr >= kFw) ? x_upd : ((qr > 0 && qr < kFw) ? x_row : X[v]);
+    for (int q = 1; q < kFw; ++q) {
+      aop = (qa == q) ? -ar[q] * iq[q] : aop;
+      bop = (qa == q) ? as[q] : bop;
+      xop = (qa == q) ? xs[q] : xop;
+      dsel = (qa == q) ? dq[q] : dsel;
     }
+    aop = (ra >= c + kFw) ? aop : 0.0;
+    Tf = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, Tf, 0, 0, 0);
+    X = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, xop, X, 0, 0, 0);
+    // rows c .. c+kFw-1 sit in register (c - rbase) / 4 of this quadrant, one per lane row qa: they take
+    // x_qa at this lane's column; the pivots go to LDS (lanes 0, 16, 32, 48 of wave 0 hold q = 0..3)
+    const int vin = (c - rbase) >> 2;  // wave-uniform; outside 0..3 when the rows are in the other quadrant
+    if (vin == 0) X[0] = xop;
+    else if (vin == 1) X[1] = xop;
+    else if (vin == 2) X[2] = xop;
+    else if (vin == 3) X[3] = xop;
+    if (threadIdx.x < 64 && (threadIdx.x & 15) == 0) piv[c + qa] = dsel;
     if (c + kFw < NB) {
       double* Q = fb + ((c / kFw + 1) & 1) * kBuf;
       const int qs = s - c - kFw;
       if (qs >= 0 && qs < kFw)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Q[qs * NB + frow(v)] = T[v];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int qr = frow(v) - c - kFw;
-        if (qr >= 0 && qr < kFw) Q[(kFw + qr) * NB + s] = X[v];
-      }
+        for (int v = 0; v < 4; ++v) Q[qs * NB + frow(v)] = Tf[v];
+      const int vn = (c + kFw - rbase) >> 2;  // register of rows c+kFw .. c+2kFw-1, if in this quadrant
+      if (vn == 0) Q[(kFw + qa) * NB + s] = X[0];
+      else if (vn == 1) Q[(kFw + qa) * NB + s] = X[1];
+      else if (vn == 2) Q[(kFw + qa) * NB + s] = X[2];
+      else if (vn == 3) Q[(kFw + qa) * NB + s] = X[3];
     }
     __syncthreads();
   }
   if (!ok) return false;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) Xq[v] = (s <= frow(v)) ? X[v] / sqrt(dr[v]) : 0.0;
+  for (int v = 0; v < 4; ++v) Xq[v] = (s <= frow(v)) ? X[v] * rsqrt_nr(piv[frow(v)]) : 0.0;
   return true;
 }
 
