@@ -286,6 +286,23 @@ int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, 
                         float* grad_xyz, float* grad_conf, double* grad_tau, ds3_timer* adjoint_timer,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* Cost + adjoint plan for a graph whose matches stay fixed (the contents of xyzc_arena and the poses may
+ * change between runs; idx_arena and the topology must not). Creation inverts every match map on the
+ * device: for edge e and pixel m of keyframe i(e), the pixels n of j(e) with idx[n] = m in increasing n
+ * (CSR). It allocates device memory (about 4 B per pixel of i(e) plus 4 B per pixel of j(e), per edge)
+ * and a temporary count array of 4 B per pixel of i(e) per edge, freed before it returns; it
+ * synchronises the stream. *plan_out (host) receives the plan, NULL on failure. */
+int ds3_adjoint_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena, ds3_dtype dtype,
+                            const ds3_edge* edges, int32_t n_edges, const int32_t* idx_arena,
+                            const ds3_gn_params* params, void** plan_out, void* stream);
+/* One pass over the graph at poses (device n_kf x 8): E_global into *cost_out (device float64 scalar, may
+ * be NULL) and the gradients of ds3_gn_cost_adjoint (same layouts, scaled by dcost, overwritten), with
+ * both sides of every pixel gathered in a fixed order and stored once: no atomics, bitwise reproducible.
+ * timer (may be NULL) is recorded around the per-pixel launch. Runs on one plan must not overlap. */
+int ds3_adjoint_plan_run(void* plan, const double* poses, float dcost, float* grad_xyz, float* grad_conf,
+                         double* grad_tau, double* cost_out, ds3_timer* timer, void* stream);
+int ds3_adjoint_plan_destroy(void* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,10 @@ _SIGS = {
                               sz, vp]),
     "ds3_gn_cost_adjoint": (C.c_int, [vp, i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams),
                                       f32, vp, vp, vp, vp, vp, sz, vp]),
+    "ds3_adjoint_plan_create": (C.c_int, [i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams),
+                                          C.POINTER(vp), vp]),
+    "ds3_adjoint_plan_run": (C.c_int, [vp, vp, f32, vp, vp, vp, vp, vp, vp]),
+    "ds3_adjoint_plan_destroy": (C.c_int, [vp]),
 }
 
 

@@ -436,6 +436,45 @@ def gn_cost_adjoint(graph: Graph, poses, dcost=1.0, params=None, timer=None):
     return gx, gc, gt
 
 
+class AdjointPlan:
+    """Cost + adjoint over a graph whose matches stay fixed (ds3_adjoint_plan_*): the inverse match maps
+    are built once; each run gathers both sides of every pixel (no atomics, reproducible)."""
+
+    def __init__(self, graph: Graph, params=None):
+        self.graph = graph
+        self.params = params or default_gn_params()
+        h = C.c_void_p()
+        call("ds3_adjoint_plan_create", graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
+             len(graph.edges), _ptr(graph.idx), C.byref(self.params), C.byref(h), _stream())
+        self.handle = h
+
+    def run(self, poses, dcost=1.0, timer=None, out=None):
+        """(cost (1,) float64, dE/dxyz (P, 3) float32, dE/dconf (P,) float32, dE/dtau (N, 7) float64);
+        `out` may pass those four tensors to be overwritten."""
+        dev = poses.device
+        npx = self.graph.arena.data.shape[0]
+        if out is None:
+            out = (torch.empty(1, dtype=torch.float64, device=dev),
+                   torch.empty((npx, 3), dtype=torch.float32, device=dev),
+                   torch.empty(npx, dtype=torch.float32, device=dev),
+                   torch.empty((self.graph.n_kf, 7), dtype=torch.float64, device=dev))
+        cost, gx, gc, gt = out
+        call("ds3_adjoint_plan_run", self.handle, _ptr(poses), float(dcost), _ptr(gx), _ptr(gc), _ptr(gt),
+             _ptr(cost), timer.handle if timer is not None else None, _stream())
+        return cost, gx, gc, gt
+
+    def close(self):
+        if self.handle:
+            L.load().ds3_adjoint_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class DenseSim3Cost(torch.autograd.Function):
     """E_global (eq. 5) as an autograd function of (xyz (P, 3), conf (P,), tau (N, 7)) at poses
     Exp(tau) T0 with tau = 0 at the evaluation point: forward packs the pointmaps into a float32 arena

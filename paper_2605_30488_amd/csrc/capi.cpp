@@ -173,6 +173,16 @@ int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_
                    const int64_t* kf_off, const int32_t* kf_npx, const int32_t* node_ptr,
                    const int32_t* node_adj, double* grad_tau, ds3_timer* timer, hipStream_t s);
 
+int launch_inverse_maps(const EdgeDev* edges, int n_edges, int max_npx_j, int max_npx_i, const int32_t* idx,
+                        const int64_t* cbase, const int64_t* obase, const int64_t* sbase, int32_t* cnt,
+                        size_t cnt_len, int32_t* off, int32_t* src, hipStream_t s);
+int launch_adjoint_gather(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
+                          int max_npx_kf, const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c,
+                          float dcost, float* grad_xyz, float* grad_conf, float* part7, double* b_e,
+                          double* cost_e, int64_t* count_e, int n_kf, const int64_t* kf_off,
+                          const int32_t* kf_npx, const int32_t* node_ptr, const int32_t* node_adj,
+                          const int64_t* obase, const int64_t* sbase, const int32_t* inv_off,
+                          const int32_t* inv_src, double* grad_tau, ds3_timer* timer, hipStream_t s);
 int launch_cost_batched(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
                         const EdgeXf* xf, const int32_t* idx, GnConst c, float* part, double* cost_e,
                         int64_t* count_e, hipStream_t s);
@@ -821,6 +831,138 @@ int ds3_gn_plan_info(void* plan, int64_t* info) {
 
 int ds3_gn_plan_destroy(void* plan) {
   plan_free(static_cast<Plan*>(plan));
+  return DS3_OK;
+}
+
+// ---- cost + adjoint plan over a graph with fixed matches ----------------------------------------------
+struct AdjPlan {
+  Topology T;
+  void* ws = nullptr;
+  EdgeDev* edges = nullptr;
+  EdgeXf* xf = nullptr;
+  double *Ad = nullptr, *b_e = nullptr, *cost_e = nullptr;
+  int64_t* count_e = nullptr;
+  int64_t* kf_off = nullptr;
+  int32_t *kf_npx = nullptr, *node_ptr = nullptr, *node_adj = nullptr;
+  float* part7 = nullptr;
+  int64_t *obase = nullptr, *sbase = nullptr;
+  int32_t *inv_off = nullptr, *inv_src = nullptr;
+  const void* arena = nullptr;
+  const int32_t* idx = nullptr;
+  ds3_dtype dt = DS3_F32;
+  GnConst c;
+  int max_npx_j = 0, max_npx_kf = 0;
+};
+
+static size_t carve_adj(void* base, const Topology& T, AdjPlan& A, size_t off_len, size_t src_len) {
+  Carver c(base);
+  const int E = std::max(T.n_edges, 1);
+  A.edges = c.take<EdgeDev>(E);
+  A.xf = c.take<EdgeXf>(E);
+  A.Ad = c.take<double>(49 * size_t(E));
+  A.b_e = c.take<double>(7 * size_t(E));
+  A.cost_e = c.take<double>(E);
+  A.count_e = c.take<int64_t>(E);
+  A.kf_off = c.take<int64_t>(T.n_kf);
+  A.kf_npx = c.take<int32_t>(T.n_kf);
+  A.node_ptr = c.take<int32_t>(T.n_kf + 1);
+  A.node_adj = c.take<int32_t>(2 * size_t(E));
+  A.part7 = c.take<float>(size_t(std::max(adjoint_part_floats(T.n_edges, max_npx_j(T)), 8)));
+  A.obase = c.take<int64_t>(E);
+  A.sbase = c.take<int64_t>(E);
+  A.inv_off = c.take<int32_t>(std::max<size_t>(off_len, 1));
+  A.inv_src = c.take<int32_t>(std::max<size_t>(src_len, 1));
+  return c.used;
+}
+
+static void adj_plan_free(AdjPlan* A) {
+  if (!A) return;
+  if (A->ws) (void)hipFree(A->ws);
+  delete A;
+}
+
+int ds3_adjoint_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3_dtype dtype,
+                            const ds3_edge* edges, int32_t n_edges, const int32_t* idx,
+                            const ds3_gn_params* params, void** plan_out, void* stream) {
+  if (!plan_out) return fail(DS3_EINVAL, "plan_out is null");
+  *plan_out = nullptr;
+  static const double kNotPoses = 0.0;  // the plan takes its poses at run time
+  DS3_TRY(check_gn_args(&kNotPoses, arena, idx, dtype, params));
+  DS3_TRY(check_arch());
+  hipStream_t s = S(stream);
+  AdjPlan* A = new AdjPlan();
+  int rc = build_topology(n_kf, kf, n_edges, edges, nullptr, 0, kReduceThreads * kPlainPPT, A->T);
+  if (rc != DS3_OK) { adj_plan_free(A); return rc; }
+  const Topology& T = A->T;
+  std::vector<int64_t> cbase(std::max(T.n_edges, 1), 0), obase(std::max(T.n_edges, 1), 0),
+      sbase(std::max(T.n_edges, 1), 0);
+  size_t cnt_len = 0, off_len = 0, src_len = 0;
+  int max_npx_i = 0;
+  for (int e = 0; e < T.n_edges; ++e) {
+    cbase[e] = int64_t(cnt_len);
+    obase[e] = int64_t(off_len);
+    sbase[e] = int64_t(src_len);
+    cnt_len += size_t(T.edges[e].npx_i);
+    off_len += size_t(T.edges[e].npx_i) + 1;
+    src_len += size_t(T.edges[e].npx_j);
+    max_npx_i = std::max(max_npx_i, int(T.edges[e].npx_i));
+  }
+  const size_t ws = carve_adj(nullptr, T, *A, off_len, src_len);
+  rc = check_hip(hipMalloc(&A->ws, ws), "hipMalloc(adjoint plan)");
+  if (rc != DS3_OK) { adj_plan_free(A); return rc; }
+  carve_adj(A->ws, T, *A, off_len, src_len);
+  A->arena = arena;
+  A->idx = idx;
+  A->dt = dtype;
+  A->c = make_gn_const(*params);
+  A->max_npx_j = max_npx_j(T);
+  A->max_npx_kf = *std::max_element(T.kf_npx.begin(), T.kf_npx.end());
+  // counts and the per-edge bases of the count array live in a temporary allocation
+  void* tmp = nullptr;
+  Carver tc(nullptr);
+  tc.take<int64_t>(cbase.size());
+  tc.take<int32_t>(std::max<size_t>(cnt_len, 1));
+  rc = check_hip(hipMalloc(&tmp, tc.used), "hipMalloc(adjoint plan build)");
+  if (rc != DS3_OK) { adj_plan_free(A); return rc; }
+  Carver tcc(tmp);
+  int64_t* d_cbase = tcc.take<int64_t>(cbase.size());
+  int32_t* d_cnt = tcc.take<int32_t>(std::max<size_t>(cnt_len, 1));
+  rc = upload(A->edges, T.edges, s);
+  if (rc == DS3_OK) rc = upload(A->kf_off, T.kf_off, s);
+  if (rc == DS3_OK) rc = upload(A->kf_npx, T.kf_npx, s);
+  if (rc == DS3_OK) rc = upload(A->node_ptr, T.node_ptr, s);
+  if (rc == DS3_OK) rc = upload(A->node_adj, T.node_adj, s);
+  if (rc == DS3_OK) rc = upload(A->obase, obase, s);
+  if (rc == DS3_OK) rc = upload(A->sbase, sbase, s);
+  if (rc == DS3_OK) rc = upload(d_cbase, cbase, s);
+  if (rc == DS3_OK)
+    rc = launch_inverse_maps(A->edges, T.n_edges, A->max_npx_j, max_npx_i, idx, d_cbase, A->obase, A->sbase,
+                             d_cnt, cnt_len, A->inv_off, A->inv_src, s);
+  const int rs = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize(adjoint plan build)");
+  (void)hipFree(tmp);
+  if (rc == DS3_OK) rc = rs;
+  if (rc != DS3_OK) { adj_plan_free(A); return rc; }
+  *plan_out = A;
+  return DS3_OK;
+}
+
+int ds3_adjoint_plan_run(void* plan, const double* poses, float dcost, float* grad_xyz, float* grad_conf,
+                         double* grad_tau, double* cost_out, ds3_timer* timer, void* stream) {
+  AdjPlan* A = static_cast<AdjPlan*>(plan);
+  if (!A || !poses || !grad_xyz || !grad_conf || !grad_tau) return fail(DS3_EINVAL, "null pointer");
+  hipStream_t s = S(stream);
+  const Topology& T = A->T;
+  DS3_TRY(launch_gn_prep(poses, A->edges, T.n_edges, A->xf, A->Ad, nullptr, s));
+  DS3_TRY(launch_adjoint_gather(A->dt, A->arena, A->edges, T.n_edges, A->max_npx_j, A->max_npx_kf, A->xf, A->Ad,
+                                A->idx, A->c, dcost, grad_xyz, grad_conf, A->part7, A->b_e, A->cost_e,
+                                A->count_e, T.n_kf, A->kf_off, A->kf_npx, A->node_ptr, A->node_adj, A->obase,
+                                A->sbase, A->inv_off, A->inv_src, grad_tau, timer, s));
+  if (cost_out) DS3_TRY(launch_sum_costs(A->cost_e, A->count_e, T.n_edges, cost_out, nullptr, s));
+  return DS3_OK;
+}
+
+int ds3_adjoint_plan_destroy(void* plan) {
+  adj_plan_free(static_cast<AdjPlan*>(plan));
   return DS3_OK;
 }
 

@@ -41,14 +41,15 @@ struct CholArgs {
   double* Inv;  // nt tiles: inverse of each diagonal factor (row-major 32x32, zero above the diagonal)
   double* b;    // np: -g after forward elimination
   double* y;    // np: L^-1 (-g) per block
-  double* x;    // np: solution blocks (fallback back substitution)
+  double* x;    // np: solution blocks as published by the back substitutions
   unsigned* sync;  // [0] barrier count, [1] generation, [2] error, [3] attempt-0 failed,
                    // [4 .. 4 + attempts*nt) failure of diagonal tile s in attempt r, then nt ready flags
-                   // of the fallback; from 4 + 17 nt the nt ready flags of the back substitution
+                   // of the fallback
 };
 
-// Ready flags of the back substitution's blocks, after the fallback's flags.
-__device__ inline unsigned* bs_ready(const CholArgs& a) { return a.sync + 4 + (kMaxAttempts + 1) * a.nt; }
+// Pending marker of the solution values read by the back substitution (a signalling-NaN bit pattern:
+// arithmetic only produces quiet NaNs).
+constexpr unsigned long long kXPending = 0x7ff4dead00000000ull;
 
 // Columns per barrier of the diagonal factorisation, and its LDS scratch: double-buffered groups of kFw
 // published columns of T and kFw rows of X, then the block of b, then the NB pivots.
@@ -356,8 +357,9 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_init(CholArgs a) {
   __shared__ double fb[kFactorScratch];
   int i, j;
   tile_index(blockIdx.x, i, j);
-  if (i == 0)  // flags of the back substitution start at zero
-    for (int k = threadIdx.x; k < a.nt; k += blockDim.x) bs_ready(a)[k] = 0u;
+  if (i == 0)  // every solution value starts as pending for the back substitution
+    for (int k = threadIdx.x; k < a.np; k += blockDim.x)
+      reinterpret_cast<unsigned long long*>(a.x)[k] = kXPending;
   const bool ok = init_tile(a, i, j, a.eps0, S, fb);
   if (i == 0 && threadIdx.x == 0) {
     a.sync[3] = ok ? 0u : 1u;
@@ -383,15 +385,23 @@ __device__ inline unsigned ld_acq(unsigned* p) {
 // Back substitution L^T x = y over ceil(nt / 8) workgroups. Workgroup w owns the eight diagonal blocks
 // [8w, 8w + 8) and keeps, per owned column j, acc_j = sum over the rows below its block of L[row][j] x[row]
 // (thread = column slot x half of the 32 rows of a block row). It walks the block rows from the last one
-// down: a block row above its range is applied once its owner has published x_i (flag ready[i], agent
-// scope), a block row of its own is first solved, x_i = Inv_i^T (y_i - acc_i), and published. The factor
-// rows and Inv of the next own block are prefetched one block row ahead (after a publish, so that its
-// release does not wait for them); y of the own blocks sits in LDS.
+// down: a block row above its range is applied once its owner has published x_i, a block row of its own
+// is first solved, x_i = Inv_i^T (y_i - acc_i), and published. Each published value is its own ready
+// flag: x starts as a signalling-NaN pattern no arithmetic produces, the owner overwrites it with a
+// relaxed agent-scope store and the readers poll the 32 values of the block, so no fence (which would
+// also wait for the loads in flight) sits on the chain. Factor rows and Inv blocks are loaded two block
+// rows ahead into a ring of three register buffers.
 // Every wait is bounded; a timeout sets sync[2], zeroes the workgroup's part of tau and ends in status -2.
 constexpr int kBsBlocks = 8;
 constexpr int kBsCols = kBsBlocks * NB;  // 256
 constexpr int kBsThreads = 2 * kBsCols;  // 512
 constexpr int kBsRows = NB / 2;          // rows of a block row per thread
+constexpr int kInvPer = NB * NB / kBsThreads;
+
+__device__ inline unsigned long long x_load(const double* p) {
+  return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(CholArgs a) {
   const int nt = a.nt, w = blockIdx.x;
@@ -413,47 +423,60 @@ __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(CholArgs a) {
   const int col = b0 * NB + cs;
   const bool has_col = col < b1 * NB;
   const int64_t np = a.np;
-  unsigned* ready = bs_ready(a);
   if (t < kBsCols) ys[t] = has_col ? a.y[col] : 0.0;
-  double cur[kBsRows], nxt[kBsRows];
   auto load_rows = [&](int i, double* buf) {
 #pragma unroll
     for (int r = 0; r < kBsRows; ++r)
       buf[r] = (has_col && col < i * NB) ? a.L[int64_t(i * NB + kBsRows * h + r) * np + col] : 0.0;
   };
-  constexpr int kInvPer = NB * NB / kBsThreads;
-  double inv[kInvPer];
+  auto load_inv = [&](int i, double* buf) {
+    if (i >= b0 && i < b1)
 #pragma unroll
-  for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(b1 - 1) * NB * NB + t + e * kBsThreads];
-  load_rows(nt - 1, cur);
+      for (int e = 0; e < kInvPer; ++e) buf[e] = a.Inv[int64_t(i) * NB * NB + t + e * kBsThreads];
+  };
+  double R0[kBsRows], R1[kBsRows], R2[kBsRows], I0[kInvPer], I1[kInvPer], I2[kInvPer];
+  load_rows(nt - 1, R0);
+  load_inv(nt - 1, I0);
+  if (nt - 2 >= b0) {
+    load_rows(nt - 2, R1);
+    load_inv(nt - 2, I1);
+  }
   double acc = 0.0;
   bool ok = true;
-  for (int i = nt - 1; i >= b0; --i) {
+  // one block row: cur / icur hold its factor rows and Inv, ld / ild receive those of block row i - 2
+  auto step = [&](int i, double* cur, double* ld, const double* icur, double* ild) {
+    if (i - 2 >= b0) {
+      load_rows(i - 2, ld);
+      load_inv(i - 2, ild);
+    }
     if (i >= b1) {  // block row of a later workgroup: wait for its x_i
-      if (i - 1 >= b0) load_rows(i - 1, nxt);
-      if (t == 0) {
+      if (t < 64) {
+        const double* px = a.x + i * NB + (t & (NB - 1));
         long spins = 0;
-        int good = 1;
-        while (ld_acq(&ready[i]) == 0u) {
-          if (ld_acq(&a.sync[2]) != 0u || ++spins > kSpinLimit) {
-            atomicOr(&a.sync[2], 1u);
-            good = 0;
+        bool good = true;
+        unsigned long long v = x_load(px);
+        while (!__all(v != kXPending)) {
+          if (++spins > kSpinLimit || ld_acq(&a.sync[2]) != 0u) {
+            good = false;
             break;
           }
-          __builtin_amdgcn_s_sleep(2);
+          __builtin_amdgcn_s_sleep(1);
+          v = x_load(px);
         }
-        s_ok = good;
+        if (t < NB) xs[t] = __longlong_as_double(static_cast<long long>(v));
+        if (t == 0) {
+          if (!good) atomicOr(&a.sync[2], 1u);
+          s_ok = good;
+        }
       }
       __syncthreads();
       if (!s_ok) {
         ok = false;
-        break;
+        return;
       }
-      if (t < NB) xs[t] = __hip_atomic_load(&a.x[i * NB + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __syncthreads();
     } else {  // own block: solve and publish
 #pragma unroll
-      for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBsThreads] = inv[e];
+      for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBsThreads] = icur[e];
       red[h][cs] = acc;
       __syncthreads();
       if (t < 8 * NB) {  // x_i[c] = sum_{u >= c} Inv_i[u][c] (y_i[u] - acc_i[u]), eight threads per c
@@ -470,24 +493,23 @@ __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(CholArgs a) {
         if (p == 0) {
           xs[c] = v;
           if (i * NB + c < a.n) a.tau[i * NB + c] = v;
-          __hip_atomic_store(&a.x[i * NB + c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __threadfence();
+          __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.x + i * NB + c),
+                             static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       __syncthreads();
-      if (t == 0) __hip_atomic_store(&ready[i], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      // the next block's loads go out only now, so that the release above never waits for them
-      if (i - 1 >= b0) {
-        load_rows(i - 1, nxt);
-#pragma unroll
-        for (int e = 0; e < kInvPer; ++e) inv[e] = a.Inv[int64_t(i - 1) * NB * NB + t + e * kBsThreads];
-      }
     }
 #pragma unroll
     for (int r = 0; r < kBsRows; ++r) acc = fma(cur[r], xs[kBsRows * h + r], acc);
-#pragma unroll
-    for (int r = 0; r < kBsRows; ++r) cur[r] = nxt[r];
     __syncthreads();  // xs, red and sinv are rewritten by the next block row
+  };
+  for (int i = nt - 1; i >= b0 && ok; i -= 3) {
+    step(i, R0, R2, I0, I2);
+    if (i - 1 < b0 || !ok) break;
+    step(i - 1, R1, R0, I1, I0);
+    if (i - 2 < b0 || !ok) break;
+    step(i - 2, R2, R1, I2, I1);
   }
   if (!ok) {
     for (int k = b0 * NB + t; k < min(a.n, b1 * NB); k += kBsThreads) a.tau[k] = 0.0;
@@ -654,7 +676,7 @@ size_t chol_workspace_bytes(int n) {
   c.take<double>(np);
   c.take<double>(np);
   c.take<double>(np);
-  c.take<unsigned>(4 + (kMaxAttempts + 2) * nt);
+  c.take<unsigned>(4 + (kMaxAttempts + 1) * nt);
   return c.used;
 }
 
@@ -678,7 +700,7 @@ int launch_chol_ladder(const double* H, const double* g, int n, double lambda, d
   a.b = c.take<double>(a.np);
   a.y = c.take<double>(a.np);
   a.x = c.take<double>(a.np);
-  a.sync = c.take<unsigned>(4 + (kMaxAttempts + 2) * a.nt);
+  a.sync = c.take<unsigned>(4 + (kMaxAttempts + 1) * a.nt);
   a.H = H; a.g = g; a.n = n;
   a.lambda = lambda; a.eps0 = eps0; a.mult = mult; a.attempts = attempts;
   a.tau = tau; a.status = status;

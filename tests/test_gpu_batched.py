@@ -267,3 +267,39 @@ def test_kernel_timers(dev, single, use_graph):
     pa.close()
     pb.close()
     t.close()
+
+
+def test_adjoint_plan_matches_oracle_and_is_reproducible(dev):
+    """ds3_adjoint_plan (inverse match maps + one gather pass) against the FP64 oracle's cost and gradient,
+    on a graph where several query pixels share a match (lists of length >= 2 in the inverse maps) and one
+    edge has no valid match at all; two runs are bitwise identical and agree with the atomic path."""
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=4, H=20, W=24, seed=71, frac_valid=0.8,
+                                            edges=[(0, 1), (1, 2), (2, 3), (0, 3), (3, 1)])
+    idx = [np.asarray(v, np.int32).copy() for v in idx]
+    rng = np.random.default_rng(72)
+    valid = np.flatnonzero(idx[0] >= 0)
+    dup = rng.choice(valid, size=40, replace=False)
+    idx[0][dup[20:]] = idx[0][dup[:20]]  # 20 targets matched twice (or more)
+    idx[4][:] = -1
+    xyz = [np.asarray(x, np.float32) for x in xyz]
+    conf = [np.asarray(c, np.float32) for c in conf]
+    poses = perturb(gt, np.random.default_rng(73), rot=0.01, trans=0.01, scale=0.01, fixed=())
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    G = ds3.Graph(a, edges, _t(np.concatenate(idx), dev, torch.int32), anchors=(0,))
+    P = _t(poses, dev)
+    plan = ds3.AdjointPlan(G)
+    c1, gx1, gc1, gt1 = [x.clone() for x in plan.run(P, dcost=2.0)]
+    c2, gx2, gc2, gt2 = plan.run(P, dcost=2.0)
+    torch.cuda.synchronize()
+    assert torch.equal(gx1, gx2) and torch.equal(gc1, gc2) and torch.equal(gt1, gt2) and torch.equal(c1, c2)
+    og = O.Graph(xyz, conf, edges, idx, anchors=())
+    E, rx, rc, rt = O.cost_grad(og, poses)
+    assert abs(c1.item() - E) <= 1e-5 * E
+    gx, gc, gtn = gx1.cpu().numpy(), gc1.cpu().numpy(), gt1.cpu().numpy()
+    assert np.abs(gx - 2 * rx).max() <= 2e-4 * np.abs(2 * rx).max()
+    assert np.abs(gc - 2 * rc).max() <= 2e-4 * np.abs(2 * rc).max()
+    assert np.abs(gtn - 2 * rt).max() <= 2e-4 * np.abs(2 * rt).max()
+    ax, ac, at = ds3.gn_cost_adjoint(G, P, dcost=2.0)
+    assert torch.allclose(ax, gx1, rtol=0, atol=1e-5 * float(gx1.abs().max()))
+    assert torch.allclose(ac, gc1, rtol=0, atol=1e-5 * float(gc1.abs().max()))
+    plan.close()

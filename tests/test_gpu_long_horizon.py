@@ -91,3 +91,24 @@ def test_adjoint_fullsize_pose_gradients_sum_to_zero(dev, long_graph):
     m = np.abs(gt_np).sum(0)
     print(f"|sum_k dE/dtau_k| {s} vs sum_k |dE/dtau_k| {m}")
     assert np.all(s <= 1e-4 * m)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_plan_fullsize_against_atomic_path(dev, long_graph):
+    """The gather-only plan on the full long-horizon graph, as the benchmark times it: cost equal to
+    ds3_gn_cost within FP32 summation error, gradients equal to the atomic two-pass adjoint within FP32
+    summation-order error, and two runs bitwise identical."""
+    g, G, P, idx, cost, gx, gc, gt = long_graph
+    plan = ds3.AdjointPlan(G)
+    c1, px1, pc1, pt1 = [x.clone() for x in plan.run(P)]
+    c2, px2, pc2, pt2 = plan.run(P)
+    torch.cuda.synchronize()
+    assert torch.equal(px1, px2) and torch.equal(pc1, pc2) and torch.equal(pt1, pt2)
+    print(f"plan cost {c1.item():.9e} vs batched cost kernel {cost:.9e}")
+    assert abs(c1.item() - cost) <= 1e-5 * cost
+    ex = float((px1 - gx).abs().max() / gx.abs().max())
+    ec = float((pc1 - gc).abs().max() / gc.abs().max())
+    et = float((pt1 - gt).abs().max() / gt.abs().max())
+    print(f"plan vs atomic path: rel max diff dE/dxyz {ex:.2e} dE/dconf {ec:.2e} dE/dtau {et:.2e}")
+    assert ex <= 1e-5 and ec <= 1e-5 and et <= 1e-5
+    plan.close()
