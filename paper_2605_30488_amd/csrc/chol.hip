@@ -383,20 +383,21 @@ __device__ inline unsigned ld_acq(unsigned* p) {
 }
 
 // Back substitution L^T x = y over ceil(nt / 8) workgroups. Workgroup w owns the eight diagonal blocks
-// [8w, 8w + 8) and keeps, per owned column j, acc_j = sum over the rows below its block of L[row][j] x[row]
-// (thread = column slot x half of the 32 rows of a block row). It walks the block rows from the last one
-// down: a block row above its range is applied once its owner has published x_i, a block row of its own
-// is first solved, x_i = Inv_i^T (y_i - acc_i), and published. Each published value is its own ready
-// flag: x starts as a signalling-NaN pattern no arithmetic produces, the owner overwrites it with a
-// relaxed agent-scope store and the readers poll the 32 values of the block, so no fence (which would
-// also wait for the loads in flight) sits on the chain. Factor rows and Inv blocks are loaded two block
-// rows ahead into a ring of three register buffers.
+// [8w, 8w + 8). Its first eight waves keep, per owned column j, acc_j = sum over the rows below its block
+// of L[row][j] x[row] (thread = column slot x half of the 32 rows of a block row) and keep the factor rows
+// of the next two block rows in two register buffers, refilling a buffer right after its use. The ninth wave does everything on the chain: it waits for the x_i of later workgroups, solves its
+// own blocks x_i = Inv_i^T (y_i - acc_i) from the Inv blocks staged in LDS at the start, and publishes
+// them. A loaded value only becomes usable once every older load of its wave has returned (one in-order
+// counter per wave), so the chain lives in a wave that has no loads in flight. Each published value is
+// its own ready flag: x starts as a signalling-NaN pattern no arithmetic produces, the owner overwrites it
+// with a relaxed agent-scope store and the readers poll the 32 values of the block, so no fence sits on
+// the chain.
 // Every wait is bounded; a timeout sets sync[2], zeroes the workgroup's part of tau and ends in status -2.
 constexpr int kBsBlocks = 8;
-constexpr int kBsCols = kBsBlocks * NB;  // 256
-constexpr int kBsThreads = 2 * kBsCols;  // 512
-constexpr int kBsRows = NB / 2;          // rows of a block row per thread
-constexpr int kInvPer = NB * NB / kBsThreads;
+constexpr int kBsCols = kBsBlocks * NB;       // 256
+constexpr int kBsColThreads = 2 * kBsCols;    // 512
+constexpr int kBsThreads = kBsColThreads + 64;
+constexpr int kBsRows = NB / 2;               // rows of a block row per column thread
 
 __device__ inline unsigned long long x_load(const double* p) {
   return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
@@ -413,45 +414,46 @@ __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(CholArgs a) {
     }
     return;
   }
-  __shared__ double sinv[NB * NB];
+  __shared__ double sinv[kBsBlocks * NB * NB];  // Inv of the eight own blocks, staged once
   __shared__ double ys[kBsCols];
   __shared__ double red[2][kBsCols];
   __shared__ double xs[NB];
   __shared__ int s_ok;
   const int t = threadIdx.x;
-  const int cs = t & (kBsCols - 1), h = t >> 8;
+  const bool chain = t >= kBsColThreads;  // the ninth wave
+  for (int e = t; e < kBsBlocks * NB * NB; e += kBsThreads) {
+    const int blk = b0 + e / (NB * NB);
+    sinv[e] = (blk < b1) ? a.Inv[int64_t(b0) * NB * NB + e] : 0.0;
+  }
+  const int cs = t & (kBsCols - 1), h = (t >> 8) & 1;
   const int col = b0 * NB + cs;
-  const bool has_col = col < b1 * NB;
+  const bool has_col = !chain && col < b1 * NB;
   const int64_t np = a.np;
-  if (t < kBsCols) ys[t] = has_col ? a.y[col] : 0.0;
+  if (t < kBsCols) ys[t] = (col < b1 * NB) ? a.y[col] : 0.0;
+  // column waves: factor rows of block row i from a clamped (always valid) address; entries outside the
+  // strictly lower part are masked where they are used, so that no load is waited for before its use
   auto load_rows = [&](int i, double* buf) {
+    const int ii = max(i, 0);
 #pragma unroll
-    for (int r = 0; r < kBsRows; ++r)
-      buf[r] = (has_col && col < i * NB) ? a.L[int64_t(i * NB + kBsRows * h + r) * np + col] : 0.0;
+    for (int r = 0; r < kBsRows; ++r) buf[r] = a.L[int64_t(ii * NB + kBsRows * h + r) * np + (has_col ? col : 0)];
   };
-  auto load_inv = [&](int i, double* buf) {
-    if (i >= b0 && i < b1)
-#pragma unroll
-      for (int e = 0; e < kInvPer; ++e) buf[e] = a.Inv[int64_t(i) * NB * NB + t + e * kBsThreads];
-  };
-  double R0[kBsRows], R1[kBsRows], R2[kBsRows], I0[kInvPer], I1[kInvPer], I2[kInvPer];
-  load_rows(nt - 1, R0);
-  load_inv(nt - 1, I0);
-  if (nt - 2 >= b0) {
+  // chain wave: lane l solves column c = l % 32 over the half u in 16 (l / 32) .. + 15
+  const int lc = t & 31, lh = (t >> 5) & 1;
+  double R0[kBsRows], R1[kBsRows];
+  if (!chain) {
+    load_rows(nt - 1, R0);
     load_rows(nt - 2, R1);
-    load_inv(nt - 2, I1);
   }
   double acc = 0.0;
   bool ok = true;
-  // one block row: cur / icur hold its factor rows and Inv, ld / ild receive those of block row i - 2
-  auto step = [&](int i, double* cur, double* ld, const double* icur, double* ild) {
-    if (i - 2 >= b0) {
-      load_rows(i - 2, ld);
-      load_inv(i - 2, ild);
-    }
-    if (i >= b1) {  // block row of a later workgroup: wait for its x_i
-      if (t < 64) {
-        const double* px = a.x + i * NB + (t & (NB - 1));
+  // one block row: the column waves apply cur (rows of block row i) once x_i is in xs and then refill it
+  // with block row i - 2; the chain wave either waits for x_i or solves it from Inv_i in LDS
+  auto step = [&](int i, double* cur) {
+    if (!chain) red[h][cs] = acc;
+    __syncthreads();  // acc of block i complete in red
+    if (chain) {
+      if (i >= b1) {  // a later workgroup's block
+        const double* px = a.x + i * NB + lc;
         long spins = 0;
         bool good = true;
         unsigned long long v = x_load(px);
@@ -463,53 +465,48 @@ __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(CholArgs a) {
           __builtin_amdgcn_s_sleep(1);
           v = x_load(px);
         }
-        if (t < NB) xs[t] = __longlong_as_double(static_cast<long long>(v));
-        if (t == 0) {
+        if (t == kBsColThreads) {
           if (!good) atomicOr(&a.sync[2], 1u);
           s_ok = good;
         }
-      }
-      __syncthreads();
-      if (!s_ok) {
-        ok = false;
-        return;
-      }
-    } else {  // own block: solve and publish
-#pragma unroll
-      for (int e = 0; e < kInvPer; ++e) sinv[t + e * kBsThreads] = icur[e];
-      red[h][cs] = acc;
-      __syncthreads();
-      if (t < 8 * NB) {  // x_i[c] = sum_{u >= c} Inv_i[u][c] (y_i[u] - acc_i[u]), eight threads per c
-        const int c = t >> 3, p = t & 7, base = (i - b0) * NB;
+        if (lh == 0) xs[lc] = __longlong_as_double(static_cast<long long>(v));
+      } else {  // own block: x_i[c] = sum_{u >= c} Inv_i[u][c] (y_i[u] - acc_i[u])
+        const int base = (i - b0) * NB;
+        const double* inv = sinv + (i - b0) * NB * NB;
         double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < NB / 8; ++q) {
-          const int u = p + 8 * q;  // Inv_i is zero above its diagonal
-          v = fma(sinv[u * NB + c], ys[base + u] - (red[0][base + u] + red[1][base + u]), v);
+        for (int q = 0; q < kBsRows; ++q) {
+          const int u = 16 * lh + q;
+          v = fma(inv[u * NB + lc], ys[base + u] - (red[0][base + u] + red[1][base + u]), v);
         }
-        v += __shfl_xor(v, 1, 8);
-        v += __shfl_xor(v, 2, 8);
-        v += __shfl_xor(v, 4, 8);
-        if (p == 0) {
-          xs[c] = v;
-          if (i * NB + c < a.n) a.tau[i * NB + c] = v;
-          __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.x + i * NB + c),
+        v += __shfl_xor(v, 32);
+        if (lh == 0) {
+          xs[lc] = v;
+          if (i * NB + lc < a.n) a.tau[i * NB + lc] = v;
+          __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.x + i * NB + lc),
                              static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
         }
+        if (t == kBsColThreads) s_ok = 1;
       }
-      __syncthreads();
     }
+    __syncthreads();  // x_i in xs
+    if (!s_ok) {
+      ok = false;
+      return;
+    }
+    if (!chain) {
+      if (has_col && col < i * NB) {
 #pragma unroll
-    for (int r = 0; r < kBsRows; ++r) acc = fma(cur[r], xs[kBsRows * h + r], acc);
-    __syncthreads();  // xs, red and sinv are rewritten by the next block row
+        for (int r = 0; r < kBsRows; ++r) acc = fma(cur[r], xs[kBsRows * h + r], acc);
+      }
+      load_rows(i - 2, cur);  // two buffers: this one is current again at block row i - 2
+    }
   };
-  for (int i = nt - 1; i >= b0 && ok; i -= 3) {
-    step(i, R0, R2, I0, I2);
+  for (int i = nt - 1; i >= b0 && ok; i -= 2) {
+    step(i, R0);
     if (i - 1 < b0 || !ok) break;
-    step(i - 1, R1, R0, I1, I0);
-    if (i - 2 < b0 || !ok) break;
-    step(i - 2, R2, R1, I2, I1);
+    step(i - 1, R1);
   }
   if (!ok) {
     for (int k = b0 * NB + t; k < min(a.n, b1 * NB); k += kBsThreads) a.tau[k] = 0.0;
