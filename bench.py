@@ -50,11 +50,15 @@ TRAFFIC = {
     "k_edge_reduce_batched": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "543ae9aba0cfc2d2", "bytes": 1859157892},
+        "sha": "f07d21af0a20218f", "bytes": 1868527002},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
-        "sha": "8a7b6109915a8b08", "bytes": 9303763584},
+        "sha": "8a7b6109915a8b08", "bytes": 9303755571},
+    "k_adjoint_gather": {
+        "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
+                    "paper_2605_30488_amd/csrc/internal.hpp"],
+        "sha": "5a3ef7c89ec94316", "bytes": 21874706637},
 }
 
 
