@@ -108,6 +108,7 @@ static ItemMap as_map(const ItemMapBufs& m) { return ItemMap{m.bin_start, m.pref
 // Workspace of a batched match over `dirs` directions and `sides` mutual sides.
 struct MatchWs {
   float4* rays;
+  float* conf;
   int32_t* idx_tmp;
   MatchDir* dirs;
   MutualDir* md;
@@ -121,6 +122,7 @@ static size_t carve_match(void* base, int64_t ray_px, int64_t tmp_idx, int n_dir
                           MatchWs& W) {
   Carver c(base);
   W.rays = c.take<float4>(size_t(std::max<int64_t>(ray_px, 1)));
+  W.conf = c.take<float>(size_t(std::max<int64_t>(ray_px, 1)));
   W.idx_tmp = c.take<int32_t>(size_t(std::max<int64_t>(tmp_idx, 1)));
   W.dirs = c.take<MatchDir>(std::max(n_dirs, 1));
   W.md = c.take<MutualDir>(std::max(n_sides, 1));
@@ -160,8 +162,9 @@ static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dty
     dtiles.push_back(int32_t((int64_t(E.Hj) * E.Wj + 255) / 256));
     dirs.push_back(b);
     dtiles.push_back(int32_t((int64_t(E.Hi) * E.Wi + 255) / 256));
-    MutualDir sj{E.tmp_ji, E.tmp_ij, E.out_off, E.ref_j, E.ref_i, E.Hj, E.Wj, E.Hi, E.Wi, 2 * e + 1, 1};
-    MutualDir si{E.tmp_ij, E.tmp_ji, 0, E.ref_i, E.ref_j, E.Hi, E.Wi, E.Hj, E.Wj, 2 * e, 0};
+    MutualDir sj{E.tmp_ji, E.tmp_ij, E.out_off, W.conf + E.ray_j, W.conf + E.ray_i, E.Hj, E.Wj, E.Hi, E.Wi,
+                 2 * e + 1, 1};
+    MutualDir si{E.tmp_ij, E.tmp_ji, 0, W.conf + E.ray_i, W.conf + E.ray_j, E.Hi, E.Wi, E.Hj, E.Wj, 2 * e, 0};
     sides.push_back(sj);
     stiles.push_back(int32_t((int64_t(E.Hj) * E.Wj + 255) / 256));
     sides.push_back(si);
@@ -237,7 +240,7 @@ int ds3_match(const void* ref_xyzc, ds3_image ref, const void* qry_xyzc, ds3_ima
   const char* rp = static_cast<const char*>(ref_xyzc) + ref.px_offset * pxb;
   const char* qp = static_cast<const char*>(qry_xyzc) + qry.px_offset * pxb;
   float4* rays = static_cast<float4*>(workspace);
-  DS3_TRY(launch_raymap(rp, int64_t(ref.H) * ref.W, dtype, rays, s));
+  DS3_TRY(launch_raymap(rp, int64_t(ref.H) * ref.W, dtype, rays, nullptr, s));
   return launch_match_one(rays, ref.H, ref.W, qp, qry.H, qry.W, dtype, make_match_const(*params), idx_out,
                           p_out, iters_out, s);
 }
@@ -272,8 +275,8 @@ int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const 
   auto at = [&](const void* p, int64_t off) { return static_cast<const char*>(p) + off * pxb; };
   const void* ii = at(X_ii, img_i.px_offset);
   const void* jj = at(X_jj, img_j.px_offset);
-  DS3_TRY(launch_raymap(ii, ni, dtype, W.rays, s));
-  DS3_TRY(launch_raymap(jj, nj, dtype, W.rays + ni, s));
+  DS3_TRY(launch_raymap(ii, ni, dtype, W.rays, W.conf, s));
+  DS3_TRY(launch_raymap(jj, nj, dtype, W.rays + ni, W.conf + ni, s));
   // the two cross-view maps live in different buffers: run the two directions as single launches and
   // reuse the batched mutual kernel over both sides
   const MatchConst C = make_match_const(*params);
@@ -282,8 +285,8 @@ int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const 
   DS3_TRY(launch_match_one(W.rays + ni, img_j.H, img_j.W, at(X_ij, img_i.px_offset), img_i.H, img_i.W,
                            dtype, C, W.idx_tmp + nj, nullptr, nullptr, s));
   std::vector<MutualDir> sides = {
-      MutualDir{0, nj, 0, jj, ii, img_j.H, img_j.W, img_i.H, img_i.W, 1, 1},
-      MutualDir{nj, 0, 0, ii, jj, img_i.H, img_i.W, img_j.H, img_j.W, 0, 0}};
+      MutualDir{0, nj, 0, W.conf + ni, W.conf, img_j.H, img_j.W, img_i.H, img_i.W, 1, 1},
+      MutualDir{nj, 0, 0, W.conf, W.conf + ni, img_i.H, img_i.W, img_j.H, img_j.W, 0, 0}};
   std::vector<int32_t> stiles = {int32_t((nj + 255) / 256), int32_t((ni + 255) / 256)};
   std::vector<int32_t> order, prefix, bs, bt;
   const int grid = bin_items(stiles, order, prefix, bs, bt);
@@ -355,7 +358,7 @@ int ds3_match_batch(const void* kf_arena, const ds3_image* kf, int32_t n_kf, con
   }
   MatchWs W;
   carve_match(workspace, ray_px, tmp, 2 * n_edges, 2 * n_edges, n_edges, W);
-  DS3_TRY(launch_raymap(kf_arena, ray_px, dtype, W.rays, s));
+  DS3_TRY(launch_raymap(kf_arena, ray_px, dtype, W.rays, W.conf, s));
   return run_match(es, cross_arena, dtype, make_match_const(*params), params->nu_min, W, idx_arena,
                    valid_arena, nu, admit, lm_steps, match_timer, s);
 }

@@ -19,12 +19,16 @@
 
 namespace ds3 {
 
+// Ray image (psi, |X|) of every pixel and, when conf is given, its confidence as a plain float array
+// (the mutual check then reads 4 B per pixel instead of a 16 B or 8 B xyzc entry).
 template <int DT>
-__global__ void k_raymap(const void* __restrict__ arena, int64_t n, float4* __restrict__ rays) {
+__global__ void k_raymap(const void* __restrict__ arena, int64_t n, float4* __restrict__ rays,
+                         float* __restrict__ conf) {
   int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (; k < n; k += stride) {
     float4 X = Px<DT>::load(arena, k);
+    if (conf) conf[k] = X.w;
     float d2 = fmaf(X.x, X.x, fmaf(X.y, X.y, X.z * X.z));
     float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
     if (finite3(X.x, X.y, X.z) && d2 > 1e-18f) {
@@ -36,14 +40,14 @@ __global__ void k_raymap(const void* __restrict__ arena, int64_t n, float4* __re
   }
 }
 
-int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, hipStream_t s) {
+int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, float* conf, hipStream_t s) {
   if (n <= 0) return DS3_OK;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   if (dt == DS3_F32)
-    hipLaunchKernelGGL(k_raymap<DS3_F32>, dim3(blocks), dim3(256), 0, s, arena, n, rays);
+    hipLaunchKernelGGL(k_raymap<DS3_F32>, dim3(blocks), dim3(256), 0, s, arena, n, rays, conf);
   else
-    hipLaunchKernelGGL(k_raymap<DS3_BF16>, dim3(blocks), dim3(256), 0, s, arena, n, rays);
+    hipLaunchKernelGGL(k_raymap<DS3_BF16>, dim3(blocks), dim3(256), 0, s, arena, n, rays, conf);
   return check_hip(hipGetLastError(), "k_raymap");
 }
 
@@ -311,11 +315,6 @@ __device__ inline bool round_trip(const int32_t* __restrict__ fwd, const int32_t
 }
 
 template <int DT>
-__device__ inline float conf_at(const void* arena, int64_t px) {
-  return Px<DT>::conf(arena, px);  // the confidence word only
-}
-
-template <int DT>
 __global__ __launch_bounds__(256) void k_mutual(const MutualDir* __restrict__ md, ItemMap map,
                                                 MatchConst P, const int32_t* __restrict__ idx_tmp,
                                                 int32_t* __restrict__ idx_final, uint8_t* __restrict__ valid,
@@ -331,8 +330,8 @@ __global__ __launch_bounds__(256) void k_mutual(const MutualDir* __restrict__ md
     const bool ok = round_trip(idx_tmp + M.fwd_off, idx_tmp + M.bwd_off, n, M.W_self, n_self,
                                int64_t(M.H_other) * M.W_other, P.radius, m);
     if (ok) {
-      const double cs = double(conf_at<DT>(M.conf_self, n));
-      const double co = double(conf_at<DT>(M.conf_other, m));
+      const double cs = double(M.conf_self[n]);
+      const double co = double(M.conf_other[m]);
       hit = (sqrt(co * cs) >= P.q_min) ? 1 : 0;
     }
     if (M.write_out) {

@@ -28,8 +28,8 @@ struct MatchDir {
 struct MutualDir {
   int64_t fwd_off, bwd_off;  // offsets in the temporary idx buffer (self->other, other->self)
   int64_t out_off;           // offset of the final idx / valid outputs (write_out only)
-  const void* conf_self;     // xyzc of self (pixel 0); c = confidence
-  const void* conf_other;    // xyzc of other (pixel 0)
+  const float* conf_self;    // confidences of self (pixel 0), written by the ray-image pass
+  const float* conf_other;   // confidences of other (pixel 0)
   int32_t H_self, W_self, H_other, W_other;
   int32_t count_slot;        // nu counter index
   int32_t write_out;         // 1 for the j side of an edge
@@ -43,7 +43,7 @@ struct ItemMap {
   const int32_t* bin_tiles;  // 8
 };
 
-int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, hipStream_t s);
+int launch_raymap(const void* arena, int64_t n, ds3_dtype dt, float4* rays, float* conf, hipStream_t s);
 int launch_match_one(const float4* rays, int H, int W, const void* qry, int Hq, int Wq, ds3_dtype dt,
                      const MatchConst& P, int32_t* idx_out, float* p_out, int32_t* it_out, hipStream_t s);
 // LM step counting of the batched launch: per-block sums spread over kStepStripes counters, 128 B apart.

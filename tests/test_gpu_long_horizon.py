@@ -4,9 +4,11 @@ long-horizon mode times: one ds3_gn_cost and one ds3_gn_cost_adjoint over the wh
 
 The oracle cannot redo the whole graph in seconds, so the full-size outputs are checked on sampled
 keyframes (every edge that touches a sampled keyframe goes into an oracle subgraph, which makes the
-sampled keyframes' pose gradients and per-pixel gradients complete), and through a property that holds
-at any size: the pose tangent gradients sum to zero over the keyframes (gauge invariance of E under a
-common left Sim(3) perturbation)."""
+sampled keyframes' pose gradients and per-pixel gradients complete), through a property that holds at
+any size (the pose tangent gradients sum to zero over the keyframes: gauge invariance of E under a
+common left Sim(3) perturbation), and by finite differences on 64 seeded edges against the oracle's
+finite differences and analytic gradient. The gather-only adjoint plan is checked against the two-pass
+path on the whole graph."""
 import numpy as np
 import pytest
 import torch
@@ -112,3 +114,50 @@ def test_adjoint_plan_fullsize_against_atomic_path(dev, long_graph):
     print(f"plan vs atomic path: rel max diff dE/dxyz {ex:.2e} dE/dconf {ec:.2e} dE/dtau {et:.2e}")
     assert ex <= 1e-5 and ec <= 1e-5 and et <= 1e-5
     plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_fd_on_64_seeded_edges(dev, long_graph):
+    """Finite differences on a subgraph of 64 seeded edges of the long-horizon graph, along a seeded
+    direction in every pose tangent, on the same BF16-rounded inputs: the GPU cost's central difference
+    against the oracle's at the same step (FP32 cost sums need a step of 1e-3, where truncation is
+    visible), the oracle's central difference at 1e-6 against its analytic gradient, and the GPU adjoint
+    against the oracle's analytic gradient."""
+    g, G, P, idx, cost, gx, gc, gt = long_graph
+    rng = np.random.default_rng(64)
+    pick = sorted(rng.choice(len(G.edges), size=64, replace=False).tolist())
+    Gs = ds3.Graph(G.arena, [G.edges[e] for e in pick], idx, [G.idx_offsets[e] for e in pick], anchors=())
+    kfs = sorted({v for e in pick for v in G.edges[e]})
+    d = np.zeros((g.n_kf, 7))
+    d[kfs] = rng.normal(size=(len(kfs), 7)) * np.array([1, 1, 1, 0.1, 0.1, 0.1, 0.1])
+    h = 1e-3
+    D = torch.as_tensor(d).to(dev)
+
+    def gpu_cost(sign):
+        Q = P.clone()
+        ds3.sim3_update(Q, (sign * h) * D)
+        return ds3.gn_cost(Gs, Q).item()
+
+    fd_gpu = (gpu_cost(1.0) - gpu_cost(-1.0)) / (2 * h)
+    _, _, gts = ds3.gn_cost_adjoint(Gs, P)
+    an_gpu = float((gts.cpu().numpy() * d).sum())
+    remap = {k: n for n, k in enumerate(kfs)}
+    idx_np = idx.cpu().numpy()
+    sub_idx = [idx_np[G.idx_offsets[e]:G.idx_offsets[e] + g.shape(G.edges[e][1])[0] * g.shape(G.edges[e][1])[1]]
+               for e in pick]
+    og = O.Graph([_bf16(g.xyz[k]) for k in kfs], [_bf16(g.conf[k]) for k in kfs],
+                 [(remap[G.edges[e][0]], remap[G.edges[e][1]]) for e in pick], sub_idx, anchors=())
+    p0 = g.poses_init[kfs]
+
+    def ref_fd(step):
+        return (O.cost(og, O.sim3_update(p0, step * d[kfs])) - O.cost(og, O.sim3_update(p0, -step * d[kfs]))) / (2 * step)
+
+    fd_ref = ref_fd(h)        # the same step as the GPU: the same truncation (curvature, Huber kinks)
+    fd_ref_small = ref_fd(1e-6)  # FP64 allows a step where truncation is negligible
+    _, _, _, rt = O.cost_grad(og, p0)
+    an_ref = float((rt * d[kfs]).sum())
+    print(f"directional derivative: GPU FD(h={h}) {fd_gpu:.9e}, oracle FD(h={h}) {fd_ref:.9e}, "
+          f"oracle FD(h=1e-6) {fd_ref_small:.9e}, GPU adjoint {an_gpu:.9e}, oracle adjoint {an_ref:.9e}")
+    assert abs(fd_ref_small - an_ref) <= 1e-6 * abs(an_ref)
+    assert abs(an_gpu - an_ref) <= 1e-5 * abs(an_ref)
+    assert abs(fd_gpu - fd_ref) <= 1e-4 * abs(fd_ref)
