@@ -349,14 +349,32 @@ __device__ inline void tile_index(int tt, int& i, int& j) {
   j = tt - i * (i + 1) / 2;
 }
 
+// Workgroups are dealt round-robin to the eight XCDs (block b to XCD b mod 8). Block 0 carries the
+// tile whose diagonal factorisation is the critical path; the other blocks of XCD 0 carry nothing, so
+// that tile gets the compute units of an XCD to itself, and the other tiles go to the remaining seven
+// XCDs: block b > 0 with b mod 8 != 0 takes tile b - b/8. (The placement only affects speed.)
+constexpr int kXcds = 8;
+__device__ inline int tile_of_block(int b) { return b == 0 ? 0 : ((b % kXcds) == 0 ? -1 : b - b / kXcds); }
+
+static int blocks_for_tiles(int tiles) {
+  int b = 0, t = 0;
+  while (t < tiles) {
+    if (b == 0 || b % kXcds != 0) ++t;
+    ++b;
+  }
+  return b;
+}
+
 // ---------------------------------------------------------------------------------------------------
 // Attempt 0: init, panels, back substitution
 // ---------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kCholThreads) void k_chol_init(CholArgs a) {
   __shared__ double S[NB * LDT];
   __shared__ double fb[kFactorScratch];
+  const int t = tile_of_block(blockIdx.x);
+  if (t < 0 || t >= a.nt * (a.nt + 1) / 2) return;  // uniform per block
   int i, j;
-  tile_index(blockIdx.x, i, j);
+  tile_index(t, i, j);
   if (i == 0)  // every solution value starts as pending for the back substitution
     for (int k = threadIdx.x; k < a.np; k += blockDim.x)
       reinterpret_cast<unsigned long long*>(a.x)[k] = kXPending;
@@ -373,8 +391,11 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_panel(CholArgs a, int k) 
   __shared__ double S1[NB * LDT];
   __shared__ double S2[NB * LDT];
   __shared__ double fb[kFactorScratch];
+  const int m = a.nt - k - 1;
+  const int t = tile_of_block(blockIdx.x);
+  if (t < 0 || t >= m * (m + 1) / 2) return;  // uniform per block
   int ii, jj;
-  tile_index(blockIdx.x, ii, jj);
+  tile_index(t, ii, jj);
   if (!panel_tile(a, k, k + 1 + ii, k + 1 + jj, S0, S1, S2, fb) && threadIdx.x == 0) a.sync[3] = 1u;
 }
 
@@ -703,11 +724,11 @@ int launch_chol_ladder(const double* H, const double* g, int n, double lambda, d
   a.tau = tau; a.status = status;
   // barrier words start at zero (a fill kernel, not a memset, so the sequence can be captured)
   DS3_TRY(launch_fill_u32(a.sync, 3, 0u, s));
-  hipLaunchKernelGGL(k_chol_init, dim3(a.nt * (a.nt + 1) / 2), dim3(kCholThreads), 0, s, a);
+  hipLaunchKernelGGL(k_chol_init, dim3(blocks_for_tiles(a.nt * (a.nt + 1) / 2)), dim3(kCholThreads), 0, s, a);
   DS3_TRY(check_hip(hipGetLastError(), "k_chol_init"));
   for (int k = 0; k + 1 < a.nt; ++k) {
     const int m = a.nt - k - 1;
-    hipLaunchKernelGGL(k_chol_panel, dim3(m * (m + 1) / 2), dim3(kCholThreads), 0, s, a, k);
+    hipLaunchKernelGGL(k_chol_panel, dim3(blocks_for_tiles(m * (m + 1) / 2)), dim3(kCholThreads), 0, s, a, k);
     DS3_TRY(check_hip(hipGetLastError(), "k_chol_panel"));
   }
   DS3_TRY(launch_backsub(a, s));
