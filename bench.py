@@ -50,15 +50,15 @@ TRAFFIC = {
     "k_edge_reduce_batched": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "f07d21af0a20218f", "bytes": 1868527002},
+        "sha": "7d385c0f863bc90b", "bytes": 1868726432},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
-        "sha": "8a7b6109915a8b08", "bytes": 9303755571},
+        "sha": "425d30087beb6280", "bytes": 9303656128},
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "5a3ef7c89ec94316", "bytes": 21874706637},
+        "sha": "f129105fdb11bd97", "bytes": 21874706637},
 }
 
 

@@ -485,16 +485,6 @@ struct Plan {
   hipGraphExec_t exec = nullptr;
 };
 
-__global__ void k_record(const double* cost, const int32_t* status, unsigned* ctr, double* cost_hist,
-                         int32_t* status_hist) {
-  unsigned k = *ctr;
-  if (k < unsigned(kHistory)) {
-    cost_hist[k] = *cost;
-    status_hist[k] = *status;
-  }
-  *ctr = k + 1;
-}
-
 // One GN iteration; `timed` records the plan's timer around the residual launch (never inside a capture).
 static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
   DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, P.B.counter, s));
@@ -505,17 +495,17 @@ static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
   DS3_TRY(launch_edge_finalize(P.B.edges, P.T.n_edges, P.B.partials, P.B.Ad, P.B.A_e, P.B.b_e, P.B.cost_e,
                                P.B.count_e, s));
   const size_t n = 7 * size_t(P.T.n_kf);
-  DS3_TRY(launch_fill(P.B.H, n * n, 0.0, s));
+  // H was cleared once at plan creation: the assembly rewrites every block of its fixed nonzero pattern
   DS3_TRY(launch_assemble(P.T.n_kf, P.B.node_ptr, P.B.node_adj, P.B.pair_ptr, P.B.pair_edges, P.B.pair_ij,
                           P.T.n_pairs, P.B.A_e, P.B.b_e, P.B.anchor, P.B.H, P.B.g, s));
-  DS3_TRY(launch_sum_costs(P.B.cost_e, P.B.count_e, P.T.n_edges, P.B.cost_tmp, P.B.count_tmp, s));
   int32_t* status = reinterpret_cast<int32_t*>(P.B.counter + 8);
   DS3_TRY(launch_chol_ladder(P.B.H, P.B.g, int(n), P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts,
                              P.B.tau, status, P.B.chol_ws, s));
   DS3_TRY(launch_sim3_update(P.poses, P.B.tau, P.B.anchor, P.T.n_kf, s));
-  hipLaunchKernelGGL(k_record, dim3(1), dim3(1), 0, s, P.B.cost_tmp, status, P.hist_ctr, P.cost_hist,
-                     P.status_hist);
-  return check_hip(hipGetLastError(), "k_record");
+  // the cost at the iteration's input poses (cost_e is rewritten only by the next iteration) and the
+  // ladder status go to the history
+  return launch_sum_costs_record(P.B.cost_e, P.B.count_e, P.T.n_edges, P.B.cost_tmp, P.B.count_tmp, status,
+                                 P.hist_ctr, P.cost_hist, P.status_hist, kHistory, s);
 }
 
 // Order (edge, tile) items by descending valid count for the current tile shape.
@@ -750,6 +740,7 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
   P->use_graph = !opts || opts->use_graph != 0;
   P->timer = opts ? opts->reduce_timer : nullptr;
   rc = upload_topology(P->T, P->B, s);
+  if (rc == DS3_OK) rc = launch_fill(P->B.H, 49 * size_t(P->T.n_kf) * size_t(P->T.n_kf), 0.0, s);
   if (rc == DS3_OK) rc = launch_fill_u32(P->B.counter, 64, 0u, s);
   if (rc == DS3_OK) rc = launch_fill_u32(P->hist_ctr, 4, 0u, s);
   if (rc == DS3_OK) {

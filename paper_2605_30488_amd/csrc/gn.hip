@@ -491,11 +491,16 @@ int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, 
   return check_hip(hipGetLastError(), "k_assemble");
 }
 
-// Deterministic sum of per-edge costs and counts (fixed strided split + fixed tree).
+// Deterministic sum of per-edge costs and counts (fixed strided split + fixed tree). With ctr, the sum
+// and *status are also appended to a history (slot *ctr, then ctr advances; slots past hist_len are
+// dropped).
 __global__ __launch_bounds__(256) void k_sum_costs(const double* __restrict__ cost_e,
                                                    const int64_t* __restrict__ count_e, int n_edges,
                                                    double* __restrict__ cost_out,
-                                                   int64_t* __restrict__ count_out) {
+                                                   int64_t* __restrict__ count_out,
+                                                   const int32_t* __restrict__ status, unsigned* __restrict__ ctr,
+                                                   double* __restrict__ cost_hist,
+                                                   int32_t* __restrict__ status_hist, int hist_len) {
   __shared__ double sc[256];
   __shared__ long long sn[256];
   double c = 0.0;
@@ -517,12 +522,30 @@ __global__ __launch_bounds__(256) void k_sum_costs(const double* __restrict__ co
   if (threadIdx.x == 0) {
     if (cost_out) *cost_out = sc[0];
     if (count_out) *count_out = sn[0];
+    if (ctr) {
+      const unsigned k = *ctr;
+      if (k < unsigned(hist_len)) {
+        cost_hist[k] = sc[0];
+        status_hist[k] = *status;
+      }
+      *ctr = k + 1;
+    }
   }
 }
 
 int launch_sum_costs(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
                      int64_t* count_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_costs, dim3(1), dim3(256), 0, s, cost_e, count_e, n_edges, cost_out, count_out);
+  hipLaunchKernelGGL(k_sum_costs, dim3(1), dim3(256), 0, s, cost_e, count_e, n_edges, cost_out, count_out,
+                     static_cast<const int32_t*>(nullptr), static_cast<unsigned*>(nullptr),
+                     static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr), 0);
+  return check_hip(hipGetLastError(), "k_sum_costs");
+}
+
+int launch_sum_costs_record(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
+                            int64_t* count_out, const int32_t* status, unsigned* ctr, double* cost_hist,
+                            int32_t* status_hist, int hist_len, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_costs, dim3(1), dim3(256), 0, s, cost_e, count_e, n_edges, cost_out, count_out, status,
+                     ctr, cost_hist, status_hist, hist_len);
   return check_hip(hipGetLastError(), "k_sum_costs");
 }
 

@@ -100,6 +100,9 @@ int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, 
                     const double* b_e, const uint8_t* anchor_mask, double* H, double* g, hipStream_t s);
 int launch_sum_costs(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
                      int64_t* count_out, hipStream_t s);
+int launch_sum_costs_record(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
+                            int64_t* count_out, const int32_t* status, unsigned* ctr, double* cost_hist,
+                            int32_t* status_hist, int hist_len, hipStream_t s);
 int launch_sim3_update(double* poses, const double* tau, const uint8_t* fixed, int n, hipStream_t s);
 int launch_fill(double* p, size_t n, double v, hipStream_t s);
 int launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s);
