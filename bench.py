@@ -318,41 +318,43 @@ def main():
     match_all(W, lm)
     torch.cuda.synchronize()
     t0 = time.time()
-    match_timer = ds3.KernelTimer()
-    reduce_timer = ds3.KernelTimer()
-    plan = ds3.GNPlan(W.graph, W.poses, autotune=not args.no_autotune, reduce_timer=reduce_timer)
+    # one pair of kernel timers per timed step, read only after the timed loop: reading a timer waits for
+    # its end event, which would keep the host from queueing the next step while the GPU works
+    match_timers = [ds3.KernelTimer() for _ in range(max(args.steps, 1))]
+    reduce_timers = [ds3.KernelTimer() for _ in range(max(args.steps, 1))]
+    plan = ds3.GNPlan(W.graph, W.poses, autotune=not args.no_autotune, reduce_timer=reduce_timers[0])
     torch.cuda.synchronize()
     info = plan.info()
     log(f"plan: {info} (created in {time.time() - t0:.1f}s)")
 
-    def step(ev):
+    def step(ev, k):
         W.poses.copy_(W.poses_init)
         ev[0].record()
-        _, _, nu, admit = match_all(W, lm, match_timer)
+        _, _, nu, admit = match_all(W, lm, match_timers[k])
         ev[1].record()
         ds3.gauge_sync(W.poses, W.agent, W.arena, W.edges, W.idx_offsets, W.idx, W.valid, admit)
         ev[2].record()
+        plan.set_timer(reduce_timers[k])
         cost, st = plan.run(args.gn_iters)
         ev[3].record()
         return cost, st, admit
 
     for k in range(args.warmup):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        step(ev)
+        step(ev, 0)
         torch.cuda.synchronize()
         log(f"warmup step {k} done")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    k_match_ms, k_reduce_ms = [], []
     for k in range(args.steps):
-        cost, st, admit = step(evs[k])
-        # kernel durations of this step from the library's events (each read waits for its end event):
-        # the matching launch and the residual launch of the step's last GN iteration
-        k_match_ms.append(match_timer.ms())
-        k_reduce_ms.append(reduce_timer.ms())
+        cost, st, admit = step(evs[k], k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    # kernel durations of every timed step from the library's events: the matching launch and the residual
+    # launch of the step's last GN iteration
+    k_match_ms = [match_timers[k].ms() for k in range(args.steps)]
+    k_reduce_ms = [reduce_timers[k].ms() for k in range(args.steps)]
     t_match = np.mean([evs[k][0].elapsed_time(evs[k][1]) for k in range(args.steps)])
     t_gauge = np.mean([evs[k][1].elapsed_time(evs[k][2]) for k in range(args.steps)])
     t_gn = np.mean([evs[k][2].elapsed_time(evs[k][3]) for k in range(args.steps)])
@@ -461,8 +463,8 @@ def main():
         out["calib_copy_bytes"] = 2 * n * 4
 
     plan.close()
-    reduce_timer.close()
-    match_timer.close()
+    for t in match_timers + reduce_timers:
+        t.close()
     print(json.dumps(out), flush=True)
 
 

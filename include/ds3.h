@@ -253,6 +253,8 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena
                        const ds3_plan_opts* opts, double* poses, void** plan_out, void* stream);
 int ds3_gn_plan_run(void* plan, int32_t iters, double* cost_per_iter, int32_t* status_per_iter,
                     void* stream);
+/* Replaces the plan's reduce_timer (NULL: none) for the following runs; the caller keeps it alive. */
+int ds3_gn_plan_set_timer(void* plan, ds3_timer* timer);
 /* Timing hook for the fused residual/Hessian kernel alone: launches it `reps` times on `stream` at the
  * plan's current poses (device prep included), bracketed by events; *ms_out (host) = mean ms per
  * launch. Synchronises. */

@@ -82,6 +82,7 @@ _SIGS = {
     "ds3_gn_plan_time_reduce": (C.c_int, [vp, i32, C.POINTER(C.c_float), vp]),
     "ds3_gn_plan_info": (C.c_int, [vp, P_i64]),
     "ds3_gn_plan_destroy": (C.c_int, [vp]),
+    "ds3_gn_plan_set_timer": (C.c_int, [vp, vp]),
     "ds3_gn_cost": (C.c_int, [vp, i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams), vp, vp,
                               sz, vp]),
     "ds3_gn_cost_adjoint": (C.c_int, [vp, i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams),

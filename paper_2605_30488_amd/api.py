@@ -384,6 +384,11 @@ class GNPlan:
         call("ds3_gn_plan_run", self.handle, iters, _ptr(cost), _ptr(st), _stream())
         return cost[:iters], st[:iters]
 
+    def set_timer(self, timer):
+        """Record `timer` (a KernelTimer, or None) around the residual launch of each later run."""
+        call("ds3_gn_plan_set_timer", self.handle, timer.handle if timer is not None else None)
+        self.reduce_timer = timer
+
     def time_reduce(self, reps: int = 10) -> float:
         ms = C.c_float()
         call("ds3_gn_plan_time_reduce", self.handle, reps, C.byref(ms), _stream())

@@ -820,6 +820,13 @@ int ds3_gn_plan_info(void* plan, int64_t* info) {
   return DS3_OK;
 }
 
+int ds3_gn_plan_set_timer(void* plan, ds3_timer* timer) {
+  Plan* P = static_cast<Plan*>(plan);
+  if (!P) return fail(DS3_EINVAL, "plan_set_timer: null plan");
+  P->timer = timer;
+  return DS3_OK;
+}
+
 int ds3_gn_plan_destroy(void* plan) {
   plan_free(static_cast<Plan*>(plan));
   return DS3_OK;

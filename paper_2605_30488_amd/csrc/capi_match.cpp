@@ -116,6 +116,8 @@ struct MatchWs {
   unsigned* counts;
   int64_t* npx;
   unsigned* step_stripes;
+  unsigned* part;   // per-tile mutual counts
+  int64_t* side;    // per count slot: first partial, number of partials
 };
 
 static size_t carve_match(void* base, int64_t ray_px, int64_t tmp_idx, int n_dirs, int n_sides, int n_edges,
@@ -131,7 +133,23 @@ static size_t carve_match(void* base, int64_t ray_px, int64_t tmp_idx, int n_dir
   W.counts = c.take<unsigned>(2 * size_t(std::max(n_edges, 1)));
   W.npx = c.take<int64_t>(2 * size_t(std::max(n_edges, 1)));
   W.step_stripes = c.take<unsigned>(size_t(kStepStripes) * kStripeStride);
+  // every side has at most npx / 256 + 1 tiles and the sides' pixels add up to tmp_idx
+  W.part = c.take<unsigned>(size_t(std::max<int64_t>(tmp_idx / 256 + n_sides + 1, 1)));
+  W.side = c.take<int64_t>(2 * size_t(std::max(n_sides, 1)));
   return c.used;
+}
+
+// Per-tile partial slots of the sides (in their original order) and the per-slot table for the sums.
+static void assign_parts(std::vector<MutualDir>& sides, const std::vector<int32_t>& stiles,
+                         std::vector<int64_t>& side_tab) {
+  side_tab.assign(2 * sides.size(), 0);
+  int64_t off = 0;
+  for (size_t k = 0; k < sides.size(); ++k) {
+    sides[k].part_off = off;
+    side_tab[2 * size_t(sides[k].count_slot)] = off;
+    side_tab[2 * size_t(sides[k].count_slot) + 1] = stiles[k];
+    off += stiles[k];
+  }
 }
 
 // Shared driver: ray images, both directions of every edge, mutual check, nu.
@@ -180,6 +198,9 @@ static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dty
   DS3_TRY(upload(W.map_m.bin_start, bs, s));
   DS3_TRY(upload(W.map_m.prefix, prefix, s));
   DS3_TRY(upload(W.map_m.bin_tiles, bt, s));
+  std::vector<int64_t> side_tab;
+  assign_parts(sides, stiles, side_tab);
+  DS3_TRY(upload(W.side, side_tab, s));
   std::vector<int32_t> order2, prefix2, bs2, bt2;
   const int grid_u = bin_items(stiles, order2, prefix2, bs2, bt2);
   std::vector<MutualDir> sides_o;
@@ -189,14 +210,14 @@ static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dty
   DS3_TRY(upload(W.map_u.prefix, prefix2, s));
   DS3_TRY(upload(W.map_u.bin_tiles, bt2, s));
   DS3_TRY(upload(W.npx, npx, s));
-  DS3_TRY(launch_fill_u32(W.counts, 2 * size_t(ne), 0u, s));
   unsigned* stripes = lm_steps ? W.step_stripes : nullptr;
   if (stripes) DS3_TRY(launch_fill_u32(stripes, size_t(kStepStripes) * kStripeStride, 0u, s));
   DS3_TRY(timer_record(timer, true, s));
   DS3_TRY(launch_match_batched(W.rays, cross, dt, W.dirs, as_map(W.map_m), grid_m, C, W.idx_tmp, stripes, s));
   DS3_TRY(timer_record(timer, false, s));
   if (stripes) DS3_TRY(launch_sum_stripes(stripes, reinterpret_cast<unsigned long long*>(lm_steps), s));
-  DS3_TRY(launch_mutual(W.md, as_map(W.map_u), grid_u, dt, C, W.idx_tmp, idx_out, valid_out, W.counts, s));
+  DS3_TRY(launch_mutual(W.md, as_map(W.map_u), grid_u, dt, C, W.idx_tmp, idx_out, valid_out, W.part, s));
+  DS3_TRY(launch_side_counts(W.part, W.side, 2 * ne, W.counts, s));
   return launch_nu_finalize(W.counts, W.npx, ne, nu_min, nu, admit, s);
 }
 
@@ -288,6 +309,9 @@ int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const 
       MutualDir{0, nj, 0, W.conf + ni, W.conf, img_j.H, img_j.W, img_i.H, img_i.W, 1, 1},
       MutualDir{nj, 0, 0, W.conf, W.conf + ni, img_i.H, img_i.W, img_j.H, img_j.W, 0, 0}};
   std::vector<int32_t> stiles = {int32_t((nj + 255) / 256), int32_t((ni + 255) / 256)};
+  std::vector<int64_t> side_tab;
+  assign_parts(sides, stiles, side_tab);
+  DS3_TRY(upload(W.side, side_tab, s));
   std::vector<int32_t> order, prefix, bs, bt;
   const int grid = bin_items(stiles, order, prefix, bs, bt);
   std::vector<MutualDir> sides_o;
@@ -298,8 +322,8 @@ int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const 
   DS3_TRY(upload(W.map_u.bin_tiles, bt, s));
   std::vector<int64_t> npx = {ni, nj};
   DS3_TRY(upload(W.npx, npx, s));
-  DS3_TRY(launch_fill_u32(W.counts, 2, 0u, s));
-  DS3_TRY(launch_mutual(W.md, as_map(W.map_u), grid, dtype, C, W.idx_tmp, idx_j2i, valid_j, W.counts, s));
+  DS3_TRY(launch_mutual(W.md, as_map(W.map_u), grid, dtype, C, W.idx_tmp, idx_j2i, valid_j, W.part, s));
+  DS3_TRY(launch_side_counts(W.part, W.side, 2, W.counts, s));
   return launch_nu_finalize(W.counts, W.npx, 1, params->nu_min, nu, admit, s);
 }
 

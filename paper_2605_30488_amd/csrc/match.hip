@@ -299,7 +299,9 @@ int launch_sum_stripes(const unsigned* step_stripes, unsigned long long* out, hi
 
 // --------------------------------------------------------------------------------------------------
 // Mutual check + nu counts. Side J (pixels of j): final idx and valid mask; side I (pixels of i):
-// count only. counts[2e] = i-side count, counts[2e+1] = j-side count.
+// count only. Every block writes its tile's count to its own slot of the partials (no atomics: the
+// blocks of one side would otherwise all hit one counter), then k_side_counts sums each side in a fixed
+// order: counts[2e] = i-side count, counts[2e+1] = j-side count.
 // --------------------------------------------------------------------------------------------------
 __device__ inline bool round_trip(const int32_t* __restrict__ fwd, const int32_t* __restrict__ bwd,
                                   int64_t n, int W_self, int64_t n_self, int64_t n_other, int radius,
@@ -318,7 +320,7 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_mutual(const MutualDir* __restrict__ md, ItemMap map,
                                                 MatchConst P, const int32_t* __restrict__ idx_tmp,
                                                 int32_t* __restrict__ idx_final, uint8_t* __restrict__ valid,
-                                                unsigned* __restrict__ counts) {
+                                                unsigned* __restrict__ part) {
   int entry, tile;
   if (!locate_item(map, blockIdx.x, entry, tile)) return;  // uniform per block
   const MutualDir M = md[entry];
@@ -343,20 +345,37 @@ __global__ __launch_bounds__(256) void k_mutual(const MutualDir* __restrict__ md
   __shared__ int s[4];
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = hit;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int tot = s[0] + s[1] + s[2] + s[3];
-    if (tot) atomicAdd(&counts[M.count_slot], unsigned(tot));
-  }
+  if (threadIdx.x == 0) part[M.part_off + tile] = unsigned(s[0] + s[1] + s[2] + s[3]);
+}
+
+// One wave per side: lanes stride the side's tile partials, then a fixed-shape wave sum.
+__global__ __launch_bounds__(256) void k_side_counts(const unsigned* __restrict__ part,
+                                                     const int64_t* __restrict__ side, int n_slots,
+                                                     unsigned* __restrict__ counts) {
+  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (slot >= n_slots) return;  // uniform per wave
+  const int lane = threadIdx.x & 63;
+  const int64_t off = side[2 * slot], n = side[2 * slot + 1];
+  int c = 0;
+  for (int64_t t = lane; t < n; t += 64) c += int(part[off + t]);
+  c = wave_sum(c);
+  if (lane == 0) counts[slot] = unsigned(c);
+}
+
+int launch_side_counts(const unsigned* part, const int64_t* side, int n_slots, unsigned* counts, hipStream_t s) {
+  if (n_slots <= 0) return DS3_OK;
+  hipLaunchKernelGGL(k_side_counts, dim3((n_slots + 3) / 4), dim3(256), 0, s, part, side, n_slots, counts);
+  return check_hip(hipGetLastError(), "k_side_counts");
 }
 
 int launch_mutual(const MutualDir* md, ItemMap map, int grid, ds3_dtype dt, const MatchConst& P,
-                  const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* counts,
+                  const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* part,
                   hipStream_t s) {
   if (grid <= 0) return DS3_OK;
   if (dt == DS3_F32)
-    hipLaunchKernelGGL(k_mutual<DS3_F32>, dim3(grid), dim3(256), 0, s, md, map, P, idx_tmp, idx_final, valid, counts);
+    hipLaunchKernelGGL(k_mutual<DS3_F32>, dim3(grid), dim3(256), 0, s, md, map, P, idx_tmp, idx_final, valid, part);
   else
-    hipLaunchKernelGGL(k_mutual<DS3_BF16>, dim3(grid), dim3(256), 0, s, md, map, P, idx_tmp, idx_final, valid, counts);
+    hipLaunchKernelGGL(k_mutual<DS3_BF16>, dim3(grid), dim3(256), 0, s, md, map, P, idx_tmp, idx_final, valid, part);
   return check_hip(hipGetLastError(), "k_mutual");
 }
 

@@ -33,6 +33,7 @@ struct MutualDir {
   int32_t H_self, W_self, H_other, W_other;
   int32_t count_slot;        // nu counter index
   int32_t write_out;         // 1 for the j side of an edge
+  int64_t part_off;          // first per-tile count of this side in the count partials
 };
 
 // Blocks are dealt to 8 bins (block b -> bin b mod 8, which the dispatcher places on XCD b mod 8);
@@ -55,8 +56,10 @@ int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, co
                          unsigned* step_stripes, hipStream_t s);
 int launch_sum_stripes(const unsigned* step_stripes, unsigned long long* out, hipStream_t s);
 int launch_mutual(const MutualDir* md, ItemMap map, int grid, ds3_dtype dt, const MatchConst& P,
-                  const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* counts,
+                  const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* part,
                   hipStream_t s);
+// counts[slot] = sum of the per-tile partials [side[2 slot], side[2 slot] + side[2 slot + 1]), fixed order.
+int launch_side_counts(const unsigned* part, const int64_t* side, int n_slots, unsigned* counts, hipStream_t s);
 int launch_nu_finalize(const unsigned* counts, const int64_t* npx, int n_edges, double nu_min, float* nu,
                        int32_t* admit, hipStream_t s);
 
