@@ -184,9 +184,9 @@ static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dty
                  2 * e + 1, 1};
     MutualDir si{E.tmp_ij, E.tmp_ji, 0, W.conf + E.ray_i, W.conf + E.ray_j, E.Hi, E.Wi, E.Hj, E.Wj, 2 * e, 0};
     sides.push_back(sj);
-    stiles.push_back(int32_t((int64_t(E.Hj) * E.Wj + 255) / 256));
+    stiles.push_back(int32_t((int64_t(E.Hj) * E.Wj + kMutualPx - 1) / kMutualPx));
     sides.push_back(si);
-    stiles.push_back(int32_t((int64_t(E.Hi) * E.Wi + 255) / 256));
+    stiles.push_back(int32_t((int64_t(E.Hi) * E.Wi + kMutualPx - 1) / kMutualPx));
     npx.push_back(int64_t(E.Hi) * E.Wi);
     npx.push_back(int64_t(E.Hj) * E.Wj);
   }
@@ -308,7 +308,7 @@ int ds3_match_bidir(const void* X_ii, const void* X_ji, const void* X_jj, const 
   std::vector<MutualDir> sides = {
       MutualDir{0, nj, 0, W.conf + ni, W.conf, img_j.H, img_j.W, img_i.H, img_i.W, 1, 1},
       MutualDir{nj, 0, 0, W.conf, W.conf + ni, img_i.H, img_i.W, img_j.H, img_j.W, 0, 0}};
-  std::vector<int32_t> stiles = {int32_t((nj + 255) / 256), int32_t((ni + 255) / 256)};
+  std::vector<int32_t> stiles = {int32_t((nj + kMutualPx - 1) / kMutualPx), int32_t((ni + kMutualPx - 1) / kMutualPx)};
   std::vector<int64_t> side_tab;
   assign_parts(sides, stiles, side_tab);
   DS3_TRY(upload(W.side, side_tab, s));

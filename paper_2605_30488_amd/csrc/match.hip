@@ -303,42 +303,52 @@ int launch_sum_stripes(const unsigned* step_stripes, unsigned long long* out, hi
 // blocks of one side would otherwise all hit one counter), then k_side_counts sums each side in a fixed
 // order: counts[2e] = i-side count, counts[2e+1] = j-side count.
 // --------------------------------------------------------------------------------------------------
-__device__ inline bool round_trip(const int32_t* __restrict__ fwd, const int32_t* __restrict__ bwd,
-                                  int64_t n, int W_self, int64_t n_self, int64_t n_other, int radius,
-                                  int32_t& m_out) {
-  const int32_t m = fwd[n];
-  m_out = m;
-  if (m < 0 || m >= n_other) return false;
-  const int32_t n2 = bwd[m];
-  if (n2 < 0 || n2 >= n_self) return false;
-  const int du = abs(int(n2 % W_self) - int(n % W_self));
-  const int dv = abs(int(n2 / W_self) - int(n / W_self));
-  return max(du, dv) <= radius;
-}
-
 template <int DT>
 __global__ __launch_bounds__(256) void k_mutual(const MutualDir* __restrict__ md, ItemMap map,
                                                 MatchConst P, const int32_t* __restrict__ idx_tmp,
                                                 int32_t* __restrict__ idx_final, uint8_t* __restrict__ valid,
                                                 unsigned* __restrict__ part) {
+  constexpr int kPer = kMutualPx / 256;
   int entry, tile;
   if (!locate_item(map, blockIdx.x, entry, tile)) return;  // uniform per block
   const MutualDir M = md[entry];
-  int hit = 0;
-  const int64_t n = int64_t(tile) * 256 + threadIdx.x;
   const int64_t n_self = int64_t(M.H_self) * M.W_self;
-  if (n < n_self) {
-    int32_t m;
-    const bool ok = round_trip(idx_tmp + M.fwd_off, idx_tmp + M.bwd_off, n, M.W_self, n_self,
-                               int64_t(M.H_other) * M.W_other, P.radius, m);
+  const int64_t n_other = int64_t(M.H_other) * M.W_other;
+  const int32_t* fwd = idx_tmp + M.fwd_off;
+  const int32_t* bwd = idx_tmp + M.bwd_off;
+  // four independent pixels per thread, every load of a stage issued before its first use:
+  // forward matches, then the backward matches and both confidences
+  int64_t n[kPer];
+  int32_t m[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    n[u] = int64_t(tile) * kMutualPx + u * 256 + threadIdx.x;
+    m[u] = (n[u] < n_self) ? fwd[n[u]] : -1;
+    m[u] = (m[u] < n_other) ? m[u] : -1;
+  }
+  int32_t n2[kPer];
+  float cs[kPer], co[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const bool has = m[u] >= 0;
+    n2[u] = has ? bwd[m[u]] : -1;
+    co[u] = has ? M.conf_other[m[u]] : 0.0f;
+    cs[u] = (n[u] < n_self) ? M.conf_self[n[u]] : 0.0f;
+  }
+  int hit = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    if (n[u] >= n_self) continue;
+    bool ok = m[u] >= 0 && n2[u] >= 0 && n2[u] < n_self;
     if (ok) {
-      const double cs = double(M.conf_self[n]);
-      const double co = double(M.conf_other[m]);
-      hit = (sqrt(co * cs) >= P.q_min) ? 1 : 0;
+      const int du = abs(int(n2[u] % M.W_self) - int(n[u] % M.W_self));
+      const int dv = abs(int(n2[u] / M.W_self) - int(n[u] / M.W_self));
+      ok = max(du, dv) <= P.radius;
     }
+    if (ok) hit += (sqrt(double(co[u]) * double(cs[u])) >= P.q_min) ? 1 : 0;
     if (M.write_out) {
-      idx_final[M.out_off + n] = ok ? m : -1;
-      valid[M.out_off + n] = ok ? 1 : 0;
+      idx_final[M.out_off + n[u]] = ok ? m[u] : -1;
+      valid[M.out_off + n[u]] = ok ? 1 : 0;
     }
   }
   hit = wave_sum(hit);

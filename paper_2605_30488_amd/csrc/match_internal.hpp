@@ -37,7 +37,8 @@ struct MutualDir {
 };
 
 // Blocks are dealt to 8 bins (block b -> bin b mod 8, which the dispatcher places on XCD b mod 8);
-// entries of bin x are [bin_start[x], bin_start[x+1]) with within-bin tile prefixes; 256 px per tile.
+// entries of bin x are [bin_start[x], bin_start[x+1]) with within-bin tile prefixes (256 px per tile for
+// the matching, kMutualPx for the mutual check).
 struct ItemMap {
   const int32_t* bin_start;  // 9
   const int32_t* prefix;     // per entry: first tile of the entry within its bin
@@ -58,6 +59,9 @@ int launch_sum_stripes(const unsigned* step_stripes, unsigned long long* out, hi
 int launch_mutual(const MutualDir* md, ItemMap map, int grid, ds3_dtype dt, const MatchConst& P,
                   const int32_t* idx_tmp, int32_t* idx_final, uint8_t* valid, unsigned* part,
                   hipStream_t s);
+// Pixels per block of the mutual check (four per thread).
+constexpr int kMutualPx = 1024;
+
 // counts[slot] = sum of the per-tile partials [side[2 slot], side[2 slot] + side[2 slot + 1]), fixed order.
 int launch_side_counts(const unsigned* part, const int64_t* side, int n_slots, unsigned* counts, hipStream_t s);
 int launch_nu_finalize(const unsigned* counts, const int64_t* npx, int n_edges, double nu_min, float* nu,
