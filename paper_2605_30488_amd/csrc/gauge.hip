@@ -69,12 +69,25 @@ __global__ __launch_bounds__(kGaugeThreads) void k_gauge_moments(
 
 // Sum block partials in block order (single block of 64 threads). out: [0..5] centroids of x and y,
 // [6] count, [10..20] pass-1 sums.
-__global__ void k_gauge_reduce(const double* __restrict__ partials, int nblocks, int pass,
-                               double* __restrict__ out) {
-  const int k = threadIdx.x;
-  double s = 0.0;
-  if (k < 11)
-    for (int b = 0; b < nblocks; ++b) s += partials[int64_t(b) * kMom + k];
+// Fixed-order sum of the per-block moments: thread t takes blocks t, t + 256, ..., then a fixed tree.
+__global__ __launch_bounds__(256) void k_gauge_reduce(const double* __restrict__ partials, int nblocks,
+                                                      int pass, double* __restrict__ out) {
+  __shared__ double red[11][256];
+  const int t = threadIdx.x;
+  double a[11];
+  for (int q = 0; q < 11; ++q) a[q] = 0.0;
+  for (int b = t; b < nblocks; b += 256)
+    for (int q = 0; q < 11; ++q) a[q] += partials[int64_t(b) * kMom + q];
+  for (int q = 0; q < 11; ++q) red[q][t] = a[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int q = 0; q < 11; ++q) red[q][t] += red[q][t + w];
+    __syncthreads();
+  }
+  if (t >= 64) return;  // the first wave writes the results
+  const int k = t;
+  const double s = (k < 11) ? red[k][0] : 0.0;
   if (pass == 0) {
     // centroids x (0..2), y (3..5), count (6)
     const double cnt = __shfl(s, 6, kWave);
@@ -235,7 +248,7 @@ int launch_gauge_align(const void* Xi, int64_t npx_i, const void* Xj, int64_t np
       hipLaunchKernelGGL(k_gauge_moments<DS3_BF16>, dim3(kGaugeBlocks), dim3(kGaugeThreads), 0, s, Xi, Xj,
                          npx_j, npx_i, idx, valid, poses, i, j, pass, mom, partials);
     DS3_TRY(check_hip(hipGetLastError(), "k_gauge_moments"));
-    hipLaunchKernelGGL(k_gauge_reduce, dim3(1), dim3(64), 0, s, partials, kGaugeBlocks, pass, mom);
+    hipLaunchKernelGGL(k_gauge_reduce, dim3(1), dim3(256), 0, s, partials, kGaugeBlocks, pass, mom);
     DS3_TRY(check_hip(hipGetLastError(), "k_gauge_reduce"));
   }
   hipLaunchKernelGGL(k_gauge_solve, dim3(1), dim3(64), 0, s, mom, poses, i, j, ref_is_i, nc_min, T_out, used);
