@@ -390,7 +390,16 @@ __global__ __launch_bounds__(64) void k_edge_finalize(const EdgeDev* __restrict_
   if (t < 37) {
     double s = 0.0;
     const float* p = partials + int64_t(E.tile0) * kPartial + t;
-    for (int k = 0; k < E.n_tiles; ++k) s += double(p[int64_t(k) * kPartial]);
+    // eight loads in flight, summed in tile order
+    int k = 0;
+    for (; k + 8 <= E.n_tiles; k += 8) {
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[int64_t(k + q) * kPartial];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += double(v[q]);
+    }
+    for (; k < E.n_tiles; ++k) s += double(p[int64_t(k) * kPartial]);
     S[t] = s;
   }
   if (t < 49) Ad[t] = Ad_all[49 * int64_t(e) + t];
@@ -455,7 +464,16 @@ __global__ __launch_bounds__(64) void k_assemble(int n_kf, const int32_t* __rest
     const bool anc = anchor && anchor[k];
     if (t < 49) {
       double s = 0.0;
-      for (int p = node_ptr[k]; p < node_ptr[k + 1]; ++p) s += A_e[49 * int64_t(node_adj[p] >> 1) + t];
+      const int p1 = node_ptr[k + 1];
+      int p = node_ptr[k];
+      for (; p + 4 <= p1; p += 4) {  // four loads in flight, summed in edge order
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = A_e[49 * int64_t(node_adj[p + q] >> 1) + t];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += v[q];
+      }
+      for (; p < p1; ++p) s += A_e[49 * int64_t(node_adj[p] >> 1) + t];
       int r = t / 7, c = t % 7;
       H[(7 * int64_t(k) + r) * n + 7 * k + c] = anc ? (r == c ? 1.0 : 0.0) : s;
     } else if (t < 56) {
@@ -474,7 +492,16 @@ __global__ __launch_bounds__(64) void k_assemble(int n_kf, const int32_t* __rest
     const bool anc = anchor && (anchor[a] || anchor[b]);
     if (t < 49) {
       double s = 0.0;
-      for (int q = pair_ptr[p]; q < pair_ptr[p + 1]; ++q) s -= A_e[49 * int64_t(pair_edges[q]) + t];
+      const int q1 = pair_ptr[p + 1];
+      int q = pair_ptr[p];
+      for (; q + 4 <= q1; q += 4) {  // four loads in flight, summed in edge order
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = A_e[49 * int64_t(pair_edges[q + u]) + t];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s -= v[u];
+      }
+      for (; q < q1; ++q) s -= A_e[49 * int64_t(pair_edges[q]) + t];
       if (anc) s = 0.0;
       const int r = t / 7, c = t % 7;
       H[(7 * int64_t(a) + r) * n + 7 * b + c] = s;
