@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 
 METRIC = "edge-pixels/s per Sim(3) GN step + matched px/s, plain vs batched-BF16"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-VALU_FP32_PEAK_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz, non-packed FP32 FMA
+VALU_FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector: 256 CU x 4 SIMD x 32 FMA lanes x 2 FLOP x 2.4 GHz
 # FP32 operations of the matching kernel, counted from its source (an FMA counts 2): per LM trial step the
 # damped 2x2 solve (20), the clamped move (6), the bilinear sample of psi and its two derivatives (41),
 # the residual and cost (8), the damping update (2) and, on acceptance, the normal equations (25); per
