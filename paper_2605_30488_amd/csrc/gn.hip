@@ -253,15 +253,22 @@ __device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev
   const int32_t* __restrict__ idx = idx_arena + E.idx_off;
   int2* q = queue + (threadIdx.x / kWave) * kQueue;
   unsigned head = 0, tail = 0;  // wave-uniform
-#pragma unroll 1
-  for (int k0 = 0; k0 < PPT; k0 += kScanU) {
-    int32_t m[kScanU];
+  // the matches of the next scan unit are loaded before the current one is drained, so that their
+  // latency overlaps the gathers and the arithmetic of the drain
+  auto load_matches = [&](int k0, int32_t* m) {
 #pragma unroll
     for (int u = 0; u < kScanU; ++u) {
       const int64_t n = base + int64_t(k0 + u) * kReduceThreads + threadIdx.x;
       m[u] = (n < E.npx_j) ? __builtin_nontemporal_load(idx + n) : -1;
-      if (m[u] >= E.npx_i) m[u] = -1;
     }
+  };
+  int32_t m[kScanU];
+  load_matches(0, m);
+#pragma unroll 1
+  for (int k0 = 0; k0 < PPT; k0 += kScanU) {
+#pragma unroll
+    for (int u = 0; u < kScanU; ++u)
+      if (m[u] >= E.npx_i) m[u] = -1;
 #pragma unroll
     for (int u = 0; u < kScanU; ++u) {
       const bool valid = m[u] >= 0;
@@ -274,6 +281,7 @@ __device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev
       }
       tail += unsigned(__popcll(ballot));
     }
+    if (k0 + kScanU < PPT) load_matches(k0 + kScanU, m);
     __builtin_amdgcn_wave_barrier();  // the wave's queue writes are ordered before its reads
     while (tail - head >= unsigned(kRounds * kWave)) drain_rounds<DT>(a, arena, E, q, head, kRounds * kWave, M, k);
   }
