@@ -349,20 +349,24 @@ __device__ inline void tile_index(int tt, int& i, int& j) {
   j = tt - i * (i + 1) / 2;
 }
 
-// Workgroups are dealt round-robin to the eight XCDs (block b to XCD b mod 8). Block 0 carries the
-// tile whose diagonal factorisation is the critical path; the other blocks of XCD 0 carry nothing, so
-// that tile gets the compute units of an XCD to itself, and the other tiles go to the remaining seven
-// XCDs: block b > 0 with b mod 8 != 0 takes tile b - b/8. (The placement only affects speed.)
+// Workgroups are dealt round-robin to the eight XCDs (block b to XCD b mod 8). Block 0 carries tile 0,
+// whose diagonal factorisation is the critical path, and blocks 8 and 16 carry tiles 1 and 2, the two
+// tiles the next panel's diagonal workgroup (again on XCD 0) starts from; the other blocks of XCD 0 carry
+// nothing, so the critical tile has the compute units of an XCD nearly to itself, and tiles 3.. go to the
+// remaining seven XCDs in block order. (The placement only affects speed.)
 constexpr int kXcds = 8;
-__device__ inline int tile_of_block(int b) { return b == 0 ? 0 : ((b % kXcds) == 0 ? -1 : b - b / kXcds); }
+__device__ inline int tile_of_block(int b) {
+  if (b % kXcds == 0) return (b / kXcds <= 2) ? b / kXcds : -1;
+  return 3 + (b - b / kXcds - 1);
+}
 
 static int blocks_for_tiles(int tiles) {
-  int b = 0, t = 0;
-  while (t < tiles) {
-    if (b == 0 || b % kXcds != 0) ++t;
-    ++b;
-  }
-  return b;
+  // enough blocks for tile `tiles - 1`: tiles 0..2 sit at blocks 0, 8, 16, tile t >= 3 at the
+  // (t - 3)-th block that is not a multiple of 8
+  if (tiles <= 3) return 8 * (tiles - 1) + 1;
+  const int j = tiles - 4;  // index among the blocks that are not multiples of 8
+  const int b = j + j / 7 + 1;
+  return std::max(b + 1, 17);
 }
 
 // ---------------------------------------------------------------------------------------------------
