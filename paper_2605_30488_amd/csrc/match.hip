@@ -157,6 +157,12 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
     const float cn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
     const bool acc = moved && (cn < c);
     const float step = fmaxf(fabsf(un - u), fabsf(vn - v));
+    // A rejected trial shorter than the tolerance also ends the search: in float32 the cost stops
+    // decreasing at the rounding floor, so such a step is rejected and every later one (ten times
+    // shorter per rejection) would be too; in exact arithmetic the search would stop at the next
+    // accepted step, which moves p by less than the tolerance. (Singular systems still retry with a
+    // larger damping.)
+    if (!acc && det_ok && step < P.step_tol) active = false;
     lam = acc ? fmaxf(lam * 0.1f, P.lambda_min) : lam * 10.0f;
     if (acc) {
       u = un; v = vn; S = Sn; c = cn;
