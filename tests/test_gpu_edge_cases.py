@@ -1,0 +1,123 @@
+"""GPU edge cases of the path: graphs without edges, edges whose matches are all invalid, non-finite
+pointmap entries (holes), the largest system the Cholesky accepts and the first it rejects. Every result
+is compared with the FP64 oracle or with what the definitions fix (an empty sum is zero, a zero gradient
+gives a zero step)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2605_30488_amd import DS3Error
+from tests.helpers import exact_graph, perturb
+
+pytestmark = pytest.mark.gpu
+
+ds3 = pytest.importorskip("paper_2605_30488_amd.api")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(dev)
+
+
+def _small(dev, seed=91):
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=3, H=16, W=20, seed=seed, frac_valid=0.8)
+    xyz = [np.asarray(x, np.float32) for x in xyz]
+    conf = [np.asarray(c, np.float32) for c in conf]
+    poses = perturb(gt, np.random.default_rng(seed + 1), rot=0.01, trans=0.01, scale=0.01, fixed=(0,))
+    return xyz, conf, edges, idx, poses
+
+
+def test_graph_without_edges(dev):
+    """No edges: E = 0, zero gradients, and a GN step (plain and plan) that leaves the poses unchanged
+    with ladder status 0 (the regularised system is eps I with a zero right-hand side)."""
+    xyz, conf, _, _, poses = _small(dev)
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    idx = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    G = ds3.Graph(a, [], idx, [], anchors=(0,))
+    P = _t(poses, dev)
+    assert ds3.gn_cost(G, P).item() == 0.0
+    gx, gc, gt = ds3.gn_cost_adjoint(G, P)
+    assert float(gx.abs().max()) == 0.0 and float(gc.abs().max()) == 0.0 and float(gt.abs().max()) == 0.0
+    plan = ds3.AdjointPlan(G)
+    c, px, pc, pt = plan.run(P)
+    assert c.item() == 0.0 and float(px.abs().max()) == 0.0 and float(pt.abs().max()) == 0.0
+    plan.close()
+    Q = P.clone()
+    cost, st = ds3.sim3_gn_step(G, Q)
+    assert cost.item() == 0.0 and int(st.item()) == 0
+    assert torch.equal(Q, P)
+    Q = P.clone()
+    gp = ds3.GNPlan(G, Q)
+    costs, sts = gp.run(2)
+    torch.cuda.synchronize()
+    assert costs.cpu().numpy().tolist() == [0.0, 0.0] and sts.cpu().numpy().tolist() == [0, 0]
+    assert torch.equal(Q, P)
+    gp.close()
+
+
+def test_edges_with_no_valid_match(dev):
+    """Every idx = -1: the same as no edges for the cost, the gradients and the step."""
+    xyz, conf, edges, idx, poses = _small(dev, seed=93)
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    flat = torch.full((sum(len(v) for v in idx),), -1, dtype=torch.int32, device=dev)
+    G = ds3.Graph(a, edges, flat, anchors=(0,))
+    P = _t(poses, dev)
+    assert ds3.gn_cost(G, P).item() == 0.0
+    _, _, gt = ds3.gn_cost_adjoint(G, P)
+    assert float(gt.abs().max()) == 0.0
+    Q = P.clone()
+    cost, st = ds3.sim3_gn_step(G, Q)
+    assert cost.item() == 0.0 and int(st.item()) == 0 and torch.equal(Q, P)
+
+
+def test_non_finite_pixels_are_holes(dev):
+    """NaN and infinite pointmap entries and zero vectors are holes on either side of a match: the
+    GPU cost, gradient and GN step equal the oracle's, which skips them by definition."""
+    xyz, conf, edges, idx, poses = _small(dev, seed=95)
+    rng = np.random.default_rng(96)
+    for k in range(len(xyz)):
+        flat = xyz[k].reshape(-1, 3)
+        pick = rng.choice(flat.shape[0], size=12, replace=False)
+        flat[pick[:4]] = np.nan
+        flat[pick[4:8], 1] = np.inf
+        flat[pick[8:]] = 0.0
+    a = ds3.build_arena(xyz, conf, "f32", dev)
+    G = ds3.Graph(a, edges, _t(np.concatenate(idx), dev, torch.int32), anchors=(0,))
+    P = _t(poses, dev)
+    og = O.Graph(xyz, conf, edges, idx, anchors=(0,))
+    E, rx, rc, rt = O.cost_grad(og, poses)
+    assert np.isfinite(E) and E > 0
+    c = ds3.gn_cost(G, P).item()
+    assert abs(c - E) <= 1e-5 * E
+    gx, gc, gt = ds3.gn_cost_adjoint(G, P)
+    assert np.all(np.isfinite(gt.cpu().numpy())) and np.all(np.isfinite(gx.cpu().numpy()))
+    assert np.abs(gt.cpu().numpy() - rt).max() <= 2e-4 * np.abs(rt).max()
+    Q = P.clone()
+    ds3.sim3_gn_step(G, Q)
+    ref, _, s, _ = O.gn_step(og, poses)
+    assert s == 0
+    assert O.pose_error(Q.cpu().numpy(), ref).max() <= 1e-5
+
+
+def test_chol_largest_and_first_rejected_size(dev):
+    """n = 8192 (the largest order the solver takes) against numpy's dense solve; n = 8193 is an
+    argument error, reported before anything is launched."""
+    n = 8192
+    rng = np.random.default_rng(97)
+    B = rng.normal(size=(n, 64)) / 8.0
+    H = B @ B.T + np.diag(rng.uniform(1.0, 2.0, size=n))
+    g = rng.normal(size=n)
+    tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev), attempts=1)
+    ref = np.linalg.solve(H + 1e-6 * np.eye(n), -g)
+    assert int(st.item()) == 0
+    assert np.allclose(tau.cpu().numpy(), ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
+    with pytest.raises(DS3Error):
+        ds3.chol_ladder_solve(torch.eye(n + 1, dtype=torch.float64, device=dev),
+                              torch.zeros(n + 1, dtype=torch.float64, device=dev))
