@@ -20,7 +20,7 @@
 namespace ds3 {
 
 constexpr int kAdjThreads = 256;
-constexpr int kAdjPPT = 4;
+constexpr int kAdjPPT = 2;  // 65 VGPRs, 7 waves per SIMD in the gather (4: 99 VGPRs and 15% slower; 1: block reductions dominate)
 
 // Forward pass and cotangents of one match (n of j, m of i), scaled by dcost. Returns false for the
 // pixels the cost skips (holes, zero ranges, bad confidences, non-finite values).
