@@ -50,15 +50,15 @@ TRAFFIC = {
     "k_edge_reduce_batched": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "7d385c0f863bc90b", "bytes": 1868726432},
+        "sha": "15575f24559a0da1", "bytes": 1879326880},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
-        "sha": "425d30087beb6280", "bytes": 9303656128},
+        "sha": "3f05dc8d7e15c9b5", "bytes": 9303943488},
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "f129105fdb11bd97", "bytes": 21874706637},
+        "sha": "cb9ceb410efa1742", "bytes": 22959625472},
 }
 
 
