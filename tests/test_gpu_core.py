@@ -142,6 +142,25 @@ def test_chol_ladder_fallback_many_tiles(dev):
     assert np.allclose(tau.cpu().numpy(), ref, rtol=1e-8, atol=1e-10 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("p", [5, 40, 70, 110, 140])
+def test_chol_ladder_failure_in_each_tile_of_a_pair(dev, p):
+    """n = 150 (five 32-wide tiles: the leading pair, one more pair, a last single tile) with one negative
+    diagonal entry at row p on top of a weakly coupled SPD part: attempt 0 fails at the tile holding p
+    (the first or the second factorisation of a pair, or the last single tile), the ladder's later
+    attempt succeeds, and status and solution equal the oracle's."""
+    n = 150
+    rng = np.random.default_rng(150 + p)
+    A = rng.normal(size=(n, n)) / np.sqrt(n)
+    H = 0.01 * (A @ A.T) + np.diag(rng.uniform(1.5, 2.5, size=n))
+    H[p, p] = -0.5
+    g = rng.normal(size=n)
+    tau, st = ds3.chol_ladder_solve(_t(H, dev), _t(g, dev))
+    ref, st_ref = O.chol_ladder(H, g)
+    assert st_ref > 0
+    assert int(st.item()) == st_ref
+    assert np.allclose(tau.cpu().numpy(), ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("n", [3600, 5000])
 def test_chol_large_against_direct_solve(dev, n):
     """Sizes whose back substitution keeps 8 and 12 columns per thread, against a direct dense solve
