@@ -162,10 +162,20 @@ __device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
       as[q] = P[q * NB + s];
       xs[q] = P[(kFw + q) * NB + s];
     }
+    // keep every read above the pivot chain, so that their latency overlaps it (the scheduler would
+    // otherwise sink them below the chain and add the LDS round trip to every step)
+    __builtin_amdgcn_sched_barrier(0);
     // pivot block (identical in every thread, so the verdict is uniform)
+    // D[p][r] -= D[p][q] D[r][q] / d_q: the products are formed while the reciprocal of the pivot is
+    // in flight, so the chain from one pivot to the next is the reciprocal and one fma
     double dq[kFw], iq[kFw], g[kFw][kFw];
 #pragma unroll
     for (int q = 0; q < kFw; ++q) {
+      double pr[kFw][kFw];
+#pragma unroll
+      for (int p = q + 1; p < kFw; ++p)
+#pragma unroll
+        for (int r = q + 1; r <= p; ++r) pr[p][r] = D[p][q] * D[r][q];
       dq[q] = D[q][q];
       ok = ok && pivot_ok(dq[q]);
       iq[q] = recip(dq[q]);
@@ -174,7 +184,7 @@ __device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
 #pragma unroll
       for (int p = q + 1; p < kFw; ++p)
 #pragma unroll
-        for (int r = q + 1; r <= p; ++r) D[p][r] = fma(-g[p][q], D[r][q], D[p][r]);
+        for (int r = q + 1; r <= p; ++r) D[p][r] = fma(-pr[p][r], iq[q], D[p][r]);
     }
 #pragma unroll
     for (int q = 1; q < kFw; ++q)
