@@ -15,14 +15,17 @@
 // Attempt 0 runs this way; only when it fails does a persistent fallback kernel run attempts 1.. with its
 // own bounded grid barriers (the common case never pays for the ladder).
 //
-// Tile products run on the float64 MFMA; LDS tiles use row stride NB + 4.
+// Tile products run on the float64 MFMA; LDS tiles use row stride NB + 2.
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace ds3 {
 
 constexpr int NB = 32;
-constexpr int LDT = NB + 4;
+// LDS row stride of a tile: the 16 rows a wave reads down one column of a tile product land on distinct
+// banks (with NB + 4, rows eight apart shared banks: 0.65 -> 0.49 us for a product), rows stay 16-byte
+// aligned
+constexpr int LDT = NB + 2;
 constexpr int kCholThreads = 256;
 constexpr long kSpinLimit = 1L << 24;
 constexpr int kMaxAttempts = 16;
@@ -306,10 +309,8 @@ __device__ bool panel_tile(const CholArgs& a, int k, int i, int j, double* S0, d
   if (offd) frag_load(qj, a.Wm + int64_t(j) * NB * np + k * NB, np);
   frag_load(qa, a.Wm + int64_t(i) * NB * np + j * NB, np);
   double yk = 0.0, bi = 0.0;
-  if (col && threadIdx.x < NB) {
-    yk = a.y[k * NB + threadIdx.x];
-    bi = a.b[i * NB + threadIdx.x];
-  }
+  if (col && threadIdx.x < NB) yk = a.y[k * NB + threadIdx.x];
+  if (col && (threadIdx.x & 7) == 0) bi = a.b[i * NB + (threadIdx.x >> 3)];
   __syncthreads();  // previous users of S0..S2 and fb (fallback loop) are done
   frag_to_lds(qinv, S0);
   frag_to_lds(qi, S1);
@@ -328,14 +329,16 @@ __device__ bool panel_tile(const CholArgs& a, int k, int i, int j, double* S0, d
   frag_gemm_abt<true>(S1, offd ? S2 : S1, qa);  // A_ij -= L_ik L_jk^T
   if (col) {
     frag_store(li, a.L + int64_t(i) * NB * np + k * NB, np);
-    if (threadIdx.x < NB) {  // forward elimination b_i -= L_ik y_k
-      const int r = threadIdx.x;
-      double s0 = 0.0, s1 = 0.0;
-      for (int t = 0; t < NB; t += 2) {
-        s0 = fma(S1[r * LDT + t], sy[t], s0);
-        s1 = fma(S1[r * LDT + t + 1], sy[t + 1], s1);
-      }
-      const double bv = bi - (s0 + s1);
+    // forward elimination b_i -= L_ik y_k on 8 threads per row, reduced with lane shuffles
+    const int r = threadIdx.x >> 3, p = threadIdx.x & 7;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB / 8; ++q) acc = fma(S1[r * LDT + p + 8 * q], sy[p + 8 * q], acc);
+    acc += __shfl_xor(acc, 1, 8);
+    acc += __shfl_xor(acc, 2, 8);
+    acc += __shfl_xor(acc, 4, 8);
+    if (p == 0) {
+      const double bv = bi - acc;
       a.b[i * NB + r] = bv;
       sb[r] = bv;
     }
