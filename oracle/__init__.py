@@ -5,8 +5,8 @@ TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU-bas
 
 The heavy loops (matching, per-pixel linearisation, Cholesky) live in ``ds3_oracle.cpp`` (plain FP64
 C++, compiled by :func:`build`); this module marshals numpy arrays into it and holds the parts that are
-plain numpy: Umeyama's closed form (eq. 4), the component tracker of Sec. III-C, BF16 rounding and the
-pose-error measure.
+plain numpy: Umeyama's closed form (eq. 4), the component tracker of Sec. III-C, the canonical pointmap
+fusion of eq. (2), BF16 rounding and the pose-error measure.
 
 Pose layout everywhere: ``[tx, ty, tz, qx, qy, qz, qw, s]`` (float64), ``T_WC = [[sR, t], [0, 1]]``.
 Tangent layout: ``tau = (v, omega, zeta)`` (Sec. III-D).
@@ -412,6 +412,32 @@ def transform_points(pose, X) -> np.ndarray:
     M = pose_to_mat(pose)
     X = _f64(X).reshape(-1, 3)
     return X @ M[:3, :3].T + M[:3, 3]
+
+
+def fuse(canon, pred, pairs, poses) -> np.ndarray:
+    """Confidence-weighted running average of eq. (2) (Sec. III-A), applied pair by pair in order.
+
+    canon: (N, 4) xyz + confidence of the canonical keyframe pointmaps (X-hat, C-hat); pred: (M, 4) the
+    registered predictions, pixel-aligned with their keyframe and expressed in the frame's camera, with
+    their confidence C; pairs: rows (canon_off, pred_off, n_px); poses: one pose per pair, T_kf mapping
+    the frame into the keyframe. For pixel m of a pair, with y = T_kf x:
+        X-hat <- (C-hat X-hat + C y) / (C-hat + C),   C-hat <- C-hat + C.
+    A pixel whose prediction is not finite, or whose summed confidence is not positive, is left as it
+    is. Returns the updated copy of canon (float64)."""
+    out = _f64(canon).reshape(-1, 4).copy()
+    P = _f64(pred).reshape(-1, 4)
+    for (co, po, n), pose in zip(np.asarray(pairs, dtype=np.int64).reshape(-1, 3), np.asarray(poses).reshape(-1, 8)):
+        x = P[po:po + n]
+        c_new = x[:, 3]
+        c_old = out[co:co + n, 3]
+        tot = c_old + c_new
+        ok = np.isfinite(x).all(axis=1) & (tot > 0)
+        with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+            y = transform_points(pose, x[:, :3])
+            avg = (c_old[:, None] * out[co:co + n, :3] + c_new[:, None] * y) / tot[:, None]
+        out[co:co + n, :3] = np.where(ok[:, None], avg, out[co:co + n, :3])
+        out[co:co + n, 3] = np.where(ok, tot, c_old)
+    return out
 
 
 @dataclass
