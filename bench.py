@@ -125,6 +125,92 @@ def match_all(W, lm_steps=None, timer=None):
                            idx_out=W.idx, valid_out=W.valid, ws=W.mws, lm_steps=lm_steps, timer=timer)
 
 
+class Fusion:
+    pass
+
+
+def build_fusion(g, dev, seed=21):
+    """The canonical-map fusion workload of eq. (2) on the batched graph's keyframes: FP32 canonical
+    xyzc (the keyframes' points and confidences) and one registered prediction per keyframe, synthetic:
+    the keyframe's points seen from a frame T_kf^-1 away (rotation up to ~3 degrees, translation ~5 cm,
+    scale ~2%) plus 1% range noise, with confidences U(1, 5)."""
+    import torch
+    from paper_2605_30488_amd import api as ds3
+    F = Fusion()
+    rng = np.random.default_rng(seed)
+    sizes = [g.shape(k)[0] * g.shape(k)[1] for k in range(g.n_kf)]
+    F.n_px = int(sum(sizes))
+    offs = np.cumsum([0] + sizes)
+    F.pairs = [(int(offs[k]), int(offs[k]), int(sizes[k])) for k in range(g.n_kf)]
+    F.canon = torch.empty((F.n_px, 4), dtype=torch.float32, device=dev)
+    F.pred = torch.empty((F.n_px, 4), dtype=torch.float32, device=dev)
+    T = np.zeros((g.n_kf, 8))
+    for k in range(g.n_kf):
+        X = torch.as_tensor(np.asarray(g.xyz[k], np.float64).reshape(-1, 3)).to(dev)
+        c = torch.as_tensor(np.asarray(g.conf[k], np.float64).reshape(-1)).to(dev)
+        tau = np.concatenate([rng.normal(size=3) * 0.05, rng.normal(size=3) * 0.03, rng.normal(size=1) * 0.02])
+        Tk = ds3.sim3_exp(torch.as_tensor(tau).to(dev))[0]
+        T[k] = Tk.cpu().numpy()
+        q = Tk[3:7] / torch.linalg.norm(Tk[3:7])
+        x_, y_, z_, w_ = q
+        R = torch.stack([torch.stack([1 - 2 * (y_ * y_ + z_ * z_), 2 * (x_ * y_ - w_ * z_), 2 * (x_ * z_ + w_ * y_)]),
+                         torch.stack([2 * (x_ * y_ + w_ * z_), 1 - 2 * (x_ * x_ + z_ * z_), 2 * (y_ * z_ - w_ * x_)]),
+                         torch.stack([2 * (x_ * z_ - w_ * y_), 2 * (y_ * z_ + w_ * x_), 1 - 2 * (x_ * x_ + y_ * y_)])])
+        xf = ((X - Tk[:3]) @ R) / Tk[7]  # T^-1 X
+        xf = xf * (1.0 + 0.01 * torch.randn(xf.shape[0], 1, dtype=torch.float64, device=dev,
+                                              generator=torch.Generator(device=dev).manual_seed(seed + k)))
+        a, b = offs[k], offs[k + 1]
+        F.canon[a:b, :3] = X.float()
+        F.canon[a:b, 3] = c.float()
+        F.pred[a:b, :3] = xf.float()
+        F.pred[a:b, 3] = torch.as_tensor(rng.uniform(1, 5, sizes[k]), dtype=torch.float32).to(dev)
+    F.T = torch.as_tensor(T).to(dev)
+    F.plan = ds3.FusePlan(F.pairs, dev)
+    return F
+
+
+def measure_fusion(g, dev, reps=10, with_cpu=True):
+    """One ds3_fuse launch over all 200 keyframes, timed with HIP events on the launch stream; the
+    algorithmic traffic is 48 B per pixel (canonical xyzc read and written, prediction read)."""
+    import torch
+    F = build_fusion(g, dev)
+    for _ in range(2):
+        F.plan.run(F.canon, F.pred, F.T)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        F.plan.run(F.canon, F.pred, F.T)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nbytes = 48 * F.n_px
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    res = {"kernel": "k_fuse", "pairs": len(F.pairs), "px": F.n_px, "launch_ms": round(ms, 4),
+           "px_per_s": round(F.n_px / (ms * 1e-3), 1),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes}}
+    if with_cpu:
+        import oracle as O
+        from threadpoolctl import threadpool_limits
+        T = F.T.cpu().numpy()
+        sample = F.pairs[:8]
+        lo, hi = sample[0][0], sample[-1][0] + sample[-1][2]
+        c0 = F.canon[lo:hi].cpu().numpy()
+        pr = F.pred[lo:hi].cpu().numpy()
+        rows = [(co - lo, po - lo, n) for co, po, n in sample]
+        with threadpool_limits(1):
+            t0 = time.time()
+            O.fuse(c0, pr, rows, T[:len(sample)])
+            t = time.time() - t0
+        npx = sum(n for _, _, n in sample)
+        res["cpu_baseline"] = {"value": round(npx / t, 1), "unit": "px/s", "cores": 1, "kind": "oracle",
+                               "sample": f"eq. (2) fusion of {len(sample)} of {len(F.pairs)} keyframes "
+                                         f"({npx} px) in {t:.2f} s (numpy, FP64, one thread)"}
+    del F
+    return res
+
+
 def source_fingerprint(files):
     import hashlib
     h = hashlib.sha256()
@@ -452,6 +538,10 @@ def main():
             t0 = time.time()
             out["cpu_baseline"] = cpu_baseline(g)
             log(f"cpu baseline in {time.time() - t0:.1f}s")
+
+    # the next row past the graph step: canonical pointmap fusion of eq. (2) over the same keyframes
+    out["next_fusion"] = measure_fusion(g, dev, with_cpu=not (args.quick or args.no_cpu_baseline))
+    log(f"fusion: {out['next_fusion']['launch_ms']:.3f} ms per launch over {out['next_fusion']['px']} px")
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4

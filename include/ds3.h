@@ -305,6 +305,37 @@ int ds3_adjoint_plan_run(void* plan, const double* poses, float dcost, float* gr
                          double* grad_tau, double* cost_out, ds3_timer* timer, void* stream);
 int ds3_adjoint_plan_destroy(void* plan);
 
+/* ---------------------------------------------------------------------------------------------------
+ * Canonical pointmap fusion (Sec. III-A, eq. 2)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* One registered prediction to fuse into a keyframe's canonical pointmap: n_px pixels starting at pixel
+ * canon_off of the canonical arena and at pixel pred_off of the prediction arena. */
+typedef struct {
+  int64_t canon_off;
+  int64_t pred_off;
+  int64_t n_px;
+} ds3_fuse_pair;
+
+/* Workspace bytes of ds3_fuse for n_pairs pairs (the pair table on the device). */
+size_t ds3_fuse_workspace_bytes(int32_t n_pairs);
+
+/* The confidence-weighted running average of eq. (2) for n_pairs (keyframe, frame) pairs in one launch.
+ * For pair p and pixel m < pairs[p].n_px, with c = canon[canon_off + m] (xyz: canonical point X-hat of
+ * the keyframe, w: its confidence C-hat) and x = pred[pred_off + m] (xyz: the frame's prediction of the
+ * same keyframe pixel in the frame's camera, w: its confidence C):
+ *   y = T_p x,   X-hat <- (C-hat X-hat + C y) / (C-hat + C),   C-hat <- C-hat + C,
+ * evaluated in float64 from the float32 inputs and rounded once to float32.
+ *   canon (device, float4 xyzc per pixel, updated in place); pred (device, float4 xyzc per pixel);
+ *   T (device, n_pairs x 8 float64 in the pose layout, T_p = T_kf mapping the frame into the keyframe);
+ *   pairs (host, n_pairs entries).
+ * A pixel whose prediction has a non-finite entry, or whose summed confidence is not positive, is left
+ * unchanged. Two pairs may not share a canonical pixel (checked on the host: DS3_EINVAL), since they
+ * would race within the launch; fuse them in separate calls in their order. n_pairs = 0 is a no-op.
+ * Workspace from ds3_fuse_workspace_bytes. */
+int ds3_fuse(float* canon, const float* pred, const ds3_fuse_pair* pairs, int32_t n_pairs, const double* T,
+             void* workspace, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

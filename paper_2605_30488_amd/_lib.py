@@ -32,6 +32,10 @@ class GNParams(C.Structure):
                 ("max_attempts", C.c_int32)]
 
 
+class FusePair(C.Structure):
+    _fields_ = [("canon_off", C.c_int64), ("pred_off", C.c_int64), ("n_px", C.c_int64)]
+
+
 class PlanOpts(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("px_per_thread", C.c_int32), ("use_graph", C.c_int32),
                 ("reduce_timer", C.c_void_p)]
@@ -91,6 +95,8 @@ _SIGS = {
                                           C.POINTER(vp), vp]),
     "ds3_adjoint_plan_run": (C.c_int, [vp, vp, f32, vp, vp, vp, vp, vp, vp]),
     "ds3_adjoint_plan_destroy": (C.c_int, [vp]),
+    "ds3_fuse_workspace_bytes": (sz, [i32]),
+    "ds3_fuse": (C.c_int, [vp, vp, C.POINTER(FusePair), i32, vp, vp, sz, vp]),
 }
 
 

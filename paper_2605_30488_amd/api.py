@@ -504,3 +504,33 @@ class DenseSim3Cost(torch.autograd.Function):
         gx, gc, gt = gn_cost_adjoint(ctx.graph, ctx.poses, d, ctx.params)
         return (gx.to(xyz.dtype).reshape(xyz.shape), gc.to(conf.dtype).reshape(conf.shape),
                 gt.to(tau.dtype), None, None, None)
+
+
+# ------------------------------------------------------------------------------------------------
+# Canonical pointmap fusion (eq. 2)
+# ------------------------------------------------------------------------------------------------
+class FusePlan:
+    """A fixed pair table for ds3_fuse, uploaded through a workspace owned by the plan. pairs: rows
+    (canon_off, pred_off, n_px) in pixels."""
+
+    def __init__(self, pairs, device):
+        rows = [tuple(int(v) for v in p) for p in pairs]
+        self.n = len(rows)
+        self.table = (L.FusePair * max(self.n, 1))(*[L.FusePair(*r) for r in rows])
+        self.ws = _ws(L.load().ds3_fuse_workspace_bytes(self.n), device)
+
+    def run(self, canon: torch.Tensor, pred: torch.Tensor, T: torch.Tensor):
+        """In place on canon ((N, 4) float32 xyzc): X-hat <- (C-hat X-hat + C T x) / (C-hat + C),
+        C-hat <- C-hat + C per pixel of every pair; pred (M, 4) float32 xyzc in the frames' cameras; T
+        (n_pairs, 8) float64 poses mapping each frame into its keyframe."""
+        _need_cuda(canon, pred, T)
+        if canon.dtype != torch.float32 or pred.dtype != torch.float32 or T.dtype != torch.float64:
+            raise ValueError("fuse takes float32 xyzc arenas and float64 poses")
+        call("ds3_fuse", _ptr(canon), _ptr(pred), self.table, self.n, _ptr(T), _ptr(self.ws), self.ws.numel(),
+             _stream())
+        return canon
+
+
+def fuse(canon: torch.Tensor, pred: torch.Tensor, pairs, T: torch.Tensor):
+    """One ds3_fuse call (eq. 2) with a fresh pair table; see FusePlan.run."""
+    return FusePlan(pairs, canon.device).run(canon, pred, T)

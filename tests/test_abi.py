@@ -64,3 +64,25 @@ def test_pure_host_entry_points(lib):
     assert ds3.ds3_match(None, L.Image(2, 2, 0), None, L.Image(2, 2, 0), 0, ctypes.byref(p), None, None,
                          None, None, 0, None) == -1
     assert ds3.ds3_pack_xyzc(None, None, 5, 0, None, None) == -1
+
+
+def test_fuse_argument_checks_on_the_host(lib):
+    """ds3_fuse rejects bad pair tables before any HIP call: negative sizes, two pairs sharing canonical
+    pixels, misaligned arenas, a short workspace; an empty call is a no-op. (Pointers are never
+    dereferenced on these paths.)"""
+    from paper_2605_30488_amd import _lib as L
+    ds3 = L.load()
+    fake = ctypes.c_void_p(1 << 20)  # 16-byte aligned, never touched
+    T = ctypes.c_void_p(1 << 21)
+    ws_n = ds3.ds3_fuse_workspace_bytes(2)
+    assert ws_n >= 2 * 32 and ds3.ds3_fuse_workspace_bytes(0) == 0
+    ws = ctypes.c_void_p(1 << 22)
+    ok = (L.FusePair * 2)(L.FusePair(0, 0, 100), L.FusePair(100, 100, 50))
+    overlap = (L.FusePair * 2)(L.FusePair(0, 0, 100), L.FusePair(99, 100, 50))
+    neg = (L.FusePair * 1)(L.FusePair(0, 0, -1))
+    assert ds3.ds3_fuse(fake, fake, overlap, 2, T, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(fake, fake, neg, 1, T, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(ctypes.c_void_p((1 << 20) + 4), fake, ok, 2, T, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(fake, fake, ok, 2, T, ws, 8, None) == -4
+    assert ds3.ds3_fuse(fake, fake, ok, 0, T, ws, ws_n, None) == 0
+    assert ds3.ds3_fuse(fake, fake, ok, -1, T, ws, ws_n, None) == -1
