@@ -50,15 +50,19 @@ TRAFFIC = {
     "k_edge_reduce_batched": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "15575f24559a0da1", "bytes": 1879326880},
+        "sha": "15575f24559a0da1", "bytes": 1879252384},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
-        "sha": "3f05dc8d7e15c9b5", "bytes": 9303943488},
+        "sha": "3f05dc8d7e15c9b5", "bytes": 9303931968},
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
         "sha": "cb9ceb410efa1742", "bytes": 22959625472},
+    "k_fuse": {
+        "sources": ["paper_2605_30488_amd/csrc/fuse.hip", "paper_2605_30488_amd/csrc/common.hpp",
+                    "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/sim3.hpp"],
+        "sha": "c1fbb04d6487b796", "bytes": 1651931989},
 }
 
 
@@ -189,7 +193,8 @@ def measure_fusion(g, dev, reps=10, with_cpu=True):
     res = {"kernel": "k_fuse", "pairs": len(F.pairs), "px": F.n_px, "launch_ms": round(ms, 4),
            "px_per_s": round(F.n_px / (ms * 1e-3), 1),
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes}}
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_for("k_fuse"),
+                        "bytes_per_launch": nbytes}}
     if with_cpu:
         import oracle as O
         from threadpoolctl import threadpool_limits
