@@ -380,7 +380,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

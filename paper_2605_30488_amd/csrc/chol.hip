@@ -169,7 +169,7 @@ __device__ bool factor_frag(f64x4& Tf, double* fb, f64x4& Xq) {
     // keep every read above the pivot chain, so that their latency overlaps it (the scheduler would
     // otherwise sink them below the chain and add the LDS round trip to every step)
     __builtin_amdgcn_sched_barrier(0);
-    // pivot block (identical in every thread, so the verdict is uniform)
+    // pivot block (identical in every thread, so the outcome is uniform)
     // D[p][r] -= D[p][q] D[r][q] / d_q: the products are formed while the reciprocal of the pivot is
     // in flight, so the chain from one pivot to the next is the reciprocal and one fma
     double dq[kFw], iq[kFw], g[kFw][kFw];
