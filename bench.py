@@ -216,6 +216,51 @@ def measure_fusion(g, dev, reps=10, with_cpu=True):
     return res
 
 
+def pose_error(p, p_ref):
+    """Relative pose error per keyframe: max(rotation angle of R R_ref^T, |t - t_ref| / max(|t_ref|, 1 m),
+    |s / s_ref - 1|), poses as [t, q(xyzw), s]."""
+    p = np.asarray(p, np.float64).reshape(-1, 8)
+    r = np.asarray(p_ref, np.float64).reshape(-1, 8)
+    q = p[:, 3:7] / np.linalg.norm(p[:, 3:7], axis=1, keepdims=True)
+    qr = r[:, 3:7] / np.linalg.norm(r[:, 3:7], axis=1, keepdims=True)
+    w = np.abs(np.sum(q * qr, axis=1))
+    v = qr[:, 3:4] * q[:, :3] - q[:, 3:4] * qr[:, :3] - np.cross(q[:, :3], qr[:, :3])
+    ang = 2.0 * np.arctan2(np.linalg.norm(v, axis=1), w)
+    dt = np.linalg.norm(p[:, :3] - r[:, :3], axis=1) / np.maximum(np.linalg.norm(r[:, :3], axis=1), 1.0)
+    ds = np.abs(p[:, 7] / r[:, 7] - 1.0)
+    return np.maximum(np.maximum(ang, dt), ds)
+
+
+def measure_pose_error(g, W, dev):
+    """Pose error of the benchmarked plan form against the FP64 oracle, per agent: the same plan settings
+    on ground-truth matches, 20 iterations from the tracker-synchronised start, compared with the oracle's
+    20 iterations on the BF16-rounded inputs (arithmetic error) and on the FP32 inputs (total error),
+    both stored by tests/golden/make_pose_ref.py (an oracle-only script)."""
+    import torch
+
+    from paper_2605_30488_amd import api as ds3
+    path = os.path.join(ROOT, "tests", "golden", "pose_ref_batched.json")
+    ref = json.load(open(path))
+    idx = g.gt_idx_all()
+    flat = torch.as_tensor(np.concatenate([np.asarray(v).reshape(-1) for v in idx]), dtype=torch.int32).to(dev)
+    G = ds3.Graph(W.arena, W.edges, flat, W.idx_offsets, anchors=(0,))
+    P = torch.as_tensor(np.array(ref["start"])).to(dev)
+    plan = ds3.GNPlan(G, P, autotune=True)
+    plan.run(ref["iters"])
+    torch.cuda.synchronize()
+    got = P.cpu().numpy()
+    plan.close()
+    agents = range(int(np.max(g.agent)) + 1)
+    out = {"iters": ref["iters"], "matches": "ground truth", "start": "tracker-synchronised noisy poses"}
+    same = "poses_bf16" if W.dtype == "bf16" else "poses_f32"
+    for name, key in (("arithmetic", same), ("total", "poses_f32")):
+        e = pose_error(got, np.array(ref[key]))
+        out[name] = {"max": float(e.max()), "per_agent": [float(e[g.agent == a].max()) for a in agents]}
+    e = pose_error(np.array(ref["poses_bf16"]), np.array(ref["poses_f32"]))
+    out["oracle_bf16_vs_f32"] = {"max": float(e.max()), "per_agent": [float(e[g.agent == a].max()) for a in agents]}
+    return out
+
+
 def source_fingerprint(files):
     import hashlib
     h = hashlib.sha256()
@@ -503,6 +548,11 @@ def main():
            "ladder_status_min": int(statuses.min()), "ladder_status_max": int(statuses.max()), "plan": info}
     if statuses.min() < 0:
         log("WARNING: the Cholesky ladder gave a zero step in some iteration (status -1)")
+
+    if args.config in (3, 4) and not args.quick:
+        t0 = time.time()
+        out["pose_error"] = measure_pose_error(g, W, dev)
+        log(f"pose error vs the FP64 oracle: {out['pose_error']} ({time.time() - t0:.1f}s)")
 
     if not args.quick:
         # plain form: FP32, one residual launch per edge, no graph, on the same matches

@@ -58,7 +58,8 @@ typedef struct {
 
 /* Matching constants. nu_min is the paper's admission gate (Sec. III-B, 0.1). The remaining values are
  * readings where the paper is silent: Levenberg-Marquardt on the bilinear ray interpolant (max_iters
- * trial steps, damping lambda0, floor lambda_min, stop after an accepted step below step_tol_px),
+ * trial steps, damping lambda0, floor lambda_min, stop after a trial step (accepted or not) below
+ * step_tol_px in a non-singular system),
  * validity = no hole, final angular residual <= ang_tol_px * min(|ds/du|, |ds/dv|), and
  * | |x| - |X_ref[idx]| | <= range_rel_tol * |X_ref[idx]|; mutual check within a Chebyshev radius;
  * q_min the confidence sqrt(C_i C_j) needed to count towards nu.
@@ -263,6 +264,12 @@ int ds3_gn_plan_time_reduce(void* plan, int32_t reps, float* ms_out, void* strea
  * iteration by the residual kernel under the streaming model]. */
 int ds3_gn_plan_info(void* plan, int64_t* info5);
 int ds3_gn_plan_destroy(void* plan);
+/* The autotuner's cache: one line per (device, dtype, shape mix) with the tile shape it picked, in the
+ * file named by the environment variable DS3_TUNE_CACHE, else $HOME/.cache/ds3_tune.txt. Host only (no
+ * GPU call): creates the file's directory if it is missing (mkdir, no child process) and removes the
+ * file, so that the next plan with opts->autotune times its candidates again. DS3_EINVAL if the file
+ * exists and cannot be removed. */
+int ds3_tune_cache_reset(void);
 
 /* ---------------------------------------------------------------------------------------------------
  * Cost and its adjoint (gradient of eq. 5 with the matches held fixed)
@@ -326,15 +333,17 @@ size_t ds3_fuse_workspace_bytes(int32_t n_pairs);
  * same keyframe pixel in the frame's camera, w: its confidence C):
  *   y = T_p x,   X-hat <- (C-hat X-hat + C y) / (C-hat + C),   C-hat <- C-hat + C,
  * evaluated in float64 from the float32 inputs and rounded once to float32.
- *   canon (device, float4 xyzc per pixel, updated in place); pred (device, float4 xyzc per pixel);
- *   T (device, n_pairs x 8 float64 in the pose layout, T_p = T_kf mapping the frame into the keyframe);
- *   pairs (host, n_pairs entries).
+ *   canon (device, n_canon_px float4 xyzc pixels, updated in place); pred (device, n_pred_px float4
+ *   xyzc pixels; it may not overlap canon); T (device, n_T >= n_pairs poses of 8 float64 in the pose
+ *   layout, T_p = T_kf mapping the frame into the keyframe); pairs (host, n_pairs entries). Every pair
+ *   must lie inside both arenas (DS3_EINVAL otherwise, checked on the host before any launch).
  * A pixel whose prediction has a non-finite entry, or whose summed confidence is not positive, is left
  * unchanged. Two pairs may not share a canonical pixel (checked on the host: DS3_EINVAL), since they
  * would race within the launch; fuse them in separate calls in their order. n_pairs = 0 is a no-op.
  * Workspace from ds3_fuse_workspace_bytes. */
-int ds3_fuse(float* canon, const float* pred, const ds3_fuse_pair* pairs, int32_t n_pairs, const double* T,
-             void* workspace, size_t ws_bytes, void* stream);
+int ds3_fuse(float* canon, int64_t n_canon_px, const float* pred, int64_t n_pred_px,
+             const ds3_fuse_pair* pairs, int32_t n_pairs, const double* T, int32_t n_T, void* workspace,
+             size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

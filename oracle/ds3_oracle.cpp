@@ -43,7 +43,7 @@ typedef struct {
   int32_t max_iters;        // LM trial steps per query
   double lambda0;           // initial LM damping
   double lambda_min;        // floor of the damping after an accepted step
-  double step_tol_px;       // stop after an accepted step with max(|du|,|dv|) below this
+  double step_tol_px;       // stop after a trial step (accepted or not) with max(|du|,|dv|) below this
   double ang_tol_px;        // validity: |r| <= ang_tol_px * min(|ds/du|, |ds/dv|)
   double range_rel_tol;     // validity: ||x| - |X_ref[idx]|| <= range_rel_tol * |X_ref[idx]|
   int32_t mutual_radius_px; // mutual check: Chebyshev distance of the round trip
@@ -383,14 +383,17 @@ MatchOut match_one(const double* x, int qu, int qv, int Hq, int Wq, const double
     RaySample Sn = sample_rays(rays, holes, H, W, un, vn);
     if (Sn.hole) { o.iters = it + 1; return o; }
     double cn = cost_of(Sn);
+    double step = std::max(std::fabs(un - u), std::fabs(vn - v));
     if (cn < c) {
-      double step = std::max(std::fabs(un - u), std::fabs(vn - v));
       u = un; v = vn; S = Sn; c = cn;
       lam = std::max(lam * 0.1, P.lambda_min);
-      if (step < P.step_tol_px) { ++it; break; }
     } else {
       lam *= 10.0;
     }
+    // convergence: a trial step below the tolerance ends the search, accepted or not (a rejected one
+    // that short means the cost no longer decreases along the damped Gauss-Newton direction, and the
+    // tenfold damping would only shorten the next steps further)
+    if (step < P.step_tol_px) { ++it; break; }
   }
   o.iters = it;
   o.pu = u;

@@ -87,6 +87,7 @@ _SIGS = {
     "ds3_gn_plan_info": (C.c_int, [vp, P_i64]),
     "ds3_gn_plan_destroy": (C.c_int, [vp]),
     "ds3_gn_plan_set_timer": (C.c_int, [vp, vp]),
+    "ds3_tune_cache_reset": (C.c_int, []),
     "ds3_gn_cost": (C.c_int, [vp, i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams), vp, vp,
                               sz, vp]),
     "ds3_gn_cost_adjoint": (C.c_int, [vp, i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams),
@@ -96,7 +97,7 @@ _SIGS = {
     "ds3_adjoint_plan_run": (C.c_int, [vp, vp, f32, vp, vp, vp, vp, vp, vp]),
     "ds3_adjoint_plan_destroy": (C.c_int, [vp]),
     "ds3_fuse_workspace_bytes": (sz, [i32]),
-    "ds3_fuse": (C.c_int, [vp, vp, C.POINTER(FusePair), i32, vp, vp, sz, vp]),
+    "ds3_fuse": (C.c_int, [vp, i64, vp, i64, C.POINTER(FusePair), i32, vp, i32, vp, sz, vp]),
 }
 
 

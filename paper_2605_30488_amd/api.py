@@ -526,8 +526,14 @@ class FusePlan:
         _need_cuda(canon, pred, T)
         if canon.dtype != torch.float32 or pred.dtype != torch.float32 or T.dtype != torch.float64:
             raise ValueError("fuse takes float32 xyzc arenas and float64 poses")
-        call("ds3_fuse", _ptr(canon), _ptr(pred), self.table, self.n, _ptr(T), _ptr(self.ws), self.ws.numel(),
-             _stream())
+        if canon.dim() != 2 or canon.shape[1] != 4 or pred.dim() != 2 or pred.shape[1] != 4:
+            raise ValueError("fuse takes (N, 4) xyzc arenas")
+        if not (canon.is_contiguous() and pred.is_contiguous() and T.is_contiguous()):
+            raise ValueError("fuse takes contiguous tensors")
+        if T.dim() != 2 or T.shape[1] != 8:
+            raise ValueError("fuse takes (n_pairs, 8) poses")
+        call("ds3_fuse", _ptr(canon), canon.shape[0], _ptr(pred), pred.shape[0], self.table, self.n, _ptr(T),
+             T.shape[0], _ptr(self.ws), self.ws.numel(), _stream())
         return canon
 
 

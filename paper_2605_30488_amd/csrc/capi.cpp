@@ -1,8 +1,11 @@
 // C ABI of libds3 (declared in include/ds3.h): argument checks, workspace layout, launch sequences of the
 // plain form, and the batched plan (work-item ordering, tile autotuning, hipGraph capture).
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
+#include <sys/types.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -608,16 +611,26 @@ static bool tune_lookup(const std::string& key, int& ppt, int& bpc) {
   return found;
 }
 
+// Creates every missing directory of `dir` with mkdir(2) (no child process: the caller has already
+// initialised the GPU). Errors are ignored; the cache write that follows simply fails.
+void make_dirs(const std::string& dir) {
+  for (size_t pos = 1; pos <= dir.size(); ++pos) {
+    if (pos == dir.size() || dir[pos] == '/') (void)::mkdir(dir.substr(0, pos).c_str(), 0755);
+  }
+}
+
 static void tune_store(const std::string& key, int ppt, int bpc) {
   std::string path = tune_cache_path();
   auto slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    std::string dir = path.substr(0, slash);
-    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-    if (std::system(cmd.c_str()) != 0) return;
-  }
+  if (slash != std::string::npos && slash > 0) make_dirs(path.substr(0, slash));
   std::ofstream f(path, std::ios::app);
   if (f) f << key << "\t" << ppt << " " << bpc << "\n";
+}
+
+static std::string tune_cache_dir() {
+  const std::string path = tune_cache_path();
+  const auto slash = path.rfind('/');
+  return (slash != std::string::npos && slash > 0) ? path.substr(0, slash) : std::string();
 }
 
 static int plan_autotune(Plan& P, hipStream_t s) {
@@ -817,6 +830,14 @@ int ds3_gn_plan_info(void* plan, int64_t* info) {
   info[2] = P->px_scanned;
   info[3] = P->px_valid;
   info[4] = 4 * P->px_scanned + 2 * int64_t(px_bytes) * P->px_valid;
+  return DS3_OK;
+}
+
+int ds3_tune_cache_reset(void) {
+  const std::string dir = tune_cache_dir();
+  if (!dir.empty()) make_dirs(dir);
+  const std::string path = tune_cache_path();
+  if (std::remove(path.c_str()) != 0 && errno != ENOENT) return fail(DS3_EINVAL, "tune cache: cannot remove " + path);
   return DS3_OK;
 }
 

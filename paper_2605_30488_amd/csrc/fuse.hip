@@ -89,19 +89,30 @@ using namespace ds3;
 
 extern "C" size_t ds3_fuse_workspace_bytes(int32_t n_pairs) { return n_pairs > 0 ? fuse_workspace(n_pairs) : 0; }
 
-extern "C" int ds3_fuse(float* canon, const float* pred, const ds3_fuse_pair* pairs, int32_t n_pairs,
-                        const double* T, void* workspace, size_t ws_bytes, void* stream) {
+extern "C" int ds3_fuse(float* canon, int64_t n_canon_px, const float* pred, int64_t n_pred_px,
+                        const ds3_fuse_pair* pairs, int32_t n_pairs, const double* T, int32_t n_T,
+                        void* workspace, size_t ws_bytes, void* stream) {
   if (n_pairs < 0) return fail(DS3_EINVAL, "fuse: n_pairs < 0");
   if (n_pairs == 0) return DS3_OK;
   if (!canon || !pred || !pairs || !T || !workspace) return fail(DS3_EINVAL, "fuse: null pointer");
+  if (n_canon_px < 0 || n_pred_px < 0) return fail(DS3_EINVAL, "fuse: negative arena size");
+  if (n_T < n_pairs) return fail(DS3_EINVAL, "fuse: fewer poses than pairs");
   if ((reinterpret_cast<uintptr_t>(canon) | reinterpret_cast<uintptr_t>(pred)) & 15u)
     return fail(DS3_EINVAL, "fuse: arenas must be 16-byte aligned (float4 per pixel)");
+  {
+    // the canonical arena is written in place: it may not share memory with the prediction arena
+    const uintptr_t c0 = reinterpret_cast<uintptr_t>(canon), c1 = c0 + 16u * uint64_t(n_canon_px);
+    const uintptr_t p0 = reinterpret_cast<uintptr_t>(pred), p1 = p0 + 16u * uint64_t(n_pred_px);
+    if (c0 < p1 && p0 < c1) return fail(DS3_EINVAL, "fuse: canonical and prediction arenas overlap");
+  }
   if (ws_bytes < fuse_workspace(n_pairs)) return fail(DS3_ENOSPACE, "fuse: workspace too small");
   std::vector<FusePairDev> dev(n_pairs);
   int64_t tiles = 0;
   for (int p = 0; p < n_pairs; ++p) {
     const ds3_fuse_pair& q = pairs[p];
     if (q.n_px < 0 || q.canon_off < 0 || q.pred_off < 0) return fail(DS3_EINVAL, "fuse: negative offset or size");
+    if (q.canon_off > n_canon_px - q.n_px || q.pred_off > n_pred_px - q.n_px)
+      return fail(DS3_EINVAL, "fuse: pair " + std::to_string(p) + " reaches past the end of an arena");
     dev[p] = FusePairDev{q.canon_off, q.pred_off, q.n_px, int32_t(tiles), 0};
     tiles += (q.n_px + kFuseTile - 1) / kFuseTile;
     if (tiles > INT_MAX) return fail(DS3_EINVAL, "fuse: too many pixels for one call");

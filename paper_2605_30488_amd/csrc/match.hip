@@ -4,8 +4,8 @@
 // Per query pixel: Levenberg-Marquardt over the continuous reference pixel p on the bilinear interpolant
 // of the reference ray image psi(X_ref) (not renormalised), started at the query's own pixel scaled to
 // the reference grid; a trial step is accepted iff it lowers |s(p) - psi(x)|^2 (damping / 10, floored),
-// otherwise the damping grows x10; stop after max_iters trial steps or an accepted step below
-// step_tol_px. idx = round(p*) (ties up). Valid iff no hole was touched, the final angular residual is
+// otherwise the damping grows x10; stop after max_iters trial steps or a trial step (accepted or not)
+// below step_tol_px. idx = round(p*) (ties up). Valid iff no hole was touched, the final angular residual is
 // within ang_tol_px * min(|ds/du|, |ds/dv|) and the range agrees within range_rel_tol. The mutual check
 // keeps pixel n of j iff its match m in i maps back within a Chebyshev radius of n.
 //
@@ -56,9 +56,13 @@ struct Sample {
   bool hole;
 };
 
-// The four texels of the last cell a query sampled: a trial that stays in the same cell (the common case
-// once the steps are sub-pixel, and for every damped retry that moves a little) reuses them instead of
-// gathering again.
+// The four texels of the last cell a query sampled, each minus the query's target ray: a trial that stays
+// in the same cell (the common case once the steps are sub-pixel, and for every damped retry that moves a
+// little) reuses them instead of gathering again. Interpolating the differences gives the residual
+// s(p) - psi(x) directly: neighbouring rays differ from the target by about a pixel's angle, so their
+// differences are nearly exact in float32 and the residual keeps its relative precision down to the
+// optimum, where s(p) and psi(x) agree to six digits. (Interpolating the rays first and subtracting
+// afterwards loses those digits: the cost then stops decreasing at steps of about 1e-4 px.)
 struct Cell {
   int u0, v0;
   float a[3], b[3], c[3], d[3];
@@ -70,24 +74,25 @@ __device__ inline void cell_origin(int H, int W, float u, float v, int& u0, int&
   v0 = max(min(int(floorf(v)), H - 2), 0);
 }
 
-__device__ inline void fetch_cell(const float4* __restrict__ R, int W, int u0, int v0, Cell& C) {
+__device__ inline void fetch_cell(const float4* __restrict__ R, int W, int u0, int v0, const float* t, Cell& C) {
   const int64_t i00 = int64_t(v0) * W + u0;
   const float4 a = R[i00], b = R[i00 + 1], c = R[i00 + W], d = R[i00 + W + 1];
   C.u0 = u0;
   C.v0 = v0;
   C.hole = !(a.w > 0.f) || !(b.w > 0.f) || !(c.w > 0.f) || !(d.w > 0.f);
-  C.a[0] = a.x; C.a[1] = a.y; C.a[2] = a.z;
-  C.b[0] = b.x; C.b[1] = b.y; C.b[2] = b.z;
-  C.c[0] = c.x; C.c[1] = c.y; C.c[2] = c.z;
-  C.d[0] = d.x; C.d[1] = d.y; C.d[2] = d.z;
+  C.a[0] = a.x - t[0]; C.a[1] = a.y - t[1]; C.a[2] = a.z - t[2];
+  C.b[0] = b.x - t[0]; C.b[1] = b.y - t[1]; C.b[2] = b.z - t[2];
+  C.c[0] = c.x - t[0]; C.c[1] = c.y - t[1]; C.c[2] = c.z - t[2];
+  C.d[0] = d.x - t[0]; C.d[1] = d.y - t[1]; C.d[2] = d.z - t[2];
 }
 
-// Bilinear sample of the ray image and its in-cell derivatives at (u, v); gathers only when the cell
-// differs from the cached one.
-__device__ inline Sample sample_rays(const float4* __restrict__ R, int H, int W, float u, float v, Cell& C) {
+// Bilinear sample of (ray image - target ray), i.e. the residual, and its in-cell derivatives at (u, v);
+// gathers only when the cell differs from the cached one.
+__device__ inline Sample sample_rays(const float4* __restrict__ R, int H, int W, float u, float v, const float* t,
+                                     Cell& C) {
   int u0, v0;
   cell_origin(H, W, u, v, u0, v0);
-  if (u0 != C.u0 || v0 != C.v0) fetch_cell(R, W, u0, v0, C);
+  if (u0 != C.u0 || v0 != C.v0) fetch_cell(R, W, u0, v0, t, C);
   const float fu = u - float(u0), fv = v - float(v0);
   Sample S;
   S.hole = C.hole;
@@ -113,15 +118,15 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
   if (!finite3(x.x, x.y, x.z) || !(dx2 > 1e-18f)) return -1;
   const float dx = sqrtf(dx2);
   const float rdx = 1.0f / dx;
-  const float t0 = x.x * rdx, t1 = x.y * rdx, t2 = x.z * rdx;
+  const float t[3] = {x.x * rdx, x.y * rdx, x.z * rdx};
   float u = (Wq > 1) ? float(qu) * (float(W - 1) / float(Wq - 1)) : 0.0f;
   float v = (Hq > 1) ? float(qv) * (float(H - 1) / float(Hq - 1)) : 0.0f;
   Cell C;
   C.u0 = -1;
   C.v0 = -1;
-  Sample S = sample_rays(R, H, W, u, v, C);
+  Sample S = sample_rays(R, H, W, u, v, t, C);
   if (S.hole) return -1;
-  float r0 = S.s[0] - t0, r1 = S.s[1] - t1, r2 = S.s[2] - t2;
+  float r0 = S.s[0], r1 = S.s[1], r2 = S.s[2];
   float c = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
   float lam = P.lambda0;
   // normal equations at the current p; unchanged by a rejected step, so rebuilt only on acceptance
@@ -147,21 +152,18 @@ __device__ inline int32_t match_query(const float4* __restrict__ R, int H, int W
     const float vn = det_ok ? fminf(fmaxf(v + dv, 0.0f), float(H - 1)) : v;
     // no movement (singular system, clamped or vanishing step): same sample, same cost, reject
     const bool moved = (un != u) || (vn != v);
-    const Sample Sn = sample_rays(R, H, W, un, vn, C);
+    const Sample Sn = sample_rays(R, H, W, un, vn, t, C);
     if (moved && Sn.hole) {
       hole = true;
       active = false;
       continue;  // `it` advances past this trial
     }
-    const float n0 = Sn.s[0] - t0, n1 = Sn.s[1] - t1, n2 = Sn.s[2] - t2;
+    const float n0 = Sn.s[0], n1 = Sn.s[1], n2 = Sn.s[2];
     const float cn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
     const bool acc = moved && (cn < c);
     const float step = fmaxf(fabsf(un - u), fabsf(vn - v));
-    // A rejected trial shorter than the tolerance also ends the search: in float32 the cost stops
-    // decreasing at the rounding floor, so such a step is rejected and every later one (ten times
-    // shorter per rejection) would be too; in exact arithmetic the search would stop at the next
-    // accepted step, which moves p by less than the tolerance. (Singular systems still retry with a
-    // larger damping.)
+    // A trial step shorter than the tolerance ends the search whether or not it is accepted (a
+    // non-singular system: singular ones retry with a larger damping); the oracle takes the same rule.
     if (!acc && det_ok && step < P.step_tol) active = false;
     lam = acc ? fmaxf(lam * 0.1f, P.lambda_min) : lam * 10.0f;
     if (acc) {

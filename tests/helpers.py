@@ -54,3 +54,67 @@ def perturb(poses, rng, rot=0.02, trans=0.05, scale=0.02, fixed=(0,)):
         Rn = synth.axis_angle(w, np.linalg.norm(w))
         out[k] = synth.pose_vec(Rn @ R, t + rng.normal(size=3) * trans, s * math.exp(rng.normal() * scale))
     return out
+
+
+# ------------------------------------------------------------------------------------------------
+# Scale-aware comparisons: the entries of H, g and the gradients span many orders of magnitude (the ray
+# rows are weighted by 1/sigma_r^2 = 1.1e5, the range row by 1/sigma_d^2 = 0.01), so each part is
+# compared against its own magnitude, never against the largest entry of the whole array.
+# ------------------------------------------------------------------------------------------------
+def jacobi_scaled_err(H, H_ref):
+    """max_ab |H - H_ref|_ab / sqrt(H_ref_aa H_ref_bb): the difference of D^-1/2 H D^-1/2 with
+    D = diag(H_ref), so that every row and column (ray, range, scale) is measured in its own units."""
+    H, H_ref = np.asarray(H, np.float64), np.asarray(H_ref, np.float64)
+    d = np.sqrt(np.abs(np.diag(H_ref)))
+    s = np.outer(d, d)
+    ok = s > 0
+    return float((np.abs(H - H_ref)[ok] / s[ok]).max())
+
+
+def block_rel_err(H, H_ref, b=7):
+    """Largest relative difference over the nonzero b x b blocks, each against its own largest entry."""
+    H, H_ref = np.asarray(H, np.float64), np.asarray(H_ref, np.float64)
+    n = H.shape[0] // b
+    worst = 0.0
+    for r in range(n):
+        for c in range(n):
+            B = H_ref[r * b:(r + 1) * b, c * b:(c + 1) * b]
+            m = np.abs(B).max()
+            if m > 0:
+                worst = max(worst, float(np.abs(H[r * b:(r + 1) * b, c * b:(c + 1) * b] - B).max() / m))
+    return worst
+
+
+TANGENT_GROUPS = ((0, 3), (3, 6), (6, 7))  # v, omega, zeta
+
+
+def tangent_group_err(g, g_ref):
+    """Per keyframe and per tangent group (translation, rotation, scale) of (N, 7) gradients: the largest
+    relative difference, each group against its own largest entry (groups that are exactly zero in the
+    reference, such as an anchor's, must be zero)."""
+    g = np.asarray(g, np.float64).reshape(-1, 7)
+    g_ref = np.asarray(g_ref, np.float64).reshape(-1, 7)
+    worst = 0.0
+    for k in range(g.shape[0]):
+        for a, b in TANGENT_GROUPS:
+            m = np.abs(g_ref[k, a:b]).max()
+            d = np.abs(g[k, a:b] - g_ref[k, a:b]).max()
+            worst = max(worst, d / m if m > 0 else (0.0 if d == 0 else np.inf))
+    return float(worst)
+
+
+def pixel_channel_err(gx, gx_ref, px_off):
+    """Per keyframe (pixel ranges px_off[k]:px_off[k+1]) and per channel of a per-pixel gradient ((P, C)
+    or (P,)): the largest difference against that keyframe's channel's own largest entry."""
+    gx = np.asarray(gx, np.float64)
+    gx_ref = np.asarray(gx_ref, np.float64)
+    if gx.ndim == 1:
+        gx, gx_ref = gx[:, None], gx_ref[:, None]
+    worst = 0.0
+    for k in range(len(px_off) - 1):
+        a, b = px_off[k], px_off[k + 1]
+        for c in range(gx.shape[1]):
+            m = np.abs(gx_ref[a:b, c]).max()
+            d = np.abs(gx[a:b, c] - gx_ref[a:b, c]).max()
+            worst = max(worst, d / m if m > 0 else (0.0 if d == 0 else np.inf))
+    return float(worst)

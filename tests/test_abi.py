@@ -68,21 +68,59 @@ def test_pure_host_entry_points(lib):
 
 def test_fuse_argument_checks_on_the_host(lib):
     """ds3_fuse rejects bad pair tables before any HIP call: negative sizes, two pairs sharing canonical
-    pixels, misaligned arenas, a short workspace; an empty call is a no-op. (Pointers are never
-    dereferenced on these paths.)"""
+    pixels, pairs reaching past either arena, fewer poses than pairs, overlapping canonical and
+    prediction arenas, misaligned arenas, a short workspace; an empty call is a no-op. (Pointers are
+    never dereferenced on these paths.)"""
     from paper_2605_30488_amd import _lib as L
     ds3 = L.load()
-    fake = ctypes.c_void_p(1 << 20)  # 16-byte aligned, never touched
+    canon = ctypes.c_void_p(1 << 20)  # 16-byte aligned, never touched
+    pred = ctypes.c_void_p(1 << 24)
     T = ctypes.c_void_p(1 << 21)
     ws_n = ds3.ds3_fuse_workspace_bytes(2)
     assert ws_n >= 2 * 32 and ds3.ds3_fuse_workspace_bytes(0) == 0
     ws = ctypes.c_void_p(1 << 22)
+    nc, npd = 150, 150
     ok = (L.FusePair * 2)(L.FusePair(0, 0, 100), L.FusePair(100, 100, 50))
     overlap = (L.FusePair * 2)(L.FusePair(0, 0, 100), L.FusePair(99, 100, 50))
     neg = (L.FusePair * 1)(L.FusePair(0, 0, -1))
-    assert ds3.ds3_fuse(fake, fake, overlap, 2, T, ws, ws_n, None) == -1
-    assert ds3.ds3_fuse(fake, fake, neg, 1, T, ws, ws_n, None) == -1
-    assert ds3.ds3_fuse(ctypes.c_void_p((1 << 20) + 4), fake, ok, 2, T, ws, ws_n, None) == -1
-    assert ds3.ds3_fuse(fake, fake, ok, 2, T, ws, 8, None) == -4
-    assert ds3.ds3_fuse(fake, fake, ok, 0, T, ws, ws_n, None) == 0
-    assert ds3.ds3_fuse(fake, fake, ok, -1, T, ws, ws_n, None) == -1
+    past_canon = (L.FusePair * 2)(L.FusePair(0, 0, 100), L.FusePair(101, 100, 50))
+    past_pred = (L.FusePair * 2)(L.FusePair(0, 0, 100), L.FusePair(100, 101, 50))
+    assert ds3.ds3_fuse(canon, nc, pred, npd, overlap, 2, T, 2, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(canon, nc, pred, npd, neg, 1, T, 2, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(canon, nc, pred, npd, past_canon, 2, T, 2, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(canon, nc, pred, npd, past_pred, 2, T, 2, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(canon, nc, pred, npd, ok, 2, T, 1, ws, ws_n, None) == -1   # one pose for two pairs
+    assert ds3.ds3_fuse(canon, nc, pred, 149, ok, 2, T, 2, ws, ws_n, None) == -1  # prediction arena short
+    # aliasing: the prediction arena starts inside the canonical one, or is the same memory
+    assert ds3.ds3_fuse(canon, nc, ctypes.c_void_p((1 << 20) + 16 * 149), npd, ok, 2, T, 2, ws, ws_n,
+                        None) == -1
+    assert ds3.ds3_fuse(canon, nc, canon, npd, ok, 2, T, 2, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(ctypes.c_void_p((1 << 20) + 4), nc, pred, npd, ok, 2, T, 2, ws, ws_n, None) == -1
+    assert ds3.ds3_fuse(canon, nc, pred, npd, ok, 2, T, 2, ws, 8, None) == -4
+    assert ds3.ds3_fuse(canon, nc, pred, npd, ok, 0, T, 2, ws, ws_n, None) == 0
+    assert ds3.ds3_fuse(canon, nc, pred, npd, ok, -1, T, 2, ws, ws_n, None) == -1
+
+
+def test_tune_cache_directory_is_created_without_a_child_process(lib, tmp_path, monkeypatch):
+    """ds3_tune_cache_reset creates the autotuner cache's missing directories (mkdir, host only) and
+    removes a stale cache file."""
+    from paper_2605_30488_amd import _lib as L
+    ds3 = L.load()
+    path = tmp_path / "a" / "b" / "c" / "tune.txt"
+    monkeypatch.setenv("DS3_TUNE_CACHE", str(path))
+    assert not path.parent.exists()
+    assert ds3.ds3_tune_cache_reset() == 0
+    assert path.parent.is_dir() and not path.exists()
+    path.write_text("gfx950|bf16|cu256|196608x196608\t16 2\n")
+    assert ds3.ds3_tune_cache_reset() == 0
+    assert not path.exists()
+
+
+def test_library_sources_start_no_child_process():
+    """The library never forks or runs a shell: no system/popen/fork/exec call in its sources."""
+    csrc = os.path.join(ROOT, "paper_2605_30488_amd", "csrc")
+    pat = re.compile(r"\b(std::system|system|popen|fork|vfork|execl|execlp|execle|execv|execvp|execve|posix_spawn)\s*\(")
+    for name in os.listdir(csrc):
+        text = open(os.path.join(csrc, name)).read()
+        code = re.sub(r"//[^\n]*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+        assert not pat.search(code), name

@@ -9,7 +9,7 @@ import torch
 
 import oracle as O
 import synth
-from tests.helpers import exact_graph, perturb
+from tests.helpers import block_rel_err, exact_graph, jacobi_scaled_err, perturb, tangent_group_err
 
 pytestmark = pytest.mark.gpu
 
@@ -200,8 +200,11 @@ def test_gn_linearize_exact_graph(dev):
     H, g = H.cpu().numpy(), g.cpu().numpy()
     assert int(cnt.item()) == nr
     assert abs(cost.item() - cr) <= 2e-5 * cr
-    assert np.abs(H - Hr).max() <= 2e-5 * np.abs(Hr).max()
-    assert np.abs(g - gr).max() <= 2e-4 * np.abs(gr).max()
+    # every entry in the units of its own row and column, every 7x7 block against itself, and the
+    # gradient per keyframe and tangent group (translation, rotation, scale)
+    ej, eb, eg = jacobi_scaled_err(H, Hr), block_rel_err(H, Hr), tangent_group_err(g, gr)
+    print(f"H: Jacobi-scaled {ej:.2e}, per block {eb:.2e}; g per keyframe and group {eg:.2e}")
+    assert ej <= 1e-5 and eb <= 1e-4 and eg <= 1e-4
     assert np.array_equal(H, H.T)
 
 
@@ -263,12 +266,16 @@ def test_match_one_direction_bit_exact(dev):
     pv = p.cpu().numpy()
     both = (r.idx >= 0) & (idx >= 0)
     dev_p = np.abs(pv[both] - r.p[both]).max(axis=1)
+    same_its = its.cpu().numpy() == r.iters
     print(f"excluded {excl.sum()} of {excl.size}; valid {np.mean(r.idx >= 0):.3f}; "
           f"|p_gpu - p_oracle| median {np.median(dev_p):.2e} p99 {np.quantile(dev_p, 0.99):.2e} "
-          f"max {dev_p.max():.2e}; iteration counts equal {np.mean(its.cpu().numpy() == r.iters):.4f}")
+          f"max {dev_p.max():.2e}; iteration counts equal {np.mean(same_its):.4f} "
+          f"(outside the exclusions {np.mean(same_its[keep]):.4f})")
     assert excl.sum() <= 0.01 * excl.size
     assert np.array_equal(idx[keep], r.idx[keep])
     assert dev_p.max() < 2e-3
+    # one control flow: the LM search takes the same number of trial steps as the oracle's
+    assert np.mean(same_its[keep]) >= 0.99
 
 
 def test_match_bidir_config1(dev):

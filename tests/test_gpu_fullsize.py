@@ -115,3 +115,43 @@ def test_plan_fullsize_bf16_two_steps(dev, batched):
     assert err <= 1e-5
     assert rel.max() <= 1e-5
     plan.close()
+
+
+def test_plan_fullsize_bf16_pose_error_per_agent(dev, batched):
+    """The precision configuration: the batched plan on all 800 edges with BF16 pointmaps and
+    confidences, FP32 accumulation and the FP64 solve, 20 iterations from the tracker-synchronised start
+    on ground-truth matches, against the FP64 oracle's 20 iterations stored by
+    tests/golden/make_pose_ref.py. Pose error (max over each agent's keyframes) against the oracle on the
+    same BF16-rounded inputs (arithmetic only) is asserted <= 1e-5; against the oracle on the original
+    FP32 inputs (total) it is printed with the oracle's own rounded-vs-unrounded distance: the rounding of
+    the inputs to BF16 alone moves the FP64 solution by 1.1e-4 to 3.9e-4 per agent, above the 1e-4 that
+    was aimed at, whatever the arithmetic."""
+    import json
+    import os
+    import sys
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, here)
+    from make_pose_ref import fingerprint
+    ref = json.load(open(os.path.join(here, "pose_ref_batched.json")))
+    g, W = batched
+    idx = g.gt_idx_all()
+    assert fingerprint(g, idx) == ref["fingerprint"], "the generator no longer produces the stored graph"
+    flat = torch.as_tensor(np.concatenate([np.asarray(v).reshape(-1) for v in idx]), dtype=torch.int32).to(dev)
+    G = ds3.Graph(W.arena, W.edges, flat, W.idx_offsets, anchors=(0,))
+    P = torch.as_tensor(np.array(ref["start"])).to(dev)
+    plan = ds3.GNPlan(G, P, autotune=True)
+    cost, st = plan.run(ref["iters"])
+    torch.cuda.synchronize()
+    got = P.cpu().numpy()
+    e_arith = O.pose_error(got, np.array(ref["poses_bf16"]))
+    e_total = O.pose_error(got, np.array(ref["poses_f32"]))
+    e_quant = O.pose_error(np.array(ref["poses_bf16"]), np.array(ref["poses_f32"]))
+    agents = range(int(g.agent.max()) + 1)
+    per = {name: [float(e[g.agent == a].max()) for a in agents]
+           for name, e in (("arithmetic", e_arith), ("total", e_total), ("oracle_quantisation", e_quant))}
+    rel = np.abs(cost.cpu().numpy() - np.array(ref["costs_bf16"])) / np.array(ref["costs_bf16"])
+    print(f"pose error per agent after {ref['iters']} iterations: {per}; cost rel err max {rel.max():.2e}")
+    assert st.cpu().numpy().tolist() == ref["status_bf16"]
+    assert max(per["arithmetic"]) <= 1e-5
+    assert rel.max() <= 1e-5
+    plan.close()

@@ -15,6 +15,7 @@ import torch
 
 import oracle as O
 import synth
+from tests.helpers import pixel_channel_err, tangent_group_err
 
 pytestmark = pytest.mark.gpu
 
@@ -75,9 +76,10 @@ def test_adjoint_fullsize_sampled_keyframes(dev, long_graph):
         a, b = px_off[k], px_off[k + 1]
         s = remap[k]
         sa, sb = sub_off[s], sub_off[s + 1]
-        ex = np.abs(gx_np[a:b] - rx[sa:sb]).max() / np.abs(rx[sa:sb]).max()
-        ec = np.abs(gc_np[a:b] - rc[sa:sb]).max() / np.abs(rc[sa:sb]).max()
-        et = np.abs(gt_np[k] - rt[s]).max() / np.abs(rt[s]).max()
+        # each channel (x, y, z; conf) and each tangent group against its own largest entry
+        ex = pixel_channel_err(gx_np[a:b], rx[sa:sb], [0, b - a])
+        ec = pixel_channel_err(gc_np[a:b], rc[sa:sb], [0, b - a])
+        et = tangent_group_err(gt_np[k], rt[s])
         print(f"kf {k}: rel err dE/dxyz {ex:.2e} dE/dconf {ec:.2e} dE/dtau {et:.2e}")
         assert ex <= 2e-4 and ec <= 2e-4 and et <= 1e-3
 
@@ -108,11 +110,13 @@ def test_adjoint_plan_fullsize_against_atomic_path(dev, long_graph):
     assert torch.equal(px1, px2) and torch.equal(pc1, pc2) and torch.equal(pt1, pt2)
     print(f"plan cost {c1.item():.9e} vs batched cost kernel {cost:.9e}")
     assert abs(c1.item() - cost) <= 1e-5 * cost
-    ex = float((px1 - gx).abs().max() / gx.abs().max())
-    ec = float((pc1 - gc).abs().max() / gc.abs().max())
-    et = float((pt1 - gt).abs().max() / gt.abs().max())
+    # per keyframe and channel, and per keyframe and tangent group, each against its own largest entry
+    px_off = np.cumsum([0] + [g.shape(k)[0] * g.shape(k)[1] for k in range(g.n_kf)])
+    ex = pixel_channel_err(px1.cpu().numpy(), gx.cpu().numpy(), px_off)
+    ec = pixel_channel_err(pc1.cpu().numpy(), gc.cpu().numpy(), px_off)
+    et = tangent_group_err(pt1.cpu().numpy(), gt.cpu().numpy())
     print(f"plan vs atomic path: rel max diff dE/dxyz {ex:.2e} dE/dconf {ec:.2e} dE/dtau {et:.2e}")
-    assert ex <= 1e-5 and ec <= 1e-5 and et <= 1e-5
+    assert ex <= 1e-5 and ec <= 1e-5 and et <= 1e-4
     plan.close()
 
 

@@ -254,3 +254,25 @@ def test_pose_gradient_sums_to_zero():
     _, _, _, gt_tau = O.cost_grad(g, poses)
     assert np.abs(gt_tau).max() > 1e-3
     assert np.abs(gt_tau.sum(0)).max() <= 1e-9 * np.abs(gt_tau).sum(0).max()
+
+
+def test_scale_aware_comparisons_catch_errors_in_small_rows():
+    """The GPU parity tests compare H per entry after Jacobi scaling and g per tangent group: a 50% error
+    planted in the scale column of H, or in the scale entries of g (the smallest entries, set by the
+    range row with sigma_d = 10), shows up as about 1% of the largest entry, but as the full 50% (or
+    more) in these measures."""
+    from tests.helpers import block_rel_err, jacobi_scaled_err, tangent_group_err
+    xyz, conf, edges, idx, gt = exact_graph(n_kf=3, H=12, W=16, seed=5)
+    poses = perturb(gt, np.random.default_rng(1), rot=0.02, trans=0.03, scale=0.02)
+    H, g, *_ = O.gn_assemble(O.Graph(xyz, conf, edges, idx, anchors=(0,)), poses)
+    Hb = H.copy()
+    for k in range(1, 3):  # scale column and row of every non-anchor keyframe
+        Hb[:, 7 * k + 6] *= 1.5
+        Hb[7 * k + 6, :] *= 1.5
+    gb = g.copy()
+    gb[6::7] *= 1.5
+    assert np.abs(Hb - H).max() <= 2e-2 * np.abs(H).max()   # diluted by the largest entry
+    assert np.abs(gb - g).max() <= 2e-2 * np.abs(g).max()
+    assert jacobi_scaled_err(Hb, H) >= 0.5 and block_rel_err(Hb, H) > 1e-2
+    assert tangent_group_err(gb, g) >= 0.5 - 1e-12
+    assert jacobi_scaled_err(H, H) == 0.0 and tangent_group_err(g, g) == 0.0
