@@ -40,6 +40,7 @@ extern "C" {
 #define DS3_ENOTSUP (-2)  /* unsupported dtype or device architecture */
 #define DS3_EHIP (-3)     /* HIP runtime error (detail in ds3_status_string) */
 #define DS3_ENOSPACE (-4) /* workspace smaller than the size the *_workspace_bytes call returned */
+#define DS3_EDEGENERATE (-5) /* degenerate input with no unique answer (collinear correspondences) */
 
 typedef enum { DS3_F32 = 0, DS3_BF16 = 1 } ds3_dtype;
 
@@ -163,6 +164,16 @@ int ds3_gauge_align(const void* X_i, ds3_image img_i, const void* X_j, ds3_image
                     const int32_t* idx_j2i, const uint8_t* valid_j, const double* poses, int32_t i,
                     int32_t j, int32_t ref_is_i, int32_t nc_min, double* T_out, int32_t* used_umeyama,
                     void* workspace, size_t ws_bytes, void* stream);
+/* The closed form of eq. (4) on the host, float64: the similarity T* = (s, R, t) minimising
+ * sum_l |x_l - (s R y_l + t)|^2 over n correspondences x, y (host, n x 3 float64 each, row l = point l),
+ * written as a pose (T_out, host, 8 float64: T* maps y onto x). With centroids xb, yb and
+ * A = (1/n) sum (x - xb)(y - yb)^T = U Lambda V^T: R = U S V^T with S = diag(1, 1, det(U V^T)),
+ * s = tr(S Lambda) / ((1/n) sum |y - yb|^2), t = xb - s R yb (the same solve the device gauge alignment
+ * uses). Returns DS3_EINVAL for null pointers, n < 1 or non-finite input, and DS3_EDEGENERATE (T_out
+ * untouched) when rank(A) < 2 (collinear points: the rotation about their line is free) or y has no
+ * spread. No GPU call. */
+int ds3_umeyama(const double* x, const double* y, int64_t n, double* T_out);
+
 /* Workspace bytes of ds3_gauge_align and ds3_gauge_sync for a graph of n_kf keyframes. */
 size_t ds3_gauge_workspace_bytes(int32_t n_kf);
 
@@ -231,21 +242,32 @@ int ds3_chol_ladder_solve(const double* H, const double* g, int32_t n, double la
                           double mult, int32_t attempts, double* tau, int32_t* status, void* workspace,
                           size_t ws_bytes, void* stream);
 
-/* Batched form: one plan per graph topology. Creation uploads the topology, counts valid matches per
- * tile, orders (edge, tile) items longest first (an ordering hint only: every tile is processed, so the
- * plan stays valid when the idx arena is rewritten, e.g. by a new matching pass), picks tile shapes (opts->autotune: timed candidates,
- * cached per device, dtype and shape mix; synchronises) and captures one GN iteration in a hipGraph.
- * The plan owns its device buffers and graph; the keyframe arena, idx arena and poses stay the
- * caller's and must outlive the plan. ds3_gn_plan_run replays the iteration `iters` times on `stream`
- * with no host synchronisation, writing E at each iteration's input poses to cost_per_iter (device,
- * iters float64) and the ladder status to status_per_iter (device, iters int32; either may be NULL). */
+/* Batched form: one plan per graph topology (edges, keyframe images, idx offsets) over a set of matches.
+ * The matches and the pointmaps stay fixed while Gauss-Newton moves the poses, so the plan holds a match
+ * stream: for every edge, the two arena entries (X_j[n] and X_i[m]) and the weight (C_i C_j)^(1/4) of each
+ * valid match, gathered once into contiguous records (16 B per match for DS3_BF16, 32 B for DS3_F32),
+ * grouped in segments of 256 * px_per_thread pixels of keyframe j; matches with a hole, a non-finite value
+ * or a negative confidence product are dropped here, as the plain form skips them. Every iteration then
+ * streams those records (one block per segment, the heaviest segments first), instead of scanning the
+ * idx arena and gathering X_i again. Creation uploads the topology, gathers the stream, picks the
+ * segment size and the loads in flight per thread (opts->autotune: timed candidates, cached per device,
+ * dtype and shape mix; synchronises) and captures one GN iteration in a hipGraph.
+ * The plan owns its device buffers (the stream: up to (sum over edges of H_j*W_j, rounded up to whole
+ * segments) records) and its graph; the keyframe arena, idx arena and poses stay the caller's and must
+ * outlive the plan. After the caller rewrites the idx arena (a new matching pass) or the keyframe arena,
+ * ds3_gn_plan_refresh must run before the next ds3_gn_plan_run: the plan reads the snapshot, not the
+ * arenas. ds3_gn_plan_run replays the iteration `iters` times on `stream` with no host synchronisation,
+ * writing E at each iteration's input poses to cost_per_iter (device, iters float64) and the ladder status
+ * to status_per_iter (device, iters int32; either may be NULL). */
 typedef struct {
-  int32_t autotune;        /* 1: time candidate tile shapes at creation */
-  int32_t px_per_thread;   /* tile shape when not autotuning (0 = default) */
+  int32_t autotune;        /* 1: time candidate segment sizes and loads in flight at creation */
+  int32_t px_per_thread;   /* segment = 256 * px_per_thread pixels (4, 8, 16 or 32; 0 = 16) when not
+                              autotuning */
   int32_t use_graph;       /* 1: capture the iteration in a hipGraph (default), 0: direct launches */
   ds3_timer* reduce_timer; /* may be NULL: recorded around the fused residual/Hessian launch of the last
                               iteration of every ds3_gn_plan_run, which then runs as direct launches
                               instead of a graph replay (same kernels, same results) */
+  int32_t unroll;          /* match records in flight per thread (1, 2 or 4; 0 = 2) when not autotuning */
 } ds3_plan_opts;
 
 int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena, ds3_dtype dtype,
@@ -254,15 +276,21 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena
                        const ds3_plan_opts* opts, double* poses, void** plan_out, void* stream);
 int ds3_gn_plan_run(void* plan, int32_t iters, double* cost_per_iter, int32_t* status_per_iter,
                     void* stream);
+/* Re-gathers the match stream from the current idx arena and keyframe arena (one launch on `stream`, no
+ * synchronisation; same topology). Needed after either arena changes. */
+int ds3_gn_plan_refresh(void* plan, void* stream);
 /* Replaces the plan's reduce_timer (NULL: none) for the following runs; the caller keeps it alive. */
 int ds3_gn_plan_set_timer(void* plan, ds3_timer* timer);
 /* Timing hook for the fused residual/Hessian kernel alone: launches it `reps` times on `stream` at the
  * plan's current poses (device prep included), bracketed by events; *ms_out (host) = mean ms per
  * launch. Synchronises. */
 int ds3_gn_plan_time_reduce(void* plan, int32_t reps, float* ms_out, void* stream);
-/* Plan facts (host): [n_items, px_per_thread, total px scanned, total valid px, bytes read per
- * iteration by the residual kernel under the streaming model]. */
-int ds3_gn_plan_info(void* plan, int64_t* info5);
+/* Plan facts at creation (host, the first n_info of): [segments, px_per_thread, px of j scanned over all
+ * edges, valid matches (idx in range), bytes of the streaming model (4 B idx per scanned px + both arena
+ * entries per valid match), bytes the residual kernel reads per iteration (records + segment counts),
+ * bytes one ds3_gn_plan_refresh moves (idx + both entries read, records written), records in flight per
+ * thread]. */
+int ds3_gn_plan_info(void* plan, int64_t* info, int32_t n_info);
 int ds3_gn_plan_destroy(void* plan);
 /* The autotuner's cache: one line per (device, dtype, shape mix) with the tile shape it picked, in the
  * file named by the environment variable DS3_TUNE_CACHE, else $HOME/.cache/ds3_tune.txt. Host only (no

@@ -38,7 +38,7 @@ class FusePair(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("px_per_thread", C.c_int32), ("use_graph", C.c_int32),
-                ("reduce_timer", C.c_void_p)]
+                ("reduce_timer", C.c_void_p), ("unroll", C.c_int32)]
 
 
 _lib = None
@@ -68,6 +68,7 @@ _SIGS = {
     "ds3_gauge_align": (C.c_int, [vp, Image, vp, Image, C.c_int, vp, vp, vp, i32, i32, i32, i32, vp, vp,
                                   vp, sz, vp]),
     "ds3_apply_gauge": (C.c_int, [vp, i32, vp, vp, vp]),
+    "ds3_umeyama": (C.c_int, [P_f64, P_f64, i64, P_f64]),
     "ds3_gauge_sync": (C.c_int, [vp, i32, P_i32, vp, P_img, C.c_int, P_edge, i32, vp, vp, vp, i32, P_i32,
                                  vp, sz, vp]),
     "ds3_sim3_exp": (C.c_int, [vp, vp, i32, vp]),
@@ -84,7 +85,8 @@ _SIGS = {
                                      i32, C.POINTER(PlanOpts), vp, C.POINTER(vp), vp]),
     "ds3_gn_plan_run": (C.c_int, [vp, i32, vp, vp, vp]),
     "ds3_gn_plan_time_reduce": (C.c_int, [vp, i32, C.POINTER(C.c_float), vp]),
-    "ds3_gn_plan_info": (C.c_int, [vp, P_i64]),
+    "ds3_gn_plan_info": (C.c_int, [vp, P_i64, i32]),
+    "ds3_gn_plan_refresh": (C.c_int, [vp, vp]),
     "ds3_gn_plan_destroy": (C.c_int, [vp]),
     "ds3_gn_plan_set_timer": (C.c_int, [vp, vp]),
     "ds3_tune_cache_reset": (C.c_int, []),

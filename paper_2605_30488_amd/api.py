@@ -207,6 +207,20 @@ def gauge_align(arena: Arena, i: int, j: int, idx_j2i, valid_j, poses, ref_is_i=
     return T, used
 
 
+def umeyama(x, y):
+    """eq. (4) on the host (ds3_umeyama, float64): the pose of T* mapping the (n, 3) points y onto x.
+    Raises DS3Error (code DS3_EDEGENERATE = -5) for collinear correspondences."""
+    import numpy as np
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    y = np.ascontiguousarray(y, np.float64).reshape(-1, 3)
+    if x.shape != y.shape:
+        raise ValueError("umeyama takes two (n, 3) arrays of the same shape")
+    T = np.empty(8)
+    dp = C.POINTER(C.c_double)
+    call("ds3_umeyama", x.ctypes.data_as(dp), y.ctypes.data_as(dp), x.shape[0], T.ctypes.data_as(dp))
+    return T
+
+
 def apply_gauge(poses, mask, T):
     call("ds3_apply_gauge", _ptr(poses), poses.shape[0], _ptr(mask), _ptr(T), _stream())
     return poses
@@ -358,18 +372,20 @@ class KernelTimer:
 
 
 class GNPlan:
-    """Batched form (ds3_gn_plan_*): one persistent residual launch per iteration, captured with the
-    rest of the iteration in a hipGraph. Binds to `poses`, which every run updates in place.
-    reduce_timer (a KernelTimer, kept alive by the plan) is recorded around the residual launch."""
+    """Batched form (ds3_gn_plan_*): the valid matches gathered once into a match stream, one residual
+    launch over it per iteration, captured with the rest of the iteration in a hipGraph. Binds to
+    `poses`, which every run updates in place. After the graph's idx (or arena) contents change, call
+    refresh(). reduce_timer (a KernelTimer, kept alive by the plan) is recorded around the residual
+    launch."""
 
     def __init__(self, graph: Graph, poses, params=None, autotune=False, px_per_thread=0, use_graph=True,
-                 reduce_timer=None):
+                 reduce_timer=None, unroll=0):
         self.graph = graph
         self.poses = poses
         self.reduce_timer = reduce_timer
         P = params or default_gn_params()
         opts = L.PlanOpts(int(autotune), int(px_per_thread), int(use_graph),
-                          reduce_timer.handle if reduce_timer is not None else None)
+                          reduce_timer.handle if reduce_timer is not None else None, int(unroll))
         h = C.c_void_p()
         call("ds3_gn_plan_create", graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
              len(graph.edges), _ptr(graph.idx), C.byref(P), graph.an, len(graph.anchors), C.byref(opts),
@@ -384,6 +400,10 @@ class GNPlan:
         call("ds3_gn_plan_run", self.handle, iters, _ptr(cost), _ptr(st), _stream())
         return cost[:iters], st[:iters]
 
+    def refresh(self):
+        """Re-gather the match stream from the graph's current idx and arena contents."""
+        call("ds3_gn_plan_refresh", self.handle, _stream())
+
     def set_timer(self, timer):
         """Record `timer` (a KernelTimer, or None) around the residual launch of each later run."""
         call("ds3_gn_plan_set_timer", self.handle, timer.handle if timer is not None else None)
@@ -395,10 +415,10 @@ class GNPlan:
         return ms.value
 
     def info(self) -> dict:
-        a = (C.c_int64 * 5)()
-        call("ds3_gn_plan_info", self.handle, a)
+        a = (C.c_int64 * 8)()
+        call("ds3_gn_plan_info", self.handle, a, 8)
         return {"items": a[0], "px_per_thread": a[1], "px_scanned": a[2], "px_valid": a[3],
-                "bytes_streaming": a[4]}
+                "bytes_streaming": a[4], "bytes_stream_per_iter": a[5], "bytes_refresh": a[6], "unroll": a[7]}
 
     def close(self):
         if self.handle:

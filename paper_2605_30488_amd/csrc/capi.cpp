@@ -258,7 +258,7 @@ static int gn_linearize_plain(const double* poses, const Topology& T, const GnBu
                               const ds3_gn_params& p, double* H, double* g, double* cost_out,
                               int64_t* count_out, hipStream_t s) {
   const GnConst c = make_gn_const(p);
-  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
+  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, s));
   for (int e = 0; e < T.n_edges; ++e)
     DS3_TRY(launch_edge_reduce_one(dt, kPlainPPT, arena, T.edges[e], e, B.xf, idx, B.partials, c, s));
   DS3_TRY(launch_edge_finalize(B.edges, T.n_edges, B.partials, B.Ad, B.A_e, B.b_e, B.cost_e, B.count_e, s));
@@ -309,6 +309,7 @@ const char* ds3_status_string(int code) {
                      : code == DS3_ENOTSUP ? "not supported"
                      : code == DS3_EHIP ? "HIP error"
                      : code == DS3_ENOSPACE ? "workspace too small"
+                     : code == DS3_EDEGENERATE ? "degenerate input"
                                             : "unknown";
   msg = std::string(name) + (g_last_error.empty() ? "" : " (" + g_last_error + ")");
   return msg.c_str();
@@ -426,7 +427,7 @@ int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const vo
   DS3_TRY(check_arch());
   hipStream_t s = S(stream);
   DS3_TRY(upload_topology(T, B, s));
-  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
+  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, s));
   DS3_TRY(launch_cost_batched(dtype, arena, B.edges, T.n_edges, max_npx_j(T), B.xf, idx, make_gn_const(*params),
                               B.part7, B.cost_e, B.count_e, s));
   return launch_sum_costs(B.cost_e, B.count_e, T.n_edges, cost_out, nullptr, s);
@@ -447,7 +448,7 @@ int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, 
   DS3_TRY(check_arch());
   hipStream_t s = S(stream);
   DS3_TRY(upload_topology(T, B, s));
-  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, nullptr, s));
+  DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, s));
   const int max_npx_kf = *std::max_element(T.kf_npx.begin(), T.kf_npx.end());
   return launch_adjoint(dtype, arena, B.edges, T.n_edges, max_npx_j(T), max_npx_kf, B.xf, B.Ad, idx,
                         make_gn_const(*params), dcost, grad_xyz, grad_conf, B.part7, B.b_e, T.n_kf, B.kf_off,
@@ -473,10 +474,15 @@ struct Plan {
   ds3_dtype dt = DS3_F32;
   ds3_gn_params p;
   GnConst c;
-  int ppt = 16;
-  int grid = 0;
+  int ppt = 16;         // segment = kReduceThreads * ppt pixels of keyframe j
+  int unroll = 2;       // match records in flight per thread in the residual kernel
   int n_items = 0;
   WorkItem* items = nullptr;
+  void* stream = nullptr;      // match stream: records of every segment (capacity for the largest segment)
+  int32_t* seg_count = nullptr;  // records per segment
+  size_t stream_cap = 0;       // records the stream holds
+  int64_t n_records = 0;       // records gathered at creation (matches passing the static checks)
+  int reserved_tiles = 0;      // partial and count slots (tiles of the smallest segment size)
   double* cost_hist = nullptr;
   int32_t* status_hist = nullptr;
   unsigned* hist_ctr = nullptr;
@@ -490,10 +496,10 @@ struct Plan {
 
 // One GN iteration; `timed` records the plan's timer around the residual launch (never inside a capture).
 static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
-  DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, P.B.counter, s));
+  DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, s));
   if (timed) DS3_TRY(timer_record(P.timer, true, s));
-  DS3_TRY(launch_edge_reduce_batched(P.dt, P.ppt, P.grid, P.arena, P.B.edges, P.items, P.n_items, P.B.xf,
-                                     P.idx, P.B.partials, P.B.counter, P.c, s));
+  DS3_TRY(launch_reduce_stream(P.dt, P.unroll, P.stream, P.seg_count, P.B.edges, P.items, P.n_items, P.B.xf,
+                               P.T.tile_px, P.B.partials, P.c, s));
   if (timed) DS3_TRY(timer_record(P.timer, false, s));
   DS3_TRY(launch_edge_finalize(P.B.edges, P.T.n_edges, P.B.partials, P.B.Ad, P.B.A_e, P.B.b_e, P.B.cost_e,
                                P.B.count_e, s));
@@ -522,7 +528,7 @@ static int plan_build_items(Plan& P, int ppt, hipStream_t s) {
     total += E.n_tiles;
     mx = std::max(mx, E.n_tiles);
   }
-  if (total > P.T.total_tiles) return fail(DS3_EINVAL, "plan: tile table larger than reserved");
+  if (total > P.reserved_tiles) return fail(DS3_EINVAL, "plan: tile table larger than reserved");
   T2.total_tiles = total;
   T2.max_tiles = mx;
   T2.tile_px = tile_px;
@@ -547,22 +553,30 @@ static int plan_build_items(Plan& P, int ppt, hipStream_t s) {
   P.n_items = int(items.size());
   P.ppt = ppt;
   P.T.edges = T2.edges;
+  P.T.total_tiles = total;
   P.T.max_tiles = mx;
   P.T.tile_px = tile_px;
+  if (size_t(total) * size_t(tile_px) > P.stream_cap) return fail(DS3_EINVAL, "plan: stream larger than reserved");
+  // gather the match stream for this segment size and read back how many records it holds
+  DS3_TRY(launch_gather_stream(P.dt, P.arena, P.B.edges, P.items, P.n_items, P.idx, tile_px, P.stream,
+                               P.seg_count, s));
+  DS3_TRY_HIP(hipMemcpyAsync(counts.data(), P.seg_count, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
   DS3_TRY_HIP(hipStreamSynchronize(s));
+  P.n_records = 0;
+  for (int t = 0; t < total; ++t) P.n_records += counts[t];
   return DS3_OK;
 }
 
 static int plan_time_reduce(Plan& P, int reps, float* ms, hipStream_t s) {
-  DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, nullptr, s));
+  DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, s));
   DS3_TRY(launch_fill_u32(P.time_ctrs, size_t(reps), 0u, s));
   hipEvent_t a, b;
   DS3_TRY_HIP(hipEventCreate(&a));
   DS3_TRY_HIP(hipEventCreate(&b));
   int rc = check_hip(hipEventRecord(a, s), "hipEventRecord");
   for (int r = 0; r < reps && rc == DS3_OK; ++r)
-    rc = launch_edge_reduce_batched(P.dt, P.ppt, P.grid, P.arena, P.B.edges, P.items, P.n_items, P.B.xf,
-                                    P.idx, P.B.partials, P.time_ctrs + r, P.c, s);
+    rc = launch_reduce_stream(P.dt, P.unroll, P.stream, P.seg_count, P.B.edges, P.items, P.n_items, P.B.xf,
+                              P.T.tile_px, P.B.partials, P.c, s);
   if (rc == DS3_OK) rc = check_hip(hipEventRecord(b, s), "hipEventRecord");
   if (rc == DS3_OK) rc = check_hip(hipEventSynchronize(b), "hipEventSynchronize");
   float t = 0.f;
@@ -581,7 +595,7 @@ static std::string tune_key(const Plan& P) {
   std::map<std::pair<int, int>, int> shapes;
   for (auto& E : P.T.edges) shapes[{E.npx_j, E.npx_i}]++;
   std::ostringstream k;
-  k << prop.gcnArchName << "|" << (P.dt == DS3_F32 ? "f32" : "bf16") << "|cu" << prop.multiProcessorCount;
+  k << prop.gcnArchName << "|stream|" << (P.dt == DS3_F32 ? "f32" : "bf16") << "|cu" << prop.multiProcessorCount;
   for (auto& kv : shapes) k << "|" << kv.first.first << "x" << kv.first.second;
   return k.str();
 }
@@ -634,33 +648,31 @@ static std::string tune_cache_dir() {
 }
 
 static int plan_autotune(Plan& P, hipStream_t s) {
-  const int cus = device_cu_count();
   const std::string key = tune_key(P);
-  int best_ppt = 16, best_bpc = 2;
-  if (tune_lookup(key, best_ppt, best_bpc)) {
-    DS3_TRY(plan_build_items(P, best_ppt, s));
-    P.grid = std::max(1, std::min(cus * best_bpc, P.n_items));
-    return DS3_OK;
+  int best_ppt = 16, best_unroll = 2;
+  if (tune_lookup(key, best_ppt, best_unroll) && (best_unroll == 1 || best_unroll == 2 || best_unroll == 4) &&
+      (best_ppt == 8 || best_ppt == 16 || best_ppt == 32)) {
+    P.unroll = best_unroll;
+    return plan_build_items(P, best_ppt, s);
   }
   float best = 1e30f;
-  for (int ppt : {4, 8, 16, 32}) {
+  for (int ppt : {8, 16, 32}) {
     DS3_TRY(plan_build_items(P, ppt, s));
-    for (int bpc : {1, 2, 4, 8}) {
-      P.grid = std::max(1, std::min(cus * bpc, P.n_items));
+    for (int unroll : {1, 2, 4}) {
+      P.unroll = unroll;
       float ms = 0.f;
       DS3_TRY(plan_time_reduce(P, 2, &ms, s));  // warm
       DS3_TRY(plan_time_reduce(P, 5, &ms, s));
       if (ms < best) {
         best = ms;
         best_ppt = ppt;
-        best_bpc = bpc;
+        best_unroll = unroll;
       }
     }
   }
-  tune_store(key, best_ppt, best_bpc);
-  DS3_TRY(plan_build_items(P, best_ppt, s));
-  P.grid = std::max(1, std::min(cus * best_bpc, P.n_items));
-  return DS3_OK;
+  tune_store(key, best_ppt, best_unroll);
+  P.unroll = best_unroll;
+  return plan_build_items(P, best_ppt, s);
 }
 
 static void plan_free(Plan* P) {
@@ -673,6 +685,8 @@ static void plan_free(Plan* P) {
   if (P->status_hist) (void)hipFree(P->status_hist);
   if (P->hist_ctr) (void)hipFree(P->hist_ctr);
   if (P->time_ctrs) (void)hipFree(P->time_ctrs);
+  if (P->stream) (void)hipFree(P->stream);
+  if (P->seg_count) (void)hipFree(P->seg_count);
   delete P;
 }
 
@@ -742,6 +756,20 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
   if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->status_hist, sizeof(int32_t) * kHistory), "hipMalloc");
   if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->hist_ctr, sizeof(unsigned) * 4), "hipMalloc");
   if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->time_ctrs, sizeof(unsigned) * 64), "hipMalloc");
+  // match stream: room for every pixel of every edge at the largest segment size (the padding of the
+  // last segment of each edge included); segment counts for the smallest segment size
+  for (int ppt : {4, 8, 16, 32}) {
+    const size_t seg = size_t(kReduceThreads) * ppt;
+    size_t cap = 0;
+    for (auto& E : P->T.edges) cap += (size_t(E.npx_j) + seg - 1) / seg * seg;
+    P->stream_cap = std::max(P->stream_cap, cap);
+  }
+  if (rc == DS3_OK)
+    rc = check_hip(hipMalloc(&P->stream, std::max<size_t>(P->stream_cap, 1) * stream_record_bytes(dtype)),
+                   "hipMalloc(match stream)");
+  if (rc == DS3_OK)
+    rc = check_hip(hipMalloc(&P->seg_count, sizeof(int32_t) * std::max(P->T.total_tiles, 1)), "hipMalloc");
+  P->reserved_tiles = P->T.total_tiles;
   if (rc != DS3_OK) { plan_free(P); return rc; }
   carve_gn(P->ws, P->T, P->B);
   P->arena = arena;
@@ -761,9 +789,11 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
       rc = plan_autotune(*P, s);
     } else {
       int ppt = (opts && opts->px_per_thread > 0) ? opts->px_per_thread : 16;
+      int unroll = (opts && opts->unroll > 0) ? opts->unroll : 2;
       if (ppt != 4 && ppt != 8 && ppt != 16 && ppt != 32) rc = fail(DS3_EINVAL, "px_per_thread must be 4, 8, 16 or 32");
+      if (unroll != 1 && unroll != 2 && unroll != 4) rc = fail(DS3_EINVAL, "unroll must be 1, 2 or 4");
+      P->unroll = unroll;
       if (rc == DS3_OK) rc = plan_build_items(*P, ppt, s);
-      P->grid = std::max(1, std::min(device_cu_count() * 2, P->n_items));
     }
   }
   if (rc == DS3_OK) {
@@ -821,16 +851,25 @@ int ds3_gn_plan_time_reduce(void* plan, int32_t reps, float* ms_out, void* strea
   return plan_time_reduce(*P, reps, ms_out, S(stream));
 }
 
-int ds3_gn_plan_info(void* plan, int64_t* info) {
+int ds3_gn_plan_info(void* plan, int64_t* info, int32_t n_info) {
   Plan* P = static_cast<Plan*>(plan);
-  if (!P || !info) return fail(DS3_EINVAL, "plan_info: bad arguments");
-  const int px_bytes = P->dt == DS3_F32 ? 16 : 8;
-  info[0] = P->n_items;
-  info[1] = P->ppt;
-  info[2] = P->px_scanned;
-  info[3] = P->px_valid;
-  info[4] = 4 * P->px_scanned + 2 * int64_t(px_bytes) * P->px_valid;
+  if (!P || !info || n_info < 0) return fail(DS3_EINVAL, "plan_info: bad arguments");
+  const int64_t px_bytes = P->dt == DS3_F32 ? 16 : 8;
+  const int64_t rec = int64_t(stream_record_bytes(P->dt));
+  const int64_t v[8] = {P->n_items, P->ppt, P->px_scanned, P->px_valid,
+                        4 * P->px_scanned + 2 * px_bytes * P->px_valid,
+                        rec * P->n_records + 4 * int64_t(P->n_items),
+                        4 * P->px_scanned + 2 * px_bytes * P->px_valid + rec * P->n_records + 4 * int64_t(P->n_items),
+                        P->unroll};
+  for (int k = 0; k < n_info && k < 8; ++k) info[k] = v[k];
   return DS3_OK;
+}
+
+int ds3_gn_plan_refresh(void* plan, void* stream) {
+  Plan* P = static_cast<Plan*>(plan);
+  if (!P) return fail(DS3_EINVAL, "plan_refresh: null plan");
+  return launch_gather_stream(P->dt, P->arena, P->B.edges, P->items, P->n_items, P->idx, P->T.tile_px, P->stream,
+                              P->seg_count, S(stream));
 }
 
 int ds3_tune_cache_reset(void) {
@@ -971,7 +1010,7 @@ int ds3_adjoint_plan_run(void* plan, const double* poses, float dcost, float* gr
   if (!A || !poses || !grad_xyz || !grad_conf || !grad_tau) return fail(DS3_EINVAL, "null pointer");
   hipStream_t s = S(stream);
   const Topology& T = A->T;
-  DS3_TRY(launch_gn_prep(poses, A->edges, T.n_edges, A->xf, A->Ad, nullptr, s));
+  DS3_TRY(launch_gn_prep(poses, A->edges, T.n_edges, A->xf, A->Ad, s));
   DS3_TRY(launch_adjoint_gather(A->dt, A->arena, A->edges, T.n_edges, A->max_npx_j, A->max_npx_kf, A->xf, A->Ad,
                                 A->idx, A->c, dcost, grad_xyz, grad_conf, A->part7, A->b_e, A->cost_e,
                                 A->count_e, T.n_kf, A->kf_off, A->kf_npx, A->node_ptr, A->node_adj, A->obase,

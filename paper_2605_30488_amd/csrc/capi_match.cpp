@@ -2,12 +2,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <vector>
 
 #include "internal.hpp"
 #include "match_internal.hpp"
+#include "umeyama.hpp"
 
 namespace ds3 {
 
@@ -388,6 +390,41 @@ int ds3_match_batch(const void* kf_arena, const ds3_image* kf, int32_t n_kf, con
 }
 
 // ---- gauge -------------------------------------------------------------------------------------------
+int ds3_umeyama(const double* x, const double* y, int64_t n, double* T_out) {
+  if (!x || !y || !T_out || n < 1) return fail(DS3_EINVAL, "umeyama: null pointer or no correspondences");
+  // two passes in float64, index order: centroids, then the centred cross-covariance and spread of y
+  double xb[3] = {0, 0, 0}, yb[3] = {0, 0, 0};
+  for (int64_t l = 0; l < n; ++l)
+    for (int k = 0; k < 3; ++k) {
+      xb[k] += x[3 * l + k];
+      yb[k] += y[3 * l + k];
+    }
+  for (int k = 0; k < 3; ++k) {
+    xb[k] /= double(n);
+    yb[k] /= double(n);
+  }
+  double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, sy2 = 0.0;
+  for (int64_t l = 0; l < n; ++l) {
+    double xc[3], yc[3];
+    for (int k = 0; k < 3; ++k) {
+      xc[k] = x[3 * l + k] - xb[k];
+      yc[k] = y[3 * l + k] - yb[k];
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) A[3 * r + c] += xc[r] * yc[c];
+    sy2 += yc[0] * yc[0] + yc[1] * yc[1] + yc[2] * yc[2];
+  }
+  for (int e = 0; e < 9; ++e) A[e] /= double(n);
+  sy2 /= double(n);
+  for (int e = 0; e < 9 + 1; ++e)
+    if (!std::isfinite(e < 9 ? A[e] : sy2)) return fail(DS3_EINVAL, "umeyama: non-finite correspondences");
+  Sim3 T;
+  if (!umeyama_solve(xb, yb, A, sy2, T))
+    return fail(DS3_EDEGENERATE, "umeyama: degenerate correspondences (rank of the cross-covariance < 2)");
+  sim3_store(T, T_out);
+  return DS3_OK;
+}
+
 size_t ds3_gauge_workspace_bytes(int32_t n_kf) {
   Carver c(nullptr);
   c.take<char>(gauge_ws_bytes());

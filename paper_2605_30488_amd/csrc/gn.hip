@@ -31,10 +31,8 @@ GnConst make_gn_const(const ds3_gn_params& p) {
 // Pose prep: T_ij = T_i^-1 T_j (float32 copy for the residual kernel) and Ad_{T_i^-1} (float64).
 // --------------------------------------------------------------------------------------------------
 __global__ void k_gn_prep(const double* __restrict__ poses, const EdgeDev* __restrict__ edges,
-                          int n_edges, EdgeXf* __restrict__ xf, double* __restrict__ Ad,
-                          unsigned* __restrict__ queue_counter) {
+                          int n_edges, EdgeXf* __restrict__ xf, double* __restrict__ Ad) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (queue_counter && e == 0) queue_counter[0] = 0u;
   if (e >= n_edges) return;
   const EdgeDev E = edges[e];
   Sim3 Ti = sim3_load(poses + 8 * E.i);
@@ -54,12 +52,11 @@ __global__ void k_gn_prep(const double* __restrict__ poses, const EdgeDev* __res
 }
 
 int launch_gn_prep(const double* poses, const EdgeDev* edges, int n_edges, EdgeXf* xf, double* Ad,
-                   unsigned* queue_counter, hipStream_t s) {
+                   hipStream_t s) {
   int threads = 128;
   int blocks = (n_edges + threads - 1) / threads;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_gn_prep, dim3(blocks), dim3(threads), 0, s, poses, edges, n_edges, xf, Ad,
-                     queue_counter);
+  hipLaunchKernelGGL(k_gn_prep, dim3(blocks), dim3(threads), 0, s, poses, edges, n_edges, xf, Ad);
   return check_hip(hipGetLastError(), "k_gn_prep");
 }
 
@@ -106,35 +103,21 @@ __device__ inline void acc_ray_row(Acc& a, const float* J, float W, float e) {
   }
 }
 
-// One match: x = T_ij X_j, e of eq. (1), whitening, Huber weights, J_x, accumulation.
-// Returns false (nothing accumulated) for holes, non-finite values or zero ranges.
-__device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const float* M,
-                                 const GnConst& k) {
-  const float x0 = fmaf(M[0], Xj.x, fmaf(M[1], Xj.y, fmaf(M[2], Xj.z, M[9])));
-  const float x1 = fmaf(M[3], Xj.x, fmaf(M[4], Xj.y, fmaf(M[5], Xj.z, M[10])));
-  const float x2 = fmaf(M[6], Xj.x, fmaf(M[7], Xj.y, fmaf(M[8], Xj.z, M[11])));
-  const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
-  const float di2 = fmaf(Xi.x, Xi.x, fmaf(Xi.y, Xi.y, Xi.z * Xi.z));
-  const float dj2 = fmaf(Xj.x, Xj.x, fmaf(Xj.y, Xj.y, Xj.z * Xj.z));
-  const float cc = Xi.w * Xj.w;
-  // holes (|X| <= 1e-9 or non-finite) on either side, zero range after the transform, bad confidence:
-  // a NaN or infinity anywhere makes the sum non-finite
-  const float mn = fminf(fminf(d2, di2), dj2);
-  const float sum = (d2 + di2) + (dj2 + cc);
-  if (!(mn > 1e-18f) || !(cc >= 0.0f) || !(sum < __builtin_huge_valf())) return false;
+// One match after its checks: x = T_ij X_j (d2 = |x|^2 > 0), X_i with di2 = |X_i|^2 > 0 and
+// sq = (C_i C_j)^(1/4): e of eq. (1), whitening, Huber weights, J_x, accumulation.
+__device__ inline void acc_core(Acc& a, float x0, float x1, float x2, float d2, float xi0, float xi1, float xi2,
+                                float di2, float sq, const GnConst& k) {
   const float rd = rsqrtf(d2);
   const float rdi = rsqrtf(di2);
   const float d = d2 * rd;
   const float di = di2 * rdi;
   const float p0 = x0 * rd, p1 = x1 * rd, p2 = x2 * rd;
-  const float e0 = p0 - Xi.x * rdi;
-  const float e1 = p1 - Xi.y * rdi;
-  const float e2 = p2 - Xi.z * rdi;
+  const float e0 = p0 - xi0 * rdi;
+  const float e1 = p1 - xi1 * rdi;
+  const float e2 = p2 - xi2 * rdi;
   const float e3 = d - di;
-  // q = sqrt(C_i C_j) and its square root by the hardware square root (1 ulp; cc is a product of
-  // confidences, never denormal here)
-  const float q = __builtin_amdgcn_sqrtf(cc);
-  const float sq = __builtin_amdgcn_sqrtf(q);
+  // Sigma_mn^-1/2 = sqrt(q) Sigma^-1/2 with q = sqrt(C_i C_j) = sq^2
+  const float q = sq * sq;
   const float sr = sq * k.inv_sr;
   const float r0 = sr * e0, r1 = sr * e1, r2 = sr * e2;
   const float r3 = sq * k.inv_sd * e3;
@@ -184,6 +167,39 @@ __device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const
     a.b[2] = fmaf(j2, e3, a.b[2]);
     a.b[6] = fmaf(j6, e3, a.b[6]);
   }
+}
+
+// x = T_ij X_j with T_ij = [M[0..8] | M[9..11]] (sR row-major, t)
+__device__ inline void transform(const float* M, float X0, float X1, float X2, float& x0, float& x1, float& x2) {
+  x0 = fmaf(M[0], X0, fmaf(M[1], X1, fmaf(M[2], X2, M[9])));
+  x1 = fmaf(M[3], X0, fmaf(M[4], X1, fmaf(M[5], X2, M[10])));
+  x2 = fmaf(M[6], X0, fmaf(M[7], X1, fmaf(M[8], X2, M[11])));
+}
+
+// The checks of one match that do not depend on the poses: no hole (|X| <= 1e-9, or a NaN or infinity)
+// on either side and a non-negative finite confidence product. sq = (C_i C_j)^(1/4) by the hardware
+// square root (1 ulp each; the product of confidences is never denormal here).
+__device__ inline bool match_static_ok(const float4 Xj, const float4 Xi, float& dj2, float& di2, float& sq) {
+  di2 = fmaf(Xi.x, Xi.x, fmaf(Xi.y, Xi.y, Xi.z * Xi.z));
+  dj2 = fmaf(Xj.x, Xj.x, fmaf(Xj.y, Xj.y, Xj.z * Xj.z));
+  const float cc = Xi.w * Xj.w;
+  // a NaN or infinity anywhere makes the sum non-finite
+  const float sum = (di2 + dj2) + cc;
+  if (!(fminf(di2, dj2) > 1e-18f) || !(cc >= 0.0f) || !(sum < __builtin_huge_valf())) return false;
+  sq = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(cc));
+  return true;
+}
+
+// One match from the two arena entries. Returns false (nothing accumulated) for holes, non-finite
+// values, zero ranges or a negative confidence product.
+__device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const float* M, const GnConst& k) {
+  float dj2, di2, sq;
+  if (!match_static_ok(Xj, Xi, dj2, di2, sq)) return false;
+  float x0, x1, x2;
+  transform(M, Xj.x, Xj.y, Xj.z, x0, x1, x2);
+  const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+  if (!(d2 > 1e-18f) || !(d2 < __builtin_huge_valf())) return false;
+  acc_core(a, x0, x1, x2, d2, Xi.x, Xi.y, Xi.z, di2, sq, k);
   return true;
 }
 
@@ -306,31 +322,240 @@ __global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_one(
                        partials + int64_t(E.tile0 + blockIdx.x) * kPartial, k, lds, queue);
 }
 
-// Batched form: persistent blocks pop (edge, tile) items, longest first, from one queue.
-template <int DT, int PPT>
-__global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_batched(
-    const void* __restrict__ arena, const EdgeDev* __restrict__ edges, const WorkItem* __restrict__ items,
-    int n_items, const EdgeXf* __restrict__ xf, const int32_t* __restrict__ idx_arena,
-    float* __restrict__ partials, unsigned* __restrict__ queue_counter, GnConst k) {
-  __shared__ float lds[kReduceThreads / kWave][37];
-  __shared__ int2 queue[kReduceThreads / kWave * kQueue];
-  __shared__ int s_item;
-#pragma unroll 1
-  for (;;) {
-    if (threadIdx.x == 0) s_item = int(atomicAdd(queue_counter, 1u));
-    __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it >= n_items) break;
-    const WorkItem W = items[it];
-    const EdgeDev E = edges[W.edge];
-    float M[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) M[q] = xf[W.edge].m[q];
-    reduce_tile<DT, PPT>(arena, E, W.tile, M, idx_arena, partials + int64_t(E.tile0 + W.tile) * kPartial,
-                         k, lds, queue);
-    __syncthreads();
+// --------------------------------------------------------------------------------------------------
+// Match stream of the batched form. The matches and the pointmaps stay fixed while the GN iterations move
+// the poses, so the plan gathers, once per set of matches, each valid match's two pointmap entries into
+// one contiguous record in the edge's segment of a stream; every iteration then reads the stream with
+// plain coalesced loads instead of scanning the match map and gathering the reference point.
+//   BF16 record (16 B): X_j (3 bf16), X_i (3 bf16), sq = (C_i C_j)^(1/4) (float32)
+//   F32 record (32 B):  X_j (3 float32), X_i (3 float32), sq (float32), one pad
+// The bf16 values are the arena's own bits, so the stream holds exactly the stored inputs. Segment s of
+// edge e covers pixels [s*seg_px, (s+1)*seg_px) of keyframe j; its records sit at the start of slot
+// range [(tile0 + s) * seg_px, ...) in increasing pixel order, and seg_count holds how many there are.
+// --------------------------------------------------------------------------------------------------
+template <int DT>
+struct Rec;
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <>
+struct Rec<DS3_BF16> {
+  struct raw_t {
+    u32x4 w;
+  };
+  __device__ static inline raw_t make(uint2 rj, uint2 ri, float sq) {
+    raw_t r;
+    r.w = u32x4{rj.x, (rj.y & 0xffffu) | (ri.x << 16), (ri.x >> 16) | (ri.y << 16), __float_as_uint(sq)};
+    return r;
   }
+  __device__ static inline raw_t load(const raw_t* p) {
+    raw_t r;
+    r.w = __builtin_nontemporal_load(&p->w);
+    return r;
+  }
+  __device__ static inline void unpack(const raw_t& r, float* xj, float* xi, float& sq) {
+    xj[0] = bf16_lo(r.w.x); xj[1] = bf16_hi(r.w.x); xj[2] = bf16_lo(r.w.y);
+    xi[0] = bf16_hi(r.w.y); xi[1] = bf16_lo(r.w.z); xi[2] = bf16_hi(r.w.z);
+    sq = __uint_as_float(r.w.w);
+  }
+};
+
+template <>
+struct Rec<DS3_F32> {
+  struct raw_t {
+    f32x4 a, b;
+  };
+  __device__ static inline raw_t make(float4 Xj, float4 Xi, float sq) {
+    raw_t r;
+    r.a = f32x4{Xj.x, Xj.y, Xj.z, Xi.x};
+    r.b = f32x4{Xi.y, Xi.z, sq, 0.0f};
+    return r;
+  }
+  __device__ static inline raw_t load(const raw_t* p) {
+    raw_t r;
+    r.a = __builtin_nontemporal_load(&p->a);
+    r.b = __builtin_nontemporal_load(&p->b);
+    return r;
+  }
+  __device__ static inline void unpack(const raw_t& r, float* xj, float* xi, float& sq) {
+    xj[0] = r.a.x; xj[1] = r.a.y; xj[2] = r.a.z;
+    xi[0] = r.a.w; xi[1] = r.b.x; xi[2] = r.b.y;
+    sq = r.b.z;
+  }
+};
+
+template <int DT>
+__device__ inline typename Rec<DT>::raw_t make_rec(typename Px<DT>::raw_t rj, typename Px<DT>::raw_t ri, float sq);
+template <>
+__device__ inline Rec<DS3_BF16>::raw_t make_rec<DS3_BF16>(uint2 rj, uint2 ri, float sq) {
+  return Rec<DS3_BF16>::make(rj, ri, sq);
+}
+template <>
+__device__ inline Rec<DS3_F32>::raw_t make_rec<DS3_F32>(float4 rj, float4 ri, float sq) {
+  return Rec<DS3_F32>::make(rj, ri, sq);
+}
+
+constexpr int kGatherUnroll = 4;  // 256-pixel chunks whose loads are issued together
+
+// One block per segment: scans the segment's matches in pixel order, keeps those that pass the
+// pose-independent checks and writes their records compacted (order-preserving: ballot ranks within a
+// wave, wave totals through LDS), then the count.
+template <int DT>
+__global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __restrict__ arena,
+                                                                  const EdgeDev* __restrict__ edges,
+                                                                  const WorkItem* __restrict__ items,
+                                                                  const int32_t* __restrict__ idx_arena,
+                                                                  int seg_px, void* __restrict__ stream,
+                                                                  int32_t* __restrict__ seg_count) {
+  using raw_t = typename Px<DT>::raw_t;
+  using rec_t = typename Rec<DT>::raw_t;
+  __shared__ int s_tot[kGatherUnroll][kReduceThreads / kWave];
+  const WorkItem W = items[blockIdx.x];
+  const EdgeDev E = edges[W.edge];
+  const int seg = E.tile0 + W.tile;
+  rec_t* __restrict__ out = static_cast<rec_t*>(stream) + int64_t(seg) * seg_px;
+  const int32_t* __restrict__ idx = idx_arena + E.idx_off;
+  const int64_t base = int64_t(W.tile) * seg_px;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  int running = 0;  // block-uniform
+  for (int c0 = 0; c0 < seg_px; c0 += kReduceThreads * kGatherUnroll) {
+    int32_t m[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int64_t n = base + c0 + u * kReduceThreads + threadIdx.x;
+      const bool in = (c0 + u * kReduceThreads + int(threadIdx.x) < seg_px) && n < E.npx_j;
+      m[u] = in ? __builtin_nontemporal_load(idx + n) : -1;
+      if (m[u] >= E.npx_i) m[u] = -1;
+    }
+    raw_t rj[kGatherUnroll], ri[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u)
+      if (m[u] >= 0) {
+        const int64_t n = base + c0 + u * kReduceThreads + threadIdx.x;
+        rj[u] = Px<DT>::load_raw(arena, E.off_j + n);
+        ri[u] = Px<DT>::load_raw(arena, E.off_i + m[u]);
+      }
+    bool ok[kGatherUnroll];
+    float sq[kGatherUnroll];
+    unsigned rank[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      ok[u] = false;
+      sq[u] = 0.0f;
+      if (m[u] >= 0) {
+        float dj2, di2;
+        ok[u] = match_static_ok(Px<DT>::unpack(rj[u]), Px<DT>::unpack(ri[u]), dj2, di2, sq[u]);
+      }
+      const uint64_t ballot = __ballot(ok[u]);
+      rank[u] = __builtin_amdgcn_mbcnt_hi(uint32_t(ballot >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(ballot), 0u));
+      if (lane == 0) s_tot[u][wave] = __popcll(ballot);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      int off = running;
+      for (int w = 0; w < kReduceThreads / kWave; ++w) {
+        const int t = s_tot[u][w];
+        if (w < wave) off += t;
+        running += t;
+      }
+      if (ok[u]) out[off + int(rank[u])] = make_rec<DT>(rj[u], ri[u], sq[u]);
+    }
+    __syncthreads();  // s_tot is rewritten by the next chunk
+  }
+  if (threadIdx.x == 0) seg_count[seg] = running;
+}
+
+// One block per segment: the segment's records with `unroll` loads in flight per thread, accumulated
+// as in the plain form, reduced over the block in a fixed order into the segment's partial.
+template <int DT, int U>
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __restrict__ stream,
+                                                                  const int32_t* __restrict__ seg_count,
+                                                                  const EdgeDev* __restrict__ edges,
+                                                                  const WorkItem* __restrict__ items,
+                                                                  const EdgeXf* __restrict__ xf, int seg_px,
+                                                                  float* __restrict__ partials, GnConst k) {
+  using rec_t = typename Rec<DT>::raw_t;
+  __shared__ float lds[kReduceThreads / kWave][37];
+  const WorkItem W = items[blockIdx.x];
+  const EdgeDev E = edges[W.edge];
+  const int seg = E.tile0 + W.tile;
+  float M[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) M[q] = xf[W.edge].m[q];
+  const rec_t* __restrict__ in = static_cast<const rec_t*>(stream) + int64_t(seg) * seg_px;
+  const int cnt = seg_count[seg];
+  Acc a;
+  acc_zero(a);
+#pragma unroll 1
+  for (int k0 = 0; k0 < cnt; k0 += kReduceThreads * U) {
+    rec_t r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = k0 + u * kReduceThreads + int(threadIdx.x);
+      if (q < cnt) r[u] = Rec<DT>::load(in + q);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = k0 + u * kReduceThreads + int(threadIdx.x);
+      if (q < cnt) {
+        float xj[3], xi[3], sq;
+        Rec<DT>::unpack(r[u], xj, xi, sq);
+        float x0, x1, x2;
+        transform(M, xj[0], xj[1], xj[2], x0, x1, x2);
+        const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+        if (d2 > 1e-18f && d2 < __builtin_huge_valf()) {
+          const float di2 = fmaf(xi[0], xi[0], fmaf(xi[1], xi[1], xi[2] * xi[2]));
+          acc_core(a, x0, x1, x2, d2, xi[0], xi[1], xi[2], di2, sq, k);
+        }
+      }
+    }
+  }
+  acc_block_store(a, partials + int64_t(seg) * kPartial, lds);
+}
+
+size_t stream_record_bytes(ds3_dtype dt) {
+  return dt == DS3_F32 ? sizeof(Rec<DS3_F32>::raw_t) : sizeof(Rec<DS3_BF16>::raw_t);
+}
+
+int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, const WorkItem* items,
+                         int n_items, const int32_t* idx_arena, int seg_px, void* stream, int32_t* seg_count,
+                         hipStream_t s) {
+  if (n_items <= 0) return DS3_OK;
+  if (dt == DS3_F32)
+    hipLaunchKernelGGL(k_gather_stream<DS3_F32>, dim3(n_items), dim3(kReduceThreads), 0, s, arena, edges, items,
+                       idx_arena, seg_px, stream, seg_count);
+  else
+    hipLaunchKernelGGL(k_gather_stream<DS3_BF16>, dim3(n_items), dim3(kReduceThreads), 0, s, arena, edges, items,
+                       idx_arena, seg_px, stream, seg_count);
+  return check_hip(hipGetLastError(), "k_gather_stream");
+}
+
+template <int DT>
+static int launch_reduce_stream_dt(int unroll, const void* stream, const int32_t* seg_count, const EdgeDev* edges,
+                                   const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
+                                   float* partials, GnConst c, hipStream_t s) {
+  dim3 g(n_items), b(kReduceThreads);
+  switch (unroll) {
+    case 1: hipLaunchKernelGGL((k_reduce_stream<DT, 1>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c); break;
+    case 2: hipLaunchKernelGGL((k_reduce_stream<DT, 2>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c); break;
+    case 4: hipLaunchKernelGGL((k_reduce_stream<DT, 4>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c); break;
+    default: return fail(DS3_EINVAL, "unsupported stream unroll");
+  }
+  return check_hip(hipGetLastError(), "k_reduce_stream");
+}
+
+int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
+                         const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
+                         float* partials, GnConst c, hipStream_t s) {
+  if (n_items <= 0) return DS3_OK;
+  if (dt == DS3_F32)
+    return launch_reduce_stream_dt<DS3_F32>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px, partials,
+                                            c, s);
+  return launch_reduce_stream_dt<DS3_BF16>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px, partials,
+                                           c, s);
 }
 
 template <int DT>
@@ -353,33 +578,6 @@ int launch_edge_reduce_one(ds3_dtype dt, int ppt, const void* arena, const EdgeD
   if (e.n_tiles <= 0) return DS3_OK;
   if (dt == DS3_F32) return launch_one_dt<DS3_F32>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, s);
   return launch_one_dt<DS3_BF16>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, s);
-}
-
-template <int DT>
-static int launch_batched_dt(int ppt, int grid, const void* arena, const EdgeDev* edges,
-                             const WorkItem* items, int n_items, const EdgeXf* xf, const int32_t* idx,
-                             float* partials, unsigned* qc, GnConst c, hipStream_t s) {
-  dim3 g(grid), b(kReduceThreads);
-  switch (ppt) {
-    case 4: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 4>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
-    case 8: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 8>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
-    case 16: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 16>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
-    case 32: hipLaunchKernelGGL((k_edge_reduce_batched<DT, 32>), g, b, 0, s, arena, edges, items, n_items, xf, idx, partials, qc, c); break;
-    default: return fail(DS3_EINVAL, "unsupported pixels-per-thread");
-  }
-  return check_hip(hipGetLastError(), "k_edge_reduce_batched");
-}
-
-int launch_edge_reduce_batched(ds3_dtype dt, int ppt, int grid, const void* arena, const EdgeDev* edges,
-                               const WorkItem* items, int n_items, const EdgeXf* xf,
-                               const int32_t* idx_arena, float* partials, unsigned* queue_counter,
-                               GnConst c, hipStream_t s) {
-  if (n_items <= 0) return DS3_OK;
-  if (dt == DS3_F32)
-    return launch_batched_dt<DS3_F32>(ppt, grid, arena, edges, items, n_items, xf, idx_arena, partials,
-                                      queue_counter, c, s);
-  return launch_batched_dt<DS3_BF16>(ppt, grid, arena, edges, items, n_items, xf, idx_arena, partials,
-                                     queue_counter, c, s);
 }
 
 // --------------------------------------------------------------------------------------------------

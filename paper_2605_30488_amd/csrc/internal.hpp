@@ -75,7 +75,7 @@ struct GnConst {
 constexpr int kPartial = 40;  // floats per tile partial: H upper 28, b 7, cost, count, 3 pad
 constexpr int kReduceThreads = 256;
 
-// One (edge, tile) work item of the batched residual kernel.
+// One (edge, tile) work item of the batched form: a segment of the match stream.
 struct WorkItem {
   int32_t edge;
   int32_t tile;
@@ -85,14 +85,18 @@ GnConst make_gn_const(const ds3_gn_params& p);
 
 // gn.hip
 int launch_gn_prep(const double* poses, const EdgeDev* edges, int n_edges, EdgeXf* xf, double* Ad,
-                   unsigned* queue_counter, hipStream_t s);
+                   hipStream_t s);
 int launch_edge_reduce_one(ds3_dtype dt, int ppt, const void* arena, const EdgeDev& e, int edge_id,
                            const EdgeXf* xf, const int32_t* idx_arena, float* partials, GnConst c,
                            hipStream_t s);
-int launch_edge_reduce_batched(ds3_dtype dt, int ppt, int grid, const void* arena, const EdgeDev* edges,
-                               const WorkItem* items, int n_items, const EdgeXf* xf,
-                               const int32_t* idx_arena, float* partials, unsigned* queue_counter,
-                               GnConst c, hipStream_t s);
+// match stream of the batched form (gn.hip)
+size_t stream_record_bytes(ds3_dtype dt);
+int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, const WorkItem* items,
+                         int n_items, const int32_t* idx_arena, int seg_px, void* stream, int32_t* seg_count,
+                         hipStream_t s);
+int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
+                         const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
+                         float* partials, GnConst c, hipStream_t s);
 int launch_edge_finalize(const EdgeDev* edges, int n_edges, const float* partials, const double* Ad,
                          double* A_out, double* b_out, double* cost_e, int64_t* count_e, hipStream_t s);
 int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,

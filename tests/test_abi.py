@@ -124,3 +124,39 @@ def test_library_sources_start_no_child_process():
         text = open(os.path.join(csrc, name)).read()
         code = re.sub(r"//[^\n]*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
         assert not pat.search(code), name
+
+
+def test_umeyama_host_entry_point(lib):
+    """ds3_umeyama (host, FP64, eq. 4) against the oracle's closed form: exact recovery of a known
+    similarity, the optimum under noise, the reflection case of planar points (det(UV^T) = -1 must not
+    give a reflection), and rejection of collinear points and bad arguments. No GPU involved."""
+    import numpy as np
+    import oracle as O
+    from paper_2605_30488_amd import DS3Error, api
+    rng = np.random.default_rng(12)
+    y = rng.normal(size=(200, 3)) * 3.0
+    T = O.sim3_exp(np.concatenate([rng.normal(size=3), rng.normal(size=3) * 0.7, [0.4]]))[0]
+    x = O.transform_points(T, y)
+    got = api.umeyama(x, y)
+    assert np.allclose(O.pose_to_mat(got), O.pose_to_mat(T), atol=1e-12)
+    xn = x + rng.normal(size=x.shape) * 0.05
+    assert np.allclose(O.pose_to_mat(api.umeyama(xn, y)), O.pose_to_mat(O.umeyama(xn, y)), atol=1e-12)
+    # planar y and a mirrored x: the proper rotation with S = diag(1, 1, -1)
+    yp = y.copy()
+    yp[:, 2] = 0.0
+    xp = yp * np.array([1.0, 1.0, 1.0]) @ O.pose_to_mat(T)[:3, :3].T
+    xp[:, 2] *= -1.0
+    Tp = api.umeyama(xp, yp)
+    R = O.pose_to_mat(Tp)[:3, :3] / Tp[7]
+    assert abs(np.linalg.det(R) - 1.0) < 1e-12
+    assert np.allclose(O.pose_to_mat(Tp), O.pose_to_mat(O.umeyama(xp, yp)), atol=1e-10)
+    # collinear: degenerate, reported with its own code
+    yl = np.outer(np.linspace(-1, 1, 50), [1.0, 2.0, 3.0])
+    with pytest.raises(DS3Error) as e:
+        api.umeyama(yl, yl)
+    assert e.value.code == -5
+    dp = ctypes.POINTER(ctypes.c_double)
+    buf = np.zeros(8)
+    assert lib.ds3_umeyama(None, None, 3, buf.ctypes.data_as(dp)) == -1
+    one = np.zeros(3)
+    assert lib.ds3_umeyama(one.ctypes.data_as(dp), one.ctypes.data_as(dp), 0, buf.ctypes.data_as(dp)) == -1

@@ -44,15 +44,15 @@ def _bf16_inputs(g):
     return xyz, conf
 
 
-@pytest.mark.parametrize("ppt", [4, 16, 32])
-def test_plan_equals_plain_form(dev, single, ppt):
-    """Batched plan (graph replay) and plain per-edge steps give the same poses (same FP32 math, tile
-    sums in a different order) for every tile shape."""
+@pytest.mark.parametrize("ppt,unroll", [(4, 1), (16, 2), (32, 4), (8, 4)])
+def test_plan_equals_plain_form(dev, single, ppt, unroll):
+    """Batched plan (match stream, graph replay) and plain per-edge steps give the same poses (same FP32
+    math per match, sums in a different order) for every segment size and loads in flight."""
     g, idx = single
     G = _graph(g, idx, "f32", dev)
     P1 = _t(g.poses_init, dev)
     P2 = _t(g.poses_init, dev)
-    plan = ds3.GNPlan(G, P2, px_per_thread=ppt)
+    plan = ds3.GNPlan(G, P2, px_per_thread=ppt, unroll=unroll)
     costs, st = plan.run(3)
     c_plain = []
     for _ in range(3):
@@ -112,6 +112,45 @@ def test_plan_bf16_matches_oracle_on_rounded_inputs(dev, single):
           f"oracle quantisation error {e_quant:.2e}")
     assert e_arith <= 1e-5
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_plan_refresh_follows_new_matches(dev, single, dtype):
+    """The plan reads its match stream, not the idx arena: after the arena is rewritten with other
+    matches (30% dropped, 10% moved to a neighbouring pixel) and refresh() runs, two iterations give
+    bit for bit the poses and costs of a plan created on the new matches, and the plain form's within
+    FP32 summation-order error. Without the refresh the old matches keep being used."""
+    g, idx = single
+    rng = np.random.default_rng(4)
+    new = []
+    for v, (_, j) in zip(idx, g.edges):
+        v = np.asarray(v, np.int32).copy()
+        ok = np.flatnonzero(v >= 0)
+        v[rng.choice(ok, size=int(0.3 * ok.size), replace=False)] = -1
+        ok = np.flatnonzero(v >= 0)
+        mv = rng.choice(ok, size=int(0.1 * ok.size), replace=False)
+        v[mv] = np.minimum(v[mv] + 1, g.shape(0)[0] * g.shape(0)[1] - 1)
+        new.append(v)
+    a = ds3.build_arena(g.xyz, g.conf, dtype, dev)
+    flat = _t(np.concatenate(idx), dev, torch.int32)
+    G = ds3.Graph(a, g.edges, flat, anchors=(0,))
+    Pa, Pb, Pc, Pd = (_t(g.poses_init, dev) for _ in range(4))
+    pa = ds3.GNPlan(G, Pa)
+    pd = ds3.GNPlan(G, Pd)
+    flat.copy_(_t(np.concatenate(new), dev, torch.int32))
+    pa.refresh()
+    ca, _ = pa.run(2)
+    pb = ds3.GNPlan(G, Pb)
+    cb, _ = pb.run(2)
+    cd, _ = pd.run(2)  # not refreshed: still the old matches
+    cc = [ds3.sim3_gn_step(G, Pc)[0].item() for _ in range(2)]
+    torch.cuda.synchronize()
+    assert torch.equal(Pa, Pb) and torch.equal(ca, cb)
+    assert O.pose_error(Pa.cpu().numpy(), Pc.cpu().numpy()).max() < 2e-6
+    assert np.allclose(ca.cpu().numpy(), cc, rtol=1e-5)
+    assert not np.allclose(cd.cpu().numpy(), cc, rtol=1e-3)
+    for p in (pa, pb, pd):
+        p.close()
 
 
 def test_graph_replays_match_direct_launches(dev, single):

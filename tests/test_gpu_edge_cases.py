@@ -75,6 +75,15 @@ def test_edges_with_no_valid_match(dev):
     Q = P.clone()
     cost, st = ds3.sim3_gn_step(G, Q)
     assert cost.item() == 0.0 and int(st.item()) == 0 and torch.equal(Q, P)
+    # the plan's match stream is empty: every segment holds zero records
+    Q = P.clone()
+    gp = ds3.GNPlan(G, Q)
+    assert gp.info()["bytes_stream_per_iter"] == 4 * gp.info()["items"]
+    costs, sts = gp.run(2)
+    torch.cuda.synchronize()
+    assert costs.cpu().numpy().tolist() == [0.0, 0.0] and sts.cpu().numpy().tolist() == [0, 0]
+    assert torch.equal(Q, P)
+    gp.close()
 
 
 def test_non_finite_pixels_are_holes(dev):
@@ -104,6 +113,14 @@ def test_non_finite_pixels_are_holes(dev):
     ref, _, s, _ = O.gn_step(og, poses)
     assert s == 0
     assert O.pose_error(Q.cpu().numpy(), ref).max() <= 1e-5
+    # the batched plan drops the same matches while gathering its match stream
+    Q2 = P.clone()
+    gp = ds3.GNPlan(G, Q2, px_per_thread=4)
+    costs, _ = gp.run(1)
+    torch.cuda.synchronize()
+    assert abs(costs[0].item() - E) <= 1e-5 * E
+    assert O.pose_error(Q2.cpu().numpy(), ref).max() <= 1e-5
+    gp.close()
 
 
 def test_chol_largest_and_first_rejected_size(dev):
