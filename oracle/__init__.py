@@ -489,6 +489,75 @@ def gauge_sync(poses, agent_of_kf, edges, admitted, matches, xyz_list, nc_min=64
 
 
 # ---------------------------------------------------------------------------------------------
+# Ray-range tracking (Sec. III-A): one free pose T_kf under the residual of eq. (1) and LM damping
+# ---------------------------------------------------------------------------------------------
+@dataclass
+class TrackParams:
+    """LM schedule of the tracker. The paper states only that the tracker uses LM damping (text after
+    eq. 7, the lambda diag(H) term); the schedule is a reading: lambda0 = 1e-4, divided by 10 after an
+    accepted trial (floor lambda_min) and multiplied by 10 after a rejected one, at most max_trials
+    trial steps, stop after an accepted step whose largest tangent component is below step_tol."""
+    lambda0: float = 1e-4
+    lambda_min: float = 1e-9
+    lambda_up: float = 10.0
+    lambda_down: float = 0.1
+    max_trials: int = 20
+    step_tol: float = 1e-7
+
+
+@dataclass
+class TrackResult:
+    pose: np.ndarray       # T_kf after the search (8)
+    cost: float            # E_track at that pose
+    trials: int            # trial steps taken
+    costs: list = field(default_factory=list)    # E_track after each trial step (the kept pose's)
+    lambdas: list = field(default_factory=list)  # damping used by each trial step
+    accepted: list = field(default_factory=list)
+
+
+def track(xyz_kf, conf_kf, xyz_fr, conf_fr, idx, T0, params: GNParams | None = None,
+          tp: TrackParams | None = None) -> TrackResult:
+    """E_track(T_kf) = sum over the matches (m, n) of sum_c rho([Sigma_mn^-1/2 e_mn(T_kf)]_c) with e of
+    eq. (1) between the keyframe's canonical point X_k[m] and the frame's point X_f[n] (idx[n] = m, -1 =
+    no match), minimised over T_kf (frame -> keyframe) by LM: at the kept pose T with normal equations
+    H, g (the IRLS linearisation of eqs. 5-6 restricted to one edge with the keyframe fixed at the
+    identity), a trial step solves (H + lambda diag H + eps_r I) tau = -g (eq. 7 with the epsilon ladder)
+    and T' = Exp(tau) T (left update, Sec. III-D); the trial is accepted iff E_track(T') < E_track(T)."""
+    P = params or GNParams.default()
+    tp = tp or TrackParams()
+    ident = np.array([0, 0, 0, 0, 0, 0, 1, 1.0])
+    g = Graph([xyz_kf, xyz_fr], [conf_kf, conf_fr], [(0, 1)], [np.asarray(idx).reshape(-1)], anchors=(0,))
+
+    def linearise(T):
+        H, gv, E, *_ = gn_assemble(g, np.stack([ident, T]), P)
+        return H[7:, 7:].copy(), gv[7:].copy(), E
+
+    T = _f64(T0).reshape(8).copy()
+    H, b, E = linearise(T)
+    lam = tp.lambda0
+    res = TrackResult(T, E, 0)
+    for _ in range(tp.max_trials):
+        res.trials += 1
+        res.lambdas.append(lam)
+        tau, _ = chol_ladder(H, b, lam, P.eps0, P.eps_mult, P.max_attempts)
+        T1 = sim3_update(T[None], tau[None])[0]
+        H1, b1, E1 = linearise(T1)
+        if E1 < E:
+            T, H, b, E = T1, H1, b1, E1
+            lam = max(lam * tp.lambda_down, tp.lambda_min)
+            res.accepted.append(True)
+            res.costs.append(E)
+            if np.abs(tau).max() < tp.step_tol:
+                break
+        else:
+            lam = lam * tp.lambda_up
+            res.accepted.append(False)
+            res.costs.append(E)
+    res.pose, res.cost = T, E
+    return res
+
+
+# ---------------------------------------------------------------------------------------------
 # Precision helpers and metrics
 # ---------------------------------------------------------------------------------------------
 def bf16_round(a) -> np.ndarray:
