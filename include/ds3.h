@@ -300,6 +300,54 @@ int ds3_gn_plan_destroy(void* plan);
 int ds3_tune_cache_reset(void);
 
 /* ---------------------------------------------------------------------------------------------------
+ * Ray-range tracking (Sec. III-A: E_track with LM damping, eq. 7 with lambda > 0)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* LM schedule of the tracker (the paper states only that the tracker uses LM damping; these values are
+ * readings): lambda0 = 1e-4, lambda <- max(lambda * lambda_down, lambda_min) after an accepted trial
+ * (lambda_down = 0.1, lambda_min = 1e-9), lambda <- lambda * lambda_up after a rejected one
+ * (lambda_up = 10), at most max_trials = 20 trial steps, stop after an accepted step whose largest
+ * tangent component is below step_tol = 1e-7. */
+typedef struct {
+  double lambda0, lambda_min, lambda_up, lambda_down;
+  int32_t max_trials;
+  double step_tol;
+} ds3_track_params;
+void ds3_default_track_params(ds3_track_params* p);
+
+/* One tracking problem: a frame's pointmap (image `frame` of the arena) against a keyframe's canonical
+ * pointmap (image `keyframe`); its matches are H_f*W_f int32 entries at idx_offset of an idx arena:
+ * entry n is the keyframe pixel m matched to frame pixel n, or -1. */
+typedef struct {
+  ds3_image keyframe;
+  ds3_image frame;
+  int64_t idx_offset;
+} ds3_track_problem;
+
+/* Workspace bytes of ds3_track for these problems (host table) at this dtype. */
+size_t ds3_track_workspace_bytes(int32_t n, const ds3_track_problem* probs, ds3_dtype dtype);
+
+/* For each of n independent problems (host table), the pose T_kf (device, n x 8 float64, in: start,
+ * out: result) mapping the frame's camera into the keyframe's that minimises
+ *   E_track(T_kf) = sum_{(m,n)} sum_c rho([Sigma_mn^-1/2 e_mn(T_kf)]_c),
+ * e of eq. (1) with X^j_j = the frame's point, X-hat^i_i = the keyframe's point, Sigma_mn = Sigma / q_mn,
+ * q_mn = sqrt(C_k[m] C_f[n]), component-wise Huber rho and IRLS weights (gn: sigma_ray, sigma_dist,
+ * huber_k, and the epsilon ladder eps0, eps_mult, max_attempts of eq. 7; gn->lambda is not used). LM:
+ * at the kept pose T with IRLS normal equations H, g, a trial solves (H + lambda diag H + eps_r I) tau =
+ * -g and T' = Exp(tau) T; it is accepted iff E_track(T') < E_track(T) (schedule in tp). Matches with a
+ * hole, a non-finite value or a negative confidence product are skipped.
+ * Outputs (device): cost_out (n float64) = E_track at the returned pose, trials_out (n int32) = trial
+ * steps taken, status_out (n int32, may be NULL) = ladder attempt of the last solve (-1: zero step).
+ * One call gathers the matches once, then runs 1 + max_trials rounds of two launches (reduction at the
+ * trial poses, LM step) with no host synchronisation; stopped problems are skipped. reduce_timer (may be
+ * NULL) is recorded around the first reduction launch (every problem active). Workspace from
+ * ds3_track_workspace_bytes. */
+int ds3_track(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs, int32_t n,
+              const int32_t* idx_arena, const ds3_gn_params* gn, const ds3_track_params* tp, double* T,
+              double* cost_out, int32_t* trials_out, int32_t* status_out, ds3_timer* reduce_timer,
+              void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------------------
  * Cost and its adjoint (gradient of eq. 5 with the matches held fixed)
  * ------------------------------------------------------------------------------------------------- */
 

@@ -32,6 +32,15 @@ class GNParams(C.Structure):
                 ("max_attempts", C.c_int32)]
 
 
+class TrackParams(C.Structure):
+    _fields_ = [("lambda0", C.c_double), ("lambda_min", C.c_double), ("lambda_up", C.c_double),
+                ("lambda_down", C.c_double), ("max_trials", C.c_int32), ("step_tol", C.c_double)]
+
+
+class TrackProblem(C.Structure):
+    _fields_ = [("keyframe", Image), ("frame", Image), ("idx_offset", C.c_int64)]
+
+
 class FusePair(C.Structure):
     _fields_ = [("canon_off", C.c_int64), ("pred_off", C.c_int64), ("n_px", C.c_int64)]
 
@@ -98,6 +107,10 @@ _SIGS = {
                                           C.POINTER(vp), vp]),
     "ds3_adjoint_plan_run": (C.c_int, [vp, vp, f32, vp, vp, vp, vp, vp, vp]),
     "ds3_adjoint_plan_destroy": (C.c_int, [vp]),
+    "ds3_default_track_params": (None, [C.POINTER(TrackParams)]),
+    "ds3_track_workspace_bytes": (sz, [i32, C.POINTER(TrackProblem), C.c_int]),
+    "ds3_track": (C.c_int, [vp, C.c_int, C.POINTER(TrackProblem), i32, vp, C.POINTER(GNParams),
+                            C.POINTER(TrackParams), vp, vp, vp, vp, vp, vp, sz, vp]),
     "ds3_fuse_workspace_bytes": (sz, [i32]),
     "ds3_fuse": (C.c_int, [vp, i64, vp, i64, C.POINTER(FusePair), i32, vp, i32, vp, sz, vp]),
 }

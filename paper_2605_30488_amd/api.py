@@ -527,6 +527,64 @@ class DenseSim3Cost(torch.autograd.Function):
 
 
 # ------------------------------------------------------------------------------------------------
+# Ray-range tracking (Sec. III-A)
+# ------------------------------------------------------------------------------------------------
+def default_track_params() -> L.TrackParams:
+    p = L.TrackParams()
+    L.load().ds3_default_track_params(C.byref(p))
+    return p
+
+
+class Tracker:
+    """ds3_track over a fixed problem table: problems are (keyframe, frame) image indices of `arena` with
+    the frame-to-keyframe matches of problem p at idx_offsets[p] of an idx arena (H_f * W_f int32 each;
+    consecutive by default). The workspace is allocated once here."""
+
+    def __init__(self, arena: Arena, problems, idx_offsets=None, params=None, track_params=None):
+        self.arena = arena
+        self.problems = [(int(k), int(f)) for k, f in problems]
+        if idx_offsets is None:
+            idx_offsets, off = [], 0
+            for _, f in self.problems:
+                idx_offsets.append(off)
+                H, W, _ = arena.images[f]
+                off += H * W
+        self.idx_offsets = [int(o) for o in idx_offsets]
+        self.n = len(self.problems)
+        self.table = (L.TrackProblem * max(self.n, 1))()
+        for p, ((k, f), off) in enumerate(zip(self.problems, self.idx_offsets)):
+            self.table[p] = L.TrackProblem(arena.image(k), arena.image(f), off)
+        self.params = params or default_gn_params()
+        self.track_params = track_params or default_track_params()
+        self.ws = _ws(L.load().ds3_track_workspace_bytes(self.n, self.table, _dt(arena.dtype)), arena.data.device)
+
+    def run(self, idx: torch.Tensor, T: torch.Tensor, timer=None):
+        """T: (n, 8) float64 starting poses, updated in place. Returns (E_track (n,) float64, trial steps
+        (n,) int32, ladder status (n,) int32) on the device."""
+        _need_cuda(idx, T)
+        if idx.dtype != torch.int32 or T.dtype != torch.float64 or tuple(T.shape) != (self.n, 8):
+            raise ValueError("track takes int32 matches and (n, 8) float64 poses")
+        need = max((o + self.arena.images[f][0] * self.arena.images[f][1]
+                    for o, (_, f) in zip(self.idx_offsets, self.problems)), default=0)
+        if idx.numel() < need:
+            raise ValueError("the idx arena is shorter than the problem table needs")
+        dev = T.device
+        cost = torch.empty(max(self.n, 1), dtype=torch.float64, device=dev)
+        trials = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
+        status = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
+        call("ds3_track", _ptr(self.arena.data), _dt(self.arena.dtype), self.table, self.n, _ptr(idx),
+             C.byref(self.params), C.byref(self.track_params), _ptr(T), _ptr(cost), _ptr(trials), _ptr(status),
+             timer.handle if timer is not None else None, _ptr(self.ws), self.ws.numel(), _stream())
+        return cost[:self.n], trials[:self.n], status[:self.n]
+
+
+def track(arena: Arena, problems, idx: torch.Tensor, T: torch.Tensor, idx_offsets=None, params=None,
+          track_params=None):
+    """One ds3_track call (see Tracker.run)."""
+    return Tracker(arena, problems, idx_offsets, params, track_params).run(idx, T)
+
+
+# ------------------------------------------------------------------------------------------------
 # Canonical pointmap fusion (eq. 2)
 # ------------------------------------------------------------------------------------------------
 class FusePlan:

@@ -499,7 +499,7 @@ static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
   DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, s));
   if (timed) DS3_TRY(timer_record(P.timer, true, s));
   DS3_TRY(launch_reduce_stream(P.dt, P.unroll, P.stream, P.seg_count, P.B.edges, P.items, P.n_items, P.B.xf,
-                               P.T.tile_px, P.B.partials, P.c, s));
+                               P.T.tile_px, P.B.partials, P.c, nullptr, s));
   if (timed) DS3_TRY(timer_record(P.timer, false, s));
   DS3_TRY(launch_edge_finalize(P.B.edges, P.T.n_edges, P.B.partials, P.B.Ad, P.B.A_e, P.B.b_e, P.B.cost_e,
                                P.B.count_e, s));
@@ -576,7 +576,7 @@ static int plan_time_reduce(Plan& P, int reps, float* ms, hipStream_t s) {
   int rc = check_hip(hipEventRecord(a, s), "hipEventRecord");
   for (int r = 0; r < reps && rc == DS3_OK; ++r)
     rc = launch_reduce_stream(P.dt, P.unroll, P.stream, P.seg_count, P.B.edges, P.items, P.n_items, P.B.xf,
-                              P.T.tile_px, P.B.partials, P.c, s);
+                              P.T.tile_px, P.B.partials, P.c, nullptr, s);
   if (rc == DS3_OK) rc = check_hip(hipEventRecord(b, s), "hipEventRecord");
   if (rc == DS3_OK) rc = check_hip(hipEventSynchronize(b), "hipEventSynchronize");
   float t = 0.f;

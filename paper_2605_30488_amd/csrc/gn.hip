@@ -469,17 +469,20 @@ __global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __
 }
 
 // One block per segment: the segment's records with `unroll` loads in flight per thread, accumulated
-// as in the plain form, reduced over the block in a fixed order into the segment's partial.
+// as in the plain form, reduced over the block in a fixed order into the segment's partial. Segments of
+// edges flagged in skip (may be NULL) are left alone.
 template <int DT, int U>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __restrict__ stream,
                                                                   const int32_t* __restrict__ seg_count,
                                                                   const EdgeDev* __restrict__ edges,
                                                                   const WorkItem* __restrict__ items,
                                                                   const EdgeXf* __restrict__ xf, int seg_px,
-                                                                  float* __restrict__ partials, GnConst k) {
+                                                                  float* __restrict__ partials, GnConst k,
+                                                                  const int32_t* __restrict__ skip) {
   using rec_t = typename Rec<DT>::raw_t;
   __shared__ float lds[kReduceThreads / kWave][37];
   const WorkItem W = items[blockIdx.x];
+  if (skip && skip[W.edge]) return;  // edges whose caller no longer needs their sums (block-uniform)
   const EdgeDev E = edges[W.edge];
   const int seg = E.tile0 + W.tile;
   float M[12];
@@ -536,12 +539,12 @@ int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, 
 template <int DT>
 static int launch_reduce_stream_dt(int unroll, const void* stream, const int32_t* seg_count, const EdgeDev* edges,
                                    const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
-                                   float* partials, GnConst c, hipStream_t s) {
+                                   float* partials, GnConst c, const int32_t* skip, hipStream_t s) {
   dim3 g(n_items), b(kReduceThreads);
   switch (unroll) {
-    case 1: hipLaunchKernelGGL((k_reduce_stream<DT, 1>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c); break;
-    case 2: hipLaunchKernelGGL((k_reduce_stream<DT, 2>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c); break;
-    case 4: hipLaunchKernelGGL((k_reduce_stream<DT, 4>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c); break;
+    case 1: hipLaunchKernelGGL((k_reduce_stream<DT, 1>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip); break;
+    case 2: hipLaunchKernelGGL((k_reduce_stream<DT, 2>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip); break;
+    case 4: hipLaunchKernelGGL((k_reduce_stream<DT, 4>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip); break;
     default: return fail(DS3_EINVAL, "unsupported stream unroll");
   }
   return check_hip(hipGetLastError(), "k_reduce_stream");
@@ -549,13 +552,13 @@ static int launch_reduce_stream_dt(int unroll, const void* stream, const int32_t
 
 int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
                          const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
-                         float* partials, GnConst c, hipStream_t s) {
+                         float* partials, GnConst c, const int32_t* skip, hipStream_t s) {
   if (n_items <= 0) return DS3_OK;
   if (dt == DS3_F32)
     return launch_reduce_stream_dt<DS3_F32>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px, partials,
-                                            c, s);
+                                            c, skip, s);
   return launch_reduce_stream_dt<DS3_BF16>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px, partials,
-                                           c, s);
+                                           c, skip, s);
 }
 
 template <int DT>

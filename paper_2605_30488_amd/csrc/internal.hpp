@@ -83,6 +83,12 @@ struct WorkItem {
 
 GnConst make_gn_const(const ds3_gn_params& p);
 
+// Constants of the tracker's LM loop (track.hip).
+struct TrackConst {
+  double lambda0, lambda_min, lambda_up, lambda_down, step_tol, eps0, eps_mult;
+  int32_t max_trials, attempts;
+};
+
 // gn.hip
 int launch_gn_prep(const double* poses, const EdgeDev* edges, int n_edges, EdgeXf* xf, double* Ad,
                    hipStream_t s);
@@ -96,7 +102,7 @@ int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, 
                          hipStream_t s);
 int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
                          const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
-                         float* partials, GnConst c, hipStream_t s);
+                         float* partials, GnConst c, const int32_t* skip, hipStream_t s);
 int launch_edge_finalize(const EdgeDev* edges, int n_edges, const float* partials, const double* Ad,
                          double* A_out, double* b_out, double* cost_e, int64_t* count_e, hipStream_t s);
 int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,
@@ -113,6 +119,13 @@ int launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s);
 int launch_copy_f64(const double* src, double* dst, size_t n, hipStream_t s);
 int launch_count_valid(const EdgeDev* edges, int n_edges, const int32_t* idx_arena, int tile_px,
                        int max_tiles, int32_t* counts, hipStream_t s);
+
+// track.hip
+size_t track_state_bytes();
+int launch_track_init(const double* T_io, int n, EdgeXf* xf, int32_t* done, hipStream_t s);
+int launch_track_step(const EdgeDev* edges, int n, const float* partials, void* states, int32_t* done, EdgeXf* xf,
+                      double* T_io, double* cost_out, int32_t* trials_out, int32_t* status_out, TrackConst tc,
+                      int phase, hipStream_t s);
 
 // chol.hip
 size_t chol_workspace_bytes(int n);
