@@ -334,8 +334,10 @@ size_t ds3_track_workspace_bytes(int32_t n, const ds3_track_problem* probs, ds3_
  * q_mn = sqrt(C_k[m] C_f[n]), component-wise Huber rho and IRLS weights (gn: sigma_ray, sigma_dist,
  * huber_k, and the epsilon ladder eps0, eps_mult, max_attempts of eq. 7; gn->lambda is not used). LM:
  * at the kept pose T with IRLS normal equations H, g, a trial solves (H + lambda diag H + eps_r I) tau =
- * -g and T' = Exp(tau) T; it is accepted iff E_track(T') < E_track(T) (schedule in tp). Matches with a
- * hole, a non-finite value or a negative confidence product are skipped.
+ * -g and T' = Exp(tau) T; it is accepted iff E_track(T') < E_track(T) (schedule in tp), with E_track
+ * evaluated in float64 from the stored values for this test (H and g are accumulated in float32; a float32
+ * cost cannot resolve the decrease of the last steps before the optimum). Matches with a hole, a
+ * non-finite value or a negative confidence product are skipped.
  * Outputs (device): cost_out (n float64) = E_track at the returned pose, trials_out (n int32) = trial
  * steps taken, status_out (n int32, may be NULL) = ladder attempt of the last solve (-1: zero step).
  * One call gathers the matches once, then runs 1 + max_trials rounds of two launches (reduction at the

@@ -24,6 +24,9 @@ GnConst make_gn_const(const ds3_gn_params& p) {
   c.inv_sr2 = float(1.0 / (p.sigma_ray * p.sigma_ray));
   c.inv_sd2 = float(1.0 / (p.sigma_dist * p.sigma_dist));
   c.kappa = float(p.huber_k);
+  c.inv_sr_d = 1.0 / p.sigma_ray;
+  c.inv_sd_d = 1.0 / p.sigma_dist;
+  c.kappa_d = p.huber_k;
   return c;
 }
 
@@ -468,19 +471,45 @@ __global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __
   if (threadIdx.x == 0) seg_count[seg] = running;
 }
 
+// E of one match in float64 (eq. (1), whitening and Huber as acc_core) from the stored values and a
+// float64 T_ij; used where a decision compares two costs that differ by less than float32 resolves.
+__device__ inline double cost_f64(const double* T, const float* xj, const float* xi, float sq, const GnConst& k) {
+  const double X0 = xj[0], X1 = xj[1], X2 = xj[2];
+  const double x0 = T[0] * X0 + T[1] * X1 + T[2] * X2 + T[9];
+  const double x1 = T[3] * X0 + T[4] * X1 + T[5] * X2 + T[10];
+  const double x2 = T[6] * X0 + T[7] * X1 + T[8] * X2 + T[11];
+  const double d = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+  const double y0 = xi[0], y1 = xi[1], y2 = xi[2];
+  const double di = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+  const double e[4] = {x0 / d - y0 / di, x1 / d - y1 / di, x2 / d - y2 / di, d - di};
+  const double s = double(sq);
+  const double kap = k.kappa_d;
+  double c = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double r = fabs(s * e[q] * (q < 3 ? k.inv_sr_d : k.inv_sd_d));
+    c += r <= kap ? 0.5 * r * r : kap * r - 0.5 * kap * kap;
+  }
+  return c;
+}
+
 // One block per segment: the segment's records with `unroll` loads in flight per thread, accumulated
 // as in the plain form, reduced over the block in a fixed order into the segment's partial. Segments of
-// edges flagged in skip (may be NULL) are left alone.
-template <int DT, int U>
+// edges flagged in skip (may be NULL) are left alone. C64: the segment's cost is also evaluated in float64
+// at the float64 transform xf64[edge] (12 doubles, sR row-major then t) and written to cost64[segment].
+template <int DT, int U, bool C64>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __restrict__ stream,
                                                                   const int32_t* __restrict__ seg_count,
                                                                   const EdgeDev* __restrict__ edges,
                                                                   const WorkItem* __restrict__ items,
                                                                   const EdgeXf* __restrict__ xf, int seg_px,
                                                                   float* __restrict__ partials, GnConst k,
-                                                                  const int32_t* __restrict__ skip) {
+                                                                  const int32_t* __restrict__ skip,
+                                                                  const double* __restrict__ xf64,
+                                                                  double* __restrict__ cost64) {
   using rec_t = typename Rec<DT>::raw_t;
   __shared__ float lds[kReduceThreads / kWave][37];
+  __shared__ double lds64[kReduceThreads / kWave];
   const WorkItem W = items[blockIdx.x];
   if (skip && skip[W.edge]) return;  // edges whose caller no longer needs their sums (block-uniform)
   const EdgeDev E = edges[W.edge];
@@ -488,6 +517,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
   float M[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) M[q] = xf[W.edge].m[q];
+  double M64[C64 ? 12 : 1];
+  if constexpr (C64) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) M64[q] = xf64[12 * int64_t(W.edge) + q];
+  }
+  double c64 = 0.0;
   const rec_t* __restrict__ in = static_cast<const rec_t*>(stream) + int64_t(seg) * seg_px;
   const int cnt = seg_count[seg];
   Acc a;
@@ -512,11 +547,23 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
         if (d2 > 1e-18f && d2 < __builtin_huge_valf()) {
           const float di2 = fmaf(xi[0], xi[0], fmaf(xi[1], xi[1], xi[2] * xi[2]));
           acc_core(a, x0, x1, x2, d2, xi[0], xi[1], xi[2], di2, sq, k);
+          if constexpr (C64) c64 += cost_f64(M64, xj, xi, sq, k);
         }
       }
     }
   }
   acc_block_store(a, partials + int64_t(seg) * kPartial, lds);
+  if constexpr (C64) {
+    const double s = wave_sum(c64);
+    if ((threadIdx.x & (kWave - 1)) == 0) lds64[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kReduceThreads / kWave; ++w) t += lds64[w];
+      cost64[seg] = t;
+    }
+  }
 }
 
 size_t stream_record_bytes(ds3_dtype dt) {
@@ -536,15 +583,16 @@ int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, 
   return check_hip(hipGetLastError(), "k_gather_stream");
 }
 
-template <int DT>
+template <int DT, bool C64>
 static int launch_reduce_stream_dt(int unroll, const void* stream, const int32_t* seg_count, const EdgeDev* edges,
                                    const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
-                                   float* partials, GnConst c, const int32_t* skip, hipStream_t s) {
+                                   float* partials, GnConst c, const int32_t* skip, const double* xf64,
+                                   double* cost64, hipStream_t s) {
   dim3 g(n_items), b(kReduceThreads);
   switch (unroll) {
-    case 1: hipLaunchKernelGGL((k_reduce_stream<DT, 1>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip); break;
-    case 2: hipLaunchKernelGGL((k_reduce_stream<DT, 2>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip); break;
-    case 4: hipLaunchKernelGGL((k_reduce_stream<DT, 4>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip); break;
+    case 1: hipLaunchKernelGGL((k_reduce_stream<DT, 1, C64>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64); break;
+    case 2: hipLaunchKernelGGL((k_reduce_stream<DT, 2, C64>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64); break;
+    case 4: hipLaunchKernelGGL((k_reduce_stream<DT, 4, C64>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64); break;
     default: return fail(DS3_EINVAL, "unsupported stream unroll");
   }
   return check_hip(hipGetLastError(), "k_reduce_stream");
@@ -552,13 +600,19 @@ static int launch_reduce_stream_dt(int unroll, const void* stream, const int32_t
 
 int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
                          const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
-                         float* partials, GnConst c, const int32_t* skip, hipStream_t s) {
+                         float* partials, GnConst c, const int32_t* skip, hipStream_t s, const double* xf64,
+                         double* cost64) {
   if (n_items <= 0) return DS3_OK;
+  if ((xf64 == nullptr) != (cost64 == nullptr)) return fail(DS3_EINVAL, "float64 cost needs both buffers");
   if (dt == DS3_F32)
-    return launch_reduce_stream_dt<DS3_F32>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px, partials,
-                                            c, skip, s);
-  return launch_reduce_stream_dt<DS3_BF16>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px, partials,
-                                           c, skip, s);
+    return xf64 ? launch_reduce_stream_dt<DS3_F32, true>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
+                                                         partials, c, skip, xf64, cost64, s)
+                : launch_reduce_stream_dt<DS3_F32, false>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
+                                                          partials, c, skip, nullptr, nullptr, s);
+  return xf64 ? launch_reduce_stream_dt<DS3_BF16, true>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
+                                                        partials, c, skip, xf64, cost64, s)
+              : launch_reduce_stream_dt<DS3_BF16, false>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
+                                                         partials, c, skip, nullptr, nullptr, s);
 }
 
 template <int DT>

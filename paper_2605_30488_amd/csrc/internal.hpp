@@ -70,6 +70,7 @@ struct EdgeXf {
 // Constants of the residual kernel.
 struct GnConst {
   float inv_sr, inv_sd, inv_sr2, inv_sd2, kappa;
+  double inv_sr_d, inv_sd_d, kappa_d;  // the same constants in float64 (float64 cost evaluation)
 };
 
 constexpr int kPartial = 40;  // floats per tile partial: H upper 28, b 7, cost, count, 3 pad
@@ -102,7 +103,8 @@ int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, 
                          hipStream_t s);
 int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
                          const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
-                         float* partials, GnConst c, const int32_t* skip, hipStream_t s);
+                         float* partials, GnConst c, const int32_t* skip, hipStream_t s,
+                         const double* xf64 = nullptr, double* cost64 = nullptr);
 int launch_edge_finalize(const EdgeDev* edges, int n_edges, const float* partials, const double* Ad,
                          double* A_out, double* b_out, double* cost_e, int64_t* count_e, hipStream_t s);
 int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,
@@ -122,10 +124,10 @@ int launch_count_valid(const EdgeDev* edges, int n_edges, const int32_t* idx_are
 
 // track.hip
 size_t track_state_bytes();
-int launch_track_init(const double* T_io, int n, EdgeXf* xf, int32_t* done, hipStream_t s);
-int launch_track_step(const EdgeDev* edges, int n, const float* partials, void* states, int32_t* done, EdgeXf* xf,
-                      double* T_io, double* cost_out, int32_t* trials_out, int32_t* status_out, TrackConst tc,
-                      int phase, hipStream_t s);
+int launch_track_init(const double* T_io, int n, EdgeXf* xf, double* xf64, int32_t* done, hipStream_t s);
+int launch_track_step(const EdgeDev* edges, int n, const float* partials, const double* cost64, void* states,
+                      int32_t* done, EdgeXf* xf, double* xf64, double* T_io, double* cost_out, int32_t* trials_out,
+                      int32_t* status_out, TrackConst tc, int phase, hipStream_t s);
 
 // chol.hip
 size_t chol_workspace_bytes(int n);

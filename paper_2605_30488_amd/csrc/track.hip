@@ -10,6 +10,14 @@
 // so H = H_L and g = b_L), and k_track_step, one block per problem, which sums the segment partials in
 // a fixed order, takes the LM decision, solves the damped 7x7 system and writes the next trial pose.
 // Problems that have stopped are skipped by both launches.
+//
+// The accept test compares E_track at two nearby poses. Near the optimum their difference falls below
+// what a float32 evaluation resolves (each whitened ray residual is a difference of unit vectors over
+// sigma_r = 0.003, so float32 rounding alone moves a pixel's cost by ~1e-4, and a 3k-pixel sum by ~1e-3
+// while the true decrease per step reaches 1e-8): a float32 test rejects good steps there, inflates the
+// damping and stops short of the optimum. The reduction therefore also evaluates each segment's cost in
+// float64 (from the stored values and the float64 trial pose), and only that cost enters the decision;
+// H and g stay float32.
 #include <algorithm>
 #include <vector>
 
@@ -78,12 +86,17 @@ __device__ int solve7(const double* H, const double* b, double lam, double eps0,
   return -1;
 }
 
-__device__ inline void write_xf(const Sim3& T, EdgeXf* xf) {
+// The trial transform for the next reduction: float32 (H, g) and float64 (the cost of the accept test).
+__device__ inline void write_xf(const Sim3& T, EdgeXf* xf, double* xf64) {
   double R[9];
   quat_to_mat(T.q, R);
   EdgeXf X;
   for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c) X.m[3 * r + c] = float(T.s * R[3 * r + c]);
+    for (int c = 0; c < 3; ++c) {
+      xf64[3 * r + c] = T.s * R[3 * r + c];
+      X.m[3 * r + c] = float(T.s * R[3 * r + c]);
+    }
+    xf64[9 + r] = T.t[r];
     X.m[9 + r] = float(T.t[r]);
   }
   for (int k = 0; k < 4; ++k) X.pad[k] = 0.0f;
@@ -93,15 +106,23 @@ __device__ inline void write_xf(const Sim3& T, EdgeXf* xf) {
 // phase 0: the partials hold the sums at the initial poses (T_io); later phases: at the trial poses.
 __global__ __launch_bounds__(64) void k_track_step(const EdgeDev* __restrict__ edges,
                                                    const float* __restrict__ partials,
+                                                   const double* __restrict__ cost64,
                                                    TrackState* __restrict__ states, int32_t* __restrict__ done,
-                                                   EdgeXf* __restrict__ xf, double* __restrict__ T_io,
+                                                   EdgeXf* __restrict__ xf, double* __restrict__ xf64,
+                                                   double* __restrict__ T_io,
                                                    double* __restrict__ cost_out, int32_t* __restrict__ trials_out,
                                                    int32_t* __restrict__ status_out, TrackConst tc, int phase) {
   const int p = blockIdx.x;
   const int t = threadIdx.x;
   if (phase > 0 && done[p]) return;
   __shared__ double S[37];
+  __shared__ double Ecost;
   const EdgeDev E = edges[p];
+  if (t == 63) {  // the float64 cost, summed over the segments in order
+    double s = 0.0;
+    for (int k = 0; k < E.n_tiles; ++k) s += cost64[E.tile0 + k];
+    Ecost = s;
+  }
   if (t < 37) {
     double s = 0.0;
     const float* q = partials + int64_t(E.tile0) * kPartial + t;
@@ -124,18 +145,18 @@ __global__ __launch_bounds__(64) void k_track_step(const EdgeDev* __restrict__ e
     for (int k = 0; k < 8; ++k) st.T[k] = T_io[8 * int64_t(p) + k];
     for (int k = 0; k < 28; ++k) st.H[k] = S[k];
     for (int k = 0; k < 7; ++k) st.b[k] = S[28 + k];
-    st.E = S[35];
+    st.E = Ecost;
     st.count = int32_t(S[36] + 0.5);
     st.lam = tc.lambda0;
     st.trials = 0;
     st.status = 0;
   } else {
     st.trials += 1;
-    if (S[35] < st.E) {  // accept: keep the trial pose and its linearisation
+    if (Ecost < st.E) {  // accept: keep the trial pose and its linearisation
       for (int k = 0; k < 8; ++k) st.T[k] = st.Tt[k];
       for (int k = 0; k < 28; ++k) st.H[k] = S[k];
       for (int k = 0; k < 7; ++k) st.b[k] = S[28 + k];
-      st.E = S[35];
+      st.E = Ecost;
       st.count = int32_t(S[36] + 0.5);
       st.lam = fmax(st.lam * tc.lambda_down, tc.lambda_min);
       double m = 0.0;
@@ -152,7 +173,7 @@ __global__ __launch_bounds__(64) void k_track_step(const EdgeDev* __restrict__ e
     Sim3 Tn = Tt;
     quat_normalize(Tn.q);
     sim3_store(Tn, st.Tt);
-    write_xf(Tn, xf + p);
+    write_xf(Tn, xf + p, xf64 + 12 * int64_t(p));
   } else {
     done[p] = 1;
   }
@@ -162,29 +183,30 @@ __global__ __launch_bounds__(64) void k_track_step(const EdgeDev* __restrict__ e
   if (status_out) status_out[p] = st.status;
 }
 
-// Initial transform of every problem (float32 copy of T_io) for the phase-0 reduction.
+// Initial transform of every problem (float32 and float64 copies of T_io) for the phase-0 reduction.
 __global__ void k_track_init(const double* __restrict__ T_io, int n, EdgeXf* __restrict__ xf,
-                             int32_t* __restrict__ done) {
+                             double* __restrict__ xf64, int32_t* __restrict__ done) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   Sim3 T = sim3_load(T_io + 8 * int64_t(p));
   quat_normalize(T.q);
-  write_xf(T, xf + p);
+  write_xf(T, xf + p, xf64 + 12 * int64_t(p));
   done[p] = 0;
 }
 
-int launch_track_init(const double* T_io, int n, EdgeXf* xf, int32_t* done, hipStream_t s) {
+int launch_track_init(const double* T_io, int n, EdgeXf* xf, double* xf64, int32_t* done, hipStream_t s) {
   if (n <= 0) return DS3_OK;
-  hipLaunchKernelGGL(k_track_init, dim3((n + 63) / 64), dim3(64), 0, s, T_io, n, xf, done);
+  hipLaunchKernelGGL(k_track_init, dim3((n + 63) / 64), dim3(64), 0, s, T_io, n, xf, xf64, done);
   return check_hip(hipGetLastError(), "k_track_init");
 }
 
-int launch_track_step(const EdgeDev* edges, int n, const float* partials, void* states, int32_t* done, EdgeXf* xf,
-                      double* T_io, double* cost_out, int32_t* trials_out, int32_t* status_out, TrackConst tc,
-                      int phase, hipStream_t s) {
+int launch_track_step(const EdgeDev* edges, int n, const float* partials, const double* cost64, void* states,
+                      int32_t* done, EdgeXf* xf, double* xf64, double* T_io, double* cost_out, int32_t* trials_out,
+                      int32_t* status_out, TrackConst tc, int phase, hipStream_t s) {
   if (n <= 0) return DS3_OK;
-  hipLaunchKernelGGL(k_track_step, dim3(n), dim3(64), 0, s, edges, partials, static_cast<TrackState*>(states), done,
-                     xf, T_io, cost_out, trials_out, status_out, tc, phase);
+  hipLaunchKernelGGL(k_track_step, dim3(n), dim3(64), 0, s, edges, partials, cost64,
+                     static_cast<TrackState*>(states), done, xf, xf64, T_io, cost_out, trials_out, status_out, tc,
+                     phase);
   return check_hip(hipGetLastError(), "k_track_step");
 }
 
@@ -201,7 +223,9 @@ struct TrackBuffers {
   EdgeDev* edges;
   WorkItem* items;
   EdgeXf* xf;
+  double* xf64;
   float* partials;
+  double* cost64;
   void* stream;
   int32_t* seg_count;
   void* states;
@@ -246,7 +270,9 @@ static size_t carve_track(void* base, int n, int tiles, ds3_dtype dt, TrackBuffe
   B.edges = c.take<EdgeDev>(std::max(n, 1));
   B.items = c.take<WorkItem>(std::max(tiles, 1));
   B.xf = c.take<EdgeXf>(std::max(n, 1));
+  B.xf64 = c.take<double>(size_t(std::max(n, 1)) * 12);
   B.partials = c.take<float>(size_t(std::max(tiles, 1)) * kPartial);
+  B.cost64 = c.take<double>(std::max(tiles, 1));
   B.stream = c.take<char>(size_t(std::max(tiles, 1)) * seg * stream_record_bytes(dt));
   B.seg_count = c.take<int32_t>(std::max(tiles, 1));
   B.states = c.take<char>(size_t(std::max(n, 1)) * track_state_bytes());
@@ -254,34 +280,10 @@ static size_t carve_track(void* base, int n, int tiles, ds3_dtype dt, TrackBuffe
   return c.used;
 }
 
-}  // namespace ds3
-
-using namespace ds3;
-
-extern "C" {
-
-void ds3_default_track_params(ds3_track_params* p) {
-  if (!p) return;
-  p->lambda0 = 1e-4;
-  p->lambda_min = 1e-9;
-  p->lambda_up = 10.0;
-  p->lambda_down = 0.1;
-  p->max_trials = 20;
-  p->step_tol = 1e-7;
-}
-
-size_t ds3_track_workspace_bytes(int32_t n, const ds3_track_problem* probs, ds3_dtype dtype) {
-  std::vector<EdgeDev> edges;
-  std::vector<WorkItem> items;
-  if (n <= 0 || track_topology(n, probs, edges, items) != DS3_OK) return 0;
-  TrackBuffers B;
-  return carve_track(nullptr, n, int(items.size()), dtype, B);
-}
-
-int ds3_track(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs, int32_t n,
-              const int32_t* idx_arena, const ds3_gn_params* gn, const ds3_track_params* tp, double* T,
-              double* cost_out, int32_t* trials_out, int32_t* status_out, ds3_timer* reduce_timer,
-              void* workspace, size_t ws_bytes, void* stream) {
+static int track_impl(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs, int32_t n,
+                      const int32_t* idx_arena, const ds3_gn_params* gn, const ds3_track_params* tp, double* T,
+                      double* cost_out, int32_t* trials_out, int32_t* status_out, ds3_timer* reduce_timer,
+                      void* workspace, size_t ws_bytes, void* stream) {
   if (n < 0) return fail(DS3_EINVAL, "track: n < 0");
   if (n == 0) return DS3_OK;
   if (!arena || !idx_arena || !gn || !tp || !T || !cost_out || !trials_out || !workspace)
@@ -317,17 +319,50 @@ int ds3_track(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs
   tc.max_trials = tp->max_trials;
   tc.attempts = gn->max_attempts;
   DS3_TRY(launch_gather_stream(dtype, arena, B.edges, B.items, tiles, idx_arena, seg, B.stream, B.seg_count, s));
-  DS3_TRY(launch_track_init(T, n, B.xf, B.done, s));
+  DS3_TRY(launch_track_init(T, n, B.xf, B.xf64, B.done, s));
   for (int phase = 0; phase <= tp->max_trials; ++phase) {
     const bool timed = reduce_timer && phase == 0;
     if (timed) DS3_TRY(timer_record(reduce_timer, true, s));
     DS3_TRY(launch_reduce_stream(dtype, 2, B.stream, B.seg_count, B.edges, B.items, tiles, B.xf, seg, B.partials,
-                                 c, B.done, s));
+                                 c, B.done, s, B.xf64, B.cost64));
     if (timed) DS3_TRY(timer_record(reduce_timer, false, s));
-    DS3_TRY(launch_track_step(B.edges, n, B.partials, B.states, B.done, B.xf, T, cost_out, trials_out, status_out,
-                              tc, phase, s));
+    DS3_TRY(launch_track_step(B.edges, n, B.partials, B.cost64, B.states, B.done, B.xf, B.xf64, T, cost_out,
+                              trials_out, status_out, tc, phase, s));
   }
   return DS3_OK;
+}
+
+
+}  // namespace ds3
+
+using namespace ds3;
+
+extern "C" {
+
+void ds3_default_track_params(ds3_track_params* p) {
+  if (!p) return;
+  p->lambda0 = 1e-4;
+  p->lambda_min = 1e-9;
+  p->lambda_up = 10.0;
+  p->lambda_down = 0.1;
+  p->max_trials = 20;
+  p->step_tol = 1e-7;
+}
+
+size_t ds3_track_workspace_bytes(int32_t n, const ds3_track_problem* probs, ds3_dtype dtype) {
+  std::vector<EdgeDev> edges;
+  std::vector<WorkItem> items;
+  if (n <= 0 || track_topology(n, probs, edges, items) != DS3_OK) return 0;
+  TrackBuffers B;
+  return carve_track(nullptr, n, int(items.size()), dtype, B);
+}
+
+int ds3_track(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs, int32_t n,
+              const int32_t* idx_arena, const ds3_gn_params* gn, const ds3_track_params* tp, double* T,
+              double* cost_out, int32_t* trials_out, int32_t* status_out, ds3_timer* reduce_timer,
+              void* workspace, size_t ws_bytes, void* stream) {
+  return track_impl(arena, dtype, probs, n, idx_arena, gn, tp, T, cost_out, trials_out, status_out, reduce_timer,
+                    workspace, ws_bytes, stream);
 }
 
 }  // extern "C"
