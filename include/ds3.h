@@ -349,6 +349,21 @@ int ds3_track(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs
               double* cost_out, int32_t* trials_out, int32_t* status_out, ds3_timer* reduce_timer,
               void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): ds3_track without a workspace argument. Its scratch (edge table, match
+ * stream, partials, LM states) is a static device array of DS3_TRACK_SCRATCH_BYTES (64 MiB) compiled
+ * into the library: each GPU the library runs on holds its own copy until the process ends, and the call
+ * itself allocates nothing (no hipMalloc, no library allocation). Problems whose scratch exceeds that size
+ * (ds3_track_workspace_bytes reports it; about 6.4 MB per 512x384 frame in f32, 3.2 MB in bf16) are
+ * rejected with DS3_ENOSPACE and nothing is launched. Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two host threads, or two streams whose work is in flight together)
+ * race and give undefined results; calls ordered on one stream are safe. No reduce timer. Arguments,
+ * outputs and errors otherwise as ds3_track. */
+#define DS3_TRACK_SCRATCH_BYTES (64u << 20)
+int ds3_track_noalloc(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs, int32_t n,
+                      const int32_t* idx_arena, const ds3_gn_params* gn, const ds3_track_params* tp, double* T,
+                      double* cost_out, int32_t* trials_out, int32_t* status_out, void* stream);
+
 /* ---------------------------------------------------------------------------------------------------
  * Cost and its adjoint (gradient of eq. 5 with the matches held fixed)
  * ------------------------------------------------------------------------------------------------- */

@@ -111,6 +111,8 @@ _SIGS = {
     "ds3_track_workspace_bytes": (sz, [i32, C.POINTER(TrackProblem), C.c_int]),
     "ds3_track": (C.c_int, [vp, C.c_int, C.POINTER(TrackProblem), i32, vp, C.POINTER(GNParams),
                             C.POINTER(TrackParams), vp, vp, vp, vp, vp, vp, sz, vp]),
+    "ds3_track_noalloc": (C.c_int, [vp, C.c_int, C.POINTER(TrackProblem), i32, vp, C.POINTER(GNParams),
+                                    C.POINTER(TrackParams), vp, vp, vp, vp, vp]),
     "ds3_fuse_workspace_bytes": (sz, [i32]),
     "ds3_fuse": (C.c_int, [vp, i64, vp, i64, C.POINTER(FusePair), i32, vp, i32, vp, sz, vp]),
 }

@@ -538,7 +538,8 @@ def default_track_params() -> L.TrackParams:
 class Tracker:
     """ds3_track over a fixed problem table: problems are (keyframe, frame) image indices of `arena` with
     the frame-to-keyframe matches of problem p at idx_offsets[p] of an idx arena (H_f * W_f int32 each;
-    consecutive by default). The workspace is allocated once here."""
+    consecutive by default). The workspace is allocated once, at the first run that uses it (runs with
+    noalloc=True call ds3_track_noalloc, which takes its scratch from the library's static device array)."""
 
     def __init__(self, arena: Arena, problems, idx_offsets=None, params=None, track_params=None):
         self.arena = arena
@@ -556,9 +557,12 @@ class Tracker:
             self.table[p] = L.TrackProblem(arena.image(k), arena.image(f), off)
         self.params = params or default_gn_params()
         self.track_params = track_params or default_track_params()
-        self.ws = _ws(L.load().ds3_track_workspace_bytes(self.n, self.table, _dt(arena.dtype)), arena.data.device)
+        self.ws = None
 
-    def run(self, idx: torch.Tensor, T: torch.Tensor, timer=None):
+    def workspace_bytes(self) -> int:
+        return int(L.load().ds3_track_workspace_bytes(self.n, self.table, _dt(self.arena.dtype)))
+
+    def run(self, idx: torch.Tensor, T: torch.Tensor, timer=None, noalloc=False):
         """T: (n, 8) float64 starting poses, updated in place. Returns (E_track (n,) float64, trial steps
         (n,) int32, ladder status (n,) int32) on the device."""
         _need_cuda(idx, T)
@@ -572,6 +576,15 @@ class Tracker:
         cost = torch.empty(max(self.n, 1), dtype=torch.float64, device=dev)
         trials = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
         status = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
+        if noalloc:
+            if timer is not None:
+                raise ValueError("ds3_track_noalloc records no timer")
+            call("ds3_track_noalloc", _ptr(self.arena.data), _dt(self.arena.dtype), self.table, self.n, _ptr(idx),
+                 C.byref(self.params), C.byref(self.track_params), _ptr(T), _ptr(cost), _ptr(trials),
+                 _ptr(status), _stream())
+            return cost[:self.n], trials[:self.n], status[:self.n]
+        if self.ws is None:
+            self.ws = _ws(self.workspace_bytes(), self.arena.data.device)
         call("ds3_track", _ptr(self.arena.data), _dt(self.arena.dtype), self.table, self.n, _ptr(idx),
              C.byref(self.params), C.byref(self.track_params), _ptr(T), _ptr(cost), _ptr(trials), _ptr(status),
              timer.handle if timer is not None else None, _ptr(self.ws), self.ws.numel(), _stream())

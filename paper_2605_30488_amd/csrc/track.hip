@@ -19,6 +19,8 @@
 // float64 (from the stored values and the float64 trial pose), and only that cost enters the decision;
 // H and g stay float32.
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -280,6 +282,28 @@ static size_t carve_track(void* base, int n, int tiles, ds3_dtype dt, TrackBuffe
   return c.used;
 }
 
+// Static scratch of ds3_track_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends. Host code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's own name is a host-side stand-in, not a device address).
+constexpr size_t kTrackScratchBytes = size_t(DS3_TRACK_SCRATCH_BYTES);
+static __device__ __align__(256) char scratch[kTrackScratchBytes];
+
+static int track_scratch(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  int dev = 0;
+  DS3_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (int(addr.size()) <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    DS3_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return DS3_OK;
+}
+
 static int track_impl(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs, int32_t n,
                       const int32_t* idx_arena, const ds3_gn_params* gn, const ds3_track_params* tp, double* T,
                       double* cost_out, int32_t* trials_out, int32_t* status_out, ds3_timer* reduce_timer,
@@ -363,6 +387,26 @@ int ds3_track(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs
               void* workspace, size_t ws_bytes, void* stream) {
   return track_impl(arena, dtype, probs, n, idx_arena, gn, tp, T, cost_out, trials_out, status_out, reduce_timer,
                     workspace, ws_bytes, stream);
+}
+
+int ds3_track_noalloc(const void* arena, ds3_dtype dtype, const ds3_track_problem* probs, int32_t n,
+                      const int32_t* idx_arena, const ds3_gn_params* gn, const ds3_track_params* tp, double* T,
+                      double* cost_out, int32_t* trials_out, int32_t* status_out, void* stream) {
+  if (n < 0) return fail(DS3_EINVAL, "track_noalloc: n < 0");
+  if (n == 0) return DS3_OK;
+  std::vector<EdgeDev> edges;
+  std::vector<WorkItem> items;
+  DS3_TRY(track_topology(n, probs, edges, items));
+  TrackBuffers B;
+  const size_t need = carve_track(nullptr, n, int(items.size()), dtype, B);
+  if (need > kTrackScratchBytes)
+    return fail(DS3_ENOSPACE, "track_noalloc: these problems need " + std::to_string(need) +
+                                  " bytes of scratch; the static scratch holds " +
+                                  std::to_string(kTrackScratchBytes) + " (DS3_TRACK_SCRATCH_BYTES)");
+  void* ws = nullptr;
+  DS3_TRY(track_scratch(&ws));
+  return track_impl(arena, dtype, probs, n, idx_arena, gn, tp, T, cost_out, trials_out, status_out, nullptr, ws,
+                    kTrackScratchBytes, stream);
 }
 
 }  // extern "C"

@@ -160,3 +160,22 @@ def test_umeyama_host_entry_point(lib):
     assert lib.ds3_umeyama(None, None, 3, buf.ctypes.data_as(dp)) == -1
     one = np.zeros(3)
     assert lib.ds3_umeyama(one.ctypes.data_as(dp), one.ctypes.data_as(dp), 0, buf.ctypes.data_as(dp)) == -1
+
+
+def test_track_noalloc_refuses_oversized_problems_on_the_host(lib):
+    """ds3_track_noalloc sizes its scratch on the host and refuses, before any HIP call, problems that do not
+    fit the static array (12 frames of 512x384 in f32 need about 72 MiB of the 64 MiB)."""
+    from paper_2605_30488_amd import _lib as L
+    ds3 = L.load()
+    n = 12
+    table = (L.TrackProblem * n)()
+    for p in range(n):
+        table[p] = L.TrackProblem(L.Image(384, 512, 0), L.Image(384, 512, 196608 * (p + 1)), 196608 * p)
+    need = ds3.ds3_track_workspace_bytes(n, table, 0)
+    assert need > 64 << 20 and ds3.ds3_track_workspace_bytes(6, table, 0) <= 64 << 20
+    gp, tp = L.GNParams(), L.TrackParams()
+    ds3.ds3_default_gn_params(ctypes.byref(gp))
+    ds3.ds3_default_track_params(ctypes.byref(tp))
+    with pytest.raises(L.DS3Error, match=f"need {need} bytes of scratch"):
+        L.call("ds3_track_noalloc", None, 0, table, n, None, ctypes.byref(gp), ctypes.byref(tp), None, None, None,
+               None, None)
