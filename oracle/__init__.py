@@ -93,6 +93,16 @@ def lib():
                                     C.POINTER(GNParams), d, d, d, d]
         L.orc_edge_residuals.argtypes = [d, d, d, d, C.c_int64, d, d, C.c_int64, i32,
                                          C.POINTER(GNParams), d, d, u8]
+        dd = C.c_double
+        L.orc_gn_assemble_cal.argtypes = [d, C.c_int, i64, i64, i32, d, d, d, i32, i32, i64, C.c_int, i32, i32,
+                                          C.c_int, C.POINTER(GNParams), dd, dd, d, d, d, i64, d, i64]
+        L.orc_gn_step_cal.argtypes = [d, C.c_int, i64, i64, i32, d, d, d, i32, i32, i64, C.c_int, i32, i32,
+                                      C.c_int, C.POINTER(GNParams), dd, dd, d, i32, d]
+        L.orc_cost_cal.argtypes = [d, C.c_int, i64, i64, i32, d, d, d, i32, i32, i64, C.c_int, i32,
+                                   C.POINTER(GNParams), dd, dd]
+        L.orc_cost_cal.restype = C.c_double
+        L.orc_edge_residuals_cal.argtypes = [d, d, d, d, C.c_int64, C.c_int, d, d, d, C.c_int64, C.c_int, d, i32,
+                                             C.POINTER(GNParams), dd, dd, d, d, u8]
         _lib = L
     return _lib
 
@@ -254,6 +264,8 @@ class Graph:
     def __init__(self, xyz_list, conf_list, edges, idx_list, anchors=(0,)):
         self.n_kf = len(xyz_list)
         npx = np.array([int(np.prod(np.shape(x)[:2])) for x in xyz_list], np.int64)
+        # image width per keyframe (calibrated mode splits pixel indices into (u, v)); flat inputs: 0
+        self.kf_w = np.array([int(np.shape(x)[1]) if np.ndim(x) == 3 else 0 for x in xyz_list], np.int32)
         self.kf_npx = npx
         self.kf_off = np.concatenate([[0], np.cumsum(npx)[:-1]]).astype(np.int64)
         self.xyz = np.ascontiguousarray(
@@ -373,6 +385,95 @@ def cost_grad(graph: Graph, poses, params: GNParams | None = None):
     lib().orc_cost_grad(_p(poses, C.c_double), *args[1:], C.byref(P), _p(gx, C.c_double),
                         _p(gc, C.c_double), _p(gt, C.c_double), C.byref(c))
     return c.value, gx, gc, gt
+
+
+# ---------------------------------------------------------------------------------------------
+# Calibrated mode (Sec. IV-C, "Calibration"): pixel reprojection and log-depth residuals on the
+# pointmaps constrained to the calibrated rays. See ds3_oracle.cpp for the readings.
+# ---------------------------------------------------------------------------------------------
+@dataclass
+class Calib:
+    """Supplied intrinsics K (n_kf x 4: fx, fy, cx, cy) and the whitening of the residual rows (the paper
+    states no constants for this mode; readings: one pixel for the reprojection rows, 0.1 for log-depth)."""
+    K: np.ndarray
+    sigma_pix: float = 1.0
+    sigma_logz: float = 0.1
+
+
+def _cal_args(graph: Graph, calib: Calib):
+    K = np.ascontiguousarray(np.asarray(calib.K, np.float64).reshape(graph.n_kf, 4))
+    if np.any(graph.kf_w <= 0):
+        raise ValueError("calibrated mode needs (H, W, 3) pointmaps (image widths)")
+    return K
+
+
+def gn_assemble_cal(graph: Graph, poses, calib: Calib, params: GNParams | None = None):
+    """H (7N x 7N), g (7N), E, valid count, per-edge cost and count at `poses` in calibrated mode."""
+    P = params or GNParams.default()
+    poses = _f64(poses).reshape(graph.n_kf, 8)
+    K = _cal_args(graph, calib)
+    n = 7 * graph.n_kf
+    H, g = np.empty((n, n)), np.empty(n)
+    cost, count = C.c_double(), C.c_int64()
+    ec, en = np.empty(graph.n_edges), np.empty(graph.n_edges, np.int64)
+    lib().orc_gn_assemble_cal(_p(poses, C.c_double), graph.n_kf, _p(graph.kf_off, C.c_int64),
+                              _p(graph.kf_npx, C.c_int64), _p(graph.kf_w, C.c_int32), _p(K, C.c_double),
+                              _p(graph.xyz, C.c_double), _p(graph.conf, C.c_double), _p(graph.ei, C.c_int32),
+                              _p(graph.ej, C.c_int32), _p(graph.idx_off, C.c_int64), graph.n_edges,
+                              _p(graph.idx, C.c_int32), _p(graph.anchors, C.c_int32), len(graph.anchors),
+                              C.byref(P), calib.sigma_pix, calib.sigma_logz, _p(H, C.c_double), _p(g, C.c_double),
+                              C.byref(cost), C.byref(count), _p(ec, C.c_double), _p(en, C.c_int64))
+    return H, g, cost.value, count.value, ec, en
+
+
+def gn_step_cal(graph: Graph, poses, calib: Calib, params: GNParams | None = None):
+    """One GN/IRLS step in calibrated mode; returns (new poses, cost at the input poses, status, tau)."""
+    P = params or GNParams.default()
+    poses = _f64(poses).reshape(graph.n_kf, 8).copy()
+    K = _cal_args(graph, calib)
+    cost, st = C.c_double(), C.c_int32()
+    tau = np.empty(7 * graph.n_kf)
+    lib().orc_gn_step_cal(_p(poses, C.c_double), graph.n_kf, _p(graph.kf_off, C.c_int64),
+                          _p(graph.kf_npx, C.c_int64), _p(graph.kf_w, C.c_int32), _p(K, C.c_double),
+                          _p(graph.xyz, C.c_double), _p(graph.conf, C.c_double), _p(graph.ei, C.c_int32),
+                          _p(graph.ej, C.c_int32), _p(graph.idx_off, C.c_int64), graph.n_edges,
+                          _p(graph.idx, C.c_int32), _p(graph.anchors, C.c_int32), len(graph.anchors), C.byref(P),
+                          calib.sigma_pix, calib.sigma_logz, C.byref(cost), C.byref(st), _p(tau, C.c_double))
+    return poses, cost.value, st.value, tau
+
+
+def cost_cal(graph: Graph, poses, calib: Calib, params: GNParams | None = None) -> float:
+    P = params or GNParams.default()
+    poses = _f64(poses).reshape(graph.n_kf, 8)
+    K = _cal_args(graph, calib)
+    return lib().orc_cost_cal(_p(poses, C.c_double), graph.n_kf, _p(graph.kf_off, C.c_int64),
+                              _p(graph.kf_npx, C.c_int64), _p(graph.kf_w, C.c_int32), _p(K, C.c_double),
+                              _p(graph.xyz, C.c_double), _p(graph.conf, C.c_double), _p(graph.ei, C.c_int32),
+                              _p(graph.ej, C.c_int32), _p(graph.idx_off, C.c_int64), graph.n_edges,
+                              _p(graph.idx, C.c_int32), C.byref(P), calib.sigma_pix, calib.sigma_logz)
+
+
+def edge_residuals_cal(graph: Graph, poses, e: int, calib: Calib, params: GNParams | None = None):
+    """Per pixel of j for edge e in calibrated mode: whitened residuals r (npx_j, 3), IRLS weights w
+    (npx_j, 3), ok mask."""
+    P = params or GNParams.default()
+    poses = _f64(poses).reshape(graph.n_kf, 8)
+    K = _cal_args(graph, calib)
+    i, j = int(graph.ei[e]), int(graph.ej[e])
+    nj, ni = int(graph.kf_npx[j]), int(graph.kf_npx[i])
+    r, w, ok = np.empty((nj, 3)), np.empty((nj, 3)), np.empty(nj, np.uint8)
+    sl = lambda a, k, n, c=1: np.ascontiguousarray(a[graph.kf_off[k] * c:(graph.kf_off[k] + n) * c])
+    xj, xi = sl(graph.xyz.reshape(-1), j, nj, 3), sl(graph.xyz.reshape(-1), i, ni, 3)
+    cj, ci = sl(graph.conf, j, nj), sl(graph.conf, i, ni)
+    idx = np.ascontiguousarray(graph.idx[graph.idx_off[e]:graph.idx_off[e] + nj])
+    pi, pj = np.ascontiguousarray(poses[i]), np.ascontiguousarray(poses[j])
+    Kj, Ki = np.ascontiguousarray(K[j]), np.ascontiguousarray(K[i])
+    lib().orc_edge_residuals_cal(_p(pi, C.c_double), _p(pj, C.c_double), _p(xj, C.c_double), _p(cj, C.c_double), nj,
+                                 int(graph.kf_w[j]), _p(Kj, C.c_double), _p(xi, C.c_double), _p(ci, C.c_double), ni,
+                                 int(graph.kf_w[i]), _p(Ki, C.c_double), _p(idx, C.c_int32), C.byref(P),
+                                 calib.sigma_pix, calib.sigma_logz, _p(r, C.c_double), _p(w, C.c_double),
+                                 _p(ok, C.c_uint8))
+    return r, w, ok.astype(bool)
 
 
 # ---------------------------------------------------------------------------------------------

@@ -20,6 +20,8 @@
 //   left perturbation T <- Exp(tau) T, tau = (v, omega, zeta)         Sec. III-D
 //   Jacobian blocks and the -/+ Ad_{T_i^-1} endpoint maps              eq. (6) and the text after it
 //   regularised normal equations and the epsilon ladder                eq. (7) and the text after it
+//   calibrated mode: pixel reprojection and log-depth residuals on      Sec. IV-C, "Calibration"
+//   pointmaps constrained to the calibrated rays
 //
 // Readings where the paper is silent (stated in the design notes of the repository):
 //   matching = Levenberg-Marquardt on the bilinear interpolant of the reference ray image, started at
@@ -534,6 +536,142 @@ void linearize_edge(const M4& Ti, const M4& Tj, const double* xyz_j, const doubl
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Calibrated mode (Sec. IV-C, "Calibration": with supplied intrinsics the pointmaps are constrained to
+// the calibrated rays and the pose residuals are pixel reprojection and log-depth). Readings:
+//   the calibrated point of pixel n = (u, v) of keyframe k is z K_k^-1 (u, v, 1), z = the predicted
+//   point's depth (its third coordinate); for a match (m, n) of edge (i, j), x = T_ij Xcal_j[n] and
+//     r = ( fx_i x0/x2 + cx_i - u_m,  fy_i x1/x2 + cy_i - v_m,  ln x2 - ln z_i[m] ),
+//   whitened by sqrt(q)/sigma_pix (pixel rows) and sqrt(q)/sigma_logz (depth row), q = sqrt(C_i C_j);
+//   the same component-wise Huber kernel and IRLS weights; a match is used only if neither point is a
+//   hole and z_j[n], z_i[m] and x2 are above 1e-9 (both points and the transformed one in front).
+// The chain rule is the one of eq. (6) with this residual: J_x = (dr/dx) [I  -[x]x  x].
+// ------------------------------------------------------------------------------------------------
+struct CalResidual {
+  double r[3];  // unwhitened: pixel, pixel, log-depth
+  double x[3];
+  double q;
+  bool ok;
+};
+
+// K: fx, fy, cx, cy of a keyframe.
+CalResidual cal_residual(const M4& Tij, const double* Xj, int64_t n, int Wj, const double* Kj, const double* Xi,
+                         int64_t m, int Wi, const double* Ki, double Ci, double Cj) {
+  CalResidual R{};
+  R.ok = false;
+  if (is_hole(Xj) || is_hole(Xi) || !std::isfinite(Ci) || !std::isfinite(Cj)) return R;
+  const double zj = Xj[2], zi = Xi[2];
+  if (!(zj > 1e-9) || !(zi > 1e-9)) return R;
+  const double un = double(n % Wj), vn = double(n / Wj);
+  const double Xc[3] = {zj * (un - Kj[2]) / Kj[0], zj * (vn - Kj[3]) / Kj[1], zj};
+  apply_mat(Tij, Xc, R.x);
+  if (!(R.x[2] > 1e-9)) return R;
+  const double um = double(m % Wi), vm = double(m / Wi);
+  R.r[0] = Ki[0] * R.x[0] / R.x[2] + Ki[2] - um;
+  R.r[1] = Ki[1] * R.x[1] / R.x[2] + Ki[3] - vm;
+  R.r[2] = std::log(R.x[2]) - std::log(zi);
+  R.q = std::sqrt(Ci * Cj);
+  R.ok = std::isfinite(R.q) && std::isfinite(R.r[0]) && std::isfinite(R.r[1]) && std::isfinite(R.r[2]);
+  return R;
+}
+
+void linearize_edge_cal(const M4& Ti, const M4& Tj, const double* xyz_j, const double* conf_j, int64_t npx_j,
+                        int Wj, const double* Kj, const double* xyz_i, const double* conf_i, int64_t npx_i, int Wi,
+                        const double* Ki, const int32_t* idx, double sigma_pix, double sigma_logz,
+                        const orc_gn_params& P, EdgeAcc& acc) {
+  std::memset(&acc, 0, sizeof(acc));
+  M4 Tiinv = sim3_inverse_mat(Ti);
+  M4 Tij = m4_mul(Tiinv, Tj);
+  double Ad[49];
+  sim3_adjoint(Tiinv, Ad);
+  const double sig[3] = {sigma_pix, sigma_pix, sigma_logz};
+  for (int64_t n = 0; n < npx_j; ++n) {
+    int32_t m = idx[n];
+    if (m < 0 || m >= npx_i) continue;
+    CalResidual R = cal_residual(Tij, xyz_j + 3 * n, n, Wj, Kj, xyz_i + 3 * int64_t(m), m, Wi, Ki, conf_i[m],
+                                 conf_j[n]);
+    if (!R.ok) continue;
+    double sq = std::sqrt(R.q);
+    double W[3];
+    for (int c = 0; c < 3; ++c) {
+      double r = sq * R.r[c] / sig[c];
+      acc.cost += huber_rho(r, P.huber_k);
+      W[c] = huber_w(r, P.huber_k) * R.q / (sig[c] * sig[c]);
+    }
+    acc.count += 1;
+    const double* x = R.x;
+    const double z = x[2];
+    // dr/dx: 3x3
+    double Drx[3][3] = {{Ki[0] / z, 0.0, -Ki[0] * x[0] / (z * z)},
+                        {0.0, Ki[1] / z, -Ki[1] * x[1] / (z * z)},
+                        {0.0, 0.0, 1.0 / z}};
+    // Dx/Dtau = [I  -[x]x  x]: 3x7
+    double Dxt[3][7] = {{1, 0, 0, 0, x[2], -x[1], x[0]},
+                        {0, 1, 0, -x[2], 0, x[0], x[1]},
+                        {0, 0, 1, x[1], -x[0], 0, x[2]}};
+    double Jx[3][7];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 7; ++k) {
+        double s = 0.0;
+        for (int b = 0; b < 3; ++b) s += Drx[a][b] * Dxt[b][k];
+        Jx[a][k] = s;
+      }
+    // [J_i | J_j] = [-J_x Ad | +J_x Ad]
+    double J[3][14];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 7; ++k) {
+        double s = 0.0;
+        for (int l = 0; l < 7; ++l) s += Jx[a][l] * Ad[l * 7 + k];
+        J[a][k] = -s;
+        J[a][7 + k] = s;
+      }
+    for (int r = 0; r < 14; ++r) {
+      for (int c = 0; c < 14; ++c) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) s += J[a][r] * W[a] * J[a][c];
+        acc.H[r * 14 + c] += s;
+      }
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a) s += J[a][r] * W[a] * R.r[a];
+      acc.g[r] += s;
+    }
+  }
+}
+
+// Scatter of the per-edge 14x14 blocks and 14-vectors into H (7N x 7N) and g in edge order, then the
+// anchor rows and columns replaced by identity (g = 0).
+void scatter_blocks(const std::vector<EdgeAcc>& acc, int n_kf, const int32_t* ei, const int32_t* ej, int n_edges,
+                    const int32_t* anchors, int n_anchors, double* H, double* g, double* cost_out,
+                    int64_t* count_out, double* edge_cost, int64_t* edge_count) {
+  const int64_t n = 7 * int64_t(n_kf);
+  std::fill(H, H + n * n, 0.0);
+  std::fill(g, g + n, 0.0);
+  double cost = 0.0;
+  int64_t count = 0;
+  for (int e = 0; e < n_edges; ++e) {
+    const int64_t base[2] = {7 * int64_t(ei[e]), 7 * int64_t(ej[e])};
+    for (int r = 0; r < 14; ++r) {
+      int64_t gr = base[r / 7] + r % 7;
+      for (int c = 0; c < 14; ++c) H[gr * n + base[c / 7] + c % 7] += acc[e].H[r * 14 + c];
+      g[gr] += acc[e].g[r];
+    }
+    cost += acc[e].cost;
+    count += acc[e].count;
+    if (edge_cost) edge_cost[e] = acc[e].cost;
+    if (edge_count) edge_count[e] = acc[e].count;
+  }
+  for (int a = 0; a < n_anchors; ++a) {
+    int64_t b0 = 7 * int64_t(anchors[a]);
+    for (int64_t r = b0; r < b0 + 7; ++r) {
+      for (int64_t c = 0; c < n; ++c) { H[r * n + c] = 0.0; H[c * n + r] = 0.0; }
+      H[r * n + r] = 1.0;
+      g[r] = 0.0;
+    }
+  }
+  *cost_out = cost;
+  if (count_out) *count_out = count;
+}
+
 // Plain Cholesky M = L L^T (lower, row by row). Fails on a non-positive or non-finite pivot.
 bool cholesky(std::vector<double>& M, int n) {
   for (int j = 0; j < n; ++j) {
@@ -699,7 +837,6 @@ int orc_gn_assemble(const double* poses, int n_kf, const int64_t* kf_off, const 
                     const int64_t* idx_off, int n_edges, const int32_t* idx, const int32_t* anchors,
                     int n_anchors, const orc_gn_params* P, double* H, double* g, double* cost_out,
                     int64_t* count_out, double* edge_cost, int64_t* edge_count) {
-  const int64_t n = 7 * int64_t(n_kf);
   std::vector<EdgeAcc> acc(n_edges);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int e = 0; e < n_edges; ++e) {
@@ -708,32 +845,7 @@ int orc_gn_assemble(const double* poses, int n_kf, const int64_t* kf_off, const 
                    conf + kf_off[j], kf_npx[j], xyz + 3 * kf_off[i], conf + kf_off[i], kf_npx[i],
                    idx + idx_off[e], *P, acc[e]);
   }
-  std::fill(H, H + n * n, 0.0);
-  std::fill(g, g + n, 0.0);
-  double cost = 0.0;
-  int64_t count = 0;
-  for (int e = 0; e < n_edges; ++e) {
-    const int64_t base[2] = {7 * int64_t(ei[e]), 7 * int64_t(ej[e])};
-    for (int r = 0; r < 14; ++r) {
-      int64_t gr = base[r / 7] + r % 7;
-      for (int c = 0; c < 14; ++c) H[gr * n + base[c / 7] + c % 7] += acc[e].H[r * 14 + c];
-      g[gr] += acc[e].g[r];
-    }
-    cost += acc[e].cost;
-    count += acc[e].count;
-    if (edge_cost) edge_cost[e] = acc[e].cost;
-    if (edge_count) edge_count[e] = acc[e].count;
-  }
-  for (int a = 0; a < n_anchors; ++a) {
-    int64_t b0 = 7 * int64_t(anchors[a]);
-    for (int64_t r = b0; r < b0 + 7; ++r) {
-      for (int64_t c = 0; c < n; ++c) { H[r * n + c] = 0.0; H[c * n + r] = 0.0; }
-      H[r * n + r] = 1.0;
-      g[r] = 0.0;
-    }
-  }
-  *cost_out = cost;
-  if (count_out) *count_out = count;
+  scatter_blocks(acc, n_kf, ei, ej, n_edges, anchors, n_anchors, H, g, cost_out, count_out, edge_cost, edge_count);
   return 0;
 }
 
@@ -903,6 +1015,101 @@ int orc_edge_residuals(const double* pose_i, const double* pose_j, const double*
     ok_out[n] = 1;
   }
   return 0;
+}
+
+// ---- calibrated mode (Sec. IV-C) ----------------------------------------------------------------
+// As orc_gn_assemble with the calibrated residual: K (n_kf x 4: fx, fy, cx, cy) and kf_w (image width per
+// keyframe) are the supplied intrinsics; sigma_pix and sigma_logz whiten the pixel and log-depth rows.
+int orc_gn_assemble_cal(const double* poses, int n_kf, const int64_t* kf_off, const int64_t* kf_npx,
+                        const int32_t* kf_w, const double* K, const double* xyz, const double* conf, const int32_t* ei,
+                        const int32_t* ej, const int64_t* idx_off, int n_edges, const int32_t* idx,
+                        const int32_t* anchors, int n_anchors, const orc_gn_params* P, double sigma_pix,
+                        double sigma_logz, double* H, double* g, double* cost_out, int64_t* count_out,
+                        double* edge_cost, int64_t* edge_count) {
+  std::vector<EdgeAcc> acc(n_edges);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < n_edges; ++e) {
+    int i = ei[e], j = ej[e];
+    linearize_edge_cal(pose_to_mat(poses + 8 * i), pose_to_mat(poses + 8 * j), xyz + 3 * kf_off[j], conf + kf_off[j],
+                       kf_npx[j], kf_w[j], K + 4 * j, xyz + 3 * kf_off[i], conf + kf_off[i], kf_npx[i], kf_w[i],
+                       K + 4 * i, idx + idx_off[e], sigma_pix, sigma_logz, *P, acc[e]);
+  }
+  scatter_blocks(acc, n_kf, ei, ej, n_edges, anchors, n_anchors, H, g, cost_out, count_out, edge_cost, edge_count);
+  return 0;
+}
+
+// One Gauss-Newton/IRLS step in calibrated mode (assemble, ladder solve of eq. 7, left update).
+int orc_gn_step_cal(double* poses, int n_kf, const int64_t* kf_off, const int64_t* kf_npx, const int32_t* kf_w,
+                    const double* K, const double* xyz, const double* conf, const int32_t* ei, const int32_t* ej,
+                    const int64_t* idx_off, int n_edges, const int32_t* idx, const int32_t* anchors, int n_anchors,
+                    const orc_gn_params* P, double sigma_pix, double sigma_logz, double* cost_out,
+                    int32_t* status_out, double* tau_out) {
+  const int64_t n = 7 * int64_t(n_kf);
+  std::vector<double> H(n * n), g(n), tau(n);
+  orc_gn_assemble_cal(poses, n_kf, kf_off, kf_npx, kf_w, K, xyz, conf, ei, ej, idx_off, n_edges, idx, anchors,
+                      n_anchors, P, sigma_pix, sigma_logz, H.data(), g.data(), cost_out, nullptr, nullptr, nullptr);
+  int st = chol_ladder(H.data(), g.data(), int(n), P->lambda, P->eps0, P->eps_mult, P->max_attempts, tau.data());
+  std::vector<uint8_t> fixed(n_kf, 0);
+  for (int a = 0; a < n_anchors; ++a) fixed[anchors[a]] = 1;
+  orc_sim3_update(poses, tau.data(), n_kf, fixed.data());
+  if (status_out) *status_out = st;
+  if (tau_out) std::memcpy(tau_out, tau.data(), sizeof(double) * n);
+  return 0;
+}
+
+// Per pixel of j for one edge in calibrated mode: whitened residuals r (npx_j x 3), IRLS weights w
+// (npx_j x 3) and the validity flag.
+int orc_edge_residuals_cal(const double* pose_i, const double* pose_j, const double* xyz_j, const double* conf_j,
+                           int64_t npx_j, int Wj, const double* Kj, const double* xyz_i, const double* conf_i,
+                           int64_t npx_i, int Wi, const double* Ki, const int32_t* idx, const orc_gn_params* P,
+                           double sigma_pix, double sigma_logz, double* r_out, double* w_out, uint8_t* ok_out) {
+  M4 Tij = m4_mul(sim3_inverse_mat(pose_to_mat(pose_i)), pose_to_mat(pose_j));
+  const double sig[3] = {sigma_pix, sigma_pix, sigma_logz};
+  for (int64_t n = 0; n < npx_j; ++n) {
+    int32_t m = idx[n];
+    ok_out[n] = 0;
+    for (int c = 0; c < 3; ++c) { r_out[3 * n + c] = 0.0; w_out[3 * n + c] = 0.0; }
+    if (m < 0 || m >= npx_i) continue;
+    CalResidual R = cal_residual(Tij, xyz_j + 3 * n, n, Wj, Kj, xyz_i + 3 * int64_t(m), m, Wi, Ki, conf_i[m], conf_j[n]);
+    if (!R.ok) continue;
+    double sq = std::sqrt(R.q);
+    for (int c = 0; c < 3; ++c) {
+      r_out[3 * n + c] = sq * R.r[c] / sig[c];
+      w_out[3 * n + c] = huber_w(r_out[3 * n + c], P->huber_k);
+    }
+    ok_out[n] = 1;
+  }
+  return 0;
+}
+
+// E in calibrated mode at the given poses.
+double orc_cost_cal(const double* poses, int n_kf, const int64_t* kf_off, const int64_t* kf_npx, const int32_t* kf_w,
+                    const double* K, const double* xyz, const double* conf, const int32_t* ei, const int32_t* ej,
+                    const int64_t* idx_off, int n_edges, const int32_t* idx, const orc_gn_params* P, double sigma_pix,
+                    double sigma_logz) {
+  std::vector<double> ec(n_edges);
+  const double sig[3] = {sigma_pix, sigma_pix, sigma_logz};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int e = 0; e < n_edges; ++e) {
+    int i = ei[e], j = ej[e];
+    M4 Tij = m4_mul(sim3_inverse_mat(pose_to_mat(poses + 8 * i)), pose_to_mat(poses + 8 * j));
+    const int32_t* id = idx + idx_off[e];
+    double c = 0.0;
+    for (int64_t p = 0; p < kf_npx[j]; ++p) {
+      int32_t m = id[p];
+      if (m < 0 || m >= kf_npx[i]) continue;
+      CalResidual R = cal_residual(Tij, xyz + 3 * (kf_off[j] + p), p, kf_w[j], K + 4 * j,
+                                   xyz + 3 * (kf_off[i] + int64_t(m)), m, kf_w[i], K + 4 * i, conf[kf_off[i] + m],
+                                   conf[kf_off[j] + p]);
+      if (!R.ok) continue;
+      double sq = std::sqrt(R.q);
+      for (int k = 0; k < 3; ++k) c += huber_rho(sq * R.r[k] / sig[k], P->huber_k);
+    }
+    ec[e] = c;
+  }
+  double cost = 0.0;
+  for (int e = 0; e < n_edges; ++e) cost += ec[e];
+  return cost;
 }
 
 }  // extern "C"

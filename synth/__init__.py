@@ -252,6 +252,11 @@ class SynthGraph:
     def shape(self, k):
         return self.xyz[k].shape[:2]
 
+    def intrinsics(self) -> np.ndarray:
+        """(N, 4) float64 [fx, fy, cx, cy] per keyframe: the generator's pinhole cameras, the intrinsics a
+        caller supplies in calibrated mode."""
+        return np.array([[c.f, c.f, c.cx, c.cy] for c in self.cams], np.float64)
+
     def _in_cam(self, k, P):
         R, t, s = pose_parts(self.poses_gt[k])
         return (P - t) @ R / s          # canonical coordinates of camera k
