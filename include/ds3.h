@@ -74,10 +74,21 @@ typedef struct {
 
 /* Graph-step constants: sigma_r = 0.003, sigma_d = 10, Huber kappa = 1.345 (Sec. IV-A); eq. (7) damping
  * lambda (0 for the back-end) and the epsilon ladder eps_r = eps0 * eps_mult^r, r < max_attempts
- * (1e-6, 100, 6; text after eq. 7). */
+ * (1e-6, 100, 6; text after eq. 7).
+ * Calibrated mode (Sec. IV-C, "Calibration"): K != NULL (host, n_kf x 4 float64: fx, fy, cx, cy per
+ * keyframe, in the keyframe table's order) replaces the ray-range residual of eq. (1) by pixel
+ * reprojection and log-depth on the pointmaps constrained to the calibrated rays: for a match (m, n) of
+ * edge (i, j), Xcal_j[n] = z_j[n] K_j^-1 (u_n, v_n, 1) with z = the stored point's third coordinate,
+ * x = T_ij Xcal_j[n], r = (fx_i x0/x2 + cx_i - u_m, fy_i x1/x2 + cy_i - v_m, ln x2 - ln z_i[m]), whitened by
+ * sqrt(q)/sigma_pix and sqrt(q)/sigma_logz (q = sqrt(C_i C_j)), the same Huber kernel; matches with a
+ * hole, z_j[n] or z_i[m] <= 1e-9, or x2 <= 1e-9 are skipped. The paper prints no constants for this mode:
+ * sigma_pix = 1 px and sigma_logz = 0.1 are readings. Supported by ds3_gn_linearize, ds3_sim3_gn_step and
+ * the batched plan; the cost, adjoint and tracker calls return DS3_ENOTSUP when K is set. */
 typedef struct {
   double sigma_ray, sigma_dist, huber_k, lambda, eps0, eps_mult;
   int32_t max_attempts;
+  const double* K;
+  double sigma_pix, sigma_logz;
 } ds3_gn_params;
 
 void ds3_default_match_params(ds3_match_params* p);

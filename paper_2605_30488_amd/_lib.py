@@ -29,7 +29,8 @@ class MatchParams(C.Structure):
 class GNParams(C.Structure):
     _fields_ = [("sigma_ray", C.c_double), ("sigma_dist", C.c_double), ("huber_k", C.c_double),
                 ("lam", C.c_double), ("eps0", C.c_double), ("eps_mult", C.c_double),
-                ("max_attempts", C.c_int32)]
+                ("max_attempts", C.c_int32), ("K", C.POINTER(C.c_double)), ("sigma_pix", C.c_double),
+                ("sigma_logz", C.c_double)]
 
 
 class TrackParams(C.Structure):

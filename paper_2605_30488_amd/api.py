@@ -55,6 +55,21 @@ def default_gn_params() -> L.GNParams:
     return p
 
 
+def calibrated_gn_params(K, sigma_pix=1.0, sigma_logz=0.1, base: L.GNParams | None = None) -> L.GNParams:
+    """Graph-step constants of the calibrated mode (Sec. IV-C): K is (n_kf, 4) [fx, fy, cx, cy] per keyframe in
+    the arena's order. The returned struct keeps its own host copy of K alive."""
+    p = L.GNParams()
+    if base is None:
+        L.load().ds3_default_gn_params(C.byref(p))
+    else:
+        C.pointer(p)[0] = base
+    k = (C.c_double * (4 * len(K)))(*[float(v) for row in K for v in row])
+    p._K_keep = k
+    p.K = C.cast(k, C.POINTER(C.c_double))
+    p.sigma_pix, p.sigma_logz = float(sigma_pix), float(sigma_logz)
+    return p
+
+
 def version() -> int:
     return L.load().ds3_version()
 

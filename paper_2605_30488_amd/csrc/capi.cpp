@@ -74,7 +74,7 @@ struct Topology {
   int n_kf = 0, n_edges = 0, n_pairs = 0, total_tiles = 0, max_tiles = 0, tile_px = 0;
   std::vector<EdgeDev> edges;
   std::vector<int64_t> kf_off;
-  std::vector<int32_t> kf_npx, node_ptr, node_adj, pair_ptr, pair_edges, pair_ij;
+  std::vector<int32_t> kf_npx, kf_w, node_ptr, node_adj, pair_ptr, pair_edges, pair_ij;
   std::vector<uint8_t> anchor;
 };
 
@@ -88,11 +88,13 @@ static int build_topology(int n_kf, const ds3_image* kf, int n_edges, const ds3_
   T.tile_px = tile_px;
   T.kf_off.resize(n_kf);
   T.kf_npx.resize(n_kf);
+  T.kf_w.resize(n_kf);
   for (int k = 0; k < n_kf; ++k) {
     if (kf[k].H <= 0 || kf[k].W <= 0 || kf[k].px_offset < 0 || int64_t(kf[k].H) * kf[k].W > INT32_MAX)
       return fail(DS3_EINVAL, "bad keyframe image " + std::to_string(k));
     T.kf_off[k] = kf[k].px_offset;
     T.kf_npx[k] = kf[k].H * kf[k].W;
+    T.kf_w[k] = kf[k].W;
   }
   T.edges.resize(n_edges);
   T.total_tiles = 0;
@@ -249,7 +251,21 @@ static int check_gn_args(const double* poses, const void* arena, const int32_t* 
   if (!(p->sigma_ray > 0) || !(p->sigma_dist > 0) || !(p->huber_k > 0))
     return fail(DS3_EINVAL, "sigma and kappa must be positive");
   if (p->max_attempts < 1 || p->max_attempts > 16) return fail(DS3_EINVAL, "max_attempts out of range");
+  if (p->K && (!(p->sigma_pix > 0) || !(p->sigma_logz > 0)))
+    return fail(DS3_EINVAL, "calibrated mode: sigma_pix and sigma_logz must be positive");
   return DS3_OK;
+}
+
+// The calls without a calibrated form.
+static int no_calibrated(const ds3_gn_params* p, const char* what) {
+  if (p && p->K) return fail(DS3_ENOTSUP, std::string(what) + ": no calibrated mode (K must be NULL)");
+  return DS3_OK;
+}
+
+static int edge_cal_table(const ds3_gn_params& p, const Topology& T, std::vector<EdgeCal>& out) {
+  out.assign(std::max(T.n_edges, 1), EdgeCal{});
+  if (!p.K) return DS3_OK;
+  return make_edge_cal(p.K, T.n_kf, T.kf_w.data(), T.edges.data(), T.n_edges, out.data());
 }
 
 // Plain-form linearisation: prep, one residual launch per edge, finalize, assembly, cost sum.
@@ -258,9 +274,12 @@ static int gn_linearize_plain(const double* poses, const Topology& T, const GnBu
                               const ds3_gn_params& p, double* H, double* g, double* cost_out,
                               int64_t* count_out, hipStream_t s) {
   const GnConst c = make_gn_const(p);
+  std::vector<EdgeCal> cal;
+  DS3_TRY(edge_cal_table(p, T, cal));
   DS3_TRY(launch_gn_prep(poses, B.edges, T.n_edges, B.xf, B.Ad, s));
   for (int e = 0; e < T.n_edges; ++e)
-    DS3_TRY(launch_edge_reduce_one(dt, kPlainPPT, arena, T.edges[e], e, B.xf, idx, B.partials, c, s));
+    DS3_TRY(launch_edge_reduce_one(dt, kPlainPPT, arena, T.edges[e], e, B.xf, idx, B.partials, c, s,
+                                   p.K ? &cal[e] : nullptr));
   DS3_TRY(launch_edge_finalize(B.edges, T.n_edges, B.partials, B.Ad, B.A_e, B.b_e, B.cost_e, B.count_e, s));
   const size_t n = 7 * size_t(T.n_kf);
   DS3_TRY(launch_fill(H, n * n, 0.0, s));
@@ -300,6 +319,9 @@ void ds3_default_gn_params(ds3_gn_params* p) {
   p->eps0 = 1e-6;
   p->eps_mult = 100.0;
   p->max_attempts = 6;
+  p->K = nullptr;
+  p->sigma_pix = 1.0;
+  p->sigma_logz = 0.1;
 }
 
 const char* ds3_status_string(int code) {
@@ -418,6 +440,7 @@ int ds3_gn_cost(const double* poses, int32_t n_kf, const ds3_image* kf, const vo
                 const ds3_edge* edges, int32_t n_edges, const int32_t* idx, const ds3_gn_params* params,
                 double* cost_out, void* workspace, size_t ws_bytes, void* stream) {
   DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
+  DS3_TRY(no_calibrated(params, "gn_cost"));
   if (!cost_out || !workspace) return fail(DS3_EINVAL, "null output or workspace");
   Topology T;
   DS3_TRY(build_topology(n_kf, kf, n_edges, edges, nullptr, 0, kReduceThreads * kPlainPPT, T));
@@ -439,6 +462,7 @@ int ds3_gn_cost_adjoint(const double* poses, int32_t n_kf, const ds3_image* kf, 
                         double* grad_tau, ds3_timer* adjoint_timer, void* workspace, size_t ws_bytes,
                         void* stream) {
   DS3_TRY(check_gn_args(poses, arena, idx, dtype, params));
+  DS3_TRY(no_calibrated(params, "gn_cost_adjoint"));
   if (!grad_xyz || !grad_conf || !grad_tau || !workspace) return fail(DS3_EINVAL, "null output or workspace");
   Topology T;
   DS3_TRY(build_topology(n_kf, kf, n_edges, edges, nullptr, 0, kReduceThreads * kPlainPPT, T));
@@ -488,6 +512,7 @@ struct Plan {
   unsigned* hist_ctr = nullptr;
   unsigned* time_ctrs = nullptr;
   int64_t px_scanned = 0, px_valid = 0;
+  EdgeCal* ecal = nullptr;     // calibrated mode: per-edge intrinsics (device), else NULL
   bool use_graph = true;
   ds3_timer* timer = nullptr;
   hipGraph_t graph = nullptr;
@@ -499,7 +524,7 @@ static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
   DS3_TRY(launch_gn_prep(P.poses, P.B.edges, P.T.n_edges, P.B.xf, P.B.Ad, s));
   if (timed) DS3_TRY(timer_record(P.timer, true, s));
   DS3_TRY(launch_reduce_stream(P.dt, P.unroll, P.stream, P.seg_count, P.B.edges, P.items, P.n_items, P.B.xf,
-                               P.T.tile_px, P.B.partials, P.c, nullptr, s));
+                               P.T.tile_px, P.B.partials, P.c, nullptr, s, nullptr, nullptr, P.ecal));
   if (timed) DS3_TRY(timer_record(P.timer, false, s));
   DS3_TRY(launch_edge_finalize(P.B.edges, P.T.n_edges, P.B.partials, P.B.Ad, P.B.A_e, P.B.b_e, P.B.cost_e,
                                P.B.count_e, s));
@@ -559,7 +584,7 @@ static int plan_build_items(Plan& P, int ppt, hipStream_t s) {
   if (size_t(total) * size_t(tile_px) > P.stream_cap) return fail(DS3_EINVAL, "plan: stream larger than reserved");
   // gather the match stream for this segment size and read back how many records it holds
   DS3_TRY(launch_gather_stream(P.dt, P.arena, P.B.edges, P.items, P.n_items, P.idx, tile_px, P.stream,
-                               P.seg_count, s));
+                               P.seg_count, s, P.ecal));
   DS3_TRY_HIP(hipMemcpyAsync(counts.data(), P.seg_count, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
   DS3_TRY_HIP(hipStreamSynchronize(s));
   P.n_records = 0;
@@ -576,7 +601,7 @@ static int plan_time_reduce(Plan& P, int reps, float* ms, hipStream_t s) {
   int rc = check_hip(hipEventRecord(a, s), "hipEventRecord");
   for (int r = 0; r < reps && rc == DS3_OK; ++r)
     rc = launch_reduce_stream(P.dt, P.unroll, P.stream, P.seg_count, P.B.edges, P.items, P.n_items, P.B.xf,
-                              P.T.tile_px, P.B.partials, P.c, nullptr, s);
+                              P.T.tile_px, P.B.partials, P.c, nullptr, s, nullptr, nullptr, P.ecal);
   if (rc == DS3_OK) rc = check_hip(hipEventRecord(b, s), "hipEventRecord");
   if (rc == DS3_OK) rc = check_hip(hipEventSynchronize(b), "hipEventSynchronize");
   float t = 0.f;
@@ -595,7 +620,8 @@ static std::string tune_key(const Plan& P) {
   std::map<std::pair<int, int>, int> shapes;
   for (auto& E : P.T.edges) shapes[{E.npx_j, E.npx_i}]++;
   std::ostringstream k;
-  k << prop.gcnArchName << "|stream|" << (P.dt == DS3_F32 ? "f32" : "bf16") << "|cu" << prop.multiProcessorCount;
+  k << prop.gcnArchName << "|stream|" << (P.dt == DS3_F32 ? "f32" : "bf16") << (P.ecal ? "|cal" : "") << "|cu"
+    << prop.multiProcessorCount;
   for (auto& kv : shapes) k << "|" << kv.first.first << "x" << kv.first.second;
   return k.str();
 }
@@ -687,6 +713,7 @@ static void plan_free(Plan* P) {
   if (P->time_ctrs) (void)hipFree(P->time_ctrs);
   if (P->stream) (void)hipFree(P->stream);
   if (P->seg_count) (void)hipFree(P->seg_count);
+  if (P->ecal) (void)hipFree(P->ecal);
   delete P;
 }
 
@@ -765,8 +792,15 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
     P->stream_cap = std::max(P->stream_cap, cap);
   }
   if (rc == DS3_OK)
-    rc = check_hip(hipMalloc(&P->stream, std::max<size_t>(P->stream_cap, 1) * stream_record_bytes(dtype)),
+    rc = check_hip(hipMalloc(&P->stream, std::max<size_t>(P->stream_cap, 1) * stream_record_bytes(dtype, params->K)),
                    "hipMalloc(match stream)");
+  if (rc == DS3_OK && params->K) {
+    std::vector<EdgeCal> cal;
+    rc = edge_cal_table(*params, P->T, cal);
+    if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->ecal, sizeof(EdgeCal) * cal.size()), "hipMalloc(intrinsics)");
+    if (rc == DS3_OK) rc = upload(P->ecal, cal, s);
+    if (rc == DS3_OK) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize(intrinsics)");
+  }
   if (rc == DS3_OK)
     rc = check_hip(hipMalloc(&P->seg_count, sizeof(int32_t) * std::max(P->T.total_tiles, 1)), "hipMalloc");
   P->reserved_tiles = P->T.total_tiles;
@@ -777,6 +811,7 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
   P->poses = poses;
   P->dt = dtype;
   P->p = *params;
+  P->p.K = nullptr;  // the caller's intrinsics were copied into ecal; the plan keeps no host pointer
   P->c = make_gn_const(*params);
   P->use_graph = !opts || opts->use_graph != 0;
   P->timer = opts ? opts->reduce_timer : nullptr;
@@ -855,7 +890,7 @@ int ds3_gn_plan_info(void* plan, int64_t* info, int32_t n_info) {
   Plan* P = static_cast<Plan*>(plan);
   if (!P || !info || n_info < 0) return fail(DS3_EINVAL, "plan_info: bad arguments");
   const int64_t px_bytes = P->dt == DS3_F32 ? 16 : 8;
-  const int64_t rec = int64_t(stream_record_bytes(P->dt));
+  const int64_t rec = int64_t(stream_record_bytes(P->dt, P->ecal != nullptr));
   const int64_t v[8] = {P->n_items, P->ppt, P->px_scanned, P->px_valid,
                         4 * P->px_scanned + 2 * px_bytes * P->px_valid,
                         rec * P->n_records + 4 * int64_t(P->n_items),
@@ -869,7 +904,7 @@ int ds3_gn_plan_refresh(void* plan, void* stream) {
   Plan* P = static_cast<Plan*>(plan);
   if (!P) return fail(DS3_EINVAL, "plan_refresh: null plan");
   return launch_gather_stream(P->dt, P->arena, P->B.edges, P->items, P->n_items, P->idx, P->T.tile_px, P->stream,
-                              P->seg_count, S(stream));
+                              P->seg_count, S(stream), P->ecal);
 }
 
 int ds3_tune_cache_reset(void) {
@@ -946,6 +981,7 @@ int ds3_adjoint_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena
   *plan_out = nullptr;
   static const double kNotPoses = 0.0;  // the plan takes its poses at run time
   DS3_TRY(check_gn_args(&kNotPoses, arena, idx, dtype, params));
+  DS3_TRY(no_calibrated(params, "adjoint_plan"));
   DS3_TRY(check_arch());
   hipStream_t s = S(stream);
   AdjPlan* A = new AdjPlan();

@@ -11,6 +11,16 @@
 // reduces only the 28 unique entries of H_L, the 7 of b_L = J_x^T W e, the cost and the count per tile.
 // J_x = [[P/d, -[psi]x, 0], [psi^T, 0, d]] (P = I - psi psi^T) has structural zeros that the
 // accumulation skips: column 6 of the ray rows, column 3+c of ray row c, columns 3-5 of the range row.
+//
+// Calibrated mode (Sec. IV-C, "Calibration"): the same reduction of J_x^T W J_x with the pixel
+// reprojection and log-depth residual on the pointmaps constrained to the calibrated rays; with
+// iz = 1/x2, px = x0 iz, py = x1 iz, J_x = (dr/dx) [I  -[x]x  x] has the rows
+//   u: [fx iz, 0, -fx px iz, -fx px py, fx (1 + px^2), -fx py, 0]
+//   v: [0, fy iz, -fy py iz, -fy (1 + py^2), fy px py, fy px, 0]
+//   z: [0, 0, iz, py, -px, 0, 1]            (the pixel rows do not see the scale)
+#include <cmath>
+#include <string>
+
 #include "common.hpp"
 #include "internal.hpp"
 #include "sim3.hpp"
@@ -27,6 +37,11 @@ GnConst make_gn_const(const ds3_gn_params& p) {
   c.inv_sr_d = 1.0 / p.sigma_ray;
   c.inv_sd_d = 1.0 / p.sigma_dist;
   c.kappa_d = p.huber_k;
+  const double sp = p.sigma_pix > 0 ? p.sigma_pix : 1.0, sz = p.sigma_logz > 0 ? p.sigma_logz : 1.0;
+  c.inv_sp = float(1.0 / sp);
+  c.inv_sz = float(1.0 / sz);
+  c.inv_sp2 = float(1.0 / (sp * sp));
+  c.inv_sz2 = float(1.0 / (sz * sz));
   return c;
 }
 
@@ -206,6 +221,89 @@ __device__ inline bool acc_pixel(Acc& a, const float4 Xj, const float4 Xi, const
   return true;
 }
 
+// One residual row J (7 entries, nonzero only where MASK has a bit) with weight W and residual e:
+// H_L += W J^T J (upper triangle), b_L += W J^T e.
+template <unsigned MASK>
+__device__ inline void acc_row(Acc& a, const float* J, float W, float e) {
+  float wj[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) wj[k] = ((MASK >> k) & 1u) ? W * J[k] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 7; ++r) {
+    if (!((MASK >> r) & 1u)) continue;
+#pragma unroll
+    for (int c = r; c < 7; ++c) {
+      if (!((MASK >> c) & 1u)) continue;
+      a.h[HIDX(r, c)] = fmaf(wj[r], J[c], a.h[HIDX(r, c)]);
+    }
+    a.b[r] = fmaf(wj[r], e, a.b[r]);
+  }
+}
+
+// Calibrated mode, one match after its checks: x = T_ij Xcal_j (x2 > 0), target pixel (um, vm) of keyframe
+// i and izm = 1/z_i[m], sq = (C_i C_j)^(1/4), K_i = (fx, fy, cx, cy).
+__device__ inline void acc_core_cal(Acc& a, float x0, float x1, float x2, float um, float vm, float izm, float sq,
+                                    const float4 Ki, const GnConst& k) {
+  const float iz = __builtin_amdgcn_rcpf(x2);
+  const float px = x0 * iz, py = x1 * iz;
+  const float e0 = fmaf(Ki.x, px, Ki.z) - um;
+  const float e1 = fmaf(Ki.y, py, Ki.w) - vm;
+  const float e2 = logf(x2 * izm);
+  const float q = sq * sq;
+  const float sp = sq * k.inv_sp;
+  const float r0 = sp * e0, r1 = sp * e1, r2 = sq * k.inv_sz * e2;
+  const float a0 = fabsf(r0), a1 = fabsf(r1), a2 = fabsf(r2);
+  const float w0 = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a0));
+  const float w1 = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a1));
+  const float w2 = fminf(1.0f, k.kappa * __builtin_amdgcn_rcpf(a2));
+  const float t0 = w0 * a0, t1 = w1 * a1, t2 = w2 * a2;
+  a.cost += t0 * fmaf(-0.5f, t0, a0) + t1 * fmaf(-0.5f, t1, a1) + t2 * fmaf(-0.5f, t2, a2);
+  a.cnt += 1.0f;
+  const float qp = q * k.inv_sp2;
+  const float fx = Ki.x, fy = Ki.y;
+  {
+    const float J[7] = {fx * iz, 0.0f, -fx * px * iz, -fx * px * py, fmaf(fx * px, px, fx), -fx * py, 0.0f};
+    acc_row<0x3Du>(a, J, w0 * qp, e0);
+  }
+  {
+    const float J[7] = {0.0f, fy * iz, -fy * py * iz, -fmaf(fy * py, py, fy), fy * px * py, fy * px, 0.0f};
+    acc_row<0x3Eu>(a, J, w1 * qp, e1);
+  }
+  {
+    const float J[7] = {0.0f, 0.0f, iz, py, -px, 0.0f, 1.0f};
+    acc_row<0x5Cu>(a, J, w2 * q * k.inv_sz2, e2);
+  }
+}
+
+// Pose-independent checks of the calibrated mode: no hole, a non-negative finite confidence product and
+// both depths above 1e-9.
+__device__ inline bool cal_static_ok(const float4 Xj, const float4 Xi, float& sq) {
+  float dj2, di2;
+  if (!match_static_ok(Xj, Xi, dj2, di2, sq)) return false;
+  return Xj.z > 1e-9f && Xi.z > 1e-9f;
+}
+
+// The calibrated point of pixel n of keyframe j: z_j (u_n - cx_j, v_n - cy_j) / (fx_j, fy_j), z_j.
+__device__ inline void cal_point(float zj, int n, const EdgeCal& C, float& X0, float& X1) {
+  const int vn = n / C.Wj, un = n - vn * C.Wj;
+  X0 = zj * ((float(un) - C.cxj) * C.ifxj);
+  X1 = zj * ((float(vn) - C.cyj) * C.ifyj);
+}
+
+// Plain form, calibrated mode: one match (n of j, m of i) from the two arena entries.
+__device__ inline void acc_pixel_cal(Acc& a, const float4 Xj, const float4 Xi, int n, int m, const float* M,
+                                     const EdgeCal& C, const GnConst& k) {
+  float sq;
+  if (!cal_static_ok(Xj, Xi, sq)) return;
+  float X0, X1;
+  cal_point(Xj.z, n, C, X0, X1);
+  float x0, x1, x2;
+  transform(M, X0, X1, Xj.z, x0, x1, x2);
+  if (!(x2 > 1e-9f) || !(x2 < __builtin_huge_valf()) || !isfinite(x0) || !isfinite(x1)) return;
+  const int vm = m / C.Wi, um = m - vm * C.Wi;
+  acc_core_cal(a, x0, x1, x2, float(um), float(vm), 1.0f / Xi.z, sq, make_float4(C.fxi, C.fyi, C.cxi, C.cyi), k);
+}
+
 // Block reduction of the 37 accumulators in a fixed order; threads 0..36 write the tile partial.
 __device__ inline void acc_block_store(Acc& a, float* __restrict__ out, float (*lds)[37]) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -238,9 +336,10 @@ constexpr int kRounds = 1;   // rounds of 64 matches per drain batch (2 gathers 
 constexpr int kQueue = 512;  // >= 64 * (kScanU + kRounds), a power of two
 static_assert(kQueue >= 64 * (kScanU + kRounds) && (kQueue & (kQueue - 1)) == 0, "queue size");
 
-template <int DT>
+template <int DT, int MODE>
 __device__ inline void drain_rounds(Acc& a, const void* __restrict__ arena, const EdgeDev& E, const int2* q,
-                                    unsigned& head, unsigned avail, const float* M, const GnConst& k) {
+                                    unsigned& head, unsigned avail, const float* M, const GnConst& k,
+                                    const EdgeCal& C) {
   using raw_t = typename Px<DT>::raw_t;
   const int lane = threadIdx.x & (kWave - 1);
   int2 e[kRounds];
@@ -259,15 +358,20 @@ __device__ inline void drain_rounds(Acc& a, const void* __restrict__ arena, cons
     }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r)
-    if (ok[r]) acc_pixel(a, Px<DT>::unpack(rj[r]), Px<DT>::unpack(ri[r]), M, k);
+    if (ok[r]) {
+      if constexpr (MODE == kCalibrated)
+        acc_pixel_cal(a, Px<DT>::unpack(rj[r]), Px<DT>::unpack(ri[r]), e[r].x, e[r].y, M, C, k);
+      else
+        acc_pixel(a, Px<DT>::unpack(rj[r]), Px<DT>::unpack(ri[r]), M, k);
+    }
   head += min(avail, unsigned(kRounds * kWave));
 }
 
-template <int DT, int PPT>
+template <int DT, int PPT, int MODE>
 __device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev& E, int tile,
                                    const float* M, const int32_t* __restrict__ idx_arena,
                                    float* __restrict__ out, const GnConst& k, float (*lds)[37],
-                                   int2* __restrict__ queue) {
+                                   int2* __restrict__ queue, const EdgeCal& C) {
   static_assert(PPT % kScanU == 0, "pixels per thread must be a multiple of the scan unroll");
   Acc a;
   acc_zero(a);
@@ -305,24 +409,25 @@ __device__ inline void reduce_tile(const void* __restrict__ arena, const EdgeDev
     }
     if (k0 + kScanU < PPT) load_matches(k0 + kScanU, m);
     __builtin_amdgcn_wave_barrier();  // the wave's queue writes are ordered before its reads
-    while (tail - head >= unsigned(kRounds * kWave)) drain_rounds<DT>(a, arena, E, q, head, kRounds * kWave, M, k);
+    while (tail - head >= unsigned(kRounds * kWave))
+      drain_rounds<DT, MODE>(a, arena, E, q, head, kRounds * kWave, M, k, C);
   }
-  while (tail != head) drain_rounds<DT>(a, arena, E, q, head, tail - head, M, k);
+  while (tail != head) drain_rounds<DT, MODE>(a, arena, E, q, head, tail - head, M, k, C);
   acc_block_store(a, out, lds);
 }
 
 // Plain form: one launch per edge, one block per tile.
-template <int DT, int PPT>
+template <int DT, int PPT, int MODE>
 __global__ __launch_bounds__(kReduceThreads) void k_edge_reduce_one(
     const void* __restrict__ arena, EdgeDev E, int edge_id, const EdgeXf* __restrict__ xf,
-    const int32_t* __restrict__ idx_arena, float* __restrict__ partials, GnConst k) {
+    const int32_t* __restrict__ idx_arena, float* __restrict__ partials, GnConst k, EdgeCal C) {
   __shared__ float lds[kReduceThreads / kWave][37];
   __shared__ int2 queue[kReduceThreads / kWave * kQueue];
   float M[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) M[q] = xf[edge_id].m[q];
-  reduce_tile<DT, PPT>(arena, E, blockIdx.x, M, idx_arena,
-                       partials + int64_t(E.tile0 + blockIdx.x) * kPartial, k, lds, queue);
+  reduce_tile<DT, PPT, MODE>(arena, E, blockIdx.x, M, idx_arena,
+                             partials + int64_t(E.tile0 + blockIdx.x) * kPartial, k, lds, queue, C);
 }
 
 // --------------------------------------------------------------------------------------------------
@@ -403,16 +508,19 @@ constexpr int kGatherUnroll = 4;  // 256-pixel chunks whose loads are issued tog
 
 // One block per segment: scans the segment's matches in pixel order, keeps those that pass the
 // pose-independent checks and writes their records compacted (order-preserving: ballot ranks within a
-// wave, wave totals through LDS), then the count.
-template <int DT>
+// wave, wave totals through LDS), then the count. Calibrated mode (MODE == kCalibrated, ecal per edge):
+// float32 records of the calibrated point Xcal_j[n] and the target (u_m, v_m, 1/z_i[m]).
+template <int DT, int MODE>
 __global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __restrict__ arena,
                                                                   const EdgeDev* __restrict__ edges,
                                                                   const WorkItem* __restrict__ items,
                                                                   const int32_t* __restrict__ idx_arena,
                                                                   int seg_px, void* __restrict__ stream,
-                                                                  int32_t* __restrict__ seg_count) {
+                                                                  int32_t* __restrict__ seg_count,
+                                                                  const EdgeCal* __restrict__ ecal) {
   using raw_t = typename Px<DT>::raw_t;
-  using rec_t = typename Rec<DT>::raw_t;
+  constexpr int RDT = MODE == kCalibrated ? int(DS3_F32) : DT;
+  using rec_t = typename Rec<RDT>::raw_t;
   __shared__ int s_tot[kGatherUnroll][kReduceThreads / kWave];
   const WorkItem W = items[blockIdx.x];
   const EdgeDev E = edges[W.edge];
@@ -422,6 +530,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __
   const int64_t base = int64_t(W.tile) * seg_px;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
+  EdgeCal C{};
+  if constexpr (MODE == kCalibrated) C = ecal[W.edge];
   int running = 0;  // block-uniform
   for (int c0 = 0; c0 < seg_px; c0 += kReduceThreads * kGatherUnroll) {
     int32_t m[kGatherUnroll];
@@ -448,8 +558,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __
       ok[u] = false;
       sq[u] = 0.0f;
       if (m[u] >= 0) {
-        float dj2, di2;
-        ok[u] = match_static_ok(Px<DT>::unpack(rj[u]), Px<DT>::unpack(ri[u]), dj2, di2, sq[u]);
+        if constexpr (MODE == kCalibrated) {
+          ok[u] = cal_static_ok(Px<DT>::unpack(rj[u]), Px<DT>::unpack(ri[u]), sq[u]);
+        } else {
+          float dj2, di2;
+          ok[u] = match_static_ok(Px<DT>::unpack(rj[u]), Px<DT>::unpack(ri[u]), dj2, di2, sq[u]);
+        }
       }
       const uint64_t ballot = __ballot(ok[u]);
       rank[u] = __builtin_amdgcn_mbcnt_hi(uint32_t(ballot >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(ballot), 0u));
@@ -464,7 +578,20 @@ __global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __
         if (w < wave) off += t;
         running += t;
       }
-      if (ok[u]) out[off + int(rank[u])] = make_rec<DT>(rj[u], ri[u], sq[u]);
+      if (ok[u]) {
+        if constexpr (MODE == kCalibrated) {
+          const int n = int(base + c0 + u * kReduceThreads + threadIdx.x);
+          const float4 Xj = Px<DT>::unpack(rj[u]), Xi = Px<DT>::unpack(ri[u]);
+          float X0, X1;
+          cal_point(Xj.z, n, C, X0, X1);
+          const int vm = m[u] / C.Wi, um = m[u] - vm * C.Wi;
+          // record: (X0, X1, z_j, u_m), (v_m, 1/z_i[m], sq, 0)
+          out[off + int(rank[u])] = Rec<DS3_F32>::make(make_float4(X0, X1, Xj.z, 0.0f),
+                                                       make_float4(float(um), float(vm), 1.0f / Xi.z, 0.0f), sq[u]);
+        } else {
+          out[off + int(rank[u])] = make_rec<DT>(rj[u], ri[u], sq[u]);
+        }
+      }
     }
     __syncthreads();  // s_tot is rewritten by the next chunk
   }
@@ -497,7 +624,8 @@ __device__ inline double cost_f64(const double* T, const float* xj, const float*
 // as in the plain form, reduced over the block in a fixed order into the segment's partial. Segments of
 // edges flagged in skip (may be NULL) are left alone. C64: the segment's cost is also evaluated in float64
 // at the float64 transform xf64[edge] (12 doubles, sR row-major then t) and written to cost64[segment].
-template <int DT, int U, bool C64>
+// MODE == kCalibrated: float32 records of the calibrated mode (DT must be DS3_F32), K_i from ecal[edge].
+template <int DT, int U, bool C64, int MODE>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __restrict__ stream,
                                                                   const int32_t* __restrict__ seg_count,
                                                                   const EdgeDev* __restrict__ edges,
@@ -506,7 +634,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
                                                                   float* __restrict__ partials, GnConst k,
                                                                   const int32_t* __restrict__ skip,
                                                                   const double* __restrict__ xf64,
-                                                                  double* __restrict__ cost64) {
+                                                                  double* __restrict__ cost64,
+                                                                  const EdgeCal* __restrict__ ecal) {
+  static_assert(MODE == kRayRange || (DT == DS3_F32 && !C64), "calibrated records are float32, no float64 cost");
   using rec_t = typename Rec<DT>::raw_t;
   __shared__ float lds[kReduceThreads / kWave][37];
   __shared__ double lds64[kReduceThreads / kWave];
@@ -521,6 +651,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
   if constexpr (C64) {
 #pragma unroll
     for (int q = 0; q < 12; ++q) M64[q] = xf64[12 * int64_t(W.edge) + q];
+  }
+  float4 Ki = make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (MODE == kCalibrated) {
+    const EdgeCal C = ecal[W.edge];
+    Ki = make_float4(C.fxi, C.fyi, C.cxi, C.cyi);
   }
   double c64 = 0.0;
   const rec_t* __restrict__ in = static_cast<const rec_t*>(stream) + int64_t(seg) * seg_px;
@@ -543,11 +678,17 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
         Rec<DT>::unpack(r[u], xj, xi, sq);
         float x0, x1, x2;
         transform(M, xj[0], xj[1], xj[2], x0, x1, x2);
-        const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
-        if (d2 > 1e-18f && d2 < __builtin_huge_valf()) {
-          const float di2 = fmaf(xi[0], xi[0], fmaf(xi[1], xi[1], xi[2] * xi[2]));
-          acc_core(a, x0, x1, x2, d2, xi[0], xi[1], xi[2], di2, sq, k);
-          if constexpr (C64) c64 += cost_f64(M64, xj, xi, sq, k);
+        if constexpr (MODE == kCalibrated) {
+          // xi holds the target (u_m, v_m, 1/z_i[m])
+          if (x2 > 1e-9f && x2 < __builtin_huge_valf() && isfinite(x0) && isfinite(x1))
+            acc_core_cal(a, x0, x1, x2, xi[0], xi[1], xi[2], sq, Ki, k);
+        } else {
+          const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+          if (d2 > 1e-18f && d2 < __builtin_huge_valf()) {
+            const float di2 = fmaf(xi[0], xi[0], fmaf(xi[1], xi[1], xi[2] * xi[2]));
+            acc_core(a, x0, x1, x2, d2, xi[0], xi[1], xi[2], di2, sq, k);
+            if constexpr (C64) c64 += cost_f64(M64, xj, xi, sq, k);
+          }
         }
       }
     }
@@ -566,33 +707,43 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
   }
 }
 
-size_t stream_record_bytes(ds3_dtype dt) {
-  return dt == DS3_F32 ? sizeof(Rec<DS3_F32>::raw_t) : sizeof(Rec<DS3_BF16>::raw_t);
+size_t stream_record_bytes(ds3_dtype dt, bool calibrated) {
+  return (dt == DS3_F32 || calibrated) ? sizeof(Rec<DS3_F32>::raw_t) : sizeof(Rec<DS3_BF16>::raw_t);
 }
 
 int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, const WorkItem* items,
                          int n_items, const int32_t* idx_arena, int seg_px, void* stream, int32_t* seg_count,
-                         hipStream_t s) {
+                         hipStream_t s, const EdgeCal* ecal) {
   if (n_items <= 0) return DS3_OK;
-  if (dt == DS3_F32)
-    hipLaunchKernelGGL(k_gather_stream<DS3_F32>, dim3(n_items), dim3(kReduceThreads), 0, s, arena, edges, items,
-                       idx_arena, seg_px, stream, seg_count);
-  else
-    hipLaunchKernelGGL(k_gather_stream<DS3_BF16>, dim3(n_items), dim3(kReduceThreads), 0, s, arena, edges, items,
-                       idx_arena, seg_px, stream, seg_count);
+  dim3 g(n_items), b(kReduceThreads);
+  if (ecal) {
+    if (dt == DS3_F32)
+      hipLaunchKernelGGL((k_gather_stream<DS3_F32, kCalibrated>), g, b, 0, s, arena, edges, items, idx_arena, seg_px,
+                         stream, seg_count, ecal);
+    else
+      hipLaunchKernelGGL((k_gather_stream<DS3_BF16, kCalibrated>), g, b, 0, s, arena, edges, items, idx_arena, seg_px,
+                         stream, seg_count, ecal);
+  } else {
+    if (dt == DS3_F32)
+      hipLaunchKernelGGL((k_gather_stream<DS3_F32, kRayRange>), g, b, 0, s, arena, edges, items, idx_arena, seg_px,
+                         stream, seg_count, nullptr);
+    else
+      hipLaunchKernelGGL((k_gather_stream<DS3_BF16, kRayRange>), g, b, 0, s, arena, edges, items, idx_arena, seg_px,
+                         stream, seg_count, nullptr);
+  }
   return check_hip(hipGetLastError(), "k_gather_stream");
 }
 
-template <int DT, bool C64>
+template <int DT, bool C64, int MODE>
 static int launch_reduce_stream_dt(int unroll, const void* stream, const int32_t* seg_count, const EdgeDev* edges,
                                    const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
                                    float* partials, GnConst c, const int32_t* skip, const double* xf64,
-                                   double* cost64, hipStream_t s) {
+                                   double* cost64, const EdgeCal* ecal, hipStream_t s) {
   dim3 g(n_items), b(kReduceThreads);
   switch (unroll) {
-    case 1: hipLaunchKernelGGL((k_reduce_stream<DT, 1, C64>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64); break;
-    case 2: hipLaunchKernelGGL((k_reduce_stream<DT, 2, C64>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64); break;
-    case 4: hipLaunchKernelGGL((k_reduce_stream<DT, 4, C64>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64); break;
+    case 1: hipLaunchKernelGGL((k_reduce_stream<DT, 1, C64, MODE>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64, ecal); break;
+    case 2: hipLaunchKernelGGL((k_reduce_stream<DT, 2, C64, MODE>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64, ecal); break;
+    case 4: hipLaunchKernelGGL((k_reduce_stream<DT, 4, C64, MODE>), g, b, 0, s, stream, seg_count, edges, items, xf, seg_px, partials, c, skip, xf64, cost64, ecal); break;
     default: return fail(DS3_EINVAL, "unsupported stream unroll");
   }
   return check_hip(hipGetLastError(), "k_reduce_stream");
@@ -601,29 +752,37 @@ static int launch_reduce_stream_dt(int unroll, const void* stream, const int32_t
 int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
                          const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
                          float* partials, GnConst c, const int32_t* skip, hipStream_t s, const double* xf64,
-                         double* cost64) {
+                         double* cost64, const EdgeCal* ecal) {
   if (n_items <= 0) return DS3_OK;
   if ((xf64 == nullptr) != (cost64 == nullptr)) return fail(DS3_EINVAL, "float64 cost needs both buffers");
+  if (ecal) {
+    if (xf64) return fail(DS3_ENOTSUP, "calibrated mode has no float64 cost");
+    return launch_reduce_stream_dt<DS3_F32, false, kCalibrated>(unroll, stream, seg_count, edges, items, n_items, xf,
+                                                                seg_px, partials, c, skip, nullptr, nullptr, ecal, s);
+  }
   if (dt == DS3_F32)
-    return xf64 ? launch_reduce_stream_dt<DS3_F32, true>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
-                                                         partials, c, skip, xf64, cost64, s)
-                : launch_reduce_stream_dt<DS3_F32, false>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
-                                                          partials, c, skip, nullptr, nullptr, s);
-  return xf64 ? launch_reduce_stream_dt<DS3_BF16, true>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
-                                                        partials, c, skip, xf64, cost64, s)
-              : launch_reduce_stream_dt<DS3_BF16, false>(unroll, stream, seg_count, edges, items, n_items, xf, seg_px,
-                                                         partials, c, skip, nullptr, nullptr, s);
+    return xf64 ? launch_reduce_stream_dt<DS3_F32, true, kRayRange>(unroll, stream, seg_count, edges, items, n_items,
+                                                                    xf, seg_px, partials, c, skip, xf64, cost64,
+                                                                    nullptr, s)
+                : launch_reduce_stream_dt<DS3_F32, false, kRayRange>(unroll, stream, seg_count, edges, items, n_items,
+                                                                     xf, seg_px, partials, c, skip, nullptr, nullptr,
+                                                                     nullptr, s);
+  return xf64 ? launch_reduce_stream_dt<DS3_BF16, true, kRayRange>(unroll, stream, seg_count, edges, items, n_items, xf,
+                                                                   seg_px, partials, c, skip, xf64, cost64, nullptr, s)
+              : launch_reduce_stream_dt<DS3_BF16, false, kRayRange>(unroll, stream, seg_count, edges, items, n_items,
+                                                                    xf, seg_px, partials, c, skip, nullptr, nullptr,
+                                                                    nullptr, s);
 }
 
-template <int DT>
+template <int DT, int MODE>
 static int launch_one_dt(int ppt, const void* arena, const EdgeDev& e, int edge_id, const EdgeXf* xf,
-                         const int32_t* idx, float* partials, GnConst c, hipStream_t s) {
+                         const int32_t* idx, float* partials, GnConst c, const EdgeCal& C, hipStream_t s) {
   dim3 grid(e.n_tiles), block(kReduceThreads);
   switch (ppt) {
-    case 4: hipLaunchKernelGGL((k_edge_reduce_one<DT, 4>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
-    case 8: hipLaunchKernelGGL((k_edge_reduce_one<DT, 8>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
-    case 16: hipLaunchKernelGGL((k_edge_reduce_one<DT, 16>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
-    case 32: hipLaunchKernelGGL((k_edge_reduce_one<DT, 32>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c); break;
+    case 4: hipLaunchKernelGGL((k_edge_reduce_one<DT, 4, MODE>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c, C); break;
+    case 8: hipLaunchKernelGGL((k_edge_reduce_one<DT, 8, MODE>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c, C); break;
+    case 16: hipLaunchKernelGGL((k_edge_reduce_one<DT, 16, MODE>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c, C); break;
+    case 32: hipLaunchKernelGGL((k_edge_reduce_one<DT, 32, MODE>), grid, block, 0, s, arena, e, edge_id, xf, idx, partials, c, C); break;
     default: return fail(DS3_EINVAL, "unsupported pixels-per-thread");
   }
   return check_hip(hipGetLastError(), "k_edge_reduce_one");
@@ -631,10 +790,42 @@ static int launch_one_dt(int ppt, const void* arena, const EdgeDev& e, int edge_
 
 int launch_edge_reduce_one(ds3_dtype dt, int ppt, const void* arena, const EdgeDev& e, int edge_id,
                            const EdgeXf* xf, const int32_t* idx_arena, float* partials, GnConst c,
-                           hipStream_t s) {
+                           hipStream_t s, const EdgeCal* cal) {
   if (e.n_tiles <= 0) return DS3_OK;
-  if (dt == DS3_F32) return launch_one_dt<DS3_F32>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, s);
-  return launch_one_dt<DS3_BF16>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, s);
+  const EdgeCal C = cal ? *cal : EdgeCal{};
+  if (cal) {
+    if (dt == DS3_F32) return launch_one_dt<DS3_F32, kCalibrated>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, C, s);
+    return launch_one_dt<DS3_BF16, kCalibrated>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, C, s);
+  }
+  if (dt == DS3_F32) return launch_one_dt<DS3_F32, kRayRange>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, C, s);
+  return launch_one_dt<DS3_BF16, kRayRange>(ppt, arena, e, edge_id, xf, idx_arena, partials, c, C, s);
+}
+
+int make_edge_cal(const double* K, int n_kf, const int32_t* kf_w, const EdgeDev* edges, int n_edges, EdgeCal* out) {
+  for (int k = 0; k < n_kf; ++k) {
+    const double* q = K + 4 * k;
+    if (!(q[0] > 0) || !(q[1] > 0) || !std::isfinite(q[0]) || !std::isfinite(q[1]) || !std::isfinite(q[2]) ||
+        !std::isfinite(q[3]))
+      return fail(DS3_EINVAL, "calibrated mode: bad intrinsics of keyframe " + std::to_string(k));
+  }
+  for (int e = 0; e < n_edges; ++e) {
+    const double* Ki = K + 4 * edges[e].i;
+    const double* Kj = K + 4 * edges[e].j;
+    EdgeCal C;
+    C.fxi = float(Ki[0]);
+    C.fyi = float(Ki[1]);
+    C.cxi = float(Ki[2]);
+    C.cyi = float(Ki[3]);
+    C.ifxj = float(1.0 / Kj[0]);
+    C.ifyj = float(1.0 / Kj[1]);
+    C.cxj = float(Kj[2]);
+    C.cyj = float(Kj[3]);
+    C.Wi = kf_w[edges[e].i];
+    C.Wj = kf_w[edges[e].j];
+    C.pad0 = C.pad1 = 0;
+    out[e] = C;
+  }
+  return DS3_OK;
 }
 
 // --------------------------------------------------------------------------------------------------

@@ -71,7 +71,25 @@ struct EdgeXf {
 struct GnConst {
   float inv_sr, inv_sd, inv_sr2, inv_sd2, kappa;
   double inv_sr_d, inv_sd_d, kappa_d;  // the same constants in float64 (float64 cost evaluation)
+  float inv_sp, inv_sz, inv_sp2, inv_sz2;  // calibrated mode: 1/sigma_pix, 1/sigma_logz and their squares
 };
+
+// Residual of the graph step: the ray-range residual of eq. (1), or the calibrated mode's pixel
+// reprojection and log-depth (Sec. IV-C).
+enum ResidualMode { kRayRange = 0, kCalibrated = 1 };
+
+// Per-edge intrinsics of the calibrated mode: K_i (projection into keyframe i), K_j^-1 (calibrated rays of
+// keyframe j) and both image widths (pixel index -> (u, v)).
+struct EdgeCal {
+  float fxi, fyi, cxi, cyi;
+  float ifxj, ifyj, cxj, cyj;
+  int32_t Wi, Wj, pad0, pad1;
+};
+
+// Host: per-edge EdgeCal from the supplied intrinsics (n_kf x 4) and the keyframe widths; checks that
+// every focal length is positive and finite.
+int make_edge_cal(const double* K, int n_kf, const int32_t* kf_w, const EdgeDev* edges, int n_edges,
+                  EdgeCal* out);
 
 constexpr int kPartial = 40;  // floats per tile partial: H upper 28, b 7, cost, count, 3 pad
 constexpr int kReduceThreads = 256;
@@ -95,16 +113,18 @@ int launch_gn_prep(const double* poses, const EdgeDev* edges, int n_edges, EdgeX
                    hipStream_t s);
 int launch_edge_reduce_one(ds3_dtype dt, int ppt, const void* arena, const EdgeDev& e, int edge_id,
                            const EdgeXf* xf, const int32_t* idx_arena, float* partials, GnConst c,
-                           hipStream_t s);
+                           hipStream_t s, const EdgeCal* cal = nullptr);
 // match stream of the batched form (gn.hip)
-size_t stream_record_bytes(ds3_dtype dt);
+// Calibrated mode (ecal != NULL, device, one EdgeCal per edge): float32 records of the calibrated point
+// and the target (u_m, v_m, 1/z_i[m]) whatever the arena dtype.
+size_t stream_record_bytes(ds3_dtype dt, bool calibrated = false);
 int launch_gather_stream(ds3_dtype dt, const void* arena, const EdgeDev* edges, const WorkItem* items,
                          int n_items, const int32_t* idx_arena, int seg_px, void* stream, int32_t* seg_count,
-                         hipStream_t s);
+                         hipStream_t s, const EdgeCal* ecal = nullptr);
 int launch_reduce_stream(ds3_dtype dt, int unroll, const void* stream, const int32_t* seg_count,
                          const EdgeDev* edges, const WorkItem* items, int n_items, const EdgeXf* xf, int seg_px,
                          float* partials, GnConst c, const int32_t* skip, hipStream_t s,
-                         const double* xf64 = nullptr, double* cost64 = nullptr);
+                         const double* xf64 = nullptr, double* cost64 = nullptr, const EdgeCal* ecal = nullptr);
 int launch_edge_finalize(const EdgeDev* edges, int n_edges, const float* partials, const double* Ad,
                          double* A_out, double* b_out, double* cost_e, int64_t* count_e, hipStream_t s);
 int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,

@@ -317,6 +317,7 @@ static int track_impl(const void* arena, ds3_dtype dtype, const ds3_track_proble
   if (!(gn->sigma_ray > 0) || !(gn->sigma_dist > 0) || !(gn->huber_k > 0) || gn->max_attempts < 1 ||
       gn->max_attempts > 16)
     return fail(DS3_EINVAL, "track: bad graph-step constants");
+  if (gn->K) return fail(DS3_ENOTSUP, "track: no calibrated mode (K must be NULL)");
   if (tp->max_trials < 0 || tp->max_trials > 1000 || !(tp->lambda0 >= 0) || !(tp->lambda_up >= 1) ||
       !(tp->lambda_down > 0) || !(tp->lambda_down <= 1) || !(tp->lambda_min >= 0) || !(tp->step_tol >= 0))
     return fail(DS3_EINVAL, "track: bad LM schedule");

@@ -1,0 +1,158 @@
+"""GPU parity of the calibrated mode (Sec. IV-C, "Calibration": pixel reprojection and log-depth residuals
+on the pointmaps constrained to the calibrated rays, supplied intrinsics) against the FP64 oracle
+(oracle.gn_assemble_cal / gn_step_cal): the normal equations of the plain form on the tiny pair and on a
+mixed-resolution graph, plain steps and the batched plan (match stream of float32 calibrated records) on
+the single-agent graph in FP32 and BF16 storage, exact recovery on rolled views, and the calls without a
+calibrated form refusing it."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests.helpers import block_rel_err, jacobi_scaled_err, tangent_group_err
+from tests.test_oracle_calib import rolled_views
+
+pytestmark = pytest.mark.gpu
+
+ds3 = pytest.importorskip("paper_2605_30488_amd.api")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(dev)
+
+
+def _graph(xyz, conf, edges, idx, dev, dtype="f32", anchors=(0,)):
+    a = ds3.build_arena(xyz, conf, dtype, dev)
+    return ds3.Graph(a, edges, _t(np.concatenate([np.asarray(i).reshape(-1) for i in idx]), dev, torch.int32),
+                     anchors=anchors)
+
+
+def _bf16(arrs):
+    return [O.bf16_to_f32(O.bf16_round(a)).reshape(np.shape(a)).astype(np.float64) for a in arrs]
+
+
+@pytest.mark.parametrize("which", ["tiny pair", "mixed resolutions"])
+def test_linearize_matches_oracle(dev, which):
+    if which == "tiny pair":
+        g = synth.make_config(1)
+        P0 = g.poses_init
+    else:
+        g = synth.make_config(3, n_agents=2, kf_per_agent=3, n_edges=6)
+        P0 = g.poses_init
+    idx = g.gt_idx_all()
+    K = g.intrinsics()
+    params = ds3.calibrated_gn_params(K)
+    G = _graph(g.xyz, g.conf, g.edges, idx, dev)
+    H, gv, cost, cnt = ds3.gn_linearize(G, _t(P0, dev), params)
+    og = O.Graph(g.xyz, g.conf, g.edges, idx, anchors=(0,))
+    Hr, gr, cr, nr, _, _ = O.gn_assemble_cal(og, P0, O.Calib(K))
+    H, gv = H.cpu().numpy(), gv.cpu().numpy()
+    ej, eb, eg = jacobi_scaled_err(H, Hr), block_rel_err(H, Hr), tangent_group_err(gv, gr)
+    print(f"{which}: count {int(cnt.item())}/{nr}, cost {cost.item():.6e}/{cr:.6e}; H Jacobi-scaled {ej:.2e}, "
+          f"per block {eb:.2e}; g per keyframe and group {eg:.2e}")
+    assert int(cnt.item()) == nr
+    assert abs(cost.item() - cr) <= 2e-5 * cr
+    assert ej <= 2e-5 and eb <= 1e-4 and eg <= 1e-3
+    assert np.array_equal(H, H.T)
+
+
+def test_plain_steps_match_oracle_tiny(dev):
+    g = synth.make_config(1)
+    idx = [g.gt_idx(0)]
+    K = g.intrinsics()
+    G = _graph(g.xyz, g.conf, g.edges, idx, dev)
+    og = O.Graph(g.xyz, g.conf, g.edges, idx, anchors=(0,))
+    P = _t(g.poses_init, dev)
+    ref = g.poses_init.copy()
+    params = ds3.calibrated_gn_params(K)
+    for it in range(6):
+        cost, st = ds3.sim3_gn_step(G, P, params)
+        ref, cr, sr, _ = O.gn_step_cal(og, ref, O.Calib(K))
+        assert abs(cost.item() - cr) <= 1e-4 * cr, it
+        assert int(st.item()) == sr
+    err = O.pose_error(P.cpu().numpy(), ref).max()
+    print(f"tiny pair, 6 calibrated plain steps: pose error {err:.2e}")
+    assert err <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def single():
+    g = synth.make_config(2)
+    return g, g.gt_idx_all()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_plan_matches_oracle_single_agent(dev, single, dtype):
+    """Three iterations of the batched plan in calibrated mode on the 20-keyframe graph (40 edges, 512x384)
+    from its noisy start, against three oracle steps on the same (for bf16: the same rounded) inputs, and
+    the plain form's three steps."""
+    g, idx = single
+    K = g.intrinsics()
+    params = ds3.calibrated_gn_params(K)
+    G = _graph(g.xyz, g.conf, g.edges, idx, dev, dtype)
+    P = _t(g.poses_init, dev)
+    plan = ds3.GNPlan(G, P, params)
+    info = plan.info()
+    rec_bytes = info["bytes_stream_per_iter"] - 4 * info["items"]  # float32 records of 32 B whatever the arena
+    assert rec_bytes % 32 == 0 and 0.9 * info["px_valid"] <= rec_bytes // 32 <= info["px_valid"]
+    costs, st = plan.run(3)
+    Pp = _t(g.poses_init, dev)
+    c_plain = [ds3.sim3_gn_step(G, Pp, params)[0].item() for _ in range(3)]
+    xyz, conf = (_bf16(g.xyz), _bf16(g.conf)) if dtype == "bf16" else (g.xyz, g.conf)
+    og = O.Graph(xyz, conf, g.edges, idx, anchors=(0,))
+    ref = g.poses_init.copy()
+    rc = []
+    for _ in range(3):
+        ref, c, s, _ = O.gn_step_cal(og, ref, O.Calib(K))
+        rc.append(c)
+    got = P.cpu().numpy()
+    err = O.pose_error(got, ref).max()
+    err_plain = O.pose_error(got, Pp.cpu().numpy()).max()
+    print(f"{dtype}: calibrated plan vs oracle {err:.2e}, vs plain form {err_plain:.2e}; costs "
+          f"{costs.cpu().numpy()} vs {rc}")
+    assert err <= 1e-5 and err_plain <= 2e-6
+    assert np.allclose(costs.cpu().numpy(), rc, rtol=1e-4)
+    assert np.allclose(costs.cpu().numpy(), c_plain, rtol=1e-5)
+    assert np.all(st.cpu().numpy() == 0)
+    plan.close()
+
+
+def test_rolled_views_recover_the_truth(dev):
+    """Exact correspondences (views rolled by multiples of 90 degrees): the plan converges to the truth
+    within float32 resolution."""
+    xyz, edges, idx, gt, K = rolled_views(H=40)
+    xyz = [np.asarray(x, np.float32) for x in xyz]
+    conf = [np.full(x.shape[:2], 2.0, np.float32) for x in xyz]
+    rng = np.random.default_rng(3)
+    P0 = gt.copy()
+    for k in (1, 2):
+        tau = np.zeros((3, 7))
+        tau[k] = np.concatenate([rng.normal(size=3) * 0.05, rng.normal(size=3) * 0.03, [rng.normal() * 0.03]])
+        P0 = O.sim3_update(P0, tau)
+    G = _graph(xyz, conf, edges, idx, dev)
+    P = _t(P0, dev)
+    plan = ds3.GNPlan(G, P, ds3.calibrated_gn_params(K), px_per_thread=4)
+    plan.run(10)
+    err = O.pose_error(P.cpu().numpy(), gt).max()
+    print(f"rolled views: pose error vs truth after 10 iterations {err:.2e} (start {O.pose_error(P0, gt).max():.2e})")
+    assert err <= 1e-5
+    plan.close()
+
+
+def test_calls_without_a_calibrated_form_refuse_it(dev):
+    g = synth.make_config(1)
+    idx = [g.gt_idx(0)]
+    G = _graph(g.xyz, g.conf, g.edges, idx, dev)
+    P = _t(g.poses_init, dev)
+    params = ds3.calibrated_gn_params(g.intrinsics())
+    for fn in (lambda: ds3.gn_cost(G, P, params), lambda: ds3.gn_cost_adjoint(G, P, params=params)):
+        with pytest.raises(RuntimeError, match="calibrated"):
+            fn()
