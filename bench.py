@@ -47,10 +47,22 @@ MATCH_FLOP_PER_QUERY = 110
 # and the calibration against a plain device copy are in profiles/), valid only for the kernel sources
 # they were taken on: reported as null once any of those files changes.
 TRAFFIC = {
+    "k_reduce_stream": {
+        "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
+                    "paper_2605_30488_amd/csrc/internal.hpp"],
+        "sha": "72e7906963f6079b", "bytes": 1148688998},
+    "k_reduce_stream (calibrated)": {
+        "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
+                    "paper_2605_30488_amd/csrc/internal.hpp"],
+        "sha": "72e7906963f6079b", "bytes": 2313069363},
+    "k_reduce_stream (tracker, float64 cost)": {
+        "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
+                    "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/track.hip"],
+        "sha": "e9931fb8060f19d7", "bytes": 344592691},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
-        "sha": "3f05dc8d7e15c9b5", "bytes": 9303931968},
+        "sha": "da602c972d82fe98", "bytes": 9303955661},
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
@@ -58,7 +70,7 @@ TRAFFIC = {
     "k_fuse": {
         "sources": ["paper_2605_30488_amd/csrc/fuse.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/sim3.hpp"],
-        "sha": "c1fbb04d6487b796", "bytes": 1651931989},
+        "sha": "9e055dcf17122682", "bytes": 1651930419},
 }
 
 
@@ -276,36 +288,191 @@ def traffic_for(kernel):
 # --------------------------------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # --------------------------------------------------------------------------------------------------
-def cpu_baseline(g, n_edges_gn=None, n_edges_match=32):
-    """About 10-30 s of oracle work: one FP64 GN step over (a sample of) the edges and the bidirectional
-    matching of a sample of edges, scaled to per-second rates."""
+def _median_time(fn, reps=5):
+    """1 untimed warm-up call, then the median wall time of `reps` calls."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def _sub_graph(g, pick):
     import oracle as O
-    E = len(g.edges)
-    n_edges_gn = E if n_edges_gn is None else n_edges_gn
-    pick = list(range(0, E, max(1, E // n_edges_gn)))[:n_edges_gn]
     kfs = sorted({int(v) for e in pick for v in g.edges[e]})
     remap = {k: n for n, k in enumerate(kfs)}
     idx = [g.gt_idx(e) for e in pick]
     og = O.Graph([g.xyz[k] for k in kfs], [g.conf[k] for k in kfs],
                  [(remap[int(g.edges[e][0])], remap[int(g.edges[e][1])]) for e in pick], idx, anchors=(0,))
-    poses = g.poses_init[kfs]
-    valid = int(sum((i >= 0).sum() for i in idx))
-    t0 = time.perf_counter()
-    O.gn_step(og, poses)
-    t_gn = time.perf_counter() - t0
-    q_px = 0
-    t0 = time.perf_counter()
-    for e in pick[::max(1, len(pick) // n_edges_match)][:n_edges_match]:
-        i, j = (int(v) for v in g.edges[e])
-        Xji, Xij = g.cross_view(e)
-        O.match_bidir(g.xyz[i], Xji, g.xyz[j], Xij, g.conf[i], g.conf[j])
-        q_px += Xji.shape[0] * Xji.shape[1] + Xij.shape[0] * Xij.shape[1]
-    t_m = time.perf_counter() - t0
+    return og, kfs, int(sum((i >= 0).sum() for i in idx))
+
+
+def cpu_baseline(g, n_edges_1t=100, n_edges_match=32, n_edges_match_1t=4):
+    """The FP64 oracle on the host, 1 warm-up + median of 5 runs each: one GN step over every edge on all
+    the cores it was given, one GN step over a sample of edges on one thread, and the bidirectional
+    matching of a sample of edges on all cores and on one thread; rates per second."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    E = len(g.edges)
+    og, kfs, valid = _sub_graph(g, list(range(E)))
+    t_gn = _median_time(lambda: O.gn_step(og, g.poses_init[kfs]))
+    pick1 = list(range(0, E, max(1, E // n_edges_1t)))[:n_edges_1t]
+    og1, kfs1, valid1 = _sub_graph(g, pick1)
+    with threadpool_limits(1):
+        t_gn1 = _median_time(lambda: O.gn_step(og1, g.poses_init[kfs1]))
+
+    def match_edges(edges):
+        def run():
+            for e in edges:
+                i, j = (int(v) for v in g.edges[e])
+                Xji, Xij = g.cross_view(e)
+                O.match_bidir(g.xyz[i], Xji, g.xyz[j], Xij, g.conf[i], g.conf[j])
+        px = sum(g.shape(int(g.edges[e][0]))[0] * g.shape(int(g.edges[e][0]))[1] +
+                 g.shape(int(g.edges[e][1]))[0] * g.shape(int(g.edges[e][1]))[1] for e in edges)
+        return run, px
+
+    me = list(range(0, E, max(1, E // n_edges_match)))[:n_edges_match]
+    run_m, q_px = match_edges(me)
+    t_m = _median_time(run_m)
+    run_m1, q_px1 = match_edges(me[:n_edges_match_1t])
+    with threadpool_limits(1):
+        t_m1 = _median_time(run_m1)
+    try:
+        cpu = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except (OSError, IndexError):
+        cpu = "unknown"
     return {"value": valid / t_gn, "unit": "edge-px/s", "cores": O.num_threads(), "kind": "oracle",
-            "matched_px_per_s": q_px / t_m,
-            "sample": f"one FP64 GN step (assembly + dense Cholesky ladder + update) over {len(pick)} of {E} "
-                      f"edges ({valid} valid edge-pixels, {len(kfs)} keyframes) in {t_gn:.2f} s; "
-                      f"bidirectional matching of {n_edges_match} edges ({q_px} query px) in {t_m:.2f} s"}
+            "matched_px_per_s": q_px / t_m, "cpu": cpu,
+            "timing": "1 warm-up + median of 5 runs",
+            "single_thread": {"edge_px_per_s": valid1 / t_gn1, "matched_px_per_s": q_px1 / t_m1,
+                              "sample": f"GN step over {len(pick1)} edges ({valid1} valid edge-pixels) in "
+                                        f"{t_gn1:.2f} s; matching of {len(me[:n_edges_match_1t])} edges "
+                                        f"({q_px1} query px) in {t_m1:.2f} s"},
+            "sample": f"one FP64 GN step (assembly + dense Cholesky ladder + update) over all {E} edges ({valid} "
+                      f"valid edge-pixels, {len(kfs)} keyframes) in {t_gn:.2f} s; bidirectional matching of "
+                      f"{len(me)} edges ({q_px} query px) in {t_m:.2f} s"}
+
+
+# --------------------------------------------------------------------------------------------------
+# Next rows on the same workload: the ray-range tracker and the calibrated mode
+# --------------------------------------------------------------------------------------------------
+def measure_tracker(g, W, dev, with_cpu=True, reps=5):
+    """ds3_track over every sequential (intra-agent) edge of the batched graph: frame j tracked against
+    keyframe i on its ground-truth matches from the noisy relative pose (BF16 arena), all problems in one
+    call. The dominant kernel is the match-stream reduction at every problem's trial pose; its first
+    launch of each call is timed with the library's events (every problem active)."""
+    import torch
+
+    import oracle as O
+    from paper_2605_30488_amd import api as ds3
+    seq = [e for e, (i, j) in enumerate(W.edges) if g.agent[i] == g.agent[j]]
+    problems = [W.edges[e] for e in seq]
+    idx_np = [g.gt_idx(e) for e in seq]
+    idx = torch.as_tensor(np.concatenate(idx_np)).to(dev)
+    T0 = torch.as_tensor(np.stack([O.relative(g.poses_init[i], g.poses_init[j]) for i, j in problems])).to(dev)
+    trk = ds3.Tracker(W.arena, problems)
+    timer = ds3.KernelTimer()
+    T = T0.clone()
+    trk.run(idx, T)
+    torch.cuda.synchronize()
+    walls, kms = [], []
+    for _ in range(reps):
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cost, trials, st = trk.run(idx, T, timer=timer)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        kms.append(timer.ms())
+    wall = float(np.median(walls))
+    k_ms = float(np.mean(kms))
+    px = sum(g.shape(j)[0] * g.shape(j)[1] for _, j in problems)
+    valid = int(sum((v >= 0).sum() for v in idx_np))
+    tr = trials.cpu().numpy()
+    rec = 16 if W.dtype == "bf16" else 32
+    n_seg = sum((g.shape(j)[0] * g.shape(j)[1] + 4095) // 4096 for _, j in problems)
+    kbytes = rec * valid + 4 * n_seg      # records (holes among the valid matches are dropped at the gather)
+    gbs = kbytes / (k_ms * 1e-3) / 1e9
+    res = {"problems": len(problems), "frame_px": px, "valid_matches": valid,
+           "call_ms": round(wall * 1e3, 3), "frames_per_s": round(len(problems) / wall, 1),
+           "trial_steps_mean": round(float(tr.mean()), 2), "trial_steps_max": int(tr.max()),
+           "roofline": {"kernel": "k_reduce_stream (tracker, float64 cost)", "bound": "hbm",
+                        "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": traffic_for("k_reduce_stream (tracker, float64 cost)"), "launch_ms": round(k_ms, 4),
+                        "bytes_per_launch": kbytes}}
+    if with_cpu:
+        sample = list(range(0, len(problems), max(1, len(problems) // 4)))[:4]
+        xyz = [np.asarray(x, np.float64) for x in g.xyz]
+
+        def run():
+            for p in sample:
+                i, j = problems[p]
+                O.track(xyz[i], g.conf[i], xyz[j], g.conf[j], idx_np[p], T0[p].cpu().numpy())
+        t = _median_time(run, reps=3)
+        res["cpu_baseline"] = {"value": round(len(sample) / t, 3), "unit": "frames/s", "cores": O.num_threads(),
+                               "kind": "oracle", "timing": "1 warm-up + median of 3 runs",
+                               "sample": f"FP64 tracker on {len(sample)} of {len(problems)} problems in {t:.2f} s"}
+    timer.close()
+    return res
+
+
+def measure_calibrated(g, W, dev, gn_iters, start, with_cpu=True, reps=5):
+    """The batched plan in calibrated mode (Sec. IV-C: pixel reprojection and log-depth rows with the
+    generator's intrinsics) on the same graph, arena and matches as the timed steps; GN_ITERS iterations
+    per run from `start` (the noisy poses after the gauge synchronisation of the timed steps). The residual
+    launch of each run's last iteration is timed with the library's events; its bytes are the 32 B float32
+    calibrated records plus the segment counts."""
+    import torch
+
+    import oracle as O
+    from paper_2605_30488_amd import api as ds3
+    K = g.intrinsics()
+    params = ds3.calibrated_gn_params(K)
+    P = start.clone()
+    timer = ds3.KernelTimer()
+    plan = ds3.GNPlan(W.graph, P, params, autotune=True, reduce_timer=timer)
+    info = plan.info()
+    plan.run(gn_iters)
+    torch.cuda.synchronize()
+    walls, kms = [], []
+    for _ in range(reps):
+        P.copy_(start)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        costs, st = plan.run(gn_iters)
+        b.record()
+        torch.cuda.synchronize()
+        walls.append(a.elapsed_time(b))
+        kms.append(timer.ms())
+    ms = float(np.median(walls))
+    k_ms = float(np.mean(kms))
+    kbytes = info["bytes_stream_per_iter"]
+    gbs = kbytes / (k_ms * 1e-3) / 1e9
+    res = {"gn_iters": gn_iters, "run_ms": round(ms, 3), "gn_iter_ms": round(ms / gn_iters, 4),
+           "edge_px_per_s": round(info["px_valid"] * gn_iters / (ms * 1e-3), 1),
+           "cost_first_last": [float(costs[0].item()), float(costs[-1].item())],
+           "ladder_status_min": int(st.min().item()),
+           "roofline": {"kernel": "k_reduce_stream (calibrated)", "bound": "hbm", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": traffic_for("k_reduce_stream (calibrated)"), "launch_ms": round(k_ms, 4),
+                        "bytes_per_launch": kbytes},
+           "plan": info}
+    plan.close()
+    timer.close()
+    if with_cpu:
+        pick = list(range(0, len(g.edges), max(1, len(g.edges) // 100)))[:100]
+        og, kfs, valid = _sub_graph(g, pick)
+        cal = O.Calib(K[kfs])
+        P0 = start.cpu().numpy()[kfs]
+        t = _median_time(lambda: O.gn_step_cal(og, P0, cal), reps=3)
+        res["cpu_baseline"] = {"value": round(valid / t, 1), "unit": "edge-px/s", "cores": O.num_threads(),
+                               "kind": "oracle", "timing": "1 warm-up + median of 3 runs",
+                               "sample": f"FP64 calibrated GN step over {len(pick)} of {len(g.edges)} edges "
+                                         f"({valid} valid edge-pixels) in {t:.2f} s"}
+    return res
 
 
 # --------------------------------------------------------------------------------------------------
@@ -593,8 +760,19 @@ def main():
             out["cpu_baseline"] = cpu_baseline(g)
             log(f"cpu baseline in {time.time() - t0:.1f}s")
 
-    # the next row past the graph step: canonical pointmap fusion of eq. (2) over the same keyframes
-    out["next_fusion"] = measure_fusion(g, dev, with_cpu=not (args.quick or args.no_cpu_baseline))
+    # the next rows past the graph step on the same keyframes: tracker, calibrated mode, fusion of eq. (2)
+    with_cpu = not (args.quick or args.no_cpu_baseline)
+    if args.config in (3, 4):
+        t0 = time.time()
+        out["next_tracker"] = measure_tracker(g, W, dev, with_cpu=with_cpu)
+        log(f"tracker: {out['next_tracker']['problems']} frames in {out['next_tracker']['call_ms']:.2f} ms "
+            f"({time.time() - t0:.1f}s)")
+        t0 = time.time()
+        start = W.poses_init.clone()
+        ds3.gauge_sync(start, W.agent, W.arena, W.edges, W.idx_offsets, W.idx, W.valid, admit)
+        out["next_calibrated"] = measure_calibrated(g, W, dev, args.gn_iters, start, with_cpu=with_cpu)
+        log(f"calibrated: {out['next_calibrated']['gn_iter_ms']:.3f} ms per GN iteration ({time.time() - t0:.1f}s)")
+    out["next_fusion"] = measure_fusion(g, dev, with_cpu=with_cpu)
     log(f"fusion: {out['next_fusion']['launch_ms']:.3f} ms per launch over {out['next_fusion']['px']} px")
 
     if args.calib_copy_mib > 0:

@@ -81,7 +81,8 @@ typedef struct {
  * edge (i, j), Xcal_j[n] = z_j[n] K_j^-1 (u_n, v_n, 1) with z = the stored point's third coordinate,
  * x = T_ij Xcal_j[n], r = (fx_i x0/x2 + cx_i - u_m, fy_i x1/x2 + cy_i - v_m, ln x2 - ln z_i[m]), whitened by
  * sqrt(q)/sigma_pix and sqrt(q)/sigma_logz (q = sqrt(C_i C_j)), the same Huber kernel; matches with a
- * hole, z_j[n] or z_i[m] <= 1e-9, or x2 <= 1e-9 are skipped. The paper prints no constants for this mode:
+ * hole, z_j[n] or z_i[m] <= 1e-9, x2 <= 1e-9, or a reprojection off keyframe i's image (outside
+ * [-0.5, W_i - 0.5) x [-0.5, H_i - 0.5)) are skipped. The paper prints no constants for this mode:
  * sigma_pix = 1 px and sigma_logz = 0.1 are readings. Supported by ds3_gn_linearize, ds3_sim3_gn_step and
  * the batched plan; the cost, adjoint and tracker calls return DS3_ENOTSUP when K is set. */
 typedef struct {

@@ -544,7 +544,9 @@ void linearize_edge(const M4& Ti, const M4& Tj, const double* xyz_j, const doubl
 //     r = ( fx_i x0/x2 + cx_i - u_m,  fy_i x1/x2 + cy_i - v_m,  ln x2 - ln z_i[m] ),
 //   whitened by sqrt(q)/sigma_pix (pixel rows) and sqrt(q)/sigma_logz (depth row), q = sqrt(C_i C_j);
 //   the same component-wise Huber kernel and IRLS weights; a match is used only if neither point is a
-//   hole and z_j[n], z_i[m] and x2 are above 1e-9 (both points and the transformed one in front).
+//   hole, z_j[n], z_i[m] and x2 are above 1e-9 (both points and the transformed one in front) and the
+//   reprojection lands on keyframe i's image, -0.5 <= fx_i x0/x2 + cx_i < W_i - 0.5 and likewise for v
+//   with H_i (a reprojection off the image is no pixel of i; it also keeps x0/x2 and x1/x2 bounded).
 // The chain rule is the one of eq. (6) with this residual: J_x = (dr/dx) [I  -[x]x  x].
 // ------------------------------------------------------------------------------------------------
 struct CalResidual {
@@ -556,7 +558,7 @@ struct CalResidual {
 
 // K: fx, fy, cx, cy of a keyframe.
 CalResidual cal_residual(const M4& Tij, const double* Xj, int64_t n, int Wj, const double* Kj, const double* Xi,
-                         int64_t m, int Wi, const double* Ki, double Ci, double Cj) {
+                         int64_t m, int Wi, int Hi, const double* Ki, double Ci, double Cj) {
   CalResidual R{};
   R.ok = false;
   if (is_hole(Xj) || is_hole(Xi) || !std::isfinite(Ci) || !std::isfinite(Cj)) return R;
@@ -567,8 +569,10 @@ CalResidual cal_residual(const M4& Tij, const double* Xj, int64_t n, int Wj, con
   apply_mat(Tij, Xc, R.x);
   if (!(R.x[2] > 1e-9)) return R;
   const double um = double(m % Wi), vm = double(m / Wi);
-  R.r[0] = Ki[0] * R.x[0] / R.x[2] + Ki[2] - um;
-  R.r[1] = Ki[1] * R.x[1] / R.x[2] + Ki[3] - vm;
+  const double pu = Ki[0] * R.x[0] / R.x[2] + Ki[2], pv = Ki[1] * R.x[1] / R.x[2] + Ki[3];
+  if (!(pu >= -0.5 && pu < Wi - 0.5 && pv >= -0.5 && pv < Hi - 0.5)) return R;
+  R.r[0] = pu - um;
+  R.r[1] = pv - vm;
   R.r[2] = std::log(R.x[2]) - std::log(zi);
   R.q = std::sqrt(Ci * Cj);
   R.ok = std::isfinite(R.q) && std::isfinite(R.r[0]) && std::isfinite(R.r[1]) && std::isfinite(R.r[2]);
@@ -588,8 +592,8 @@ void linearize_edge_cal(const M4& Ti, const M4& Tj, const double* xyz_j, const d
   for (int64_t n = 0; n < npx_j; ++n) {
     int32_t m = idx[n];
     if (m < 0 || m >= npx_i) continue;
-    CalResidual R = cal_residual(Tij, xyz_j + 3 * n, n, Wj, Kj, xyz_i + 3 * int64_t(m), m, Wi, Ki, conf_i[m],
-                                 conf_j[n]);
+    CalResidual R = cal_residual(Tij, xyz_j + 3 * n, n, Wj, Kj, xyz_i + 3 * int64_t(m), m, Wi, int(npx_i / Wi), Ki,
+                                 conf_i[m], conf_j[n]);
     if (!R.ok) continue;
     double sq = std::sqrt(R.q);
     double W[3];
@@ -1070,7 +1074,8 @@ int orc_edge_residuals_cal(const double* pose_i, const double* pose_j, const dou
     ok_out[n] = 0;
     for (int c = 0; c < 3; ++c) { r_out[3 * n + c] = 0.0; w_out[3 * n + c] = 0.0; }
     if (m < 0 || m >= npx_i) continue;
-    CalResidual R = cal_residual(Tij, xyz_j + 3 * n, n, Wj, Kj, xyz_i + 3 * int64_t(m), m, Wi, Ki, conf_i[m], conf_j[n]);
+    CalResidual R = cal_residual(Tij, xyz_j + 3 * n, n, Wj, Kj, xyz_i + 3 * int64_t(m), m, Wi, int(npx_i / Wi), Ki,
+                                 conf_i[m], conf_j[n]);
     if (!R.ok) continue;
     double sq = std::sqrt(R.q);
     for (int c = 0; c < 3; ++c) {
@@ -1099,8 +1104,8 @@ double orc_cost_cal(const double* poses, int n_kf, const int64_t* kf_off, const 
       int32_t m = id[p];
       if (m < 0 || m >= kf_npx[i]) continue;
       CalResidual R = cal_residual(Tij, xyz + 3 * (kf_off[j] + p), p, kf_w[j], K + 4 * j,
-                                   xyz + 3 * (kf_off[i] + int64_t(m)), m, kf_w[i], K + 4 * i, conf[kf_off[i] + m],
-                                   conf[kf_off[j] + p]);
+                                   xyz + 3 * (kf_off[i] + int64_t(m)), m, kf_w[i], int(kf_npx[i] / kf_w[i]), K + 4 * i,
+                                   conf[kf_off[i] + m], conf[kf_off[j] + p]);
       if (!R.ok) continue;
       double sq = std::sqrt(R.q);
       for (int k = 0; k < 3; ++k) c += huber_rho(sq * R.r[k] / sig[k], P->huber_k);

@@ -240,14 +240,18 @@ __device__ inline void acc_row(Acc& a, const float* J, float W, float e) {
   }
 }
 
-// Calibrated mode, one match after its checks: x = T_ij Xcal_j (x2 > 0), target pixel (um, vm) of keyframe
-// i and izm = 1/z_i[m], sq = (C_i C_j)^(1/4), K_i = (fx, fy, cx, cy).
+// Calibrated mode, one match after its pose-independent checks: x = T_ij Xcal_j (x2 > 1e-9), target pixel
+// (um, vm) of keyframe i and izm = 1/z_i[m], sq = (C_i C_j)^(1/4), K_i = (fx, fy, cx, cy). Nothing is
+// accumulated unless the reprojection lands on keyframe i's image: -0.5 <= u < W_i - 0.5 (lim.x = W_i - 0.5)
+// and likewise v with H_i (lim.y).
 __device__ inline void acc_core_cal(Acc& a, float x0, float x1, float x2, float um, float vm, float izm, float sq,
-                                    const float4 Ki, const GnConst& k) {
+                                    const float4 Ki, const float2 lim, const GnConst& k) {
   const float iz = __builtin_amdgcn_rcpf(x2);
   const float px = x0 * iz, py = x1 * iz;
-  const float e0 = fmaf(Ki.x, px, Ki.z) - um;
-  const float e1 = fmaf(Ki.y, py, Ki.w) - vm;
+  const float pu = fmaf(Ki.x, px, Ki.z), pv = fmaf(Ki.y, py, Ki.w);
+  if (!(pu >= -0.5f && pu < lim.x && pv >= -0.5f && pv < lim.y)) return;
+  const float e0 = pu - um;
+  const float e1 = pv - vm;
   const float e2 = logf(x2 * izm);
   const float q = sq * sq;
   const float sp = sq * k.inv_sp;
@@ -301,7 +305,8 @@ __device__ inline void acc_pixel_cal(Acc& a, const float4 Xj, const float4 Xi, i
   transform(M, X0, X1, Xj.z, x0, x1, x2);
   if (!(x2 > 1e-9f) || !(x2 < __builtin_huge_valf()) || !isfinite(x0) || !isfinite(x1)) return;
   const int vm = m / C.Wi, um = m - vm * C.Wi;
-  acc_core_cal(a, x0, x1, x2, float(um), float(vm), 1.0f / Xi.z, sq, make_float4(C.fxi, C.fyi, C.cxi, C.cyi), k);
+  acc_core_cal(a, x0, x1, x2, float(um), float(vm), 1.0f / Xi.z, sq, make_float4(C.fxi, C.fyi, C.cxi, C.cyi),
+               make_float2(float(C.Wi) - 0.5f, float(C.Hi) - 0.5f), k);
 }
 
 // Block reduction of the 37 accumulators in a fixed order; threads 0..36 write the tile partial.
@@ -653,9 +658,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
     for (int q = 0; q < 12; ++q) M64[q] = xf64[12 * int64_t(W.edge) + q];
   }
   float4 Ki = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 lim = make_float2(0.f, 0.f);
   if constexpr (MODE == kCalibrated) {
     const EdgeCal C = ecal[W.edge];
     Ki = make_float4(C.fxi, C.fyi, C.cxi, C.cyi);
+    lim = make_float2(float(C.Wi) - 0.5f, float(C.Hi) - 0.5f);
   }
   double c64 = 0.0;
   const rec_t* __restrict__ in = static_cast<const rec_t*>(stream) + int64_t(seg) * seg_px;
@@ -681,7 +688,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
         if constexpr (MODE == kCalibrated) {
           // xi holds the target (u_m, v_m, 1/z_i[m])
           if (x2 > 1e-9f && x2 < __builtin_huge_valf() && isfinite(x0) && isfinite(x1))
-            acc_core_cal(a, x0, x1, x2, xi[0], xi[1], xi[2], sq, Ki, k);
+            acc_core_cal(a, x0, x1, x2, xi[0], xi[1], xi[2], sq, Ki, lim, k);
         } else {
           const float d2 = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
           if (d2 > 1e-18f && d2 < __builtin_huge_valf()) {
@@ -822,7 +829,8 @@ int make_edge_cal(const double* K, int n_kf, const int32_t* kf_w, const EdgeDev*
     C.cyj = float(Kj[3]);
     C.Wi = kf_w[edges[e].i];
     C.Wj = kf_w[edges[e].j];
-    C.pad0 = C.pad1 = 0;
+    C.Hi = edges[e].npx_i / C.Wi;
+    C.pad = 0;
     out[e] = C;
   }
   return DS3_OK;

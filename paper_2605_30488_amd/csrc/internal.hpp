@@ -83,7 +83,7 @@ enum ResidualMode { kRayRange = 0, kCalibrated = 1 };
 struct EdgeCal {
   float fxi, fyi, cxi, cyi;
   float ifxj, ifyj, cxj, cyj;
-  int32_t Wi, Wj, pad0, pad1;
+  int32_t Wi, Wj, Hi, pad;
 };
 
 // Host: per-edge EdgeCal from the supplied intrinsics (n_kf x 4) and the keyframe widths; checks that
