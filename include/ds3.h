@@ -377,6 +377,57 @@ int ds3_track_noalloc(const void* arena, ds3_dtype dtype, const ds3_track_proble
                       double* cost_out, int32_t* trials_out, int32_t* status_out, void* stream);
 
 /* ---------------------------------------------------------------------------------------------------
+ * Terminal segment-level depth refinement (Sec. III-E, eqs. 8-10)
+ * ------------------------------------------------------------------------------------------------- */
+
+/* Constants: M_k segments per keyframe (about 200), C_min = 1.5, 16 pixels per segment at least,
+ * sigma_point = 0.05, lambda_smooth = lambda_prior = 1, lambda_lm = 0.05, eta_max = 0.5 (Sec. III-E); the
+ * SLIC iteration count (10) and the Huber kappa of the point residual (the pose cost's 1.345) are readings. */
+typedef struct {
+  int32_t segments_per_kf;
+  double conf_min;
+  int32_t min_seg_px, slic_iters;
+  double sigma_point, huber_k, lambda_smooth, lambda_prior, lambda_lm, eta_max;
+} ds3_depth_params;
+void ds3_default_depth_params(ds3_depth_params* p);
+
+/* Creates a refinement plan over the pristine keyframe arena (the X_init snapshot of eq. 8; caller's, must
+ * outlive the plan and stay unchanged), the graph's edges and matches (idx arena as for the graph step;
+ * caller's) and the anchor keyframes (host list; their segments stay fixed). Creation segments every
+ * keyframe on the device (SLIC over quantised normals and normalised log-range in exact integer arithmetic:
+ * F = (round(1024 (n + 1)) x3, round(1024 l)), S = round(sqrt(HW / M_k)), D = S^2 |dF|^2 + 512^2 |dxy|^2
+ * over the 3x3 neighbouring cells' centres, ties to the lowest index, centres to the floor of their members'
+ * mean), excludes pixels below conf_min and segments below min_seg_px, builds the boundary table (4-adjacent
+ * pixel pairs of two valid segments, mean log-range difference) and sets eta = 0. Segment ids are global:
+ * keyframe k owns ids [base_k, base_k + nx_k ny_k), nx_k ny_k <= 256 (else DS3_EINVAL). The plan owns its
+ * device buffers (labels 4 B and features 8 B per arena pixel, 2 x 49 x 12 B boundary slots and a few
+ * doubles per segment); creation synchronises once. */
+int ds3_depth_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3_dtype dtype,
+                          const ds3_edge* edges, int32_t n_edges, const int32_t* idx_arena, const int32_t* anchors,
+                          int32_t n_anchors, const ds3_depth_params* params, void** plan_out, void* stream);
+/* iters Jacobi-style damped Newton steps with the poses fixed (device, n_kf x 8): per segment the diagonal
+ * of the data term's normal equations (J_g = -X_i(eta), J_h = sR_ij X_j(eta), whitened by
+ * sqrt(q)/sigma_point, Huber weights), lambda_smooth per boundary pair and lambda_prior, the full gradient
+ * of E' = sum rho + (lambda_smooth/2) sum_B ((eta_g - eta_h) + Delta_gh)^2 + (lambda_prior/2) sum eta^2,
+ * step = clip(-g / ((1 + lambda_lm) H), +-eta_max); anchor segments fixed. cost_per_iter (device, iters
+ * float64, may be NULL) = E' at each iteration's input eta. data_timer (may be NULL) brackets the data-term
+ * launch of the last iteration. No host synchronisation. iters <= 1024. */
+int ds3_depth_plan_run(void* plan, const double* poses, int32_t iters, double* cost_per_iter, ds3_timer* data_timer,
+                       void* stream);
+/* [segment slots, valid segments, boundary slots in use (each unordered pair twice), data-kernel tiles,
+ * pixels of j scanned per iteration over all edges, arena pixels] */
+int ds3_depth_plan_info(void* plan, int64_t* info, int32_t n_info);
+/* Device copies: labels_out (arena pixels, int32: global segment id or -1), eta_out (segment slots, float64);
+ * either may be NULL. */
+int ds3_depth_plan_get(void* plan, int32_t* labels_out, double* eta_out, void* stream);
+/* Replaces eta (device, segment slots, float64). */
+int ds3_depth_plan_set_eta(void* plan, const double* eta, void* stream);
+/* The refined pointmaps of eq. (8), X_init exp(eta_g) per pixel (excluded pixels unchanged), as a float32
+ * xyzc arena (device, 16 B aligned, arena pixels x 4; the confidences copied). */
+int ds3_depth_plan_apply(void* plan, float* xyzc_out, void* stream);
+int ds3_depth_plan_destroy(void* plan);
+
+/* ---------------------------------------------------------------------------------------------------
  * Cost and its adjoint (gradient of eq. 5 with the matches held fixed)
  * ------------------------------------------------------------------------------------------------- */
 

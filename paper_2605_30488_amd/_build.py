@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libds3.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["capi.cpp", "capi_match.cpp", "gn.hip", "chol.hip", "match.hip", "gauge.hip", "misc.hip",
-           "adjoint.hip", "fuse.hip", "track.hip"]
+           "adjoint.hip", "fuse.hip", "track.hip", "depth.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
@@ -26,7 +26,9 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-u
 # Per-source flags. chol.hip: matrix-core products read and write ordinary VGPRs instead of the
 # accumulation registers, which removes a copy of every accumulator tile to and from them around each
 # product in the diagonal factorisation's dependent chain.
-EXTRA = {"chol.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# depth.hip: no contraction of float64 products and sums into fused multiply-adds, so that the segmentation
+# features round exactly as the operations are written.
+EXTRA = {"chol.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"], "depth.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

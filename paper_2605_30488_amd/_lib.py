@@ -42,6 +42,13 @@ class TrackProblem(C.Structure):
     _fields_ = [("keyframe", Image), ("frame", Image), ("idx_offset", C.c_int64)]
 
 
+class DepthParams(C.Structure):
+    _fields_ = [("segments_per_kf", C.c_int32), ("conf_min", C.c_double), ("min_seg_px", C.c_int32),
+                ("slic_iters", C.c_int32), ("sigma_point", C.c_double), ("huber_k", C.c_double),
+                ("lambda_smooth", C.c_double), ("lambda_prior", C.c_double), ("lambda_lm", C.c_double),
+                ("eta_max", C.c_double)]
+
+
 class FusePair(C.Structure):
     _fields_ = [("canon_off", C.c_int64), ("pred_off", C.c_int64), ("n_px", C.c_int64)]
 
@@ -114,6 +121,15 @@ _SIGS = {
                             C.POINTER(TrackParams), vp, vp, vp, vp, vp, vp, sz, vp]),
     "ds3_track_noalloc": (C.c_int, [vp, C.c_int, C.POINTER(TrackProblem), i32, vp, C.POINTER(GNParams),
                                     C.POINTER(TrackParams), vp, vp, vp, vp, vp]),
+    "ds3_default_depth_params": (None, [C.POINTER(DepthParams)]),
+    "ds3_depth_plan_create": (C.c_int, [i32, P_img, vp, C.c_int, P_edge, i32, vp, P_i32, i32,
+                                        C.POINTER(DepthParams), C.POINTER(vp), vp]),
+    "ds3_depth_plan_run": (C.c_int, [vp, vp, i32, vp, vp, vp]),
+    "ds3_depth_plan_info": (C.c_int, [vp, P_i64, i32]),
+    "ds3_depth_plan_get": (C.c_int, [vp, vp, vp, vp]),
+    "ds3_depth_plan_set_eta": (C.c_int, [vp, vp, vp]),
+    "ds3_depth_plan_apply": (C.c_int, [vp, vp, vp]),
+    "ds3_depth_plan_destroy": (C.c_int, [vp]),
     "ds3_fuse_workspace_bytes": (sz, [i32]),
     "ds3_fuse": (C.c_int, [vp, i64, vp, i64, C.POINTER(FusePair), i32, vp, i32, vp, sz, vp]),
 }

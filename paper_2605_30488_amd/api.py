@@ -613,6 +613,77 @@ def track(arena: Arena, problems, idx: torch.Tensor, T: torch.Tensor, idx_offset
 
 
 # ------------------------------------------------------------------------------------------------
+# Terminal segment-level depth refinement (Sec. III-E, eqs. 8-10)
+# ------------------------------------------------------------------------------------------------
+def default_depth_params() -> L.DepthParams:
+    p = L.DepthParams()
+    L.load().ds3_default_depth_params(C.byref(p))
+    return p
+
+
+class DepthPlan:
+    """ds3_depth_plan_*: segments the pristine keyframes of `graph.arena` at creation (labels, boundary
+    table, eta = 0), then run(poses, iters) takes Jacobi damped Newton steps of the segment log-scales."""
+
+    def __init__(self, graph: Graph, params=None):
+        self.graph = graph
+        self.params = params or default_depth_params()
+        h = C.c_void_p()
+        call("ds3_depth_plan_create", graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
+             len(graph.edges), _ptr(graph.idx), graph.an, len(graph.anchors), C.byref(self.params), C.byref(h),
+             _stream())
+        self.handle = h
+        self.info = self._info()
+
+    def _info(self) -> dict:
+        a = (C.c_int64 * 6)()
+        call("ds3_depth_plan_info", self.handle, a, 6)
+        return {"segments": a[0], "valid_segments": a[1], "boundary_slots": a[2], "tiles": a[3],
+                "px_scanned": a[4], "arena_px": a[5]}
+
+    def run(self, poses: torch.Tensor, iters: int, timer=None):
+        """Returns E' at each iteration's input eta ((iters,) float64, device)."""
+        _need_cuda(poses)
+        cost = torch.empty(max(iters, 1), dtype=torch.float64, device=poses.device)
+        call("ds3_depth_plan_run", self.handle, _ptr(poses), iters, _ptr(cost),
+             timer.handle if timer is not None else None, _stream())
+        return cost[:iters]
+
+    def labels(self) -> torch.Tensor:
+        out = torch.empty(self.info["arena_px"], dtype=torch.int32, device=self.graph.arena.data.device)
+        call("ds3_depth_plan_get", self.handle, _ptr(out), None, _stream())
+        return out
+
+    def eta(self) -> torch.Tensor:
+        out = torch.empty(self.info["segments"], dtype=torch.float64, device=self.graph.arena.data.device)
+        call("ds3_depth_plan_get", self.handle, None, _ptr(out), _stream())
+        return out
+
+    def set_eta(self, eta: torch.Tensor):
+        _need_cuda(eta)
+        if eta.dtype != torch.float64 or eta.numel() != self.info["segments"]:
+            raise ValueError("eta: float64, one entry per segment slot")
+        call("ds3_depth_plan_set_eta", self.handle, _ptr(eta), _stream())
+
+    def apply(self) -> torch.Tensor:
+        """The refined pointmaps X_init exp(eta) as a float32 (P, 4) xyzc arena."""
+        out = torch.empty((self.info["arena_px"], 4), dtype=torch.float32, device=self.graph.arena.data.device)
+        call("ds3_depth_plan_apply", self.handle, _ptr(out), _stream())
+        return out
+
+    def close(self):
+        if self.handle:
+            L.load().ds3_depth_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------------------------------
 # Canonical pointmap fusion (eq. 2)
 # ------------------------------------------------------------------------------------------------
 class FusePlan:
