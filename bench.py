@@ -419,6 +419,83 @@ def measure_tracker(g, W, dev, with_cpu=True, reps=5):
     return res
 
 
+def measure_depth(g, W, dev, start, with_cpu=True, iters=10, reps=3):
+    """Terminal segment-level depth refinement (Sec. III-E) on the batched graph: the plan segments every
+    keyframe (SLIC, boundary table; timed once) and runs `iters` Jacobi damped Newton iterations of the
+    segment log-scales with the poses fixed at `start`, over the timed steps' matches. The data-term launch
+    of each run's last iteration is timed with the library's events; its algorithmic bytes are 4 B idx per
+    scanned pixel of j plus, per valid match, both pointmap entries and both pixels' labels (4 B each)."""
+    import torch
+
+    from paper_2605_30488_amd import api as ds3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = ds3.DepthPlan(W.graph)
+    torch.cuda.synchronize()
+    seg_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info
+    timer = ds3.KernelTimer()
+    zero = torch.zeros(info["segments"], dtype=torch.float64, device=dev)
+    plan.run(start, iters)
+    walls, kms = [], []
+    for _ in range(reps):
+        plan.set_eta(zero)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        costs = plan.run(start, iters, timer=timer)
+        b.record()
+        torch.cuda.synchronize()
+        walls.append(a.elapsed_time(b))
+        kms.append(timer.ms())
+    ms = float(np.median(walls))
+    k_ms = float(np.mean(kms))
+    px_valid = int((W.idx >= 0).sum().item())
+    px_bytes = 16 if W.dtype == "f32" else 8
+    kbytes = 4 * info["px_scanned"] + (2 * px_bytes + 8) * px_valid
+    gbs = kbytes / (k_ms * 1e-3) / 1e9
+    eta = plan.eta()
+    res = {"segmentation_ms": round(seg_ms, 2), "segments": info["segments"],
+           "valid_segments": info["valid_segments"], "boundary_slots": info["boundary_slots"],
+           "iters": iters, "run_ms": round(ms, 3), "iter_ms": round(ms / iters, 4),
+           "edge_px_per_s": round(px_valid * iters / (ms * 1e-3), 1),
+           "cost_first_last": [float(costs[0].item()), float(costs[-1].item())],
+           "eta_abs_max": float(eta.abs().max().item()),
+           "roofline": {"kernel": "k_dr_data", "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_for("k_dr_data"),
+                        "launch_ms": round(k_ms, 4), "bytes_per_launch": kbytes}}
+    plan.close()
+    timer.close()
+    if with_cpu:
+        from oracle import depth as D
+        kfs = [0, 1, 2, 3]
+        sub = [e for e, (i, j) in enumerate(W.edges) if i in kfs and j in kfs]
+        remap = {k: n for n, k in enumerate(kfs)}
+        idx_np = W.idx.cpu().numpy()
+        offs = W.idx_offsets
+        sizes = [g.shape(j)[0] * g.shape(j)[1] for _, j in W.edges]
+        idx_s = [idx_np[offs[e]:offs[e] + sizes[e]] for e in sub]
+        xyz = [O_bf16(g.xyz[k]) if W.dtype == "bf16" else g.xyz[k] for k in kfs]
+        conf = [O_bf16(g.conf[k]) if W.dtype == "bf16" else g.conf[k] for k in kfs]
+        t0 = time.perf_counter()
+        prob = D.DepthProblem(xyz, conf, [(remap[W.edges[e][0]], remap[W.edges[e][1]]) for e in sub], idx_s,
+                              anchors=(0,))
+        t_seg = time.perf_counter() - t0
+        P0 = start.cpu().numpy()[kfs]
+        t = _median_time(lambda: prob.run(P0, iters=iters), reps=3)
+        valid = int(sum((v >= 0).sum() for v in idx_s))
+        res["cpu_baseline"] = {"value": round(valid * iters / t, 1), "unit": "edge-px/s", "cores": 1,
+                               "kind": "oracle", "timing": "1 warm-up + median of 3 runs",
+                               "sample": f"numpy FP64 refinement of keyframes 0-3 ({len(sub)} edges, {valid} valid "
+                                         f"matches), {iters} iterations in {t:.2f} s; their segmentation "
+                                         f"{t_seg:.2f} s"}
+    return res
+
+
+def O_bf16(a):
+    import oracle as O
+    return O.bf16_to_f32(O.bf16_round(a)).reshape(np.shape(a)).astype(np.float64)
+
+
 def measure_calibrated(g, W, dev, gn_iters, start, with_cpu=True, reps=5):
     """The batched plan in calibrated mode (Sec. IV-C: pixel reprojection and log-depth rows with the
     generator's intrinsics) on the same graph, arena and matches as the timed steps; GN_ITERS iterations
@@ -772,6 +849,10 @@ def main():
         ds3.gauge_sync(start, W.agent, W.arena, W.edges, W.idx_offsets, W.idx, W.valid, admit)
         out["next_calibrated"] = measure_calibrated(g, W, dev, args.gn_iters, start, with_cpu=with_cpu)
         log(f"calibrated: {out['next_calibrated']['gn_iter_ms']:.3f} ms per GN iteration ({time.time() - t0:.1f}s)")
+        t0 = time.time()
+        out["next_depth"] = measure_depth(g, W, dev, W.poses, with_cpu=with_cpu)
+        log(f"depth refinement: segmentation {out['next_depth']['segmentation_ms']:.1f} ms, "
+            f"{out['next_depth']['iter_ms']:.3f} ms per iteration ({time.time() - t0:.1f}s)")
     out["next_fusion"] = measure_fusion(g, dev, with_cpu=with_cpu)
     log(f"fusion: {out['next_fusion']['launch_ms']:.3f} ms per launch over {out['next_fusion']['px']} px")
 

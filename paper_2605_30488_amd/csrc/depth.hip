@@ -357,7 +357,22 @@ struct DepthEdge {
 };
 
 // One block per (edge, tile of keyframe j): data-term sums of the segments it touches, flushed with float64
-// atomics; the block's cost into its partial.
+// atomics; the block's cost into its partial. A thread takes groups of kGrp consecutive pixels of j: all
+// loads of a group are issued together (matches, both points, both labels, then both log-scales), and
+// consecutive matches of one segment (the usual case: segments are tens of pixels wide and neighbouring
+// matches land in neighbouring pixels of i) are summed in registers before one LDS add per run.
+constexpr int kGrp = 4;
+
+__device__ inline void run_flush(float* H, float* G, int base, int& cur, float& h, float& g) {
+  if (cur >= 0) {
+    atomicAdd(&H[cur - base], h);
+    atomicAdd(&G[cur - base], g);
+  }
+  cur = -1;
+  h = 0.0f;
+  g = 0.0f;
+}
+
 template <int DT>
 __global__ __launch_bounds__(kDepthThreads) void k_dr_data(const void* __restrict__ arena,
                                                            const DepthEdge* __restrict__ edges,
@@ -379,45 +394,81 @@ __global__ __launch_bounds__(kDepthThreads) void k_dr_data(const void* __restric
   for (int q = 0; q < 12; ++q) M[q] = xf[W.x].m[q];
   const int32_t* __restrict__ idx = idx_arena + E.idx_off;
   float cost = 0.0f;
+  int curj = -1, curi = -1;
+  float hj = 0.0f, gj = 0.0f, hi = 0.0f, gi = 0.0f;
   const int base = W.y * (kDepthThreads * kDepthPPT);
-  for (int k = 0; k < kDepthPPT; ++k) {
-    const int n = base + k * kDepthThreads + threadIdx.x;
-    if (n >= E.npx_j) break;
-    const int m = idx[n];
-    if (m < 0 || m >= E.npx_i) continue;
-    const float4 Xj = Px<DT>::load(arena, E.off_j + n);
-    const float4 Xi = Px<DT>::load(arena, E.off_i + m);
-    const float dj2 = fmaf(Xj.x, Xj.x, fmaf(Xj.y, Xj.y, Xj.z * Xj.z));
-    const float di2 = fmaf(Xi.x, Xi.x, fmaf(Xi.y, Xi.y, Xi.z * Xi.z));
-    const float cc = Xi.w * Xj.w;
-    if (!(fminf(dj2, di2) > 1e-18f) || !(dj2 + di2 + cc < __builtin_huge_valf()) || !(cc >= 0.0f)) continue;
-    const int h = label[E.off_j + n], g = label[E.off_i + m];
-    const float fh = h >= 0 ? expf(float(eta[h])) : 1.0f;
-    const float fg = g >= 0 ? expf(float(eta[g])) : 1.0f;
-    const float a0 = Xj.x * fh, a1 = Xj.y * fh, a2 = Xj.z * fh;   // X_j(eta), eq. (8)
-    const float b0 = Xi.x * fg, b1 = Xi.y * fg, b2 = Xi.z * fg;   // X_i(eta)
-    const float s = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(cc)) * dc.inv_sigma;
-    const float R0 = fmaf(M[0], a0, fmaf(M[1], a1, M[2] * a2));   // sR_ij X_j(eta)
-    const float R1 = fmaf(M[3], a0, fmaf(M[4], a1, M[5] * a2));
-    const float R2 = fmaf(M[6], a0, fmaf(M[7], a1, M[8] * a2));
-    const float r0 = s * (R0 + M[9] - b0), r1 = s * (R1 + M[10] - b1), r2 = s * (R2 + M[11] - b2);
-    const float e0 = fabsf(r0), e1 = fabsf(r1), e2 = fabsf(r2);
-    const float w0 = fminf(1.0f, dc.kappa * __builtin_amdgcn_rcpf(e0));
-    const float w1 = fminf(1.0f, dc.kappa * __builtin_amdgcn_rcpf(e1));
-    const float w2 = fminf(1.0f, dc.kappa * __builtin_amdgcn_rcpf(e2));
-    const float t0 = w0 * e0, t1 = w1 * e1, t2 = w2 * e2;
-    cost += t0 * fmaf(-0.5f, t0, e0) + t1 * fmaf(-0.5f, t1, e1) + t2 * fmaf(-0.5f, t2, e2);
-    if (h >= 0) {
-      const float J0 = s * R0, J1 = s * R1, J2 = s * R2;
-      atomicAdd(&sHj[h - E.base_j], w0 * J0 * J0 + w1 * J1 * J1 + w2 * J2 * J2);
-      atomicAdd(&sGj[h - E.base_j], w0 * J0 * r0 + w1 * J1 * r1 + w2 * J2 * r2);
+#pragma unroll 1
+  for (int k = 0; k < kDepthPPT / kGrp; ++k) {
+    const int n0 = base + (k * kDepthThreads + int(threadIdx.x)) * kGrp;
+    int m[kGrp];
+#pragma unroll
+    for (int u = 0; u < kGrp; ++u) {
+      const int n = n0 + u;
+      m[u] = (n < E.npx_j) ? idx[n] : -1;
+      if (m[u] >= E.npx_i) m[u] = -1;
     }
-    if (g >= 0) {
-      const float J0 = -s * b0, J1 = -s * b1, J2 = -s * b2;
-      atomicAdd(&sHi[g - E.base_i], w0 * J0 * J0 + w1 * J1 * J1 + w2 * J2 * J2);
-      atomicAdd(&sGi[g - E.base_i], w0 * J0 * r0 + w1 * J1 * r1 + w2 * J2 * r2);
+    float4 Xj[kGrp], Xi[kGrp];
+    int h[kGrp], g[kGrp];
+#pragma unroll
+    for (int u = 0; u < kGrp; ++u) {
+      h[u] = g[u] = -1;
+      if (m[u] >= 0) {
+        Xj[u] = Px<DT>::load(arena, E.off_j + n0 + u);
+        Xi[u] = Px<DT>::load(arena, E.off_i + m[u]);
+        h[u] = label[E.off_j + n0 + u];
+        g[u] = label[E.off_i + m[u]];
+      }
+    }
+    double eh[kGrp], eg[kGrp];
+#pragma unroll
+    for (int u = 0; u < kGrp; ++u) {
+      eh[u] = h[u] >= 0 ? eta[h[u]] : 0.0;
+      eg[u] = g[u] >= 0 ? eta[g[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGrp; ++u) {
+      if (m[u] < 0) continue;
+      const float4 A = Xj[u], B = Xi[u];
+      const float dj2 = fmaf(A.x, A.x, fmaf(A.y, A.y, A.z * A.z));
+      const float di2 = fmaf(B.x, B.x, fmaf(B.y, B.y, B.z * B.z));
+      const float cc = B.w * A.w;
+      if (!(fminf(dj2, di2) > 1e-18f) || !(dj2 + di2 + cc < __builtin_huge_valf()) || !(cc >= 0.0f)) continue;
+      const float fh = expf(float(eh[u])), fg = expf(float(eg[u]));
+      const float a0 = A.x * fh, a1 = A.y * fh, a2 = A.z * fh;   // X_j(eta), eq. (8)
+      const float b0 = B.x * fg, b1 = B.y * fg, b2 = B.z * fg;   // X_i(eta)
+      const float s = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(cc)) * dc.inv_sigma;
+      const float R0 = fmaf(M[0], a0, fmaf(M[1], a1, M[2] * a2));  // sR_ij X_j(eta)
+      const float R1 = fmaf(M[3], a0, fmaf(M[4], a1, M[5] * a2));
+      const float R2 = fmaf(M[6], a0, fmaf(M[7], a1, M[8] * a2));
+      const float r0 = s * (R0 + M[9] - b0), r1 = s * (R1 + M[10] - b1), r2 = s * (R2 + M[11] - b2);
+      const float e0 = fabsf(r0), e1 = fabsf(r1), e2 = fabsf(r2);
+      const float w0 = fminf(1.0f, dc.kappa * __builtin_amdgcn_rcpf(e0));
+      const float w1 = fminf(1.0f, dc.kappa * __builtin_amdgcn_rcpf(e1));
+      const float w2 = fminf(1.0f, dc.kappa * __builtin_amdgcn_rcpf(e2));
+      const float t0 = w0 * e0, t1 = w1 * e1, t2 = w2 * e2;
+      cost += t0 * fmaf(-0.5f, t0, e0) + t1 * fmaf(-0.5f, t1, e1) + t2 * fmaf(-0.5f, t2, e2);
+      if (h[u] >= 0) {
+        if (h[u] != curj) {
+          run_flush(sHj, sGj, E.base_j, curj, hj, gj);
+          curj = h[u];
+        }
+        const float J0 = s * R0, J1 = s * R1, J2 = s * R2;
+        hj += w0 * J0 * J0 + w1 * J1 * J1 + w2 * J2 * J2;
+        gj += w0 * J0 * r0 + w1 * J1 * r1 + w2 * J2 * r2;
+      }
+      if (g[u] >= 0) {
+        if (g[u] != curi) {
+          run_flush(sHi, sGi, E.base_i, curi, hi, gi);
+          curi = g[u];
+        }
+        const float J0 = -s * b0, J1 = -s * b1, J2 = -s * b2;
+        hi += w0 * J0 * J0 + w1 * J1 * J1 + w2 * J2 * J2;
+        gi += w0 * J0 * r0 + w1 * J1 * r1 + w2 * J2 * r2;
+      }
     }
   }
+  run_flush(sHj, sGj, E.base_j, curj, hj, gj);
+  run_flush(sHi, sGi, E.base_i, curi, hi, gi);
   float c = wave_sum(cost);
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
   __syncthreads();

@@ -613,7 +613,9 @@ __device__ inline double cost_f64(const double* T, const float* xj, const float*
   const double d = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
   const double y0 = xi[0], y1 = xi[1], y2 = xi[2];
   const double di = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
-  const double e[4] = {x0 / d - y0 / di, x1 / d - y1 / di, x2 / d - y2 / di, d - di};
+  // one division per point (x / d within an ulp of the three divisions; the accept test needs ~1e-12)
+  const double rd = 1.0 / d, rdi = 1.0 / di;
+  const double e[4] = {x0 * rd - y0 * rdi, x1 * rd - y1 * rdi, x2 * rd - y2 * rdi, d - di};
   const double s = double(sq);
   const double kap = k.kappa_d;
   double c = 0.0;
@@ -669,13 +671,23 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
   const int cnt = seg_count[seg];
   Acc a;
   acc_zero(a);
+  // the next group of records is loaded before the current one is computed (one group in flight while the
+  // arithmetic of the other runs)
+  rec_t nxt[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = u * kReduceThreads + int(threadIdx.x);
+    if (q < cnt) nxt[u] = Rec<DT>::load(in + q);
+  }
 #pragma unroll 1
   for (int k0 = 0; k0 < cnt; k0 += kReduceThreads * U) {
     rec_t r[U];
 #pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = nxt[u];
+#pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int q = k0 + u * kReduceThreads + int(threadIdx.x);
-      if (q < cnt) r[u] = Rec<DT>::load(in + q);
+      const int q = k0 + kReduceThreads * U + u * kReduceThreads + int(threadIdx.x);
+      if (q < cnt) nxt[u] = Rec<DT>::load(in + q);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
