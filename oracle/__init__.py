@@ -22,7 +22,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ds3_oracle.cpp")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# DS3_ORACLE_LIB names another build of ds3_oracle.cpp to load (the sanitizer test's instrumented copy)
+_LIB_PATH = os.environ.get("DS3_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

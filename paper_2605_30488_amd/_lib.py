@@ -6,7 +6,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libds3.so")
+# DS3_LIB names another build of the library to load (the sanitizer test's host-instrumented copy)
+LIB_PATH = os.environ.get("DS3_LIB") or os.path.join(HERE, "libds3.so")
 
 F32, BF16 = 0, 1
 
