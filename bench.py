@@ -66,7 +66,7 @@ TRAFFIC = {
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "cb9ceb410efa1742", "bytes": 22959625472},
+        "sha": "cd177e10e74da9ba", "bytes": 22959933849},
     "k_fuse": {
         "sources": ["paper_2605_30488_amd/csrc/fuse.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/sim3.hpp"],
