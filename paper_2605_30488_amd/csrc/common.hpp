@@ -78,6 +78,20 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Sum over the 64 lanes with DPP moves (cross-lane operands of ordinary VALU adds, no LDS round trip):
+// pairs and quads (quad_perm), rows of 16 (row_shr 4 and 8), then row 15 broadcast into rows 1 and 3 and
+// lane 31 into rows 2 and 3; the total ends in lane 63 (the other lanes hold partial sums). Sources outside
+// a row or in a masked row contribute 0 (bound_ctrl, old = 0).
+__device__ inline float wave_sum_to_lane63(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, true));   // quad_perm [1,0,3,2]
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, true));   // quad_perm [2,3,0,1]
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));  // row_shr:4
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));  // row_shr:8
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, true));  // row_bcast:15
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, true));  // row_bcast:31
+  return v;
+}
+
 __device__ inline int wave_sum(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

@@ -316,8 +316,8 @@ __device__ inline void acc_block_store(Acc& a, float* __restrict__ out, float (*
   float* v = reinterpret_cast<float*>(&a);
 #pragma unroll
   for (int k = 0; k < 37; ++k) {
-    float s = wave_sum(v[k]);
-    if (lane == 0) lds[wave][k] = s;
+    const float s = wave_sum_to_lane63(v[k]);
+    if (lane == kWave - 1) lds[wave][k] = s;
   }
   __syncthreads();
   if (threadIdx.x < kPartial) {
