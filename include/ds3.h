@@ -254,6 +254,38 @@ int ds3_chol_ladder_solve(const double* H, const double* g, int32_t n, double la
                           double mult, int32_t attempts, double* tau, int32_t* status, void* workspace,
                           size_t ws_bytes, void* stream);
 
+/* Block-sparse form of ds3_chol_ladder_solve for the fixed 7x7-block pattern of a pose graph (eq. (7) and
+ * the epsilon ladder after it): H couples keyframes a and b only for the listed pairs.
+ * ds3_spchol_analyse (host only, no device use): symbolic analysis of the pattern of n_kf keyframes
+ * (1 <= n_kf <= 1170) and the n_pairs pairs pair_ij[2p], pair_ij[2p+1] (host; each in 0 .. n_kf-1,
+ * a != b, repeats allowed; DS3_EINVAL otherwise): a minimum-degree elimination order (ties: lowest id),
+ * the filled block pattern of the Cholesky factor and its elimination tree. Writes the elimination
+ * order by tree level (perm[c] = keyframe of factor column c; host, n_kf int32; may be NULL), each
+ * keyframe's tree level (level[k]; host, n_kf; may be NULL) and info (host, 6 int64): n_kf, blocks of
+ * the factor (diagonal ones included), fill blocks (not in the pattern), levels, block products of the
+ * factorisation, int32 words of the index tables.
+ * ds3_spchol_create: the same analysis, then device copies of the tables and the factor's storage
+ * (the object owns them; synchronises). DS3_ENOSPACE for more than 512 keyframes or index tables above
+ * 28672 words (the solve keeps both in LDS); the dense solver takes such patterns.
+ * ds3_spchol_solve: solves (H + lambda diag(H) + eps_r I) tau = -g with eps_r = eps0 * mult^r, r = 0 ..
+ * attempts-1 (1 <= attempts <= 16), on `stream`, in one launch and without host synchronisation. H is
+ * the symmetric (7 n_kf)^2 float64 matrix (device, row-major); only the lower triangle of its pattern
+ * blocks (the diagonal blocks and the listed pairs) is read and every other block counts as zero. g, tau:
+ * device, 7 n_kf float64; status (device int32) = the attempt used, or -1 with tau = 0 when every
+ * factorisation meets a pivot that is not positive and finite. Calls on one object must not overlap (they
+ * share its factor storage). The solve runs in one workgroup (level after level of the elimination tree;
+ * a small gather kernel over the device comes first), so one compute unit's memory pipeline bounds it:
+ * it does less arithmetic than the dense solver but is not faster on pose graphs of a few hundred
+ * keyframes, and the plans use the dense solver unless asked otherwise. */
+typedef struct ds3_spchol ds3_spchol;
+int ds3_spchol_analyse(int32_t n_kf, int32_t n_pairs, const int32_t* pair_ij, int32_t* perm, int32_t* level,
+                       int64_t* info);
+int ds3_spchol_create(int32_t n_kf, int32_t n_pairs, const int32_t* pair_ij, ds3_spchol** out);
+int ds3_spchol_info(const ds3_spchol* S, int64_t* info);
+int ds3_spchol_solve(ds3_spchol* S, const double* H, const double* g, double lambda, double eps0, double mult,
+                     int32_t attempts, double* tau, int32_t* status, void* stream);
+void ds3_spchol_destroy(ds3_spchol* S);
+
 /* Batched form: one plan per graph topology (edges, keyframe images, idx offsets) over a set of matches.
  * The matches and the pointmaps stay fixed while Gauss-Newton moves the poses, so the plan holds a match
  * stream: for every edge, the two arena entries (X_j[n] and X_i[m]) and the weight (C_i C_j)^(1/4) of each
@@ -280,6 +312,10 @@ typedef struct {
                               iteration of every ds3_gn_plan_run, which then runs as direct launches
                               instead of a graph replay (same kernels, same results) */
   int32_t unroll;          /* match records in flight per thread (1, 2 or 4; 0 = 2) when not autotuning */
+  int32_t solver;          /* normal equations of eq. (7): 0 or 1 = the dense solver (ds3_chol_ladder_solve,
+                              the default); 2 = the block-sparse solver of the plan's keyframe-pair
+                              pattern (ds3_spchol_*; DS3_ENOSPACE when the pattern does not fit it). Both
+                              run the same epsilon ladder. */
 } ds3_plan_opts;
 
 int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena, ds3_dtype dtype,
@@ -301,7 +337,8 @@ int ds3_gn_plan_time_reduce(void* plan, int32_t reps, float* ms_out, void* strea
  * edges, valid matches (idx in range), bytes of the streaming model (4 B idx per scanned px + both arena
  * entries per valid match), bytes the residual kernel reads per iteration (records + segment counts),
  * bytes one ds3_gn_plan_refresh moves (idx + both entries read, records written), records in flight per
- * thread]. */
+ * thread, solver (1 dense, 2 block-sparse), blocks of the sparse factor (0 for dense), levels of its
+ * elimination tree (0 for dense)]. */
 int ds3_gn_plan_info(void* plan, int64_t* info, int32_t n_info);
 int ds3_gn_plan_destroy(void* plan);
 /* The autotuner's cache: one line per (device, dtype, shape mix) with the tile shape it picked, in the

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libds3.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["capi.cpp", "capi_match.cpp", "gn.hip", "chol.hip", "match.hip", "gauge.hip", "misc.hip",
-           "adjoint.hip", "fuse.hip", "track.hip", "depth.hip"]
+           "adjoint.hip", "fuse.hip", "track.hip", "depth.hip", "spchol.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",

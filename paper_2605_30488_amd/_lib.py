@@ -56,7 +56,7 @@ class FusePair(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("px_per_thread", C.c_int32), ("use_graph", C.c_int32),
-                ("reduce_timer", C.c_void_p), ("unroll", C.c_int32)]
+                ("reduce_timer", C.c_void_p), ("unroll", C.c_int32), ("solver", C.c_int32)]
 
 
 _lib = None
@@ -102,6 +102,11 @@ _SIGS = {
     "ds3_gn_plan_create": (C.c_int, [i32, P_img, vp, C.c_int, P_edge, i32, vp, C.POINTER(GNParams), P_i32,
                                      i32, C.POINTER(PlanOpts), vp, C.POINTER(vp), vp]),
     "ds3_gn_plan_run": (C.c_int, [vp, i32, vp, vp, vp]),
+    "ds3_spchol_analyse": (C.c_int, [i32, i32, P_i32, P_i32, P_i32, P_i64]),
+    "ds3_spchol_create": (C.c_int, [i32, i32, P_i32, C.POINTER(vp)]),
+    "ds3_spchol_info": (C.c_int, [vp, P_i64]),
+    "ds3_spchol_solve": (C.c_int, [vp, vp, vp, f64, f64, f64, i32, vp, vp, vp]),
+    "ds3_spchol_destroy": (None, [vp]),
     "ds3_gn_plan_time_reduce": (C.c_int, [vp, i32, C.POINTER(C.c_float), vp]),
     "ds3_gn_plan_info": (C.c_int, [vp, P_i64, i32]),
     "ds3_gn_plan_refresh": (C.c_int, [vp, vp]),

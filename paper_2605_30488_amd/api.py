@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes as C
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -360,6 +361,66 @@ def chol_ladder_solve(H, g, lam=0.0, eps0=1e-6, mult=100.0, attempts=6):
     return tau, st
 
 
+def _pair_array(pairs):
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    return p, p.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+_SP_INFO = ("n_kf", "blocks", "fill_blocks", "levels", "products", "table_words")
+
+
+def spchol_analyse(n_kf: int, pairs):
+    """Host symbolic analysis of the keyframe-pair pattern (ds3_spchol_analyse): (perm, level, info)."""
+    p, pp = _pair_array(pairs)
+    perm = np.empty(max(n_kf, 1), dtype=np.int32)
+    level = np.empty(max(n_kf, 1), dtype=np.int32)
+    info = (C.c_int64 * 6)()
+    call("ds3_spchol_analyse", int(n_kf), len(p), pp, perm.ctypes.data_as(C.POINTER(C.c_int32)),
+         level.ctypes.data_as(C.POINTER(C.c_int32)), info)
+    return perm[:n_kf], level[:n_kf], dict(zip(_SP_INFO, list(info)))
+
+
+class SpChol:
+    """Block-sparse ladder solve (ds3_spchol_*) for a fixed keyframe-pair pattern of 7x7 blocks."""
+
+    def __init__(self, n_kf: int, pairs):
+        self.n_kf = int(n_kf)
+        p, pp = _pair_array(pairs)
+        h = C.c_void_p()
+        call("ds3_spchol_create", self.n_kf, len(p), pp, C.byref(h))
+        self.handle = h
+
+    def info(self) -> dict:
+        a = (C.c_int64 * 6)()
+        call("ds3_spchol_info", self.handle, a)
+        return dict(zip(_SP_INFO, list(a)))
+
+    def solve(self, H, g, lam=0.0, eps0=1e-6, mult=100.0, attempts=6, tau=None, status=None):
+        """(H + lam diag H + eps_r I) tau = -g on the pattern. Returns (tau, status int32[1])."""
+        n = 7 * self.n_kf
+        if H.shape != (n, n) or g.numel() != n or H.dtype != torch.float64 or g.dtype != torch.float64:
+            raise ValueError("H must be (7 n_kf)^2 float64 and g 7 n_kf float64")
+        H = H.contiguous()
+        g = g.contiguous()
+        _need_cuda(H, g)
+        tau = torch.empty(n, dtype=torch.float64, device=H.device) if tau is None else tau
+        st = torch.empty(1, dtype=torch.int32, device=H.device) if status is None else status
+        call("ds3_spchol_solve", self.handle, _ptr(H), _ptr(g), float(lam), float(eps0), float(mult),
+             int(attempts), _ptr(tau), _ptr(st), _stream())
+        return tau, st
+
+    def close(self):
+        if self.handle:
+            L.load().ds3_spchol_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class KernelTimer:
     """ds3_timer: HIP events that a library call records around one kernel launch on its stream."""
 
@@ -391,16 +452,16 @@ class GNPlan:
     launch over it per iteration, captured with the rest of the iteration in a hipGraph. Binds to
     `poses`, which every run updates in place. After the graph's idx (or arena) contents change, call
     refresh(). reduce_timer (a KernelTimer, kept alive by the plan) is recorded around the residual
-    launch."""
+    launch. solver: 0 or 1 the dense solve of eq. (7), 2 the block-sparse one (ds3_spchol_*)."""
 
     def __init__(self, graph: Graph, poses, params=None, autotune=False, px_per_thread=0, use_graph=True,
-                 reduce_timer=None, unroll=0):
+                 reduce_timer=None, unroll=0, solver=0):
         self.graph = graph
         self.poses = poses
         self.reduce_timer = reduce_timer
         P = params or default_gn_params()
         opts = L.PlanOpts(int(autotune), int(px_per_thread), int(use_graph),
-                          reduce_timer.handle if reduce_timer is not None else None, int(unroll))
+                          reduce_timer.handle if reduce_timer is not None else None, int(unroll), int(solver))
         h = C.c_void_p()
         call("ds3_gn_plan_create", graph.n_kf, graph.kf, _ptr(graph.arena.data), graph.dtype, graph.et,
              len(graph.edges), _ptr(graph.idx), C.byref(P), graph.an, len(graph.anchors), C.byref(opts),
@@ -430,10 +491,11 @@ class GNPlan:
         return ms.value
 
     def info(self) -> dict:
-        a = (C.c_int64 * 8)()
-        call("ds3_gn_plan_info", self.handle, a, 8)
+        a = (C.c_int64 * 11)()
+        call("ds3_gn_plan_info", self.handle, a, 11)
         return {"items": a[0], "px_per_thread": a[1], "px_scanned": a[2], "px_valid": a[3],
-                "bytes_streaming": a[4], "bytes_stream_per_iter": a[5], "bytes_refresh": a[6], "unroll": a[7]}
+                "bytes_streaming": a[4], "bytes_stream_per_iter": a[5], "bytes_refresh": a[6], "unroll": a[7],
+                "solver": "sparse" if a[8] == 2 else "dense", "factor_blocks": a[9], "factor_levels": a[10]}
 
     def close(self):
         if self.handle:

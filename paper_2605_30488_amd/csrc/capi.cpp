@@ -517,6 +517,7 @@ struct Plan {
   ds3_timer* timer = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  SpChol* sp = nullptr;        // block-sparse solver of the plan's pattern, NULL for the dense solver
 };
 
 // One GN iteration; `timed` records the plan's timer around the residual launch (never inside a capture).
@@ -533,8 +534,12 @@ static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
   DS3_TRY(launch_assemble(P.T.n_kf, P.B.node_ptr, P.B.node_adj, P.B.pair_ptr, P.B.pair_edges, P.B.pair_ij,
                           P.T.n_pairs, P.B.A_e, P.B.b_e, P.B.anchor, P.B.H, P.B.g, s));
   int32_t* status = reinterpret_cast<int32_t*>(P.B.counter + 8);
-  DS3_TRY(launch_chol_ladder(P.B.H, P.B.g, int(n), P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts,
-                             P.B.tau, status, P.B.chol_ws, s));
+  if (P.sp)
+    DS3_TRY(launch_spchol(P.sp, P.B.H, P.B.g, P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts, P.B.tau,
+                          status, s));
+  else
+    DS3_TRY(launch_chol_ladder(P.B.H, P.B.g, int(n), P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts,
+                               P.B.tau, status, P.B.chol_ws, s));
   DS3_TRY(launch_sim3_update(P.poses, P.B.tau, P.B.anchor, P.T.n_kf, s));
   // the cost at the iteration's input poses (cost_e is rewritten only by the next iteration) and the
   // ladder status go to the history
@@ -714,7 +719,23 @@ static void plan_free(Plan* P) {
   if (P->stream) (void)hipFree(P->stream);
   if (P->seg_count) (void)hipFree(P->seg_count);
   if (P->ecal) (void)hipFree(P->ecal);
+  spchol_destroy(P->sp);
   delete P;
+}
+
+// Solver of the normal equations: solver 0 or 1 the dense one, 2 the block-sparse one for the plan's pattern
+// (pairs that touch an anchor are zero blocks of H and stay out of the pattern).
+static int plan_pick_solver(Plan& P, int solver) {
+  if (solver < 0 || solver > 2) return fail(DS3_EINVAL, "plan: solver must be 0, 1 or 2");
+  if (solver != 2) return DS3_OK;
+  std::vector<int32_t> pairs;
+  for (int p = 0; p < P.T.n_pairs; ++p) {
+    const int a = P.T.pair_ij[2 * p], b = P.T.pair_ij[2 * p + 1];
+    if (P.T.anchor[a] || P.T.anchor[b]) continue;
+    pairs.push_back(a);
+    pairs.push_back(b);
+  }
+  return spchol_create(P.T.n_kf, int(pairs.size() / 2), pairs.data(), &P.sp);
 }
 
 int timer_record(ds3_timer* t, bool begin, hipStream_t s) {
@@ -816,6 +837,7 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
   P->use_graph = !opts || opts->use_graph != 0;
   P->timer = opts ? opts->reduce_timer : nullptr;
   rc = upload_topology(P->T, P->B, s);
+  if (rc == DS3_OK) rc = plan_pick_solver(*P, opts ? opts->solver : 0);
   if (rc == DS3_OK) rc = launch_fill(P->B.H, 49 * size_t(P->T.n_kf) * size_t(P->T.n_kf), 0.0, s);
   if (rc == DS3_OK) rc = launch_fill_u32(P->B.counter, 64, 0u, s);
   if (rc == DS3_OK) rc = launch_fill_u32(P->hist_ctr, 4, 0u, s);
@@ -891,12 +913,14 @@ int ds3_gn_plan_info(void* plan, int64_t* info, int32_t n_info) {
   if (!P || !info || n_info < 0) return fail(DS3_EINVAL, "plan_info: bad arguments");
   const int64_t px_bytes = P->dt == DS3_F32 ? 16 : 8;
   const int64_t rec = int64_t(stream_record_bytes(P->dt, P->ecal != nullptr));
-  const int64_t v[8] = {P->n_items, P->ppt, P->px_scanned, P->px_valid,
-                        4 * P->px_scanned + 2 * px_bytes * P->px_valid,
-                        rec * P->n_records + 4 * int64_t(P->n_items),
-                        4 * P->px_scanned + 2 * px_bytes * P->px_valid + rec * P->n_records + 4 * int64_t(P->n_items),
-                        P->unroll};
-  for (int k = 0; k < n_info && k < 8; ++k) info[k] = v[k];
+  int64_t sp[6] = {0, 0, 0, 0, 0, 0};
+  if (P->sp) spchol_stats(P->sp, sp);
+  const int64_t v[11] = {P->n_items, P->ppt, P->px_scanned, P->px_valid,
+                         4 * P->px_scanned + 2 * px_bytes * P->px_valid,
+                         rec * P->n_records + 4 * int64_t(P->n_items),
+                         4 * P->px_scanned + 2 * px_bytes * P->px_valid + rec * P->n_records + 4 * int64_t(P->n_items),
+                         P->unroll, P->sp ? 2 : 1, sp[1], sp[3]};
+  for (int k = 0; k < n_info && k < 11; ++k) info[k] = v[k];
   return DS3_OK;
 }
 

@@ -154,6 +154,14 @@ size_t chol_workspace_bytes(int n);
 int launch_chol_ladder(const double* H, const double* g, int n, double lambda, double eps0, double mult,
                        int attempts, double* tau, int32_t* status, void* ws, hipStream_t s);
 
+// spchol.hip: block-sparse ladder solve for a fixed keyframe-pair pattern
+struct SpChol;
+int spchol_create(int n_kf, int n_pairs, const int32_t* pair_ij, SpChol** out);
+void spchol_destroy(SpChol* P);
+void spchol_stats(const SpChol* P, int64_t* info);  // n_kf, blocks, fill blocks, levels, products, words
+int launch_spchol(const SpChol* P, const double* H, const double* g, double lambda, double eps0, double mult,
+                  int attempts, double* tau, int32_t* status, hipStream_t s);
+
 // sim3.hip
 int launch_sim3_exp(const double* tau, double* poses, int n, hipStream_t s);
 int launch_sim3_log(const double* poses, double* tau, int n, hipStream_t s);

@@ -153,6 +153,27 @@ def test_plan_refresh_follows_new_matches(dev, single, dtype):
         p.close()
 
 
+def test_plan_sparse_and_dense_solvers_agree(dev, single):
+    """The plan's block-sparse solve of eq. (7) (solver=2) and its dense solve (the default) give the same
+    poses over five iterations (the factorisations round differently, nothing else differs); the anchor's
+    pairs stay out of the sparse pattern."""
+    g, idx = single
+    G = _graph(g, idx, "f32", dev)
+    Ps, Pd = _t(g.poses_init, dev), _t(g.poses_init, dev)
+    ps = ds3.GNPlan(G, Ps, solver=2)
+    pd = ds3.GNPlan(G, Pd)
+    assert ps.info()["solver"] == "sparse" and pd.info()["solver"] == "dense"
+    assert 0 < ps.info()["factor_blocks"] < 20 * 21 // 2
+    cs, ss = ps.run(5)
+    cd, sd = pd.run(5)
+    err = O.pose_error(Ps.cpu().numpy(), Pd.cpu().numpy()).max()
+    assert err < 1e-9, err
+    assert np.allclose(cs.cpu().numpy(), cd.cpu().numpy(), rtol=1e-9)
+    assert np.all(ss.cpu().numpy() == 0) and np.all(sd.cpu().numpy() == 0)
+    ps.close()
+    pd.close()
+
+
 def test_graph_replays_match_direct_launches(dev, single):
     """Each replay of the captured iteration equals the same launches issued directly (bit for bit),
     with eager work and synchronisation between replays."""
