@@ -289,9 +289,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather(
     const void* __restrict__ arena, const EdgeDev* __restrict__ edges, const EdgeXf* __restrict__ xf,
     const int32_t* __restrict__ idx_arena, const int64_t* __restrict__ kf_off, const int32_t* __restrict__ kf_npx,
     const int32_t* __restrict__ node_ptr, const int32_t* __restrict__ node_adj, const int64_t* __restrict__ obase,
-    const int64_t* __restrict__ sbase, const int32_t* __restrict__ inv_off, const int32_t* __restrict__ inv_src,
-    GnConst k, float dcost, float* __restrict__ grad_xyz, float* __restrict__ grad_conf,
-    float* __restrict__ part7, int stride) {
+    const int64_t* __restrict__ sbase, const int64_t* __restrict__ cbase, const int32_t* __restrict__ inv_off,
+    const int32_t* __restrict__ inv_src, const int32_t* __restrict__ inv_head, GnConst k, float dcost,
+    float* __restrict__ grad_xyz, float* __restrict__ grad_conf, float* __restrict__ part7, int stride) {
   using raw_t = typename Px<DT>::raw_t;
   const int kf = blockIdx.y;
   const int tile = blockIdx.x;
@@ -352,8 +352,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather(
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const float v = wave_sum(g8[c]);
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
+      const float v = wave_sum_to_lane63(g8[c]);
+      if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6][c] = v;
     }
     __syncthreads();
     if (threadIdx.x < 8) {
@@ -371,25 +371,33 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather(
     float M[12];
 #pragma unroll
     for (int r = 0; r < 12; ++r) M[r] = xf[e].m[r];
-    const int32_t* lo = inv_off + obase[e];
-    const int32_t* lst = inv_src + sbase[e];
-    int la[kAdjPPT], lb[kAdjPPT], n0[kAdjPPT];
+    const int32_t* hd = inv_head + cbase[e];
+    int h[kAdjPPT], n0[kAdjPPT];
 #pragma unroll
     for (int u = 0; u < kAdjPPT; ++u) {
       const int m = p0 + u * kAdjThreads;
-      la[u] = (m < npx) ? lo[m] : 0;
-      lb[u] = (m < npx) ? lo[m + 1] : 0;
+      h[u] = (m < npx) ? hd[m] : -1;
+      n0[u] = (h[u] >= 0) ? h[u] : ((h[u] <= -2) ? -2 - h[u] : -1);
     }
-#pragma unroll
-    for (int u = 0; u < kAdjPPT; ++u) n0[u] = (la[u] < lb[u]) ? lst[la[u]] : -1;
     raw_t xj[kAdjPPT];
 #pragma unroll
     for (int u = 0; u < kAdjPPT; ++u) xj[u] = Px<DT>::load_raw(arena, E.off_j + (n0[u] >= 0 ? n0[u] : 0));
 #pragma unroll
     for (int u = 0; u < kAdjPPT; ++u) {
+      if (n0[u] < 0) continue;
       const float4 Xi = Px<DT>::unpack(xr[u]);
-      for (int x = la[u]; x < lb[u]; ++x) {  // the first entry is loaded above; more are rare
-        const float4 Xj = (x == la[u]) ? Px<DT>::unpack(xj[u]) : Px<DT>::load(arena, E.off_j + lst[x]);
+      // the first query pixel from the head word; the rest of a longer list (rare) from the CSR, in
+      // increasing n as before
+      int x = 0, xe = 0;
+      if (h[u] <= -2) {
+        const int32_t* lo = inv_off + obase[e];
+        const int m = p0 + u * kAdjThreads;
+        x = lo[m];
+        xe = lo[m + 1];
+      }
+      const int32_t* lst = inv_src + sbase[e];
+      for (bool first = true; first || x + 1 < xe; first = false) {
+        const float4 Xj = first ? Px<DT>::unpack(xj[u]) : Px<DT>::load(arena, E.off_j + lst[++x]);
         AdjPix o;
         if (!adj_pixel(Xj, Xi, M, k, dcost, o)) continue;
         const float pgi = o.pi[0] * o.gam[0] + o.pi[1] * o.gam[1] + o.pi[2] * o.gam[2];
@@ -593,9 +601,26 @@ int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_
   return check_hip(hipGetLastError(), "k_grad_tau");
 }
 
+// One word per pixel m of keyframe i(e) for the gather: -1 when no query pixel is matched to m, the pixel
+// n when exactly one is, -2 - n (n the first of the list) when several are (the rest stay in the CSR).
+__global__ __launch_bounds__(256) void k_inv_head(const EdgeDev* __restrict__ edges,
+                                                  const int64_t* __restrict__ cbase,
+                                                  const int64_t* __restrict__ obase,
+                                                  const int64_t* __restrict__ sbase,
+                                                  const int32_t* __restrict__ off, const int32_t* __restrict__ src,
+                                                  int32_t* __restrict__ head) {
+  const int e = blockIdx.y;
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= edges[e].npx_i) return;
+  const int32_t* o = off + obase[e];
+  const int a = o[m], b = o[m + 1];
+  const int32_t n0 = (b > a) ? src[sbase[e] + a] : 0;
+  head[cbase[e] + m] = (b == a) ? -1 : ((b == a + 1) ? n0 : -2 - n0);
+}
+
 int launch_inverse_maps(const EdgeDev* edges, int n_edges, int max_npx_j, int max_npx_i, const int32_t* idx,
                         const int64_t* cbase, const int64_t* obase, const int64_t* sbase, int32_t* cnt,
-                        size_t cnt_len, int32_t* off, int32_t* src, hipStream_t s) {
+                        size_t cnt_len, int32_t* off, int32_t* src, int32_t* head, hipStream_t s) {
   if (n_edges <= 0) return 0;
   DS3_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(cnt), cnt_len, 0u, s));
   const dim3 gj((max_npx_j + 255) / 256, n_edges), gi((max_npx_i + 255) / 256, n_edges);
@@ -607,7 +632,9 @@ int launch_inverse_maps(const EdgeDev* edges, int n_edges, int max_npx_j, int ma
   hipLaunchKernelGGL(k_inv_fill, gj, dim3(256), 0, s, edges, idx, cbase, obase, sbase, off, cnt, src);
   DS3_TRY(check_hip(hipGetLastError(), "k_inv_fill"));
   hipLaunchKernelGGL(k_inv_sort, gi, dim3(256), 0, s, edges, obase, sbase, off, src);
-  return check_hip(hipGetLastError(), "k_inv_sort");
+  DS3_TRY(check_hip(hipGetLastError(), "k_inv_sort"));
+  hipLaunchKernelGGL(k_inv_head, gi, dim3(256), 0, s, edges, cbase, obase, sbase, off, src, head);
+  return check_hip(hipGetLastError(), "k_inv_head");
 }
 
 int launch_adjoint_gather(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
@@ -615,8 +642,9 @@ int launch_adjoint_gather(ds3_dtype dt, const void* arena, const EdgeDev* edges,
                           float dcost, float* grad_xyz, float* grad_conf, float* part7, double* b_e,
                           double* cost_e, int64_t* count_e, int n_kf, const int64_t* kf_off,
                           const int32_t* kf_npx, const int32_t* node_ptr, const int32_t* node_adj,
-                          const int64_t* obase, const int64_t* sbase, const int32_t* inv_off,
-                          const int32_t* inv_src, double* grad_tau, ds3_timer* timer, hipStream_t s) {
+                          const int64_t* obase, const int64_t* sbase, const int64_t* cbase,
+                          const int32_t* inv_off, const int32_t* inv_src, const int32_t* inv_head, double* grad_tau,
+                          ds3_timer* timer, hipStream_t s) {
   const int tiles = (max_npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
   const int tiles_kf = (max_npx_kf + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
   DS3_TRY(timer_record(timer, true, s));
@@ -624,12 +652,12 @@ int launch_adjoint_gather(ds3_dtype dt, const void* arena, const EdgeDev* edges,
     dim3 grid(tiles_kf, n_kf), block(kAdjThreads);
     if (dt == DS3_F32)
       hipLaunchKernelGGL(k_adjoint_gather<DS3_F32>, grid, block, 0, s, arena, edges, xf, idx, kf_off, kf_npx,
-                         node_ptr, node_adj, obase, sbase, inv_off, inv_src, c, dcost, grad_xyz, grad_conf, part7,
-                         tiles);
+                         node_ptr, node_adj, obase, sbase, cbase, inv_off, inv_src, inv_head, c, dcost, grad_xyz,
+                         grad_conf, part7, tiles);
     else
       hipLaunchKernelGGL(k_adjoint_gather<DS3_BF16>, grid, block, 0, s, arena, edges, xf, idx, kf_off, kf_npx,
-                         node_ptr, node_adj, obase, sbase, inv_off, inv_src, c, dcost, grad_xyz, grad_conf, part7,
-                         tiles);
+                         node_ptr, node_adj, obase, sbase, cbase, inv_off, inv_src, inv_head, c, dcost, grad_xyz,
+                         grad_conf, part7, tiles);
     DS3_TRY(check_hip(hipGetLastError(), "k_adjoint_gather"));
   }
   DS3_TRY(timer_record(timer, false, s));

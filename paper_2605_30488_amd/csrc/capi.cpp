@@ -180,14 +180,15 @@ int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_
 
 int launch_inverse_maps(const EdgeDev* edges, int n_edges, int max_npx_j, int max_npx_i, const int32_t* idx,
                         const int64_t* cbase, const int64_t* obase, const int64_t* sbase, int32_t* cnt,
-                        size_t cnt_len, int32_t* off, int32_t* src, hipStream_t s);
+                        size_t cnt_len, int32_t* off, int32_t* src, int32_t* head, hipStream_t s);
 int launch_adjoint_gather(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
                           int max_npx_kf, const EdgeXf* xf, const double* Ad, const int32_t* idx, GnConst c,
                           float dcost, float* grad_xyz, float* grad_conf, float* part7, double* b_e,
                           double* cost_e, int64_t* count_e, int n_kf, const int64_t* kf_off,
                           const int32_t* kf_npx, const int32_t* node_ptr, const int32_t* node_adj,
-                          const int64_t* obase, const int64_t* sbase, const int32_t* inv_off,
-                          const int32_t* inv_src, double* grad_tau, ds3_timer* timer, hipStream_t s);
+                          const int64_t* obase, const int64_t* sbase, const int64_t* cbase,
+                          const int32_t* inv_off, const int32_t* inv_src, const int32_t* inv_head, double* grad_tau,
+                          ds3_timer* timer, hipStream_t s);
 int launch_cost_batched(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
                         const EdgeXf* xf, const int32_t* idx, GnConst c, float* part, double* cost_e,
                         int64_t* count_e, hipStream_t s);
@@ -962,8 +963,8 @@ struct AdjPlan {
   int64_t* kf_off = nullptr;
   int32_t *kf_npx = nullptr, *node_ptr = nullptr, *node_adj = nullptr;
   float* part7 = nullptr;
-  int64_t *obase = nullptr, *sbase = nullptr;
-  int32_t *inv_off = nullptr, *inv_src = nullptr;
+  int64_t *obase = nullptr, *sbase = nullptr, *cbase = nullptr;
+  int32_t *inv_off = nullptr, *inv_src = nullptr, *inv_head = nullptr;
   const void* arena = nullptr;
   const int32_t* idx = nullptr;
   ds3_dtype dt = DS3_F32;
@@ -971,7 +972,8 @@ struct AdjPlan {
   int max_npx_j = 0, max_npx_kf = 0;
 };
 
-static size_t carve_adj(void* base, const Topology& T, AdjPlan& A, size_t off_len, size_t src_len) {
+static size_t carve_adj(void* base, const Topology& T, AdjPlan& A, size_t off_len, size_t src_len,
+                        size_t cnt_len) {
   Carver c(base);
   const int E = std::max(T.n_edges, 1);
   A.edges = c.take<EdgeDev>(E);
@@ -987,8 +989,10 @@ static size_t carve_adj(void* base, const Topology& T, AdjPlan& A, size_t off_le
   A.part7 = c.take<float>(size_t(std::max(adjoint_part_floats(T.n_edges, max_npx_j(T)), 8)));
   A.obase = c.take<int64_t>(E);
   A.sbase = c.take<int64_t>(E);
+  A.cbase = c.take<int64_t>(E);
   A.inv_off = c.take<int32_t>(std::max<size_t>(off_len, 1));
   A.inv_src = c.take<int32_t>(std::max<size_t>(src_len, 1));
+  A.inv_head = c.take<int32_t>(std::max<size_t>(cnt_len, 1));
   return c.used;
 }
 
@@ -1025,25 +1029,23 @@ int ds3_adjoint_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena
     src_len += size_t(T.edges[e].npx_j);
     max_npx_i = std::max(max_npx_i, int(T.edges[e].npx_i));
   }
-  const size_t ws = carve_adj(nullptr, T, *A, off_len, src_len);
+  const size_t ws = carve_adj(nullptr, T, *A, off_len, src_len, cnt_len);
   rc = check_hip(hipMalloc(&A->ws, ws), "hipMalloc(adjoint plan)");
   if (rc != DS3_OK) { adj_plan_free(A); return rc; }
-  carve_adj(A->ws, T, *A, off_len, src_len);
+  carve_adj(A->ws, T, *A, off_len, src_len, cnt_len);
   A->arena = arena;
   A->idx = idx;
   A->dt = dtype;
   A->c = make_gn_const(*params);
   A->max_npx_j = max_npx_j(T);
   A->max_npx_kf = *std::max_element(T.kf_npx.begin(), T.kf_npx.end());
-  // counts and the per-edge bases of the count array live in a temporary allocation
+  // the counts live in a temporary allocation
   void* tmp = nullptr;
   Carver tc(nullptr);
-  tc.take<int64_t>(cbase.size());
   tc.take<int32_t>(std::max<size_t>(cnt_len, 1));
   rc = check_hip(hipMalloc(&tmp, tc.used), "hipMalloc(adjoint plan build)");
   if (rc != DS3_OK) { adj_plan_free(A); return rc; }
   Carver tcc(tmp);
-  int64_t* d_cbase = tcc.take<int64_t>(cbase.size());
   int32_t* d_cnt = tcc.take<int32_t>(std::max<size_t>(cnt_len, 1));
   rc = upload(A->edges, T.edges, s);
   if (rc == DS3_OK) rc = upload(A->kf_off, T.kf_off, s);
@@ -1052,10 +1054,10 @@ int ds3_adjoint_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena
   if (rc == DS3_OK) rc = upload(A->node_adj, T.node_adj, s);
   if (rc == DS3_OK) rc = upload(A->obase, obase, s);
   if (rc == DS3_OK) rc = upload(A->sbase, sbase, s);
-  if (rc == DS3_OK) rc = upload(d_cbase, cbase, s);
+  if (rc == DS3_OK) rc = upload(A->cbase, cbase, s);
   if (rc == DS3_OK)
-    rc = launch_inverse_maps(A->edges, T.n_edges, A->max_npx_j, max_npx_i, idx, d_cbase, A->obase, A->sbase,
-                             d_cnt, cnt_len, A->inv_off, A->inv_src, s);
+    rc = launch_inverse_maps(A->edges, T.n_edges, A->max_npx_j, max_npx_i, idx, A->cbase, A->obase, A->sbase,
+                             d_cnt, cnt_len, A->inv_off, A->inv_src, A->inv_head, s);
   const int rs = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize(adjoint plan build)");
   (void)hipFree(tmp);
   if (rc == DS3_OK) rc = rs;
@@ -1074,7 +1076,7 @@ int ds3_adjoint_plan_run(void* plan, const double* poses, float dcost, float* gr
   DS3_TRY(launch_adjoint_gather(A->dt, A->arena, A->edges, T.n_edges, A->max_npx_j, A->max_npx_kf, A->xf, A->Ad,
                                 A->idx, A->c, dcost, grad_xyz, grad_conf, A->part7, A->b_e, A->cost_e,
                                 A->count_e, T.n_kf, A->kf_off, A->kf_npx, A->node_ptr, A->node_adj, A->obase,
-                                A->sbase, A->inv_off, A->inv_src, grad_tau, timer, s));
+                                A->sbase, A->cbase, A->inv_off, A->inv_src, A->inv_head, grad_tau, timer, s));
   if (cost_out) DS3_TRY(launch_sum_costs(A->cost_e, A->count_e, T.n_edges, cost_out, nullptr, s));
   return DS3_OK;
 }
