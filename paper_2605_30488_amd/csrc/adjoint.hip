@@ -20,6 +20,7 @@
 namespace ds3 {
 
 constexpr int kAdjThreads = 256;
+constexpr int kAdjWaves = kAdjThreads / kWave;  // per-edge partials are written per wave (no block barrier)
 constexpr int kAdjPPT = 2;  // 65 VGPRs, 7 waves per SIMD in the gather (4: 99 VGPRs and 15% slower; 1: block reductions dominate)
 
 // Forward pass and cotangents of one match (n of j, m of i), scaled by dcost. Returns false for the
@@ -102,7 +103,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather_j(
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[u][c] = 0.0f;
   }
-  __shared__ float red[kAdjThreads / kWave][8];
   for (int q = node_ptr[kf]; q < node_ptr[kf + 1]; ++q) {
     const int code = node_adj[q];
     if (!(code & 1)) continue;  // this keyframe is the gathered side of that edge
@@ -134,18 +134,13 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather_j(
       g7[5] += o.x[0] * o.gx[1] - o.x[1] * o.gx[0];
       g7[6] += o.x[0] * o.gx[0] + o.x[1] * o.gx[1] + o.x[2] * o.gx[2];
     }
+    // one partial per wave and edge, summed in a fixed order by the edge finalize
+    float* pw = part7 + ((int64_t(e) * stride + tile) * kAdjWaves + (threadIdx.x >> 6)) * 8;
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
-      const float v = wave_sum(g7[c]);
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
+      const float v = wave_sum_to_lane63(g7[c]);
+      if ((threadIdx.x & 63) == 63) pw[c] = v;
     }
-    __syncthreads();
-    if (threadIdx.x < 7) {
-      float v = 0.0f;
-      for (int w = 0; w < kAdjThreads / kWave; ++w) v += red[w][threadIdx.x];
-      part7[(int64_t(e) * stride + tile) * 8 + threadIdx.x] = v;
-    }
-    __syncthreads();  // red is reused by the next edge
   }
 #pragma unroll
   for (int u = 0; u < kAdjPPT; ++u) {
@@ -308,7 +303,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather(
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[u][c] = 0.0f;
   }
-  __shared__ float red[kAdjThreads / kWave][8];
   const int q0 = node_ptr[kf], q1 = node_ptr[kf + 1];
   for (int q = q0; q < q1; ++q) {  // query side: pixel n of this keyframe, its match m in i
     const int code = node_adj[q];
@@ -350,18 +344,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint_gather(
       g8[6] += o.x[0] * o.gx[0] + o.x[1] * o.gx[1] + o.x[2] * o.gx[2];
       g8[7] += o.rho;
     }
+    // one partial per wave and edge (the waves of the block never wait for each other), summed in a
+    // fixed order by the edge finalize
+    float* pw = part7 + ((int64_t(e) * stride + tile) * kAdjWaves + (threadIdx.x >> 6)) * 8;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const float v = wave_sum_to_lane63(g8[c]);
-      if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6][c] = v;
+      if ((threadIdx.x & 63) == 63) pw[c] = v;
     }
-    __syncthreads();
-    if (threadIdx.x < 8) {
-      float v = 0.0f;
-      for (int w = 0; w < kAdjThreads / kWave; ++w) v += red[w][threadIdx.x];
-      part7[(int64_t(e) * stride + tile) * 8 + threadIdx.x] = v;
-    }
-    __syncthreads();  // red is reused by the next edge
   }
   for (int q = q0; q < q1; ++q) {  // gathered side: pixel m of this keyframe, the query pixels matched to it
     const int code = node_adj[q];
@@ -529,7 +519,8 @@ __global__ void k_adjoint_edge_finalize(const EdgeDev* __restrict__ edges, int t
   const int tiles_e = (E.npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
   double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = 0; t < tiles_e; ++t)
-    for (int c = 0; c < 8; ++c) s[c] += double(part7[(int64_t(e) * tiles_stride + t) * 8 + c]);
+    for (int w = 0; w < kAdjWaves; ++w)
+      for (int c = 0; c < 8; ++c) s[c] += double(part7[((int64_t(e) * tiles_stride + t) * kAdjWaves + w) * 8 + c]);
   if (cost_e) {
     cost_e[e] = s[7];
     count_e[e] = 0;
@@ -559,7 +550,7 @@ __global__ void k_grad_tau(int n_kf, const int32_t* __restrict__ node_ptr, const
 
 int adjoint_part_floats(int n_edges, int max_npx_j) {
   const int tiles = (max_npx_j + kAdjThreads * kAdjPPT - 1) / (kAdjThreads * kAdjPPT);
-  return n_edges * tiles * 8;
+  return n_edges * tiles * kAdjWaves * 8;
 }
 
 int launch_adjoint(ds3_dtype dt, const void* arena, const EdgeDev* edges, int n_edges, int max_npx_j,
