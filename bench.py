@@ -74,7 +74,7 @@ TRAFFIC = {
     "k_dr_data": {
         "sources": ["paper_2605_30488_amd/csrc/depth.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "aa4a89855ba4b3bf", "bytes": 2761144627},
+        "sha": "71ec44623495df06", "bytes": 2785807770},
 }
 
 

@@ -357,8 +357,9 @@ struct DepthEdge {
 };
 
 // One block per (edge, tile of keyframe j): data-term sums of the segments it touches, flushed with float64
-// atomics; the block's cost into its partial. A thread takes groups of kGrp consecutive pixels of j: all
-// loads of a group are issued together (matches, both points, both labels, then both log-scales), and
+// atomics; the block's cost into its partial. The scale factors exp(eta) of both keyframes' segments are
+// formed once per block into LDS. A thread takes groups of kGrp consecutive pixels of j: all loads of a
+// group are issued together (matches, both points, both labels), and
 // consecutive matches of one segment (the usual case: segments are tens of pixels wide and neighbouring
 // matches land in neighbouring pixels of i) are summed in registers before one LDS add per run.
 constexpr int kGrp = 4;
@@ -380,14 +381,19 @@ __global__ __launch_bounds__(kDepthThreads) void k_dr_data(const void* __restric
                                                            const EdgeXf* __restrict__ xf,
                                                            const int32_t* __restrict__ idx_arena,
                                                            const int32_t* __restrict__ label,
-                                                           const double* __restrict__ eta, DepthConst dc,
+                                                           const double* __restrict__ eta, int n_seg, DepthConst dc,
                                                            double* __restrict__ Hd, double* __restrict__ gd,
                                                            float* __restrict__ cost_part) {
   __shared__ float sHj[kMaxSegPerKf], sGj[kMaxSegPerKf], sHi[kMaxSegPerKf], sGi[kMaxSegPerKf];
+  __shared__ float sEj[kMaxSegPerKf], sEi[kMaxSegPerKf];  // exp(eta) of the two keyframes' segments, eq. (8)
   __shared__ float red[kDepthThreads / kWave];
   const int2 W = items[blockIdx.x];
   const DepthEdge E = edges[W.x];
-  for (int q = threadIdx.x; q < kMaxSegPerKf; q += kDepthThreads) sHj[q] = sGj[q] = sHi[q] = sGi[q] = 0.0f;
+  for (int q = threadIdx.x; q < kMaxSegPerKf; q += kDepthThreads) {
+    sHj[q] = sGj[q] = sHi[q] = sGi[q] = 0.0f;
+    sEj[q] = (E.base_j + q < n_seg) ? expf(float(eta[E.base_j + q])) : 1.0f;
+    sEi[q] = (E.base_i + q < n_seg) ? expf(float(eta[E.base_i + q])) : 1.0f;
+  }
   __syncthreads();
   float M[12];
 #pragma unroll
@@ -419,12 +425,6 @@ __global__ __launch_bounds__(kDepthThreads) void k_dr_data(const void* __restric
         g[u] = label[E.off_i + m[u]];
       }
     }
-    double eh[kGrp], eg[kGrp];
-#pragma unroll
-    for (int u = 0; u < kGrp; ++u) {
-      eh[u] = h[u] >= 0 ? eta[h[u]] : 0.0;
-      eg[u] = g[u] >= 0 ? eta[g[u]] : 0.0;
-    }
 #pragma unroll
     for (int u = 0; u < kGrp; ++u) {
       if (m[u] < 0) continue;
@@ -433,7 +433,8 @@ __global__ __launch_bounds__(kDepthThreads) void k_dr_data(const void* __restric
       const float di2 = fmaf(B.x, B.x, fmaf(B.y, B.y, B.z * B.z));
       const float cc = B.w * A.w;
       if (!(fminf(dj2, di2) > 1e-18f) || !(dj2 + di2 + cc < __builtin_huge_valf()) || !(cc >= 0.0f)) continue;
-      const float fh = expf(float(eh[u])), fg = expf(float(eg[u]));
+      const float fh = h[u] >= 0 ? sEj[h[u] - E.base_j] : 1.0f;  // exp(0) for a pixel without a segment
+      const float fg = g[u] >= 0 ? sEi[g[u] - E.base_i] : 1.0f;
       const float a0 = A.x * fh, a1 = A.y * fh, a2 = A.z * fh;   // X_j(eta), eq. (8)
       const float b0 = B.x * fg, b1 = B.y * fg, b2 = B.z * fg;   // X_i(eta)
       const float s = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(cc)) * dc.inv_sigma;
@@ -847,10 +848,10 @@ int ds3_depth_plan_run(void* plan, const double* poses, int32_t iters, double* c
     if (P->n_items > 0) {
       if (P->dt == DS3_F32)
         hipLaunchKernelGGL(k_dr_data<DS3_F32>, dim3(P->n_items), dim3(kDepthThreads), 0, s, P->arena, P->edges, P->items,
-                           P->xf, P->idx, P->label, P->eta, P->dc, P->Hd, P->gd, P->data_part);
+                           P->xf, P->idx, P->label, P->eta, P->n_seg, P->dc, P->Hd, P->gd, P->data_part);
       else
         hipLaunchKernelGGL(k_dr_data<DS3_BF16>, dim3(P->n_items), dim3(kDepthThreads), 0, s, P->arena, P->edges, P->items,
-                           P->xf, P->idx, P->label, P->eta, P->dc, P->Hd, P->gd, P->data_part);
+                           P->xf, P->idx, P->label, P->eta, P->n_seg, P->dc, P->Hd, P->gd, P->data_part);
       DS3_TRY(check_hip(hipGetLastError(), "k_dr_data"));
     }
     if (timed) DS3_TRY(timer_record(data_timer, false, s));
