@@ -605,16 +605,25 @@ __global__ __launch_bounds__(kReduceThreads) void k_gather_stream(const void* __
 
 // E of one match in float64 (eq. (1), whitening and Huber as acc_core) from the stored values and a
 // float64 T_ij; used where a decision compares two costs that differ by less than float32 resolves.
+__device__ inline double rsqrt_f64(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
 __device__ inline double cost_f64(const double* T, const float* xj, const float* xi, float sq, const GnConst& k) {
   const double X0 = xj[0], X1 = xj[1], X2 = xj[2];
   const double x0 = T[0] * X0 + T[1] * X1 + T[2] * X2 + T[9];
   const double x1 = T[3] * X0 + T[4] * X1 + T[5] * X2 + T[10];
   const double x2 = T[6] * X0 + T[7] * X1 + T[8] * X2 + T[11];
-  const double d = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
   const double y0 = xi[0], y1 = xi[1], y2 = xi[2];
-  const double di = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
-  // one division per point (x / d within an ulp of the three divisions; the accept test needs ~1e-12)
-  const double rd = 1.0 / d, rdi = 1.0 / di;
+  // 1/|x| from the hardware estimate refined by two Newton steps (to the last bits; the accept test needs
+  // ~1e-12), |x| = |x|^2 / |x|: no square root and no division per point
+  const double d2 = x0 * x0 + x1 * x1 + x2 * x2, di2 = y0 * y0 + y1 * y1 + y2 * y2;
+  const double rd = rsqrt_f64(d2), rdi = rsqrt_f64(di2);
+  const double d = d2 * rd, di = di2 * rdi;
   const double e[4] = {x0 * rd - y0 * rdi, x1 * rd - y1 * rdi, x2 * rd - y2 * rdi, d - di};
   const double s = double(sq);
   const double kap = k.kappa_d;
