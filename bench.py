@@ -50,15 +50,15 @@ TRAFFIC = {
     "k_reduce_stream": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "39a58bcb0332be64", "bytes": 1148654387},
+        "sha": "86acab22fa296854", "bytes": 1148651725},
     "k_reduce_stream (calibrated)": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "39a58bcb0332be64", "bytes": 2325910630},
+        "sha": "86acab22fa296854", "bytes": 2325998080},
     "k_reduce_stream (tracker, float64 cost)": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/track.hip"],
-        "sha": "2ff58f7d7ee65f7e", "bytes": 344581427},
+        "sha": "4caeaec8f522aaf0", "bytes": 344588800},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
