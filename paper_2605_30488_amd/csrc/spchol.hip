@@ -11,17 +11,22 @@
 // products L_xj L_kj^T that left-looking elimination subtracts from it (j runs over the descendants of
 // k whose columns hold both rows), in increasing j.
 //
-// Numeric factorisation (one workgroup, all of it in one launch): level by level, every block of the
-// level's columns is A_xk minus its products (float64 matrix-core products, one wave per block); the wave
-// of a diagonal block also factors it (Cholesky of the 7x7 block and the inverse of its factor, carried out
-// redundantly in every lane) and eliminates the right-hand side; then every off-diagonal block is
+// Numeric solve: a gather kernel over the device copies attempt 0's blocks of H and -g into the factor's
+// storage; then one workgroup does the rest in one launch. Level by level, every block of the level's
+// columns is A_xk minus its products (float64 matrix-core products, one wave per block, the operand loads
+// of a batch of products issued together); the wave of a diagonal block carries the right-hand side as an
+// extra row of its products, then factors the block (Cholesky of the 7x7 block and the inverse of its
+// factor, carried out redundantly in every lane) and forms y_k; then every off-diagonal block is
 // multiplied by the inverse of its column's diagonal factor. Columns of one level never depend on each
 // other, so a level needs two workgroup barriers. A non-positive or non-finite pivot fails the attempt,
-// and the next attempt starts over from H with the next eps. The back substitution runs the levels in
-// reverse. No step waits on another workgroup, so nothing can hang.
+// and the next attempt starts over from H (read again inside the workgroup) with the next eps. The back
+// substitution runs the levels in reverse with the solution blocks in LDS. No step waits on another
+// workgroup, so nothing can hang.
 //
-// The index tables live in LDS for the whole launch; patterns whose tables do not fit are refused at
-// creation (the dense solver takes any pattern).
+// The index tables and the solution blocks live in LDS for the whole launch; patterns whose tables do not
+// fit are refused at creation (the dense solver takes any pattern). One compute unit's load pipeline bounds
+// the solve (every product is four 64-lane operand loads), which is why the plans default to the dense
+// solver on the pose graphs measured here.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
