@@ -425,9 +425,9 @@ def measure_tracker(g, W, dev, with_cpu=True, reps=5):
 
 def measure_solvers(g, dev, reps=10):
     """The solve of eq. (7) on the batched graph's pattern (7 n_kf unknowns, keyframe 0 anchored): the dense
-    ladder solver (the plans' default) and the block-sparse one, median of `reps` solves each (HIP events,
-    one warm-up), on a symmetric positive definite H with exactly that pattern (a sum of random per-pair
-    Gauss-Newton terms)."""
+    ladder solver, the block-sparse one and the tile-sparse one (the plans' default on this pattern),
+    median of `reps` solves each (HIP events, one warm-up), on a symmetric positive definite H with exactly
+    that pattern (a sum of random per-pair Gauss-Newton terms)."""
     import torch
 
     from paper_2605_30488_amd import api as ds3
@@ -447,6 +447,7 @@ def measure_solvers(g, dev, reps=10):
     Ht = torch.as_tensor(H, device=dev)
     gt = torch.as_tensor(rng.normal(size=7 * n), device=dev)
     sp = ds3.SpChol(n, pairs)
+    tc = ds3.TileChol(n, pairs)
 
     def time_it(fn):
         fn()
@@ -463,13 +464,21 @@ def measure_solvers(g, dev, reps=10):
 
     dense_ms = time_it(lambda: ds3.chol_ladder_solve(Ht, gt))
     sparse_ms = time_it(lambda: sp.solve(Ht, gt))
+    tile_ms = time_it(lambda: tc.solve(Ht, gt))
     td, _ = ds3.chol_ladder_solve(Ht, gt)
     ts_, _ = sp.solve(Ht, gt)
-    info = sp.info()
+    tt, _ = tc.solve(Ht, gt)
+    info, tinfo = sp.info(), tc.info()
     sp.close()
+    tc.close()
+    panels = (7 * n + 31) // 32
     return {"n": 7 * n, "dense_ms": round(dense_ms, 4), "sparse_ms": round(sparse_ms, 4),
-            "sparse_blocks": info["blocks"], "dense_blocks": n * (n + 1) // 2, "levels": info["levels"],
-            "max_abs_diff": float((td - ts_).abs().max().item()), "default": "dense"}
+            "tile_ms": round(tile_ms, 4), "sparse_blocks": info["blocks"], "dense_blocks": n * (n + 1) // 2,
+            "levels": info["levels"], "dense_panels": panels, "tile_tiles": tinfo["factor_tiles"],
+            "dense_tiles": panels * (panels + 1) // 2, "tile_levels": tinfo["levels"],
+            "max_abs_diff": float((td - ts_).abs().max().item()),
+            "max_abs_diff_tile": float((td - tt).abs().max().item()),
+            "default": "tile" if tinfo["levels"] < panels else "dense"}
 
 
 def measure_depth(g, W, dev, start, with_cpu=True, iters=10, reps=3):
@@ -913,7 +922,8 @@ def main():
             f"{out['next_depth']['iter_ms']:.3f} ms per iteration ({time.time() - t0:.1f}s)")
     if args.config in (3, 4):
         out["solvers"] = measure_solvers(g, dev)
-        log(f"solve of eq. (7): dense {out['solvers']['dense_ms']:.3f} ms, block-sparse {out['solvers']['sparse_ms']:.3f} ms")
+        log(f"solve of eq. (7): dense {out['solvers']['dense_ms']:.3f} ms, block-sparse {out['solvers']['sparse_ms']:.3f} ms, "
+            f"tile-sparse {out['solvers']['tile_ms']:.3f} ms")
     out["next_fusion"] = measure_fusion(g, dev, with_cpu=with_cpu)
     log(f"fusion: {out['next_fusion']['launch_ms']:.3f} ms per launch over {out['next_fusion']['px']} px")
 

@@ -286,6 +286,43 @@ int ds3_spchol_solve(ds3_spchol* S, const double* H, const double* g, double lam
                      int32_t attempts, double* tau, int32_t* status, void* stream);
 void ds3_spchol_destroy(ds3_spchol* S);
 
+/* Tile-sparse form of ds3_chol_ladder_solve for the same keyframe-pair pattern (eq. (7) and the epsilon
+ * ladder after it). The dense solver's float64 32x32 tiles, laid out so that the pose graph's independent
+ * parts fall into different tiles: a minimum-degree elimination order of the keyframe graph, a postorder
+ * of its elimination tree in which sibling subtrees of at least `thr` keyframes (all but the largest child
+ * of a node) start and end on tile boundaries (padding rows are identity rows), the symbolic tile
+ * factorisation of that layout and its tile elimination tree. Attempt 0 then runs one launch per tree
+ * level (instead of one per 32-row panel) and a dataflow back substitution over the tree; attempts 1..
+ * run in the dense solver's persistent fallback.
+ * ds3_tilechol_analyse (host only, no device use): the analysis of n_kf keyframes (1 <= n_kf <= 1170)
+ * and the n_pairs pairs pair_ij[2p], pair_ij[2p+1] (host; each in 0 .. n_kf-1, a != b, repeats allowed;
+ * DS3_EINVAL otherwise). Writes each keyframe's first row in the tile layout (kf_row0[k]: its 7 rows are
+ * kf_row0[k] .. +6; host, n_kf int32; may be NULL) and info (host, 7 int64): n_kf, tiles per side of the
+ * layout, factor tiles (lower, diagonal included, fill included), tree levels, tile updates (trailing
+ * tile x pivot products), padding rows, the threshold chosen (the fewest levels, then the fewest factor
+ * tiles, over 2, 3, 4, 6, 9, 14, 20 and no alignment). DS3_ENOSPACE when every layout has more than 1024
+ * tiles per side.
+ * ds3_tilechol_create: the same analysis, then device copies of the tables and the factor's storage
+ * (the object owns them: 16 KiB per factor tile; synchronises).
+ * ds3_tilechol_solve: solves (H + lambda diag(H) + eps_r I) tau = -g with eps_r = eps0 * mult^r, r = 0 ..
+ * attempts-1 (1 <= attempts <= 16), on `stream`, without host synchronisation. H: the symmetric
+ * (7 n_kf)^2 float64 matrix (device, row-major); only the lower triangle of its pattern blocks (the
+ * diagonal blocks and the listed pairs) is read and every other block counts as zero. g, tau: device,
+ * 7 n_kf float64; status (device int32) = the attempt used, -1 with tau = 0 when every factorisation
+ * meets a pivot that is not positive and finite, -2 when a bounded wait of the back substitution timed
+ * out. workspace: caller-owned device memory of at least ds3_chol_workspace_bytes(7 n_kf) bytes (its
+ * synchronisation words and the fallback's storage; DS3_ENOSPACE when workspace_bytes is smaller). Calls
+ * on one object or one workspace must not overlap. */
+typedef struct ds3_tilechol ds3_tilechol;
+int ds3_tilechol_analyse(int32_t n_kf, int32_t n_pairs, const int32_t* pair_ij, int32_t* kf_row0,
+                         int64_t* info);
+int ds3_tilechol_create(int32_t n_kf, int32_t n_pairs, const int32_t* pair_ij, ds3_tilechol** out);
+int ds3_tilechol_info(const ds3_tilechol* S, int64_t* info);
+int ds3_tilechol_solve(ds3_tilechol* S, const double* H, const double* g, double lambda, double eps0,
+                       double mult, int32_t attempts, double* tau, int32_t* status, void* workspace,
+                       size_t workspace_bytes, void* stream);
+void ds3_tilechol_destroy(ds3_tilechol* S);
+
 /* Batched form: one plan per graph topology (edges, keyframe images, idx offsets) over a set of matches.
  * The matches and the pointmaps stay fixed while Gauss-Newton moves the poses, so the plan holds a match
  * stream: for every edge, the two arena entries (X_j[n] and X_i[m]) and the weight (C_i C_j)^(1/4) of each
@@ -312,10 +349,13 @@ typedef struct {
                               iteration of every ds3_gn_plan_run, which then runs as direct launches
                               instead of a graph replay (same kernels, same results) */
   int32_t unroll;          /* match records in flight per thread (1, 2 or 4; 0 = 2) when not autotuning */
-  int32_t solver;          /* normal equations of eq. (7): 0 or 1 = the dense solver (ds3_chol_ladder_solve,
-                              the default); 2 = the block-sparse solver of the plan's keyframe-pair
-                              pattern (ds3_spchol_*; DS3_ENOSPACE when the pattern does not fit it). Both
-                              run the same epsilon ladder. */
+  int32_t solver;          /* normal equations of eq. (7): 1 = the dense solver (ds3_chol_ladder_solve);
+                              2 = the block-sparse solver of the plan's keyframe-pair pattern
+                              (ds3_spchol_*; DS3_ENOSPACE when the pattern does not fit it); 3 = the
+                              tile-sparse solver of that pattern (ds3_tilechol_*); 0 (the default) = the
+                              tile-sparse solver when its elimination tree has fewer levels than the
+                              dense solver has 32-row panels, else the dense one. All run the same
+                              epsilon ladder. */
 } ds3_plan_opts;
 
 int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* xyzc_arena, ds3_dtype dtype,
@@ -337,8 +377,8 @@ int ds3_gn_plan_time_reduce(void* plan, int32_t reps, float* ms_out, void* strea
  * edges, valid matches (idx in range), bytes of the streaming model (4 B idx per scanned px + both arena
  * entries per valid match), bytes the residual kernel reads per iteration (records + segment counts),
  * bytes one ds3_gn_plan_refresh moves (idx + both entries read, records written), records in flight per
- * thread, solver (1 dense, 2 block-sparse), blocks of the sparse factor (0 for dense), levels of its
- * elimination tree (0 for dense)]. */
+ * thread, solver (1 dense, 2 block-sparse, 3 tile-sparse), blocks (block-sparse) or 32x32 tiles
+ * (tile-sparse) of the sparse factor (0 for dense), levels of its elimination tree (0 for dense)]. */
 int ds3_gn_plan_info(void* plan, int64_t* info, int32_t n_info);
 int ds3_gn_plan_destroy(void* plan);
 /* The autotuner's cache: one line per (device, dtype, shape mix) with the tile shape it picked, in the

@@ -16,19 +16,20 @@ LIB = os.path.join(HERE, "libds3.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["capi.cpp", "capi_match.cpp", "gn.hip", "chol.hip", "match.hip", "gauge.hip", "misc.hip",
-           "adjoint.hip", "fuse.hip", "track.hip", "depth.hip", "spchol.hip"]
+           "adjoint.hip", "fuse.hip", "track.hip", "depth.hip", "spchol.hip", "tilechol.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
          "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 
-# Per-source flags. chol.hip: matrix-core products read and write ordinary VGPRs instead of the
+# Per-source flags. chol.hip, tilechol.hip: matrix-core products read and write ordinary VGPRs instead of the
 # accumulation registers, which removes a copy of every accumulator tile to and from them around each
 # product in the diagonal factorisation's dependent chain.
 # depth.hip: no contraction of float64 products and sums into fused multiply-adds, so that the segmentation
 # features round exactly as the operations are written.
-EXTRA = {"chol.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"], "depth.hip": ["-ffp-contract=off"]}
+EXTRA = {"chol.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"], "tilechol.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "depth.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

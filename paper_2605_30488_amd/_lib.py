@@ -107,6 +107,11 @@ _SIGS = {
     "ds3_spchol_info": (C.c_int, [vp, P_i64]),
     "ds3_spchol_solve": (C.c_int, [vp, vp, vp, f64, f64, f64, i32, vp, vp, vp]),
     "ds3_spchol_destroy": (None, [vp]),
+    "ds3_tilechol_analyse": (C.c_int, [i32, i32, P_i32, P_i32, P_i64]),
+    "ds3_tilechol_create": (C.c_int, [i32, i32, P_i32, C.POINTER(vp)]),
+    "ds3_tilechol_info": (C.c_int, [vp, P_i64]),
+    "ds3_tilechol_solve": (C.c_int, [vp, vp, vp, f64, f64, f64, i32, vp, vp, vp, sz, vp]),
+    "ds3_tilechol_destroy": (None, [vp]),
     "ds3_gn_plan_time_reduce": (C.c_int, [vp, i32, C.POINTER(C.c_float), vp]),
     "ds3_gn_plan_info": (C.c_int, [vp, P_i64, i32]),
     "ds3_gn_plan_refresh": (C.c_int, [vp, vp]),

@@ -421,6 +421,65 @@ class SpChol:
             pass
 
 
+_TC_INFO = ("n_kf", "tiles", "factor_tiles", "levels", "updates", "pad_rows", "threshold")
+
+
+def tilechol_analyse(n_kf: int, pairs):
+    """Host analysis of the tile-sparse solver (ds3_tilechol_analyse): (kf_row0, info)."""
+    p, pp = _pair_array(pairs)
+    row0 = np.empty(max(n_kf, 1), dtype=np.int32)
+    info = (C.c_int64 * 7)()
+    call("ds3_tilechol_analyse", int(n_kf), len(p), pp, row0.ctypes.data_as(C.POINTER(C.c_int32)), info)
+    return row0[:n_kf], dict(zip(_TC_INFO, list(info)))
+
+
+class TileChol:
+    """Tile-sparse ladder solve (ds3_tilechol_*) for a fixed keyframe-pair pattern of 7x7 blocks."""
+
+    def __init__(self, n_kf: int, pairs):
+        self.n_kf = int(n_kf)
+        p, pp = _pair_array(pairs)
+        h = C.c_void_p()
+        call("ds3_tilechol_create", self.n_kf, len(p), pp, C.byref(h))
+        self.handle = h
+        self._ws = None
+
+    def info(self) -> dict:
+        a = (C.c_int64 * 7)()
+        call("ds3_tilechol_info", self.handle, a)
+        return dict(zip(_TC_INFO, list(a)))
+
+    def solve(self, H, g, lam=0.0, eps0=1e-6, mult=100.0, attempts=6, tau=None, status=None, ws=None):
+        """(H + lam diag H + eps_r I) tau = -g on the pattern. Returns (tau, status int32[1]). ws: the dense
+        workspace (uint8 device tensor of ds3_chol_workspace_bytes(7 n_kf) bytes), kept per object if None."""
+        n = 7 * self.n_kf
+        if H.shape != (n, n) or g.numel() != n or H.dtype != torch.float64 or g.dtype != torch.float64:
+            raise ValueError("H must be (7 n_kf)^2 float64 and g 7 n_kf float64")
+        H = H.contiguous()
+        g = g.contiguous()
+        _need_cuda(H, g)
+        if ws is None:
+            if self._ws is None or self._ws.device != H.device:
+                self._ws = _ws(L.load().ds3_chol_workspace_bytes(n), H.device)
+            ws = self._ws
+        tau = torch.empty(n, dtype=torch.float64, device=H.device) if tau is None else tau
+        st = torch.empty(1, dtype=torch.int32, device=H.device) if status is None else status
+        call("ds3_tilechol_solve", self.handle, _ptr(H), _ptr(g), float(lam), float(eps0), float(mult),
+             int(attempts), _ptr(tau), _ptr(st), _ptr(ws), ws.numel(), _stream())
+        return tau, st
+
+    def close(self):
+        if self.handle:
+            L.load().ds3_tilechol_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class KernelTimer:
     """ds3_timer: HIP events that a library call records around one kernel launch on its stream."""
 
@@ -452,7 +511,8 @@ class GNPlan:
     launch over it per iteration, captured with the rest of the iteration in a hipGraph. Binds to
     `poses`, which every run updates in place. After the graph's idx (or arena) contents change, call
     refresh(). reduce_timer (a KernelTimer, kept alive by the plan) is recorded around the residual
-    launch. solver: 0 or 1 the dense solve of eq. (7), 2 the block-sparse one (ds3_spchol_*)."""
+    launch. solver: 1 the dense solve of eq. (7), 2 the block-sparse one (ds3_spchol_*), 3 the tile-sparse
+    one (ds3_tilechol_*), 0 the tile-sparse one when its tree has fewer levels than the dense panels."""
 
     def __init__(self, graph: Graph, poses, params=None, autotune=False, px_per_thread=0, use_graph=True,
                  reduce_timer=None, unroll=0, solver=0):
@@ -495,7 +555,7 @@ class GNPlan:
         call("ds3_gn_plan_info", self.handle, a, 11)
         return {"items": a[0], "px_per_thread": a[1], "px_scanned": a[2], "px_valid": a[3],
                 "bytes_streaming": a[4], "bytes_stream_per_iter": a[5], "bytes_refresh": a[6], "unroll": a[7],
-                "solver": "sparse" if a[8] == 2 else "dense", "factor_blocks": a[9], "factor_levels": a[10]}
+                "solver": {2: "sparse", 3: "tile"}.get(a[8], "dense"), "factor_blocks": a[9], "factor_levels": a[10]}
 
     def close(self):
         if self.handle:

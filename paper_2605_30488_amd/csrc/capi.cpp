@@ -518,7 +518,8 @@ struct Plan {
   ds3_timer* timer = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  SpChol* sp = nullptr;        // block-sparse solver of the plan's pattern, NULL for the dense solver
+  SpChol* sp = nullptr;        // block-sparse solver of the plan's pattern, NULL otherwise
+  TileChol* tc = nullptr;      // tile-sparse solver of the plan's pattern, NULL otherwise
 };
 
 // One GN iteration; `timed` records the plan's timer around the residual launch (never inside a capture).
@@ -538,6 +539,9 @@ static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
   if (P.sp)
     DS3_TRY(launch_spchol(P.sp, P.B.H, P.B.g, P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts, P.B.tau,
                           status, s));
+  else if (P.tc)
+    DS3_TRY(launch_tilechol(P.tc, P.B.H, P.B.g, P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts, P.B.tau,
+                            status, P.B.chol_ws, s));
   else
     DS3_TRY(launch_chol_ladder(P.B.H, P.B.g, int(n), P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts,
                                P.B.tau, status, P.B.chol_ws, s));
@@ -721,14 +725,17 @@ static void plan_free(Plan* P) {
   if (P->seg_count) (void)hipFree(P->seg_count);
   if (P->ecal) (void)hipFree(P->ecal);
   spchol_destroy(P->sp);
+  tilechol_destroy(P->tc);
   delete P;
 }
 
-// Solver of the normal equations: solver 0 or 1 the dense one, 2 the block-sparse one for the plan's pattern
-// (pairs that touch an anchor are zero blocks of H and stay out of the pattern).
+// Solver of the normal equations: 1 the dense one, 2 the block-sparse one and 3 the tile-sparse one for
+// the plan's pattern (pairs that touch an anchor are zero blocks of H and stay out of the pattern); 0 the
+// tile-sparse one when its elimination tree has fewer levels than the dense solver has panels, else the
+// dense one.
 static int plan_pick_solver(Plan& P, int solver) {
-  if (solver < 0 || solver > 2) return fail(DS3_EINVAL, "plan: solver must be 0, 1 or 2");
-  if (solver != 2) return DS3_OK;
+  if (solver < 0 || solver > 3) return fail(DS3_EINVAL, "plan: solver must be 0, 1, 2 or 3");
+  if (solver == 1) return DS3_OK;
   std::vector<int32_t> pairs;
   for (int p = 0; p < P.T.n_pairs; ++p) {
     const int a = P.T.pair_ij[2 * p], b = P.T.pair_ij[2 * p + 1];
@@ -736,7 +743,18 @@ static int plan_pick_solver(Plan& P, int solver) {
     pairs.push_back(a);
     pairs.push_back(b);
   }
-  return spchol_create(P.T.n_kf, int(pairs.size() / 2), pairs.data(), &P.sp);
+  if (solver == 2) return spchol_create(P.T.n_kf, int(pairs.size() / 2), pairs.data(), &P.sp);
+  DS3_TRY(tilechol_create(P.T.n_kf, int(pairs.size() / 2), pairs.data(), &P.tc));
+  if (solver == 0) {
+    int64_t info[7];
+    tilechol_stats(P.tc, info);
+    const int64_t panels = (7 * int64_t(P.T.n_kf) + 31) / 32;
+    if (info[3] >= panels) {
+      tilechol_destroy(P.tc);
+      P.tc = nullptr;
+    }
+  }
+  return DS3_OK;
 }
 
 int timer_record(ds3_timer* t, bool begin, hipStream_t s) {
@@ -914,13 +932,20 @@ int ds3_gn_plan_info(void* plan, int64_t* info, int32_t n_info) {
   if (!P || !info || n_info < 0) return fail(DS3_EINVAL, "plan_info: bad arguments");
   const int64_t px_bytes = P->dt == DS3_F32 ? 16 : 8;
   const int64_t rec = int64_t(stream_record_bytes(P->dt, P->ecal != nullptr));
-  int64_t sp[6] = {0, 0, 0, 0, 0, 0};
-  if (P->sp) spchol_stats(P->sp, sp);
+  int64_t sp[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t solver = 1, blocks = 0, levels = 0;
+  if (P->sp) {
+    spchol_stats(P->sp, sp);
+    solver = 2, blocks = sp[1], levels = sp[3];
+  } else if (P->tc) {
+    tilechol_stats(P->tc, sp);
+    solver = 3, blocks = sp[2], levels = sp[3];
+  }
   const int64_t v[11] = {P->n_items, P->ppt, P->px_scanned, P->px_valid,
                          4 * P->px_scanned + 2 * px_bytes * P->px_valid,
                          rec * P->n_records + 4 * int64_t(P->n_items),
                          4 * P->px_scanned + 2 * px_bytes * P->px_valid + rec * P->n_records + 4 * int64_t(P->n_items),
-                         P->unroll, P->sp ? 2 : 1, sp[1], sp[3]};
+                         P->unroll, solver, blocks, levels};
   for (int k = 0; k < n_info && k < 11; ++k) info[k] = v[k];
   return DS3_OK;
 }

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/ds3.h"
 
@@ -154,13 +155,31 @@ size_t chol_workspace_bytes(int n);
 int launch_chol_ladder(const double* H, const double* g, int n, double lambda, double eps0, double mult,
                        int attempts, double* tau, int32_t* status, void* ws, hipStream_t s);
 
-// spchol.hip: block-sparse ladder solve for a fixed keyframe-pair pattern
+// the dense workspace's synchronisation words ([2] error, [3] attempt 0 failed) and its persistent
+// fallback alone (attempts 1.., run only when attempt 0 failed)
+unsigned* chol_sync_words(void* ws, int n);
+int launch_chol_fallback(const double* H, const double* g, int n, double lambda, double eps0, double mult,
+                         int attempts, double* tau, int32_t* status, void* ws, hipStream_t s);
+
+// spchol.hip: block-sparse ladder solve for a fixed keyframe-pair pattern, and the minimum-degree order
+// both sparse solvers start from
+int min_degree_order(int n, int n_pairs, const int32_t* pair_ij, std::vector<int>& order,
+                     std::vector<std::vector<int>>& rows, std::vector<uint64_t>* pattern);
 struct SpChol;
 int spchol_create(int n_kf, int n_pairs, const int32_t* pair_ij, SpChol** out);
 void spchol_destroy(SpChol* P);
 void spchol_stats(const SpChol* P, int64_t* info);  // n_kf, blocks, fill blocks, levels, products, words
 int launch_spchol(const SpChol* P, const double* H, const double* g, double lambda, double eps0, double mult,
                   int attempts, double* tau, int32_t* status, hipStream_t s);
+
+// tilechol.hip: tile-sparse ladder solve for a fixed keyframe-pair pattern (attempt 0 over the tile
+// elimination tree, the dense fallback after it in the dense workspace ws)
+struct TileChol;
+int tilechol_create(int n_kf, int n_pairs, const int32_t* pair_ij, TileChol** out);
+void tilechol_destroy(TileChol* P);
+void tilechol_stats(const TileChol* P, int64_t* info);  // n_kf, tiles, factor tiles, levels, updates, pad rows, thr
+int launch_tilechol(const TileChol* P, const double* H, const double* g, double lambda, double eps0,
+                    double mult, int attempts, double* tau, int32_t* status, void* ws, hipStream_t s);
 
 // sim3.hip
 int launch_sim3_exp(const double* tau, double* poses, int n, hipStream_t s);

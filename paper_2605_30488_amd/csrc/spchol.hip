@@ -72,27 +72,27 @@ static int popcount_row(const uint64_t* r, int W) {
   return s;
 }
 
-// Symbolic analysis of the block pattern given by the keyframe pairs (a, b), a != b; repeated pairs are
-// allowed. Returns DS3_EINVAL for bad arguments.
-static int spchol_symbolic(int n_kf, int n_pairs, const int32_t* pair_ij, SpSymbolic& S) {
-  if (n_kf < 1 || n_kf > kSpMaxKf) return fail(DS3_EINVAL, "spchol: n_kf must be in 1 .. 1170");
-  if (n_pairs < 0 || (n_pairs > 0 && !pair_ij)) return fail(DS3_EINVAL, "spchol: bad pair table");
-  const int n = n_kf, W = (n + 63) / 64;
+// Minimum-degree elimination order of the keyframe graph given by the pairs (a, b), a != b (repeated pairs
+// allowed), on the exact elimination graph with ties to the lowest keyframe id. rows[v]: the neighbours of
+// v when it is eliminated, i.e. the rows of its column in the filled factor. pattern (optional): the
+// adjacency bitset of the pairs themselves, ceil(n / 64) words per keyframe.
+int min_degree_order(int n, int n_pairs, const int32_t* pair_ij, std::vector<int>& order,
+                     std::vector<std::vector<int>>& rows, std::vector<uint64_t>* pattern) {
+  if (n_pairs < 0 || (n_pairs > 0 && !pair_ij)) return fail(DS3_EINVAL, "min_degree: bad pair table");
+  const int W = (n + 63) / 64;
   std::vector<uint64_t> adj(size_t(n) * W, 0);
-  std::vector<uint64_t> in_pattern(size_t(n) * W, 0);
   for (int p = 0; p < n_pairs; ++p) {
     const int a = pair_ij[2 * p], b = pair_ij[2 * p + 1];
     if (a < 0 || b < 0 || a >= n || b >= n || a == b)
-      return fail(DS3_EINVAL, "spchol: pair " + std::to_string(p) + " out of range or on the diagonal");
+      return fail(DS3_EINVAL, "pair " + std::to_string(p) + " out of range or on the diagonal");
     adj[size_t(a) * W + b / 64] |= 1ull << (b % 64);
     adj[size_t(b) * W + a / 64] |= 1ull << (a % 64);
   }
-  in_pattern = adj;
-  // minimum-degree elimination on the exact elimination graph (ties: lowest keyframe id); the neighbours
-  // of a vertex when it is eliminated are its column's rows in L
-  std::vector<int> deg(n), order, pos(n, -1);
-  std::vector<std::vector<int>> rows(n);
+  if (pattern) *pattern = adj;
+  std::vector<int> deg(n);
+  order.clear();
   order.reserve(n);
+  rows.assign(n, {});
   for (int v = 0; v < n; ++v) deg[v] = popcount_row(&adj[size_t(v) * W], W);
   std::vector<uint8_t> alive(n, 1);
   for (int step = 0; step < n; ++step) {
@@ -111,9 +111,22 @@ static int spchol_symbolic(int n_kf, int n_pairs, const int32_t* pair_ij, SpSymb
     }
     for (int a : nb) deg[a] = popcount_row(&adj[size_t(a) * W], W);
     alive[v] = 0;
-    pos[v] = step;
     order.push_back(v);
   }
+  return DS3_OK;
+}
+
+// Symbolic analysis of the block pattern given by the keyframe pairs (a, b), a != b; repeated pairs are
+// allowed. Returns DS3_EINVAL for bad arguments.
+static int spchol_symbolic(int n_kf, int n_pairs, const int32_t* pair_ij, SpSymbolic& S) {
+  if (n_kf < 1 || n_kf > kSpMaxKf) return fail(DS3_EINVAL, "spchol: n_kf must be in 1 .. 1170");
+  if (n_pairs < 0 || (n_pairs > 0 && !pair_ij)) return fail(DS3_EINVAL, "spchol: bad pair table");
+  const int n = n_kf, W = (n + 63) / 64;
+  std::vector<uint64_t> in_pattern;
+  std::vector<int> order, pos(n, -1);
+  std::vector<std::vector<int>> rows;
+  DS3_TRY(min_degree_order(n, n_pairs, pair_ij, order, rows, &in_pattern));
+  for (int k = 0; k < n; ++k) pos[order[k]] = k;
   // elimination tree (parent = earliest-eliminated row) and levels from the leaves
   S.level.assign(n, 0);
   for (int v : order) {

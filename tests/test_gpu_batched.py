@@ -154,23 +154,33 @@ def test_plan_refresh_follows_new_matches(dev, single, dtype):
 
 
 def test_plan_sparse_and_dense_solvers_agree(dev, single):
-    """The plan's block-sparse solve of eq. (7) (solver=2) and its dense solve (the default) give the same
-    poses over five iterations (the factorisations round differently, nothing else differs); the anchor's
-    pairs stay out of the sparse pattern."""
+    """The plan's block-sparse (solver=2), tile-sparse (solver=3) and default (0: the tile-sparse one when
+    its tree is shorter than the dense panels) solves of eq. (7) give the dense solve's (solver=1) poses over
+    five iterations (the factorisations round differently, nothing else differs); the anchor's pairs stay
+    out of the sparse patterns."""
     g, idx = single
     G = _graph(g, idx, "f32", dev)
-    Ps, Pd = _t(g.poses_init, dev), _t(g.poses_init, dev)
-    ps = ds3.GNPlan(G, Ps, solver=2)
-    pd = ds3.GNPlan(G, Pd)
-    assert ps.info()["solver"] == "sparse" and pd.info()["solver"] == "dense"
-    assert 0 < ps.info()["factor_blocks"] < 20 * 21 // 2
-    cs, ss = ps.run(5)
+    Pd = _t(g.poses_init, dev)
+    pd = ds3.GNPlan(G, Pd, solver=1)
+    assert pd.info()["solver"] == "dense"
     cd, sd = pd.run(5)
-    err = O.pose_error(Ps.cpu().numpy(), Pd.cpu().numpy()).max()
-    assert err < 1e-9, err
-    assert np.allclose(cs.cpu().numpy(), cd.cpu().numpy(), rtol=1e-9)
-    assert np.all(ss.cpu().numpy() == 0) and np.all(sd.cpu().numpy() == 0)
-    ps.close()
+    assert np.all(sd.cpu().numpy() == 0)
+    for solver, name in ((2, "sparse"), (3, "tile"), (0, None)):
+        Ps = _t(g.poses_init, dev)
+        ps = ds3.GNPlan(G, Ps, solver=solver)
+        info = ps.info()
+        if name is not None:
+            assert info["solver"] == name
+        if info["solver"] == "sparse":
+            assert 0 < info["factor_blocks"] < 20 * 21 // 2
+        if info["solver"] == "tile":
+            assert 0 < info["factor_blocks"] and info["factor_levels"] < (7 * 20 + 31) // 32
+        cs, ss = ps.run(5)
+        err = O.pose_error(Ps.cpu().numpy(), Pd.cpu().numpy()).max()
+        assert err < 1e-9, (solver, err)
+        assert np.allclose(cs.cpu().numpy(), cd.cpu().numpy(), rtol=1e-9)
+        assert np.all(ss.cpu().numpy() == 0)
+        ps.close()
     pd.close()
 
 

@@ -2,7 +2,7 @@
 
 * the FP64 oracle (g++ -fsanitize=address,undefined), under its pin tests;
 * the library's host code (the C ABI's argument checks, topology and workspace carving, the Umeyama solve,
-  the tracker's scratch sizing, the block-sparse solver's symbolic analysis): every source compiled by
+  the tracker's scratch sizing, the block-sparse and tile-sparse solvers' symbolic analyses): every source compiled by
   hipcc with the sanitizers on the host side only (-Xarch_host before each -fsanitize=), under the
   host-only ABI and analysis tests.
 
@@ -67,4 +67,4 @@ def test_library_host_code_under_asan_and_ubsan(tmp_path):
         pytest.skip("clang's AddressSanitizer runtime is not installed")
     env = dict(os.environ, DS3_LIB=lib, LD_PRELOAD=rt[0],
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
-    _child_pytest(env, ["tests/test_abi.py", "tests/test_spchol_host.py"])
+    _child_pytest(env, ["tests/test_abi.py", "tests/test_spchol_host.py", "tests/test_tilechol_host.py"])

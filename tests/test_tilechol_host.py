@@ -1,0 +1,162 @@
+"""Host-side analysis of the tile-sparse solver (ds3_tilechol_analyse; no GPU). The keyframe layout, the tile
+pattern, its symbolic factorisation, the tile elimination tree's levels and the update count are recomputed
+here from their definitions and must agree exactly:
+  * the minimum-degree elimination order of the keyframe graph (ties to the lowest id) and its tree;
+  * a postorder of that tree, children in increasing (subtree size, id), in which every child but the last
+    one laid out that holds at least `thr` keyframes starts and ends on a 32-row tile boundary (roots are
+    the children of a virtual root);
+  * the threshold with the fewest levels, then the fewest factor tiles, among 2, 3, 4, 6, 9, 14, 20, none;
+  * the tile pattern: tiles (I, J) holding part of a block of H (a keyframe's diagonal block or a listed
+    pair), closed under elimination column by column (column K's rows below its first one join that row's
+    column);
+  * levels: leaves 0, a column one above its deepest child; updates: for each column K below the top
+    level, one per pair of its rows (I >= J)."""
+import numpy as np
+import pytest
+
+from paper_2605_30488_amd import api
+from paper_2605_30488_amd._lib import DS3Error
+from tests.test_spchol_host import PATTERNS, _adjacency, _chains_and_links
+
+NB = 32
+THRESHOLDS = (2, 3, 4, 6, 9, 14, 20, 1 << 30)
+
+
+def _md_tree(n, pairs):
+    adj = _adjacency(n, pairs)
+    alive, order, rows = set(range(n)), [], {}
+    while alive:
+        v = min(alive, key=lambda u: (len(adj[u]), u))
+        nb = set(adj[v])
+        rows[v] = nb
+        for a in nb:
+            adj[a] |= nb - {a}
+            adj[a].discard(v)
+        alive.remove(v)
+        order.append(v)
+    pos = {v: k for k, v in enumerate(order)}
+    parent = [min(rows[v], key=lambda u: pos[u]) if rows[v] else -1 for v in range(n)]
+    size = [1] * n
+    for v in order:
+        if parent[v] >= 0:
+            size[parent[v]] += size[v]
+    child = [[] for _ in range(n)]
+    for v in range(n):
+        if parent[v] >= 0:
+            child[parent[v]].append(v)
+    key = lambda c: (size[c], c)
+    for c in child:
+        c.sort(key=key)
+    roots = sorted([v for v in range(n) if parent[v] < 0], key=key)
+    return parent, size, child, roots
+
+
+def _layout(n, tree, thr):
+    parent, size, child, roots = tree
+    out, pad = [], []
+
+    def fence():
+        if pad:
+            pad[-1] = True
+
+    def lay(v):
+        for k, c in enumerate(child[v]):
+            big = k != len(child[v]) - 1 and size[c] >= thr
+            if big:
+                fence()
+            lay(c)
+            if big:
+                fence()
+        out.append(v)
+        pad.append(False)
+
+    for k, r in enumerate(roots):
+        big = k != len(roots) - 1 and size[r] >= thr
+        if big:
+            fence()
+        lay(r)
+        if big:
+            fence()
+    row0, r = [0] * n, 0
+    for v, p in zip(out, pad):
+        row0[v] = r
+        r += 7
+        if p:
+            r = -(-r // NB) * NB
+    return row0, max(NB, -(-r // NB) * NB)
+
+
+def _tiles(n, pairs, row0, np_):
+    nt = np_ // NB
+    tiles = [(row0[v] // NB, (row0[v] + 6) // NB) for v in range(n)]
+    cols = [set() for _ in range(nt)]
+    blocks = [(v, v) for v in range(n)] + [(a, b) for a, b in pairs] + [(b, a) for a, b in pairs]
+    for a, b in blocks:
+        for I in range(tiles[a][0], tiles[a][1] + 1):
+            for J in range(tiles[b][0], tiles[b][1] + 1):
+                if I > J:
+                    cols[J].add(I)
+    level = [0] * nt
+    for K in range(nt):
+        if cols[K]:
+            p = min(cols[K])
+            cols[p] |= cols[K] - {p}
+            level[p] = max(level[p], level[K] + 1)
+    slots = nt + sum(len(c) for c in cols)
+    nlev = max(level) + 1
+    updates = sum(len(cols[K]) * (len(cols[K]) + 1) // 2 for K in range(nt) if level[K] < nlev - 1)
+    return nt, slots, nlev, updates
+
+
+def _reference(n, pairs):
+    tree = _md_tree(n, pairs)
+    best = None
+    for thr in THRESHOLDS:
+        row0, np_ = _layout(n, tree, thr)
+        nt, slots, nlev, updates = _tiles(n, pairs, row0, np_)
+        if nt > 1024:
+            continue
+        if best is None or (nlev, slots) < (best[3], best[2]):
+            best = (row0, nt, slots, nlev, updates, np_ - 7 * n, thr)
+    return best, tree
+
+
+@pytest.mark.parametrize("name", sorted(PATTERNS))
+def test_analysis_matches_definitions(name):
+    n, pairs = PATTERNS[name]
+    row0, info = api.tilechol_analyse(n, pairs)
+    (ref_row0, nt, slots, nlev, updates, pad, thr), tree = _reference(n, pairs)
+    assert list(row0) == ref_row0
+    assert info == {"n_kf": n, "tiles": nt, "factor_tiles": slots, "levels": nlev, "updates": updates,
+                    "pad_rows": pad, "threshold": thr}
+    # a valid layout: disjoint 7-row blocks inside the tiles, children before their parent
+    spans = sorted((r, r + 7) for r in row0)
+    assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:])) and spans[-1][1] <= NB * nt
+    parent = tree[0]
+    assert all(row0[v] < row0[parent[v]] for v in range(n) if parent[v] >= 0)
+
+
+def test_batched_pattern_has_a_short_tree():
+    """Four keyframe chains with cross links: the tile tree has far fewer levels than the dense solver has
+    panels, and far fewer factor tiles than the dense lower triangle."""
+    n, pairs = _chains_and_links(per=50, links=3)
+    _, info = api.tilechol_analyse(n, pairs)
+    panels = -(-7 * n // NB)
+    assert info["levels"] < 0.6 * panels
+    assert info["factor_tiles"] < 0.4 * panels * (panels + 1) / 2
+
+
+def test_dense_pattern_is_the_dense_factor():
+    """Every pair of 30 keyframes: no padding pays, so the layout is packed and the factor is the full lower
+    triangle of ceil(210 / 32) = 7 tiles, one level per tile."""
+    n = 30
+    pairs = [(a, b) for a in range(n) for b in range(a)]
+    _, info = api.tilechol_analyse(n, pairs)
+    assert info["tiles"] == 7 and info["factor_tiles"] == 28 and info["levels"] == 7 and info["pad_rows"] == 14
+
+
+@pytest.mark.parametrize("n,pairs", [(0, []), (1171, []), (4, [(1, 1)]), (4, [(0, 4)]), (4, [(-1, 2)])])
+def test_argument_errors(n, pairs):
+    with pytest.raises(DS3Error) as e:
+        api.tilechol_analyse(n, pairs)
+    assert e.value.code == -1
