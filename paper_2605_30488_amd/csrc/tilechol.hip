@@ -22,10 +22,11 @@
 // Numeric solve (one launch per level, so that kernel boundaries order everything):
 //   init      every factor tile from H (only the blocks of the keyframe pattern are read) and -g; the
 //             level-0 diagonal tiles are factored at once;
-//   level l   one workgroup per trailing tile (I, J) of the level: for each of its pivots K it forms
-//             L_IK = A_IK Inv_K^T and L_JK, subtracts L_IK L_JK^T; the workgroup of a diagonal tile
-//             (I, I) also stores L_IK and eliminates b_I -= L_IK y_K, and factors the tile when it is on
-//             the next level;
+//   level l   one workgroup per trailing tile (I, J) with updates in this launch: for each of its pivots
+//             K (of level l, or of earlier levels for an off-diagonal tile whose updates are spread over
+//             the launches before it is read) it forms L_IK = A_IK Inv_K^T and L_JK, subtracts
+//             L_IK L_JK^T; the workgroup of a diagonal tile (I, I) also stores L_IK and eliminates
+//             b_I -= L_IK y_K, and factors the tile when it is on the next level;
 //   backsub   one workgroup per tile column, dataflow over the tree: column K waits for the solution of
 //             the tile rows of its column (its ancestors), then solves x_K = Inv_K^T (y_K - sum L_IK^T x_I)
 //             and publishes it; every wait is bounded.
@@ -269,38 +270,61 @@ static int tc_symbolic(int n_kf, int n_pairs, const int32_t* pair_ij, TcSymbolic
     if (S.tlevel[K] == 0) S.init_order.push_back(S.col_ptr[K]);
   for (int s = 0; s < int(S.nslot); ++s)
     if (!(S.slot_row[s] == S.slot_col[s] && S.tlevel[S.slot_col[s]] == 0)) S.init_order.push_back(s);
-  // trailing tiles per level: target slot -> pivots
+  // trailing tiles per launch: target slot -> pivots. An update of (I, J) by pivot K can run in any launch
+  // from level(K) on, as long as it is done before the tile is read: an off-diagonal tile (I, J) is read
+  // as a pivot tile in the launch of level(J), so its updates may be spread over the launches up to
+  // level(J) - 1; a diagonal tile (I, I) is factored in the launch of level(I) - 1, right after that
+  // launch's own updates (its workgroup is on the critical path), so its earlier updates are spread over
+  // the launches up to level(I) - 2. A launch takes at most kSpread of a tile's pending updates, or more
+  // when the deadline needs it, so that no workgroup carries many more products than the factoring ones.
+  constexpr int kSpread = 2;
   std::vector<std::vector<int>> lev_cols(S.nlev);
   for (int K = 0; K < nt; ++K) lev_cols[S.tlevel[K]].push_back(K);
   S.lt_ptr.assign(S.nlev, 0);
   S.tgt.clear();
   S.piv.clear();
   S.nupd = 0;
-  std::vector<std::vector<int>> piv_of(S.nslot);
+  std::vector<std::vector<int>> pending(S.nslot);
+  std::vector<int> open;  // slots with pending updates
   for (int l = 0; l + 1 < S.nlev; ++l) {
-    std::vector<int> touched;
     for (int K : lev_cols[l]) {
       const std::vector<int>& r = best.cols[K];
       for (size_t a = 0; a < r.size(); ++a)
         for (size_t b = 0; b <= a; ++b) {
           const int s = slot_of(r[a], r[b]);
           if (s < 0) return fail(DS3_EINVAL, "tilechol: internal error (update outside the factor pattern)");
-          if (piv_of[s].empty()) touched.push_back(s);
-          piv_of[s].push_back(K);
+          if (pending[s].empty()) open.push_back(s);
+          pending[s].push_back(K);
         }
     }
     auto is_factor = [&](int s) { return S.slot_row[s] == S.slot_col[s] && S.tlevel[S.slot_row[s]] == l + 1; };
-    std::sort(touched.begin(), touched.end(), [&](int a, int b) {
-      const bool fa = is_factor(a), fb = is_factor(b);
+    std::vector<std::pair<int, int>> take;  // (slot, updates taken in this launch)
+    std::vector<int> still;
+    for (int s : open) {
+      const int I = S.slot_row[s], J = S.slot_col[s];
+      const int npend = int(pending[s].size());
+      int t = npend;
+      const int deadline = (I != J) ? S.tlevel[J] - 1 : S.tlevel[I] - 2;
+      if (I != J && deadline < l) return fail(DS3_EINVAL, "tilechol: internal error (update after its deadline)");
+      if (deadline >= l) {
+        const int left = deadline - l + 1;
+        t = std::min(npend, std::max((npend + left - 1) / left, kSpread));
+      }
+      take.push_back({s, t});
+      if (t < npend) still.push_back(s);
+    }
+    std::sort(take.begin(), take.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+      const bool fa = is_factor(a.first), fb = is_factor(b.first);
       if (fa != fb) return fa;
-      if (piv_of[a].size() != piv_of[b].size()) return piv_of[a].size() > piv_of[b].size();
-      return a < b;
+      if (a.second != b.second) return a.second > b.second;
+      return a.first < b.first;
     });
     S.lt_ptr[l] = int(S.tgt.size() / kTgtWords);
-    for (int s : touched) {
-      const int I = S.slot_row[s], J = S.slot_col[s];
+    for (const auto& st : take) {
+      const int s = st.first, I = S.slot_row[s], J = S.slot_col[s];
       const int pb = int(S.piv.size() / kPivWords);
-      for (int K : piv_of[s]) {
+      for (int k = 0; k < st.second; ++k) {
+        const int K = pending[s][k];
         S.piv.push_back(K);
         S.piv.push_back(slot_of(I, K));
         S.piv.push_back(slot_of(J, K));
@@ -308,9 +332,11 @@ static int tc_symbolic(int n_kf, int n_pairs, const int32_t* pair_ij, TcSymbolic
       const int pe = int(S.piv.size() / kPivWords);
       S.tgt.insert(S.tgt.end(), {s, I, J, pb, pe, is_factor(s) ? 1 : 0});
       S.nupd += pe - pb;
-      piv_of[s].clear();
+      pending[s].erase(pending[s].begin(), pending[s].begin() + st.second);
     }
+    open.swap(still);
   }
+  if (!open.empty()) return fail(DS3_EINVAL, "tilechol: internal error (updates left after the last launch)");
   if (S.nlev >= 1) S.lt_ptr.back() = int(S.tgt.size() / kTgtWords);
   // lt_ptr[l] .. lt_ptr[l + 1] for l < nlev - 1; the last entry closes the list
   // keyframe-pair pattern bits (diagonal blocks included)
@@ -442,19 +468,26 @@ __global__ __launch_bounds__(kTcThreads) void k_tc_level(TcArgs a, int t0) {
   const int r8 = threadIdx.x >> 3, p8 = threadIdx.x & 7;
   double bi = 0.0;
   if (diag && p8 == 0) bi = a.b[I * NB + r8];
-  for (int p = pb; p < pe; ++p) {
+  // operands of pivot p: Inv_K, A_IK, A_JK (off-diagonal targets) and y_K (diagonal ones); the next
+  // pivot's are loaded while the current one's products run
+  f64x4 qinv, qi, qj = {0.0, 0.0, 0.0, 0.0};
+  double yk = 0.0;
+  auto load_pivot = [&](int p) {
     const int K = a.piv[kPivWords * p], sIK = a.piv[kPivWords * p + 1], sJK = a.piv[kPivWords * p + 2];
-    f64x4 qinv, qi, qj;
     frag_load(qinv, a.Inv + int64_t(K) * NB * NB, NB);
     frag_load(qi, a.W + int64_t(sIK) * NB * NB, NB);
     if (!diag) frag_load(qj, a.W + int64_t(sJK) * NB * NB, NB);
-    double yk = 0.0;
     if (diag && threadIdx.x < NB) yk = a.y[K * NB + threadIdx.x];
+  };
+  if (pb < pe) load_pivot(pb);
+  for (int p = pb; p < pe; ++p) {
+    const int sIK = a.piv[kPivWords * p + 1];
     __syncthreads();  // the previous pivot's readers of S0..S2 and sy are done
     frag_to_lds(qinv, S0);
     frag_to_lds(qi, S1);
     if (!diag) frag_to_lds(qj, S2);
     if (diag && threadIdx.x < NB) sy[threadIdx.x] = yk;
+    if (p + 1 < pe) load_pivot(p + 1);
     __syncthreads();
     f64x4 li = {0.0, 0.0, 0.0, 0.0}, lj = {0.0, 0.0, 0.0, 0.0};
     frag_gemm_abt<false>(S1, S0, li);  // L_IK = A_IK Inv_K^T
