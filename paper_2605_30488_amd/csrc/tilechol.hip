@@ -28,8 +28,9 @@
 //             L_IK L_JK^T; the workgroup of a diagonal tile (I, I) also stores L_IK and eliminates
 //             b_I -= L_IK y_K, and factors the tile when it is on the next level;
 //   backsub   one workgroup per tile column, dataflow over the tree: column K waits for the solution of
-//             the tile rows of its column (its ancestors), then solves x_K = Inv_K^T (y_K - sum L_IK^T x_I)
-//             and publishes it; every wait is bounded.
+//             the tile rows of its column (its ancestors), solves x_K = Inv_K^T (y_K - sum L_IK^T x_I) with
+//             everything but its parent's term done before the parent's solution arrives, and publishes
+//             it; every wait is bounded.
 // The diagonal factorisations, the tile products and the inverse of each diagonal factor are the dense
 // solver's (shared tile primitives). Attempt 0 runs this way; when it fails, the dense solver's
 // persistent fallback runs attempts 1.. from H in the caller's dense workspace.
@@ -533,12 +534,25 @@ __device__ inline unsigned long long tc_x_load(const double* p) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Back substitution, one workgroup per tile column K (the highest columns, the tree's roots, first).
-// Each thread holds its fragment's four rows of one column of L_IK; for every tile row I of the column,
-// from the highest (solved first) down to the parent, the waves poll the 32 values of x_I (each value is
-// its own ready flag: the signalling-NaN pending pattern until its owner stores it) and accumulate
-// L_IK^T x_I, with the next tile of L already loading. Then x_K = Inv_K^T (y_K - acc) is published with
-// relaxed agent-scope stores. A wait that times out sets sync[2]; the status then stays -2.
+// Back substitution, one workgroup per tile column K (the highest columns, the tree's roots, first):
+//   x_K = Inv_K^T (y_K - sum_I L_IK^T x_I) = z_K - M_K x_p,
+//   z_K = Inv_K^T (y_K - sum_{I != p} L_IK^T x_I),   M_K = Inv_K^T L_pK^T,
+// p the parent of K (its lowest tile row). The rows I of the column are K's ancestors, and every one but
+// p is also a row of p's column, so x_p is the last solution K waits for. Everything except the last
+// product is done before it arrives: M_K on the matrix cores at the start; for the other rows, from the
+// highest (solved first) down, the waves poll the 32 values of x_I (each value is its own ready flag: the
+// signalling-NaN pending pattern until its owner stores it) and accumulate L_IK^T x_I with the next tile
+// of L already loading, then z_K. One wave then polls x_p with two loads in flight, broadcasts its values
+// from the lanes and finishes x_K[c] = z_K[c] - sum_r M_K[c][r] x_p[r] in each lane, without a barrier, and
+// publishes it with relaxed agent-scope stores. A wait that times out sets sync[2]; the status then stays
+// -2.
+__device__ inline double lane_value(double v, int r) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), r);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), r);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
 __global__ __launch_bounds__(kTcThreads) void k_tc_backsub(TcArgs a) {
   const int K = a.nt - 1 - int(blockIdx.x);
   if (a.sync[3] != 0u) {  // attempt 0 failed: the fallback takes over, or gives up with one attempt
@@ -551,18 +565,34 @@ __global__ __launch_bounds__(kTcThreads) void k_tc_backsub(TcArgs a) {
     }
     return;
   }
-  __shared__ double sinv[NB * NB];
+  __shared__ double sInvT[NB * LDT];  // Inv_K transposed
+  __shared__ double sM[NB * LDT];     // L_pK, then M_K
   __shared__ double red[2][NB];
   __shared__ double rs[NB];
+  __shared__ double zs[NB];
+  __shared__ int s_bad;
   const int c = fcol(), l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < NB * NB; e += kTcThreads) sinv[e] = a.Inv[int64_t(K) * NB * NB + e];
   const int sb = a.col_ptr[K] + 1, se = a.col_ptr[K + 1];
+  const bool has_parent = se > sb;  // slot sb holds the parent row
+  {
+    f64x4 q, qL = {0.0, 0.0, 0.0, 0.0};
+    frag_load(q, a.Inv + int64_t(K) * NB * NB, NB);
+    if (has_parent) frag_load(qL, a.L + int64_t(sb) * NB * NB, NB);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sInvT[c * LDT + frow(v)] = q[v];
+    frag_to_lds(qL, sM);
+  }
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  f64x4 M = {0.0, 0.0, 0.0, 0.0};
+  frag_gemm_abt<false>(sInvT, sM, M);  // M[c][r] = sum_u Inv_K[u][c] L_pK[r][u]
+  // the other rows of the column, highest first
   double acc = 0.0;
   bool ok = true;
   f64x4 Lc = {0.0, 0.0, 0.0, 0.0}, Ln = {0.0, 0.0, 0.0, 0.0};
-  if (se > sb) frag_load(Lc, a.L + int64_t(se - 1) * NB * NB, NB);
-  for (int q = se - 1; q >= sb; --q) {
-    if (q > sb) frag_load(Ln, a.L + int64_t(q - 1) * NB * NB, NB);
+  if (se - 1 > sb) frag_load(Lc, a.L + int64_t(se - 1) * NB * NB, NB);
+  for (int q = se - 1; q > sb; --q) {
+    if (q - 1 > sb) frag_load(Ln, a.L + int64_t(q - 1) * NB * NB, NB);
     const int I = a.slot_row[q];
     const double* px = a.x + I * NB;
     unsigned long long v[4];
@@ -576,7 +606,8 @@ __global__ __launch_bounds__(kTcThreads) void k_tc_backsub(TcArgs a) {
         ready = ready && (v[k] != kXPending);
       }
       if (__all(ready)) break;
-      if (++spins > kTcSpinLimit || __hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      if (++spins > kTcSpinLimit ||
+          __hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
         ok = false;
         break;
       }
@@ -587,43 +618,71 @@ __global__ __launch_bounds__(kTcThreads) void k_tc_backsub(TcArgs a) {
     for (int k = 0; k < 4; ++k) acc = fma(Lc[k], __longlong_as_double(static_cast<long long>(v[k])), acc);
     Lc = Ln;
   }
-  // a timed-out wave leaves its partial sum; the workgroup agrees on the outcome below
-  __shared__ int s_bad;
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
+  __syncthreads();  // every wave is past the product's reads of sM
   if (!ok) s_bad = 1;
+  frag_to_lds(M, sM);
   // column c's partial sums: lanes l, l^16, l^32, l^48 of a wave, then the two row halves
   acc += __shfl_xor(acc, 16);
   acc += __shfl_xor(acc, 32);
   if (l < 16) red[w >> 1][c] = acc;
   __syncthreads();
-  if (s_bad) {
-    if (threadIdx.x == 0) atomicOr(&a.sync[2], 1u);
-    if (threadIdx.x < NB) {
-      const int rr = a.rowmap[K * NB + threadIdx.x];
+  if (threadIdx.x < NB) rs[threadIdx.x] = a.y[K * NB + threadIdx.x] - (red[0][threadIdx.x] + red[1][threadIdx.x]);
+  __syncthreads();
+  {  // z_K[cz] = sum_u Inv_K[u][cz] rs[u], 8 threads per entry
+    const int cz = threadIdx.x >> 3, p8 = threadIdx.x & 7;
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB / 8; ++q) z = fma(sInvT[cz * LDT + p8 + 8 * q], rs[p8 + 8 * q], z);
+    z += __shfl_xor(z, 1, 8);
+    z += __shfl_xor(z, 2, 8);
+    z += __shfl_xor(z, 4, 8);
+    if (p8 == 0) zs[cz] = z;
+  }
+  __syncthreads();
+  if (w != 0) return;
+  const int cl = l & 31;
+  bool good = !s_bad;
+  double xk = zs[cl];
+  if (good && has_parent) {
+    double m[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) m[r] = sM[cl * LDT + r];
+    const double* px = a.x + a.slot_row[sb] * NB + cl;
+    unsigned long long cur = tc_x_load(px);
+    long spins = 0;
+    while (true) {
+      const unsigned long long nxt = tc_x_load(px);  // the next poll is in flight while this one is tested
+      if (__all(cur != kXPending)) break;
+      if (++spins > kTcSpinLimit ||
+          ((spins & 255) == 0 &&
+           __hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+        good = false;
+        break;
+      }
+      cur = nxt;
+    }
+    if (good) {
+      const double xp = __longlong_as_double(static_cast<long long>(cur));
+#pragma unroll
+      for (int r = 0; r < NB; ++r) xk = fma(-m[r], lane_value(xp, r), xk);
+    }
+  }
+  if (!good) {
+    if (l == 0) atomicOr(&a.sync[2], 1u);
+    if (l < NB) {
+      const int rr = a.rowmap[K * NB + l];
       if (rr >= 0) a.tau[rr] = 0.0;
     }
     return;
   }
-  if (threadIdx.x < NB) rs[threadIdx.x] = a.y[K * NB + threadIdx.x] - (red[0][threadIdx.x] + red[1][threadIdx.x]);
-  __syncthreads();
-  // x_K[cx] = sum_u Inv_K[u][cx] rs[u] (Inv_K is zero above its diagonal), 8 threads per entry
-  const int cx = threadIdx.x >> 3, p8 = threadIdx.x & 7;
-  double xs = 0.0;
-#pragma unroll
-  for (int q = 0; q < NB / 8; ++q) xs = fma(sinv[(p8 + 8 * q) * NB + cx], rs[p8 + 8 * q], xs);
-  xs += __shfl_xor(xs, 1, 8);
-  xs += __shfl_xor(xs, 2, 8);
-  xs += __shfl_xor(xs, 4, 8);
-  if (p8 == 0) {
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.x + K * NB + cx),
-                       static_cast<unsigned long long>(__double_as_longlong(xs)), __ATOMIC_RELAXED,
+  if (l < NB) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(a.x + K * NB + l),
+                       static_cast<unsigned long long>(__double_as_longlong(xk)), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-    const int rr = a.rowmap[K * NB + cx];
-    if (rr >= 0) a.tau[rr] = xs;
+    const int rr = a.rowmap[K * NB + l];
+    if (rr >= 0) a.tau[rr] = xk;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (l == 0) {
     const unsigned prev = atomicAdd(a.done, 1u);
     if (prev == unsigned(a.nt - 1)) *a.status = (tc_ld_acq(&a.sync[2]) != 0u) ? -2 : 0;
   }
