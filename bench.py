@@ -50,19 +50,19 @@ TRAFFIC = {
     "k_reduce_stream": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "86acab22fa296854", "bytes": 1148651725},
+        "sha": "4b646c83fbd0fc61", "bytes": 1148702618},
     "k_reduce_stream (calibrated)": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "86acab22fa296854", "bytes": 2325998080},
+        "sha": "4b646c83fbd0fc61", "bytes": 2326333850},
     "k_reduce_stream (tracker, float64 cost)": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/track.hip"],
-        "sha": "4caeaec8f522aaf0", "bytes": 344588800},
+        "sha": "43c4545a3cf8f5ec", "bytes": 344592077},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
-        "sha": "cd5f23ae7f6dc636", "bytes": 9303985562},
+        "sha": "cd5f23ae7f6dc636", "bytes": 9303938662},
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
@@ -70,11 +70,11 @@ TRAFFIC = {
     "k_fuse": {
         "sources": ["paper_2605_30488_amd/csrc/fuse.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/sim3.hpp"],
-        "sha": "1eeb7b2558c23433", "bytes": 1651929805},
+        "sha": "48eddae909e40a16", "bytes": 1651933901},
     "k_dr_data": {
         "sources": ["paper_2605_30488_amd/csrc/depth.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "71ec44623495df06", "bytes": 2785807770},
+        "sha": "f13d2ed2e526222c", "bytes": 2785228186},
 }
 
 

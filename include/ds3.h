@@ -276,7 +276,7 @@ int ds3_chol_ladder_solve(const double* H, const double* g, int32_t n, double la
  * share its factor storage). The solve runs in one workgroup (level after level of the elimination tree;
  * a small gather kernel over the device comes first), so one compute unit's memory pipeline bounds it:
  * it does less arithmetic than the dense solver but is not faster on pose graphs of a few hundred
- * keyframes, and the plans use the dense solver unless asked otherwise. */
+ * keyframes, and the plans use it only when asked (ds3_plan_opts.solver = 2). */
 typedef struct ds3_spchol ds3_spchol;
 int ds3_spchol_analyse(int32_t n_kf, int32_t n_pairs, const int32_t* pair_ij, int32_t* perm, int32_t* level,
                        int64_t* info);

@@ -25,8 +25,8 @@
 //
 // The index tables and the solution blocks live in LDS for the whole launch; patterns whose tables do not
 // fit are refused at creation (the dense solver takes any pattern). One compute unit's load pipeline bounds
-// the solve (every product is four 64-lane operand loads), which is why the plans default to the dense
-// solver on the pose graphs measured here.
+// the solve (every product is four 64-lane operand loads), which is why the plans use it only when asked
+// (the tile-sparse solver is faster on the pose graphs measured here).
 #include <algorithm>
 #include <cstring>
 #include <numeric>
