@@ -66,7 +66,7 @@ TRAFFIC = {
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "9e2367af50932dbc", "bytes": 21994668134},
+        "sha": "6647c33331d842e0", "bytes": 21994359398},
     "k_fuse": {
         "sources": ["paper_2605_30488_amd/csrc/fuse.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/sim3.hpp"],
