@@ -179,9 +179,9 @@ static int run_match(const std::vector<EdgeSpec>& es, const void* cross, ds3_dty
     MatchDir a{E.ray_i, E.q_ji, E.tmp_ji, E.Hi, E.Wi, E.Hj, E.Wj};   // queries: pixels of j
     MatchDir b{E.ray_j, E.q_ij, E.tmp_ij, E.Hj, E.Wj, E.Hi, E.Wi};   // queries: pixels of i
     dirs.push_back(a);
-    dtiles.push_back(int32_t((int64_t(E.Hj) * E.Wj + 255) / 256));
+    dtiles.push_back(match_tiles(E.Hj, E.Wj));
     dirs.push_back(b);
-    dtiles.push_back(int32_t((int64_t(E.Hi) * E.Wi + 255) / 256));
+    dtiles.push_back(match_tiles(E.Hi, E.Wi));
     MutualDir sj{E.tmp_ji, E.tmp_ij, E.out_off, W.conf + E.ray_j, W.conf + E.ray_i, E.Hj, E.Wj, E.Hi, E.Wi,
                  2 * e + 1, 1};
     MutualDir si{E.tmp_ij, E.tmp_ji, 0, W.conf + E.ray_i, W.conf + E.ray_j, E.Hi, E.Wi, E.Hj, E.Wj, 2 * e, 0};

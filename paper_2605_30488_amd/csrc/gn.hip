@@ -309,16 +309,69 @@ __device__ inline void acc_pixel_cal(Acc& a, const float4 Xj, const float4 Xi, i
                make_float2(float(C.Wi) - 0.5f, float(C.Hi) - 0.5f), k);
 }
 
+// Wave reduce-scatter of the 37 accumulators in six halvings. In each step a lane and its partner (lane
+// l^32, l^16, l^8, l^7 (the mirror within eight lanes), l^2, l^1) hold the same list of partial sums; the
+// lane whose bit of the step is set keeps the upper part of the list (entries h .. L-1, h = ceil(L/2)), the
+// other the lower part, and each adds its partner's copy of the part it keeps. The first two exchanges are
+// the gfx950 lane-half swaps, the other four DPP moves. After the last step every lane holds the wave's
+// total of one accumulator (its slot) or padding (slot -1): 40 exchanges and adds instead of 37 full-wave
+// sums of six DPP adds each.
+__device__ inline float swap32_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ inline float swap16_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// keeps `hi` when `upper`, else `lo`, plus the partner's copy of the same entry (DPP control CTRL)
+template <int CTRL>
+__device__ inline float dpp_pair_sum(float lo, float hi, bool upper) {
+  const float keep = upper ? hi : lo, send = upper ? lo : hi;
+  return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xf, 0xf, true));
+}
+
+__device__ inline float acc_reduce_scatter(const Acc& a, int lane, int& slot) {
+  const float* v = reinterpret_cast<const float*>(&a);
+  float w1[19], w2[10], w3[5], w4[3], w5[2];
+#pragma unroll
+  for (int k = 0; k < 19; ++k) w1[k] = swap32_sum(v[k], k + 19 < 37 ? v[k + 19] : 0.0f);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) w2[k] = swap16_sum(w1[k], k + 10 < 19 ? w1[k + 10] : 0.0f);
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) w3[k] = dpp_pair_sum<0x128>(w2[k], k + 5 < 10 ? w2[k + 5] : 0.0f, b3);  // row_ror:8
+#pragma unroll
+  for (int k = 0; k < 3; ++k) w4[k] = dpp_pair_sum<0x141>(w3[k], k + 3 < 5 ? w3[k + 3] : 0.0f, b2);  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < 2; ++k) w5[k] = dpp_pair_sum<0x4e>(w4[k], k + 2 < 3 ? w4[k + 2] : 0.0f, b1);  // quad_perm [2,3,0,1]
+  const float tot = dpp_pair_sum<0xb1>(w5[0], w5[1], b0);                                            // quad_perm [1,0,3,2]
+  // the entry a lane ends with: its kept offsets, last step first; padding once a kept entry is past a list
+  int s = b0 ? 1 : 0;
+  bool ok = true;
+  s += b1 ? 2 : 0;
+  ok = ok && s < 3;
+  s += b2 ? 3 : 0;
+  ok = ok && s < 5;
+  s += b3 ? 5 : 0;
+  ok = ok && s < 10;
+  s += (lane & 16) ? 10 : 0;
+  ok = ok && s < 19;
+  s += (lane & 32) ? 19 : 0;
+  ok = ok && s < 37;
+  slot = ok ? s : -1;
+  return tot;
+}
+
 // Block reduction of the 37 accumulators in a fixed order; threads 0..36 write the tile partial.
 __device__ inline void acc_block_store(Acc& a, float* __restrict__ out, float (*lds)[37]) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  float* v = reinterpret_cast<float*>(&a);
-#pragma unroll
-  for (int k = 0; k < 37; ++k) {
-    const float s = wave_sum_to_lane63(v[k]);
-    if (lane == kWave - 1) lds[wave][k] = s;
-  }
+  int slot;
+  const float t = acc_reduce_scatter(a, lane, slot);
+  if (slot >= 0) lds[wave][slot] = t;
   __syncthreads();
   if (threadIdx.x < kPartial) {
     float s = 0.0f;
@@ -680,30 +733,25 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_stream(const void* __
   const int cnt = seg_count[seg];
   Acc a;
   acc_zero(a);
-  // the next group of records is loaded before the current one is computed (one group in flight while the
-  // arithmetic of the other runs)
-  rec_t nxt[U];
+  // U records in flight per thread: a ring of U registers, each refilled with the record U groups ahead as
+  // soon as its current record has been taken, so that U loads are outstanding while one record is computed
+  // (deeper rings cost 4 registers per record, not a second copy of the arithmetic's registers)
+  rec_t buf[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int q = u * kReduceThreads + int(threadIdx.x);
-    if (q < cnt) nxt[u] = Rec<DT>::load(in + q);
+    if (q < cnt) buf[u] = Rec<DT>::load(in + q);
   }
 #pragma unroll 1
   for (int k0 = 0; k0 < cnt; k0 += kReduceThreads * U) {
-    rec_t r[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) r[u] = nxt[u];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int q = k0 + kReduceThreads * U + u * kReduceThreads + int(threadIdx.x);
-      if (q < cnt) nxt[u] = Rec<DT>::load(in + q);
-    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int q = k0 + u * kReduceThreads + int(threadIdx.x);
+      const rec_t r = buf[u];
+      if (q + kReduceThreads * U < cnt) buf[u] = Rec<DT>::load(in + q + kReduceThreads * U);
       if (q < cnt) {
         float xj[3], xi[3], sq;
-        Rec<DT>::unpack(r[u], xj, xi, sq);
+        Rec<DT>::unpack(r, xj, xi, sq);
         float x0, x1, x2;
         transform(M, xj[0], xj[1], xj[2], x0, x1, x2);
         if constexpr (MODE == kCalibrated) {

@@ -243,7 +243,7 @@ __device__ inline bool locate_item(const ItemMap& M, int b, int& entry, int& til
   return true;
 }
 
-// Batched: 256 query pixels per block; blocks of one direction share an XCD. The LM trial-step count is
+// Batched: one 16x16 tile of query pixels per block; blocks of one direction share an XCD. The LM trial-step count is
 // summed per block and added to one of kStepStripes counters 128 B apart (block b to stripe b mod
 // kStepStripes): a single counter hit by every wave becomes a hot spot of one L2 channel that stalls the
 // whole launch.
@@ -256,13 +256,17 @@ __global__ __launch_bounds__(256) void k_match_batched(const float4* __restrict_
   int entry, tile;
   if (!locate_item(map, blockIdx.x, entry, tile)) return;  // uniform per block
   const MatchDir D = dirs[entry];
-  const int64_t n = int64_t(tile) * 256 + threadIdx.x;
+  // a 16x16 tile of query pixels: their matches (and the LM steps towards them) cover a compact window of
+  // the reference ray image, so the block's gathers share far more L2 lines than a 256-pixel row segment's
+  const int tiles_x = (D.Wq + kMatchTile - 1) / kMatchTile;
+  const int qu = (tile % tiles_x) * kMatchTile + int(threadIdx.x % kMatchTile);
+  const int qv = (tile / tiles_x) * kMatchTile + int(threadIdx.x / kMatchTile);
   int its = 0;
-  if (n < int64_t(D.Hq) * D.Wq) {
+  if (qu < D.Wq && qv < D.Hq) {
+    const int64_t n = int64_t(qv) * D.Wq + qu;
     const float4 x = Px<DT>::load(cross, D.qry_off + n);
     float pu, pv;
-    idx_tmp[D.out_off + n] = match_query(rays + D.ref_off, D.Hr, D.Wr, x, int(n % D.Wq), int(n / D.Wq),
-                                         D.Hq, D.Wq, P, &pu, &pv, &its);
+    idx_tmp[D.out_off + n] = match_query(rays + D.ref_off, D.Hr, D.Wr, x, qu, qv, D.Hq, D.Wq, P, &pu, &pv, &its);
   }
   if (step_stripes) {
     __shared__ int s[4];

@@ -37,8 +37,8 @@ struct MutualDir {
 };
 
 // Blocks are dealt to 8 bins (block b -> bin b mod 8, which the dispatcher places on XCD b mod 8);
-// entries of bin x are [bin_start[x], bin_start[x+1]) with within-bin tile prefixes (256 px per tile for
-// the matching, kMutualPx for the mutual check).
+// entries of bin x are [bin_start[x], bin_start[x+1]) with within-bin tile prefixes (one kMatchTile^2
+// tile of query pixels per block for the matching, kMutualPx pixels for the mutual check).
 struct ItemMap {
   const int32_t* bin_start;  // 9
   const int32_t* prefix;     // per entry: first tile of the entry within its bin
@@ -52,6 +52,11 @@ int launch_match_one(const float4* rays, int H, int W, const void* qry, int Hq, 
 constexpr int kStepStripes = 256;
 constexpr int kStripeStride = 32;
 // step_stripes may be NULL (no counting); it must start at zero.
+// Query tiles of the batched matching: kMatchTile x kMatchTile pixels, one block of 256 threads each.
+constexpr int kMatchTile = 16;
+inline int32_t match_tiles(int H, int W) {
+  return int32_t(((H + kMatchTile - 1) / kMatchTile) * ((W + kMatchTile - 1) / kMatchTile));
+}
 int launch_match_batched(const float4* rays, const void* cross, ds3_dtype dt, const MatchDir* dirs,
                          ItemMap map, int grid, const MatchConst& P, int32_t* idx_tmp,
                          unsigned* step_stripes, hipStream_t s);
