@@ -342,7 +342,7 @@ void ds3_tilechol_destroy(ds3_tilechol* S);
  * to status_per_iter (device, iters int32; either may be NULL). */
 typedef struct {
   int32_t autotune;        /* 1: time candidate segment sizes and loads in flight at creation */
-  int32_t px_per_thread;   /* segment = 256 * px_per_thread pixels (4, 8, 16 or 32; 0 = 16) when not
+  int32_t px_per_thread;   /* segment = 256 * px_per_thread pixels (4, 8, 16, 32 or 64; 0 = 16) when not
                               autotuning */
   int32_t use_graph;       /* 1: capture the iteration in a hipGraph (default), 0: direct launches */
   ds3_timer* reduce_timer; /* may be NULL: recorded around the fused residual/Hessian launch of the last

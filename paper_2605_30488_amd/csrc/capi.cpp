@@ -687,12 +687,12 @@ static int plan_autotune(Plan& P, hipStream_t s) {
   const std::string key = tune_key(P);
   int best_ppt = 16, best_unroll = 2;
   if (tune_lookup(key, best_ppt, best_unroll) && (best_unroll == 1 || best_unroll == 2 || best_unroll == 4) &&
-      (best_ppt == 8 || best_ppt == 16 || best_ppt == 32)) {
+      (best_ppt == 8 || best_ppt == 16 || best_ppt == 32 || best_ppt == 64)) {
     P.unroll = best_unroll;
     return plan_build_items(P, best_ppt, s);
   }
   float best = 1e30f;
-  for (int ppt : {8, 16, 32}) {
+  for (int ppt : {8, 16, 32, 64}) {
     DS3_TRY(plan_build_items(P, ppt, s));
     for (int unroll : {1, 2, 4}) {
       P.unroll = unroll;
@@ -825,7 +825,7 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
   if (rc == DS3_OK) rc = check_hip(hipMalloc(&P->time_ctrs, sizeof(unsigned) * 64), "hipMalloc");
   // match stream: room for every pixel of every edge at the largest segment size (the padding of the
   // last segment of each edge included); segment counts for the smallest segment size
-  for (int ppt : {4, 8, 16, 32}) {
+  for (int ppt : {4, 8, 16, 32, 64}) {
     const size_t seg = size_t(kReduceThreads) * ppt;
     size_t cap = 0;
     for (auto& E : P->T.edges) cap += (size_t(E.npx_j) + seg - 1) / seg * seg;
@@ -866,7 +866,8 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
     } else {
       int ppt = (opts && opts->px_per_thread > 0) ? opts->px_per_thread : 16;
       int unroll = (opts && opts->unroll > 0) ? opts->unroll : 2;
-      if (ppt != 4 && ppt != 8 && ppt != 16 && ppt != 32) rc = fail(DS3_EINVAL, "px_per_thread must be 4, 8, 16 or 32");
+      if (ppt != 4 && ppt != 8 && ppt != 16 && ppt != 32 && ppt != 64)
+        rc = fail(DS3_EINVAL, "px_per_thread must be 4, 8, 16, 32 or 64");
       if (unroll != 1 && unroll != 2 && unroll != 4) rc = fail(DS3_EINVAL, "unroll must be 1, 2 or 4");
       P->unroll = unroll;
       if (rc == DS3_OK) rc = plan_build_items(*P, ppt, s);

@@ -44,7 +44,7 @@ def _bf16_inputs(g):
     return xyz, conf
 
 
-@pytest.mark.parametrize("ppt,unroll", [(4, 1), (16, 2), (32, 4), (8, 4)])
+@pytest.mark.parametrize("ppt,unroll", [(4, 1), (16, 2), (32, 4), (8, 4), (64, 2)])
 def test_plan_equals_plain_form(dev, single, ppt, unroll):
     """Batched plan (match stream, graph replay) and plain per-edge steps give the same poses (same FP32
     math per match, sums in a different order) for every segment size and loads in flight."""
