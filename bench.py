@@ -50,19 +50,19 @@ TRAFFIC = {
     "k_reduce_stream": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "4b646c83fbd0fc61", "bytes": 1148702618},
+        "sha": "e2bf40bc49f375e2", "bytes": 1145486643},
     "k_reduce_stream (calibrated)": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
-        "sha": "4b646c83fbd0fc61", "bytes": 2326333850},
+        "sha": "e2bf40bc49f375e2", "bytes": 2330764390},
     "k_reduce_stream (tracker, float64 cost)": {
         "sources": ["paper_2605_30488_amd/csrc/gn.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp", "paper_2605_30488_amd/csrc/track.hip"],
-        "sha": "43c4545a3cf8f5ec", "bytes": 344592077},
+        "sha": "6ae3ac8dc9cff23e", "bytes": 344537395},
     "k_match_batched": {
         "sources": ["paper_2605_30488_amd/csrc/match.hip", "paper_2605_30488_amd/csrc/match_internal.hpp",
                     "paper_2605_30488_amd/csrc/common.hpp"],
-        "sha": "cd5f23ae7f6dc636", "bytes": 9303938662},
+        "sha": "503738ea23f6298d", "bytes": 9308063949},
     "k_adjoint_gather": {
         "sources": ["paper_2605_30488_amd/csrc/adjoint.hip", "paper_2605_30488_amd/csrc/common.hpp",
                     "paper_2605_30488_amd/csrc/internal.hpp"],
