@@ -533,23 +533,25 @@ static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
                                P.B.count_e, s));
   const size_t n = 7 * size_t(P.T.n_kf);
   // H was cleared once at plan creation: the assembly rewrites every block of its fixed nonzero pattern
+  // with the tile-sparse solver, the assembly also clears the solve's barrier words and attempt-0 flag (one
+  // launch fewer per iteration)
+  unsigned* sync = P.tc ? chol_sync_words(P.B.chol_ws, int(n)) : nullptr;
   DS3_TRY(launch_assemble(P.T.n_kf, P.B.node_ptr, P.B.node_adj, P.B.pair_ptr, P.B.pair_edges, P.B.pair_ij,
-                          P.T.n_pairs, P.B.A_e, P.B.b_e, P.B.anchor, P.B.H, P.B.g, s));
+                          P.T.n_pairs, P.B.A_e, P.B.b_e, P.B.anchor, P.B.H, P.B.g, s, sync, sync ? 4 : 0));
   int32_t* status = reinterpret_cast<int32_t*>(P.B.counter + 8);
   if (P.sp)
     DS3_TRY(launch_spchol(P.sp, P.B.H, P.B.g, P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts, P.B.tau,
                           status, s));
   else if (P.tc)
     DS3_TRY(launch_tilechol(P.tc, P.B.H, P.B.g, P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts, P.B.tau,
-                            status, P.B.chol_ws, s));
+                            status, P.B.chol_ws, s, true));
   else
     DS3_TRY(launch_chol_ladder(P.B.H, P.B.g, int(n), P.p.lambda, P.p.eps0, P.p.eps_mult, P.p.max_attempts,
                                P.B.tau, status, P.B.chol_ws, s));
-  DS3_TRY(launch_sim3_update(P.poses, P.B.tau, P.B.anchor, P.T.n_kf, s));
-  // the cost at the iteration's input poses (cost_e is rewritten only by the next iteration) and the
-  // ladder status go to the history
-  return launch_sum_costs_record(P.B.cost_e, P.B.count_e, P.T.n_edges, P.B.cost_tmp, P.B.count_tmp, status,
-                                 P.hist_ctr, P.cost_hist, P.status_hist, kHistory, s);
+  // the update, and the cost at the iteration's input poses (cost_e is rewritten only by the next iteration)
+  // with the ladder status to the history, in one launch
+  return launch_update_record(P.poses, P.B.tau, P.B.anchor, P.T.n_kf, P.B.cost_e, P.B.count_e, P.T.n_edges,
+                              P.B.cost_tmp, P.B.count_tmp, status, P.hist_ctr, P.cost_hist, P.status_hist, kHistory, s);
 }
 
 // Order (edge, tile) items by descending valid count for the current tile shape.

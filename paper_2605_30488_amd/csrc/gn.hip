@@ -990,9 +990,11 @@ __global__ __launch_bounds__(64) void k_assemble(int n_kf, const int32_t* __rest
                                                  const double* __restrict__ A_e,
                                                  const double* __restrict__ b_e,
                                                  const uint8_t* __restrict__ anchor,
-                                                 double* __restrict__ H, double* __restrict__ g) {
+                                                 double* __restrict__ H, double* __restrict__ g,
+                                                 unsigned* __restrict__ zero, int n_zero) {
   const int t = threadIdx.x;
   const int64_t n = 7 * int64_t(n_kf);
+  if (blockIdx.x == 0 && t < n_zero) zero[t] = 0u;  // words the solve that follows needs cleared
   if (int(blockIdx.x) < n_kf) {
     const int k = blockIdx.x;
     const bool anc = anchor && anchor[k];
@@ -1046,22 +1048,22 @@ __global__ __launch_bounds__(64) void k_assemble(int n_kf, const int32_t* __rest
 
 int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,
                     const int32_t* pair_edges, const int32_t* pair_ij, int n_pairs, const double* A_e,
-                    const double* b_e, const uint8_t* anchor_mask, double* H, double* g, hipStream_t s) {
+                    const double* b_e, const uint8_t* anchor_mask, double* H, double* g, hipStream_t s,
+                    unsigned* zero, int n_zero) {
+  if (n_zero < 0 || n_zero > 64 || (n_zero > 0 && !zero)) return fail(DS3_EINVAL, "assemble: bad zero words");
   hipLaunchKernelGGL(k_assemble, dim3(n_kf + n_pairs), dim3(64), 0, s, n_kf, node_ptr, node_adj, pair_ptr,
-                     pair_edges, pair_ij, A_e, b_e, anchor_mask, H, g);
+                     pair_edges, pair_ij, A_e, b_e, anchor_mask, H, g, zero, n_zero);
   return check_hip(hipGetLastError(), "k_assemble");
 }
 
-// Deterministic sum of per-edge costs and counts (fixed strided split + fixed tree). With ctr, the sum
-// and *status are also appended to a history (slot *ctr, then ctr advances; slots past hist_len are
-// dropped).
-__global__ __launch_bounds__(256) void k_sum_costs(const double* __restrict__ cost_e,
-                                                   const int64_t* __restrict__ count_e, int n_edges,
-                                                   double* __restrict__ cost_out,
-                                                   int64_t* __restrict__ count_out,
-                                                   const int32_t* __restrict__ status, unsigned* __restrict__ ctr,
-                                                   double* __restrict__ cost_hist,
-                                                   int32_t* __restrict__ status_hist, int hist_len) {
+// Deterministic sum of per-edge costs and counts over one block of 256 threads (fixed strided split + fixed
+// tree); thread 0 writes them. With ctr, the sum and *status are also appended to a history (slot *ctr,
+// then ctr advances; slots past hist_len are dropped).
+__device__ inline void sum_costs_block(const double* __restrict__ cost_e, const int64_t* __restrict__ count_e,
+                                       int n_edges, double* __restrict__ cost_out, int64_t* __restrict__ count_out,
+                                       const int32_t* __restrict__ status, unsigned* __restrict__ ctr,
+                                       double* __restrict__ cost_hist, int32_t* __restrict__ status_hist,
+                                       int hist_len) {
   __shared__ double sc[256];
   __shared__ long long sn[256];
   double c = 0.0;
@@ -1094,19 +1096,21 @@ __global__ __launch_bounds__(256) void k_sum_costs(const double* __restrict__ co
   }
 }
 
+__global__ __launch_bounds__(256) void k_sum_costs(const double* __restrict__ cost_e,
+                                                   const int64_t* __restrict__ count_e, int n_edges,
+                                                   double* __restrict__ cost_out,
+                                                   int64_t* __restrict__ count_out,
+                                                   const int32_t* __restrict__ status, unsigned* __restrict__ ctr,
+                                                   double* __restrict__ cost_hist,
+                                                   int32_t* __restrict__ status_hist, int hist_len) {
+  sum_costs_block(cost_e, count_e, n_edges, cost_out, count_out, status, ctr, cost_hist, status_hist, hist_len);
+}
+
 int launch_sum_costs(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
                      int64_t* count_out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_costs, dim3(1), dim3(256), 0, s, cost_e, count_e, n_edges, cost_out, count_out,
                      static_cast<const int32_t*>(nullptr), static_cast<unsigned*>(nullptr),
                      static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr), 0);
-  return check_hip(hipGetLastError(), "k_sum_costs");
-}
-
-int launch_sum_costs_record(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
-                            int64_t* count_out, const int32_t* status, unsigned* ctr, double* cost_hist,
-                            int32_t* status_hist, int hist_len, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_costs, dim3(1), dim3(256), 0, s, cost_e, count_e, n_edges, cost_out, count_out, status,
-                     ctr, cost_hist, status_hist, hist_len);
   return check_hip(hipGetLastError(), "k_sum_costs");
 }
 
@@ -1127,6 +1131,39 @@ int launch_sim3_update(double* poses, const double* tau, const uint8_t* fixed, i
   if (n <= 0) return DS3_OK;
   hipLaunchKernelGGL(k_sim3_update, dim3((n + 63) / 64), dim3(64), 0, s, poses, tau, fixed, n);
   return check_hip(hipGetLastError(), "k_sim3_update");
+}
+
+// The last step of a plan iteration in one launch: block 0 sums the edge costs and records them with the
+// ladder status (as k_sum_costs), blocks 1.. apply T <- Exp(tau) T (as k_sim3_update). Both only read what the
+// solve and the reduction before them wrote.
+__global__ __launch_bounds__(256) void k_update_record(double* __restrict__ poses, const double* __restrict__ tau,
+                                                       const uint8_t* __restrict__ fixed, int n,
+                                                       const double* __restrict__ cost_e,
+                                                       const int64_t* __restrict__ count_e, int n_edges,
+                                                       double* __restrict__ cost_out, int64_t* __restrict__ count_out,
+                                                       const int32_t* __restrict__ status, unsigned* __restrict__ ctr,
+                                                       double* __restrict__ cost_hist,
+                                                       int32_t* __restrict__ status_hist, int hist_len) {
+  if (blockIdx.x == 0) {
+    sum_costs_block(cost_e, count_e, n_edges, cost_out, count_out, status, ctr, cost_hist, status_hist, hist_len);
+    return;
+  }
+  const int k = (blockIdx.x - 1) * 256 + threadIdx.x;
+  if (k >= n) return;
+  if (fixed && fixed[k]) return;
+  Sim3 E = sim3_exp(tau + 7 * int64_t(k));
+  Sim3 T = sim3_load(poses + 8 * int64_t(k));
+  sim3_store(sim3_mul(E, T), poses + 8 * int64_t(k));
+}
+
+int launch_update_record(double* poses, const double* tau, const uint8_t* fixed, int n, const double* cost_e,
+                         const int64_t* count_e, int n_edges, double* cost_out, int64_t* count_out,
+                         const int32_t* status, unsigned* ctr, double* cost_hist, int32_t* status_hist, int hist_len,
+                         hipStream_t s) {
+  const int blocks = 1 + (std::max(n, 0) + 255) / 256;
+  hipLaunchKernelGGL(k_update_record, dim3(blocks), dim3(256), 0, s, poses, tau, fixed, n, cost_e, count_e, n_edges,
+                     cost_out, count_out, status, ctr, cost_hist, status_hist, hist_len);
+  return check_hip(hipGetLastError(), "k_update_record");
 }
 
 __global__ void k_fill_f64(double* p, size_t n, double v) {

@@ -130,13 +130,17 @@ int launch_edge_finalize(const EdgeDev* edges, int n_edges, const float* partial
                          double* A_out, double* b_out, double* cost_e, int64_t* count_e, hipStream_t s);
 int launch_assemble(int n_kf, const int32_t* node_ptr, const int32_t* node_adj, const int32_t* pair_ptr,
                     const int32_t* pair_edges, const int32_t* pair_ij, int n_pairs, const double* A_e,
-                    const double* b_e, const uint8_t* anchor_mask, double* H, double* g, hipStream_t s);
+                    const double* b_e, const uint8_t* anchor_mask, double* H, double* g, hipStream_t s,
+                    unsigned* zero = nullptr, int n_zero = 0);  // also clears zero[0 .. n_zero), n_zero <= 64
 int launch_sum_costs(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
                      int64_t* count_out, hipStream_t s);
-int launch_sum_costs_record(const double* cost_e, const int64_t* count_e, int n_edges, double* cost_out,
-                            int64_t* count_out, const int32_t* status, unsigned* ctr, double* cost_hist,
-                            int32_t* status_hist, int hist_len, hipStream_t s);
 int launch_sim3_update(double* poses, const double* tau, const uint8_t* fixed, int n, hipStream_t s);
+// T <- Exp(tau) T (as launch_sim3_update) and the sum of the edge costs with the ladder status appended to the
+// history (the history counter is advanced), in one launch
+int launch_update_record(double* poses, const double* tau, const uint8_t* fixed, int n, const double* cost_e,
+                         const int64_t* count_e, int n_edges, double* cost_out, int64_t* count_out,
+                         const int32_t* status, unsigned* ctr, double* cost_hist, int32_t* status_hist, int hist_len,
+                         hipStream_t s);
 int launch_fill(double* p, size_t n, double v, hipStream_t s);
 int launch_fill_u32(unsigned* p, size_t n, unsigned v, hipStream_t s);
 int launch_copy_f64(const double* src, double* dst, size_t n, hipStream_t s);
@@ -178,8 +182,11 @@ struct TileChol;
 int tilechol_create(int n_kf, int n_pairs, const int32_t* pair_ij, TileChol** out);
 void tilechol_destroy(TileChol* P);
 void tilechol_stats(const TileChol* P, int64_t* info);  // n_kf, tiles, factor tiles, levels, updates, pad rows, thr
+// sync_cleared: the first four words of ws's barrier block (chol_sync_words) were already cleared on stream s
+// (by the plan's assembly), so the solve does not clear them itself
 int launch_tilechol(const TileChol* P, const double* H, const double* g, double lambda, double eps0,
-                    double mult, int attempts, double* tau, int32_t* status, void* ws, hipStream_t s);
+                    double mult, int attempts, double* tau, int32_t* status, void* ws, hipStream_t s,
+                    bool sync_cleared = false);
 
 // sim3.hip
 int launch_sim3_exp(const double* tau, double* poses, int n, hipStream_t s);

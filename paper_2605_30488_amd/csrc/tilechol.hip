@@ -775,7 +775,8 @@ void tilechol_stats(const TileChol* P, int64_t* info) {
 }
 
 int launch_tilechol(const TileChol* P, const double* H, const double* g, double lambda, double eps0,
-                    double mult, int attempts, double* tau, int32_t* status, void* ws, hipStream_t s) {
+                    double mult, int attempts, double* tau, int32_t* status, void* ws, hipStream_t s,
+                    bool sync_cleared) {
   if (!P || !H || !g || !tau || !status || !ws) return fail(DS3_EINVAL, "tilechol: null pointer");
   if (attempts < 1 || attempts > kTcMaxAttempts) return fail(DS3_EINVAL, "tilechol: attempts out of range");
   const TcSymbolic& S = P->S;
@@ -791,7 +792,7 @@ int launch_tilechol(const TileChol* P, const double* H, const double* g, double 
   a.done = P->done;
   // the dense fallback's barrier words and the attempt-0 flag start at zero (a fill kernel, not a memset,
   // so the sequence can be captured)
-  DS3_TRY(launch_fill_u32(a.sync, 4, 0u, s));
+  if (!sync_cleared) DS3_TRY(launch_fill_u32(a.sync, 4, 0u, s));
   hipLaunchKernelGGL(k_tc_init, dim3(unsigned(S.nslot)), dim3(kTcThreads), 0, s, a);
   DS3_TRY(check_hip(hipGetLastError(), "k_tc_init"));
   for (int l = 0; l + 1 < S.nlev; ++l) {
