@@ -693,20 +693,28 @@ static int plan_autotune(Plan& P, hipStream_t s) {
     P.unroll = best_unroll;
     return plan_build_items(P, best_ppt, s);
   }
+  // per segment size, the records-in-flight variants are timed in interleaved rounds and each keeps its
+  // fastest round: the variants differ by a few percent, less than the clock drifts over a sweep
+  constexpr int kRounds = 3;
+  constexpr int kUnrolls[3] = {1, 2, 4};
   float best = 1e30f;
   for (int ppt : {8, 16, 32, 64}) {
     DS3_TRY(plan_build_items(P, ppt, s));
-    for (int unroll : {1, 2, 4}) {
-      P.unroll = unroll;
-      float ms = 0.f;
-      DS3_TRY(plan_time_reduce(P, 2, &ms, s));  // warm
-      DS3_TRY(plan_time_reduce(P, 5, &ms, s));
-      if (ms < best) {
-        best = ms;
-        best_ppt = ppt;
-        best_unroll = unroll;
+    float t[3] = {1e30f, 1e30f, 1e30f};
+    for (int r = 0; r < kRounds; ++r)
+      for (int u = 0; u < 3; ++u) {
+        P.unroll = kUnrolls[u];
+        float ms = 0.f;
+        if (r == 0) DS3_TRY(plan_time_reduce(P, 2, &ms, s));  // warm
+        DS3_TRY(plan_time_reduce(P, 5, &ms, s));
+        t[u] = std::min(t[u], ms);
       }
-    }
+    for (int u = 0; u < 3; ++u)
+      if (t[u] < best) {
+        best = t[u];
+        best_ppt = ppt;
+        best_unroll = kUnrolls[u];
+      }
   }
   tune_store(key, best_ppt, best_unroll);
   P.unroll = best_unroll;
