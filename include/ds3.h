@@ -332,19 +332,21 @@ void ds3_tilechol_destroy(ds3_tilechol* S);
  * streams those records (one block per segment, the heaviest segments first), instead of scanning the
  * idx arena and gathering X_i again. Creation uploads the topology, gathers the stream, picks the
  * segment size and the loads in flight per thread (opts->autotune: timed candidates, cached per device,
- * dtype and shape mix; synchronises) and captures one GN iteration in a hipGraph.
+ * dtype and shape mix; synchronises) and captures one GN iteration, and eight back to back, in hipGraphs.
  * The plan owns its device buffers (the stream: up to (sum over edges of H_j*W_j, rounded up to whole
  * segments) records) and its graph; the keyframe arena, idx arena and poses stay the caller's and must
  * outlive the plan. After the caller rewrites the idx arena (a new matching pass) or the keyframe arena,
  * ds3_gn_plan_refresh must run before the next ds3_gn_plan_run: the plan reads the snapshot, not the
- * arenas. ds3_gn_plan_run replays the iteration `iters` times on `stream` with no host synchronisation,
+ * arenas. ds3_gn_plan_run replays the iteration `iters` times on `stream` with no host synchronisation
+ * (eight at a time through the eight-iteration graph while at least eight remain: a replay pays a launch
+ * gap of several microseconds before its first kernel),
  * writing E at each iteration's input poses to cost_per_iter (device, iters float64) and the ladder status
  * to status_per_iter (device, iters int32; either may be NULL). */
 typedef struct {
   int32_t autotune;        /* 1: time candidate segment sizes and loads in flight at creation */
   int32_t px_per_thread;   /* segment = 256 * px_per_thread pixels (4, 8, 16, 32 or 64; 0 = 16) when not
                               autotuning */
-  int32_t use_graph;       /* 1: capture the iteration in a hipGraph (default), 0: direct launches */
+  int32_t use_graph;       /* 1: capture the iterations in hipGraphs (default), 0: direct launches */
   ds3_timer* reduce_timer; /* may be NULL: recorded around the fused residual/Hessian launch of the last
                               iteration of every ds3_gn_plan_run, which then runs as direct launches
                               instead of a graph replay (same kernels, same results) */

@@ -516,11 +516,15 @@ struct Plan {
   EdgeCal* ecal = nullptr;     // calibrated mode: per-edge intrinsics (device), else NULL
   bool use_graph = true;
   ds3_timer* timer = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;  // one iteration
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_chunk = nullptr;  // kGraphChunk iterations in one graph (one launch gap per chunk)
+  hipGraphExec_t exec_chunk = nullptr;
   SpChol* sp = nullptr;        // block-sparse solver of the plan's pattern, NULL otherwise
   TileChol* tc = nullptr;      // tile-sparse solver of the plan's pattern, NULL otherwise
 };
+
+constexpr int kGraphChunk = 8;  // iterations per chunk graph of a plan
 
 // One GN iteration; `timed` records the plan's timer around the residual launch (never inside a capture).
 static int plan_iteration(Plan& P, hipStream_t s, bool timed) {
@@ -725,6 +729,8 @@ static void plan_free(Plan* P) {
   if (!P) return;
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->exec_chunk) (void)hipGraphExecDestroy(P->exec_chunk);
+  if (P->graph_chunk) (void)hipGraphDestroy(P->graph_chunk);
   if (P->ws) (void)hipFree(P->ws);
   if (P->items) (void)hipFree(P->items);
   if (P->cost_hist) (void)hipFree(P->cost_hist);
@@ -888,18 +894,25 @@ int ds3_gn_plan_create(int32_t n_kf, const ds3_image* kf, const void* arena, ds3
     for (auto& E : P->T.edges) P->px_scanned += E.npx_j;
   }
   if (rc == DS3_OK && P->use_graph) {
+    // one iteration, and kGraphChunk iterations back to back: a replayed graph pays a launch gap of about
+    // 8 us before its first kernel, so runs replay the chunk graph as often as they can
     hipStream_t cs;
     rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
     if (rc == DS3_OK) {
-      rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-      if (rc == DS3_OK) {
-        int rc2 = plan_iteration(*P, cs, false);
+      for (int reps : {1, kGraphChunk}) {
+        if (rc != DS3_OK) break;
+        rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        if (rc != DS3_OK) break;
+        int rc2 = DS3_OK;
+        for (int r = 0; r < reps && rc2 == DS3_OK; ++r) rc2 = plan_iteration(*P, cs, false);
         hipGraph_t g = nullptr;
         int rc3 = check_hip(hipStreamEndCapture(cs, &g), "hipStreamEndCapture");
         rc = rc2 != DS3_OK ? rc2 : rc3;
-        P->graph = g;
+        hipGraph_t& gp = reps == 1 ? P->graph : P->graph_chunk;
+        hipGraphExec_t& ep = reps == 1 ? P->exec : P->exec_chunk;
+        gp = g;
+        if (rc == DS3_OK) rc = check_hip(hipGraphInstantiate(&ep, gp, nullptr, nullptr, 0), "hipGraphInstantiate");
       }
-      if (rc == DS3_OK) rc = check_hip(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
       (void)hipStreamDestroy(cs);
     }
   }
@@ -915,16 +928,13 @@ int ds3_gn_plan_run(void* plan, int32_t iters, double* cost_per_iter, int32_t* s
   if (iters > kHistory) return fail(DS3_EINVAL, "plan_run: at most 4096 iterations per call");
   hipStream_t s = S(stream);
   DS3_TRY(launch_fill_u32(P->hist_ctr, 1, 0u, s));
-  for (int it = 0; it < iters; ++it) {
-    // with a timer, the last iteration runs as direct launches so that the events bracket its residual
-    // launch (event records are not captured into the graph)
-    const bool timed = P->timer && it == iters - 1;
-    if (P->use_graph && !timed) {
-      DS3_TRY_HIP(hipGraphLaunch(P->exec, s));
-    } else {
-      DS3_TRY(plan_iteration(*P, s, timed));
-    }
-  }
+  // with a timer, the last iteration runs as direct launches so that the events bracket its residual
+  // launch (event records are not captured into the graph)
+  const int replayed = P->use_graph ? iters - (P->timer && iters > 0 ? 1 : 0) : 0;
+  int it = 0;
+  for (; it + kGraphChunk <= replayed; it += kGraphChunk) DS3_TRY_HIP(hipGraphLaunch(P->exec_chunk, s));
+  for (; it < replayed; ++it) DS3_TRY_HIP(hipGraphLaunch(P->exec, s));
+  for (; it < iters; ++it) DS3_TRY(plan_iteration(*P, s, P->timer && it == iters - 1));
   if (iters > 0 && cost_per_iter)
     DS3_TRY_HIP(hipMemcpyAsync(cost_per_iter, P->cost_hist, sizeof(double) * iters, hipMemcpyDeviceToDevice, s));
   if (iters > 0 && status_per_iter)

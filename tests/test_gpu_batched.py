@@ -205,6 +205,35 @@ def test_graph_replays_match_direct_launches(dev, single):
     pb.close()
 
 
+def test_chunked_replays_match_direct_launches(dev, single):
+    """Runs long enough for the eight-iteration graph (11 iterations: one chunk and three single replays;
+    17 with a timer: two chunks and the timed direct iteration) equal the same launches issued directly,
+    bit for bit in the poses and in every iteration's cost and ladder status, twice in a row with eager
+    work between the runs."""
+    g, idx = single
+    G = _graph(g, idx, "f32", dev)
+    for iters, timed in ((11, False), (17, True)):
+        Pa = _t(g.poses_init, dev)
+        Pb = _t(g.poses_init, dev)
+        t = ds3.KernelTimer() if timed else None
+        pa = ds3.GNPlan(G, Pa, use_graph=True, reduce_timer=t)
+        pb = ds3.GNPlan(G, Pb, use_graph=False)
+        for _ in range(2):
+            ca, sa = pa.run(iters)
+            torch.cuda.synchronize()
+            _ = torch.zeros(1000, device=dev).sum()  # unrelated eager work between runs
+            cb, sb = pb.run(iters)
+            torch.cuda.synchronize()
+            assert ca.shape[0] == iters
+            assert torch.equal(Pa, Pb)
+            assert torch.equal(ca, cb)
+            assert torch.equal(sa, sb)
+        pa.close()
+        pb.close()
+        if t is not None:
+            t.close()
+
+
 def test_match_batch_equals_single_and_oracle(dev, single):
     """Batched matching of all 40 edges equals per-edge bidirectional calls bit for bit, and the oracle
     on >= 99.9% of valid pixels of sampled edges (full 512x384 size)."""
