@@ -10,11 +10,13 @@
 // than the panel order:
 //
 // Symbolic analysis (host, once per pattern):
-//   * a minimum-degree elimination order of the keyframe graph and its elimination tree;
+//   * two elimination orders of the keyframe graph, minimum degree and nested dissection, and their
+//     elimination trees (every layout below is tried for both);
 //   * a layout of the keyframes' 7-row blocks along a postorder of that tree in which every child
 //     subtree of a node except its largest (the last one laid out before the node) is aligned to whole
 //     tiles when it holds at least `thr` keyframes, so that sibling subtrees share no tile (padding rows
-//     are identity rows with a zero right-hand side); the threshold with the fewest tree levels wins;
+//     are identity rows with a zero right-hand side); the order and threshold with the fewest tree levels
+//     win, then the fewest factor tiles;
 //   * the tile pattern of H in that layout, its symbolic tile Cholesky factorisation (column K's rows,
 //     closed under the elimination: fill included), the tile elimination tree and its levels;
 //   * per level l, the trailing tiles (I, J) that the level's pivot columns K update (I, J both rows of
@@ -74,7 +76,7 @@ struct TcSymbolic {
 namespace {
 
 struct Tree {
-  std::vector<int> order;                // minimum-degree elimination order (keyframes)
+  std::vector<int> order;                // elimination order (keyframes)
   std::vector<int> parent, size;         // per keyframe
   std::vector<std::vector<int>> child;   // per keyframe, by (subtree size, id)
   std::vector<int> roots;                // by (subtree size, id)
@@ -182,56 +184,200 @@ void tile_shape(int n_kf, const std::vector<std::vector<int>>& adj, const std::v
   for (int K = 0; K < nt; ++K) S.nlev = std::max(S.nlev, S.level[K] + 1);
 }
 
+// Symbolic elimination of the keyframe graph (bit rows `adj`, W words each) in a given order: rows[v] =
+// the neighbours of v when it is eliminated, i.e. its column of the filled factor.
+void eliminate(int n, std::vector<uint64_t> adj, const std::vector<int>& order, std::vector<std::vector<int>>& rows) {
+  const int W = (n + 63) / 64;
+  rows.assign(n, {});
+  for (int v : order) {
+    const uint64_t* av = &adj[size_t(v) * W];
+    std::vector<int>& nb = rows[v];
+    for (int w = 0; w < W; ++w)
+      for (uint64_t m = av[w]; m; m &= m - 1) nb.push_back(64 * w + __builtin_ctzll(m));
+    for (int a : nb) {
+      uint64_t* aa = &adj[size_t(a) * W];
+      for (int w = 0; w < W; ++w) aa[w] |= av[w];
+      aa[a / 64] &= ~(1ull << (a % 64));
+      aa[v / 64] &= ~(1ull << (v % 64));
+    }
+  }
+}
+
+// Nested-dissection order of the keyframe graph. A vertex set (taken in increasing id) is ordered so:
+//   * several connected components: each in turn, in order of their smallest id;
+//   * at most kNdLeaf keyframes: increasing id;
+//   * otherwise a breadth-first search of the set from its smallest id, repeated three times from the
+//     farthest vertex found (the smallest id among the farthest), gives levels from a pseudo-peripheral
+//     vertex; with fewer than three levels (too dense to split) the set keeps increasing id; else the cut
+//     level c is the smallest of 1 .. L-1 (L the last level) holding half the set with the levels below
+//     it (L-1 if none does); the near side is the levels below c plus the level-c vertices with no
+//     neighbour on level c+1, the far side the levels above c, the separator the rest of level c; the
+//     near side, then the far side are ordered recursively, then the separator in increasing id.
+// On chains of keyframes the elimination tree is then about logarithmic in height instead of linear.
+constexpr int kNdLeaf = 4;
+void nd_order(int n, const std::vector<std::vector<int>>& adj, std::vector<int>& order) {
+  order.clear();
+  std::vector<int> stamp(n, 0), lev(n, -1), comp(n, -1);
+  int epoch = 0;
+  // components of S (sorted by id), each as its own sorted list, in order of their smallest member
+  auto components = [&](const std::vector<int>& S, std::vector<std::vector<int>>& out) {
+    out.clear();
+    ++epoch;
+    for (int v : S) stamp[v] = epoch;
+    for (int v : S) comp[v] = -1;
+    for (int r : S) {
+      if (comp[r] >= 0) continue;
+      out.push_back({r});
+      comp[r] = int(out.size()) - 1;
+      for (size_t h = 0; h < out.back().size(); ++h)
+        for (int u : adj[out.back()[h]])
+          if (stamp[u] == epoch && comp[u] < 0) {
+            comp[u] = comp[r];
+            out.back().push_back(u);
+          }
+      std::sort(out.back().begin(), out.back().end());
+    }
+  };
+  // breadth-first levels within S (stamped with the current epoch) from r; returns the farthest vertex
+  auto bfs = [&](const std::vector<int>& S, int r, int& maxlev) {
+    for (int v : S) lev[v] = -1;
+    std::vector<int> q{r};
+    lev[r] = 0;
+    int far = r;
+    for (size_t h = 0; h < q.size(); ++h) {
+      const int v = q[h];
+      if (lev[v] > lev[far] || (lev[v] == lev[far] && v < far)) far = v;
+      for (int u : adj[v])
+        if (stamp[u] == epoch && lev[u] < 0) {
+          lev[u] = lev[v] + 1;
+          q.push_back(u);
+        }
+    }
+    maxlev = lev[far];
+    return far;
+  };
+  // explicit stack of tasks: a vertex set to order, or a separator to append (emit)
+  struct Task { std::vector<int> set; bool emit; };
+  std::vector<Task> st(1);
+  for (int v = 0; v < n; ++v) st[0].set.push_back(v);
+  st[0].emit = false;
+  while (!st.empty()) {
+    Task t = std::move(st.back());
+    st.pop_back();
+    if (t.emit) {
+      for (int v : t.set) order.push_back(v);
+      continue;
+    }
+    std::sort(t.set.begin(), t.set.end());
+    std::vector<std::vector<int>> cs;
+    components(t.set, cs);
+    if (cs.size() > 1) {
+      for (size_t c = cs.size(); c-- > 0;) st.push_back({std::move(cs[c]), false});
+      continue;
+    }
+    std::vector<int>& S = cs[0];
+    if (int(S.size()) <= kNdLeaf) {
+      std::sort(S.begin(), S.end());
+      for (int v : S) order.push_back(v);
+      continue;
+    }
+    ++epoch;
+    for (int v : S) stamp[v] = epoch;
+    int L = 0;
+    int r = *std::min_element(S.begin(), S.end());
+    for (int sweep = 0; sweep < 3; ++sweep) r = bfs(S, r, L);
+    bfs(S, r, L);
+    if (L < 2) {
+      std::sort(S.begin(), S.end());
+      for (int v : S) order.push_back(v);
+      continue;
+    }
+    std::vector<int> cnt(L + 1, 0);
+    for (int v : S) ++cnt[lev[v]];
+    int cut = 1, below = cnt[0];
+    while (cut < L - 1 && 2 * (below + cnt[cut]) < int(S.size())) below += cnt[cut++];
+    std::vector<int> a, b, sep;
+    for (int v : S) {
+      if (lev[v] < cut) a.push_back(v);
+      else if (lev[v] > cut) b.push_back(v);
+      else {
+        bool far = false;
+        for (int u : adj[v])
+          if (stamp[u] == epoch && lev[u] == cut + 1) far = true;
+        (far ? sep : a).push_back(v);
+      }
+    }
+    std::sort(sep.begin(), sep.end());
+    st.push_back({std::move(sep), true});
+    st.push_back({std::move(b), false});
+    st.push_back({std::move(a), false});
+  }
+}
+
 }  // namespace
 
 static int tc_symbolic(int n_kf, int n_pairs, const int32_t* pair_ij, TcSymbolic& S) {
   if (n_kf < 1 || n_kf > kTcMaxKf) return fail(DS3_EINVAL, "tilechol: n_kf must be in 1 .. 1170");
-  Tree T;
-  std::vector<std::vector<int>> rows;
+  std::vector<std::vector<int>> md_rows;
   std::vector<uint64_t> bits;
-  DS3_TRY(min_degree_order(n_kf, n_pairs, pair_ij, T.order, rows, &bits));
+  std::vector<int> md;
+  DS3_TRY(min_degree_order(n_kf, n_pairs, pair_ij, md, md_rows, &bits));
   const int n = n_kf, W = (n + 63) / 64;
-  std::vector<int> pos(n);
-  for (int k = 0; k < n; ++k) pos[T.order[k]] = k;
-  T.parent.assign(n, -1);
-  T.size.assign(n, 1);
-  T.child.assign(n, {});
-  for (int v : T.order) {
-    int p = -1;
-    for (int u : rows[v])
-      if (p < 0 || pos[u] < pos[p]) p = u;
-    T.parent[v] = p;
-  }
-  for (int v : T.order)  // children are eliminated before their parent
-    if (T.parent[v] >= 0) T.size[T.parent[v]] += T.size[v];
-  for (int v = 0; v < n; ++v)
-    if (T.parent[v] >= 0) T.child[T.parent[v]].push_back(v);
-    else T.roots.push_back(v);
-  auto by_size = [&](int a, int b) { return T.size[a] != T.size[b] ? T.size[a] < T.size[b] : a < b; };
-  for (auto& c : T.child) std::sort(c.begin(), c.end(), by_size);
-  std::sort(T.roots.begin(), T.roots.end(), by_size);
   std::vector<std::vector<int>> adj(n);
   for (int v = 0; v < n; ++v)
     for (int w = 0; w < W; ++w)
       for (uint64_t m = bits[size_t(v) * W + w]; m; m &= m - 1) adj[v].push_back(64 * w + __builtin_ctzll(m));
-  // thresholds: the fewest tree levels, then the fewest factor tiles
+  // elimination tree of an order (parent = the earliest-eliminated row of a keyframe's factor column)
+  auto build_tree = [&](const std::vector<int>& order, const std::vector<std::vector<int>>& rows, Tree& T) {
+    T.order = order;
+    std::vector<int> pos(n);
+    for (int k = 0; k < n; ++k) pos[order[k]] = k;
+    T.parent.assign(n, -1);
+    T.size.assign(n, 1);
+    T.child.assign(n, {});
+    T.roots.clear();
+    for (int v : order) {
+      int p = -1;
+      for (int u : rows[v])
+        if (p < 0 || pos[u] < pos[p]) p = u;
+      T.parent[v] = p;
+    }
+    for (int v : order)  // children are eliminated before their parent
+      if (T.parent[v] >= 0) T.size[T.parent[v]] += T.size[v];
+    for (int v = 0; v < n; ++v)
+      if (T.parent[v] >= 0) T.child[T.parent[v]].push_back(v);
+      else T.roots.push_back(v);
+    auto by_size = [&](int a, int b) { return T.size[a] != T.size[b] ? T.size[a] < T.size[b] : a < b; };
+    for (auto& c : T.child) std::sort(c.begin(), c.end(), by_size);
+    std::sort(T.roots.begin(), T.roots.end(), by_size);
+  };
+  // two elimination orders (minimum degree, nested dissection) x the alignment thresholds: the fewest tree
+  // levels, then the fewest factor tiles
+  std::vector<int> nd;
+  std::vector<std::vector<int>> nd_rows;
+  nd_order(n, adj, nd);
+  eliminate(n, bits, nd, nd_rows);
+  Tree trees[2];
+  build_tree(md, md_rows, trees[0]);
+  build_tree(nd, nd_rows, trees[1]);
   const int cand[] = {2, 3, 4, 6, 9, 14, 20, 1 << 30};
   TileShape best;
   std::vector<int> best_ord;
   int best_thr = 0;
-  for (int thr : cand) {
-    std::vector<int> ord;
-    std::vector<uint8_t> pad;
-    layout_order(T, thr, ord, pad);
-    TileShape sh;
-    tile_shape(n, adj, ord, pad, sh);
-    if (sh.nt > kTcMaxTiles) continue;
-    if (best_thr == 0 || sh.nlev < best.nlev || (sh.nlev == best.nlev && sh.nslot < best.nslot)) {
-      best = std::move(sh);
-      best_ord = ord;
-      best_thr = thr;
+  for (const Tree& T : trees)
+    for (int thr : cand) {
+      std::vector<int> ord;
+      std::vector<uint8_t> pad;
+      layout_order(T, thr, ord, pad);
+      TileShape sh;
+      tile_shape(n, adj, ord, pad, sh);
+      if (sh.nt > kTcMaxTiles) continue;
+      if (best_thr == 0 || sh.nlev < best.nlev || (sh.nlev == best.nlev && sh.nslot < best.nslot)) {
+        best = std::move(sh);
+        best_ord = ord;
+        best_thr = thr;
+      }
     }
-  }
   if (best_thr == 0) return fail(DS3_ENOSPACE, "tilechol: more than 1024 tiles in every layout");
   S.n_kf = n;
   S.n = 7 * n;
