@@ -37,6 +37,7 @@
 // solver's (shared tile primitives). Attempt 0 runs this way; when it fails, the dense solver's
 // persistent fallback runs attempts 1.. from H in the caller's dense workspace.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -208,14 +209,17 @@ void eliminate(int n, std::vector<uint64_t> adj, const std::vector<int>& order, 
 //   * at most kNdLeaf keyframes: increasing id;
 //   * otherwise a breadth-first search of the set from its smallest id, repeated three times from the
 //     farthest vertex found (the smallest id among the farthest), gives levels from a pseudo-peripheral
-//     vertex; with fewer than three levels (too dense to split) the set keeps increasing id; else the cut
-//     level c is the smallest of 1 .. L-1 (L the last level) holding half the set with the levels below
-//     it (L-1 if none does); the near side is the levels below c plus the level-c vertices with no
-//     neighbour on level c+1, the far side the levels above c, the separator the rest of level c; the
-//     near side, then the far side are ordered recursively, then the separator in increasing id.
+//     vertex; with fewer than three levels (too dense to split) the set keeps increasing id; else the
+//     balanced level c0 is the smallest of 1 .. L-1 (L the last level) holding half the set with the
+//     levels below it (L-1 if none does). A cut at level c splits the set into the near side (the levels
+//     below c plus the level-c vertices with no neighbour on level c+1), the far side (the levels above c)
+//     and the separator (the rest of level c); among the cuts c0 - window .. c0 + window within 1 .. L-1
+//     the one with the smallest separator, then the smallest difference of the sides, then the lowest
+//     level is taken. The near side, then the far side are ordered recursively, then the separator in
+//     increasing id.
 // On chains of keyframes the elimination tree is then about logarithmic in height instead of linear.
 constexpr int kNdLeaf = 4;
-void nd_order(int n, const std::vector<std::vector<int>>& adj, std::vector<int>& order) {
+void nd_order(int n, const std::vector<std::vector<int>>& adj, int window, std::vector<int>& order) {
   order.clear();
   std::vector<int> stamp(n, 0), lev(n, -1), comp(n, -1);
   int epoch = 0;
@@ -294,17 +298,28 @@ void nd_order(int n, const std::vector<std::vector<int>>& adj, std::vector<int>&
     }
     std::vector<int> cnt(L + 1, 0);
     for (int v : S) ++cnt[lev[v]];
-    int cut = 1, below = cnt[0];
-    while (cut < L - 1 && 2 * (below + cnt[cut]) < int(S.size())) below += cnt[cut++];
+    int c0 = 1, below = cnt[0];
+    while (c0 < L - 1 && 2 * (below + cnt[c0]) < int(S.size())) below += cnt[c0++];
     std::vector<int> a, b, sep;
-    for (int v : S) {
-      if (lev[v] < cut) a.push_back(v);
-      else if (lev[v] > cut) b.push_back(v);
-      else {
-        bool far = false;
-        for (int u : adj[v])
-          if (stamp[u] == epoch && lev[u] == cut + 1) far = true;
-        (far ? sep : a).push_back(v);
+    long best_key = -1;
+    for (int cut = std::max(1, c0 - window); cut <= std::min(L - 1, c0 + window); ++cut) {
+      std::vector<int> ca, cb, cs2;
+      for (int v : S) {
+        if (lev[v] < cut) ca.push_back(v);
+        else if (lev[v] > cut) cb.push_back(v);
+        else {
+          bool far = false;
+          for (int u : adj[v])
+            if (stamp[u] == epoch && lev[u] == cut + 1) far = true;
+          (far ? cs2 : ca).push_back(v);
+        }
+      }
+      const long key = long(cs2.size()) * (n + 1) + std::abs(int(ca.size()) - int(cb.size()));
+      if (best_key < 0 || key < best_key) {
+        best_key = key;
+        a.swap(ca);
+        b.swap(cb);
+        sep.swap(cs2);
       }
     }
     std::sort(sep.begin(), sep.end());
@@ -351,15 +366,18 @@ static int tc_symbolic(int n_kf, int n_pairs, const int32_t* pair_ij, TcSymbolic
     for (auto& c : T.child) std::sort(c.begin(), c.end(), by_size);
     std::sort(T.roots.begin(), T.roots.end(), by_size);
   };
-  // two elimination orders (minimum degree, nested dissection) x the alignment thresholds: the fewest tree
-  // levels, then the fewest factor tiles
-  std::vector<int> nd;
-  std::vector<std::vector<int>> nd_rows;
-  nd_order(n, adj, nd);
-  eliminate(n, bits, nd, nd_rows);
-  Tree trees[2];
+  // elimination orders x the alignment thresholds: the fewest tree levels, then the fewest factor tiles
+  // candidates: minimum degree, nested dissection at the balanced cut, and with the smallest separator
+  // among the cuts one level around it
+  Tree trees[3];
   build_tree(md, md_rows, trees[0]);
-  build_tree(nd, nd_rows, trees[1]);
+  for (int window = 0; window < 2; ++window) {
+    std::vector<int> nd;
+    std::vector<std::vector<int>> nd_rows;
+    nd_order(n, adj, window, nd);
+    eliminate(n, bits, nd, nd_rows);
+    build_tree(nd, nd_rows, trees[1 + window]);
+  }
   const int cand[] = {2, 3, 4, 6, 9, 14, 20, 1 << 30};
   TileShape best;
   std::vector<int> best_ord;

@@ -1,19 +1,22 @@
 """Host-side analysis of the tile-sparse solver (ds3_tilechol_analyse; no GPU). The keyframe layout, the tile
 pattern, its symbolic factorisation, the tile elimination tree's levels and the update count are recomputed
 here from their definitions and must agree exactly:
-  * two elimination orders of the keyframe graph and their trees: minimum degree (ties to the lowest id)
-    and nested dissection (sets in increasing id; components in turn by smallest id; sets of at most 4
-    keyframes in id order; else breadth-first levels from a pseudo-peripheral vertex, found by three
-    searches each restarted at the smallest id among the farthest vertices, starting from the set's
-    smallest id; sets with fewer than three levels in id order; else the cut level is the smallest of
-    1 .. L-1 whose levels up to it hold half the set (L-1 if none), the near side is the levels below it
-    plus the cut-level vertices with no neighbour on the next level, the far side the levels above it, the
-    separator the rest; near side, far side, then the separator in id order);
+  * three elimination orders of the keyframe graph and their trees: minimum degree (ties to the lowest id)
+    and nested dissection with a cut window of 0 and of 1 (sets in increasing id; components in turn by
+    smallest id; sets of at most 4 keyframes in id order; else breadth-first levels from a
+    pseudo-peripheral vertex, found by three searches each restarted at the smallest id among the
+    farthest vertices, starting from the set's smallest id; sets with fewer than three levels in id
+    order; else the balanced level c0 is the smallest of 1 .. L-1 whose levels up to it hold half the set
+    (L-1 if none); a cut at level c splits off the near side (the levels below c plus the level-c
+    vertices with no neighbour on level c+1), the far side (the levels above c) and the separator (the
+    rest); among the cuts c0 - window .. c0 + window within 1 .. L-1 the smallest separator, then the
+    smallest difference of the sides, then the lowest level wins; near side, far side, then the
+    separator in id order);
   * a postorder of that tree, children in increasing (subtree size, id), in which every child but the last
     one laid out that holds at least `thr` keyframes starts and ends on a 32-row tile boundary (roots are
     the children of a virtual root);
-  * the order and threshold with the fewest levels, then the fewest factor tiles, among both orders (minimum
-    degree first) x 2, 3, 4, 6, 9, 14, 20, none (a tie keeps the earlier);
+  * the order and threshold with the fewest levels, then the fewest factor tiles, among the three orders
+    (in that order) x 2, 3, 4, 6, 9, 14, 20, none (a tie keeps the earlier);
   * the tile pattern: tiles (I, J) holding part of a block of H (a keyframe's diagonal block or a listed
     pair), closed under elimination column by column (column K's rows below its first one join that row's
     column);
@@ -63,7 +66,7 @@ def _md_tree(n, pairs):
     return _tree(n, order, rows)
 
 
-def _nd_order(n, pairs):
+def _nd_order(n, pairs, window):
     adj = _adjacency(n, pairs)
     order = []
 
@@ -115,20 +118,27 @@ def _nd_order(n, pairs):
             order.extend(S)
             return
         cnt = [sum(1 for v in S if lev[v] == k) for k in range(L + 1)]
-        cut = next((c for c in range(1, L) if 2 * sum(cnt[:c + 1]) >= len(S)), L - 1)
-        far = lambda v: any(u in lev and lev[u] == cut + 1 for u in adj[v])
-        near = [v for v in S if lev[v] < cut or (lev[v] == cut and not far(v))]
-        sep = [v for v in S if lev[v] == cut and far(v)]
+        c0 = next((c for c in range(1, L) if 2 * sum(cnt[:c + 1]) >= len(S)), L - 1)
+        best = None
+        for cut in range(max(1, c0 - window), min(L - 1, c0 + window) + 1):
+            far = lambda v: any(u in lev and lev[u] == cut + 1 for u in adj[v])
+            near = [v for v in S if lev[v] < cut or (lev[v] == cut and not far(v))]
+            sep = [v for v in S if lev[v] == cut and far(v)]
+            farside = [v for v in S if lev[v] > cut]
+            key = (len(sep), abs(len(near) - len(farside)))
+            if best is None or key < best[0]:
+                best = (key, near, farside, sep)
+        _, near, farside, sep = best
         nd(near)
-        nd([v for v in S if lev[v] > cut])
+        nd(farside)
         order.extend(sorted(sep))
 
     nd(list(range(n)))
     return order
 
 
-def _nd_tree(n, pairs):
-    order = _nd_order(n, pairs)
+def _nd_tree(n, pairs, window):
+    order = _nd_order(n, pairs, window)
     adj = _adjacency(n, pairs)
     rows = {}
     for v in order:  # symbolic elimination in the given order
@@ -199,7 +209,7 @@ def _tiles(n, pairs, row0, np_):
 
 def _reference(n, pairs):
     best, best_tree = None, None
-    for tree in (_md_tree(n, pairs), _nd_tree(n, pairs)):
+    for tree in (_md_tree(n, pairs), _nd_tree(n, pairs, 0), _nd_tree(n, pairs, 1)):
         for thr in THRESHOLDS:
             row0, np_ = _layout(n, tree, thr)
             nt, slots, nlev, updates = _tiles(n, pairs, row0, np_)
