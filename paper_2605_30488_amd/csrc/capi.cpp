@@ -697,15 +697,15 @@ static int plan_autotune(Plan& P, hipStream_t s) {
     P.unroll = best_unroll;
     return plan_build_items(P, best_ppt, s);
   }
-  // per segment size, the records-in-flight variants are timed in interleaved rounds and each keeps its
-  // fastest round: the variants differ by a few percent, less than the clock drifts over a sweep
-  constexpr int kRounds = 3;
+  // per segment size, the records-in-flight variants are timed in interleaved passes and each keeps its
+  // fastest pass: the variants differ by a few percent, less than the clock drifts over a sweep
+  constexpr int kPasses = 3;
   constexpr int kUnrolls[3] = {1, 2, 4};
   float best = 1e30f;
   for (int ppt : {8, 16, 32, 64}) {
     DS3_TRY(plan_build_items(P, ppt, s));
     float t[3] = {1e30f, 1e30f, 1e30f};
-    for (int r = 0; r < kRounds; ++r)
+    for (int r = 0; r < kPasses; ++r)
       for (int u = 0; u < 3; ++u) {
         P.unroll = kUnrolls[u];
         float ms = 0.f;
