@@ -288,10 +288,12 @@ void ds3_spchol_destroy(ds3_spchol* S);
 
 /* Tile-sparse form of ds3_chol_ladder_solve for the same keyframe-pair pattern (eq. (7) and the epsilon
  * ladder after it). The dense solver's float64 32x32 tiles, laid out so that the pose graph's independent
- * parts fall into different tiles: a minimum-degree elimination order of the keyframe graph, a postorder
- * of its elimination tree in which sibling subtrees of at least `thr` keyframes (all but the largest child
- * of a node) start and end on tile boundaries (padding rows are identity rows), the symbolic tile
- * factorisation of that layout and its tile elimination tree. Attempt 0 then runs one launch per tree
+ * parts fall into different tiles: an elimination order of the keyframe graph (minimum degree, or nested
+ * dissection cut at the balanced breadth-first level or at the smallest separator one level around it), a
+ * postorder of its elimination tree in which sibling subtrees of at least `thr` keyframes (all but the
+ * largest child of a node) start and end on tile boundaries (padding rows are identity rows), the symbolic
+ * tile factorisation of that layout and its tile elimination tree; the order and threshold with the fewest
+ * tree levels, then the fewest tiles, are kept. Attempt 0 then runs one launch per tree
  * level (instead of one per 32-row panel) and a dataflow back substitution over the tree; attempts 1..
  * run in the dense solver's persistent fallback.
  * ds3_tilechol_analyse (host only, no device use): the analysis of n_kf keyframes (1 <= n_kf <= 1170)
